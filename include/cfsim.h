@@ -1,0 +1,158 @@
+/*
+ * cfsim.h - C ABI of the MI355X complementarity-free contact step.
+ *
+ * The library advances batches of independent worlds by one time step of the
+ * complementarity-free contact model (arXiv 2603.12185, Sec. III):
+ *   v_s  = v + h M^-1 (tau - c)                         (Eq. smooth_vel)
+ *   per contact k, per facet f of its polyhedral dual cone (Eqs. dual_polyhedral,
+ *   tilde_defs) with rows J~ = J_n - mu_s d_f^T J_s:
+ *   lambda h = A_k * max(-(k_user h + d_user) J~ v_s - k_user phi_k, 0)  (Eq. cf_wrench,
+ *        with K = k_user A / h, D = d_user A / h of Eq. k_d_setting and
+ *        A_k = r/(1-r) / (tr(J_a M^-1 J_a^T) + tr(J_b M^-1 J_b^T)), r of Eq. r_scaling)
+ *   v+   = v_s + M^-1 sum J~^T lambda h                  (Eq. vel_correction)
+ *   q+   = q (+) h v+  (semi-implicit Euler)
+ * Algorithm 1 of the paper lists the same four stages; the contact set comes
+ * from the library's own analytic narrow phase.
+ *
+ * Conventions
+ *  - Quaternions (w,x,y,z).  A free joint has q = (COM position, orientation)
+ *    and v = (COM linear velocity, angular velocity), both in world
+ *    coordinates; a state quaternion denotes the rotation of its normalised
+ *    value and is re-normalised by every step.
+ *  - Contact normal n points from geom a to geom b; a plane is always geom a;
+ *    phi > 0 means separated; the contact point is the middle of the overlap;
+ *    a contact exists when phi < margin.
+ *  - Tangent basis: helper e_x if |n_x| <= 0.5 else e_y; t1 = normalised
+ *    component of the helper orthogonal to n; t2 = n x t1.
+ *  - Facet order per contact: tangential d = (1,0),(0,1),(-1,0),(0,-1) in
+ *    (t1,t2); torsional sigma = +1,-1; rolling d as tangential.  condim 1, 3,
+ *    4, 6 give 1, 4, 6, 10 facets.  Pair friction is the element-wise max of
+ *    the two geoms' (mu_t, mu_tor, mu_rol).
+ *  - Contact order: geom pairs (i < j) in index order, then the sub-contact
+ *    index (box corner bits x,y,z = bit 0,1,2 set for +half-size; capsule
+ *    minus end first).  Only the first ncon_max contacts of a world are kept
+ *    and resolved; the rest are counted in overflow.
+ *  - Pairs that never produce contacts: both geoms static, same body,
+ *    parent-child bodies, and types other than plane-sphere, plane-capsule,
+ *    plane-box and sphere-sphere (cf_model_create then returns
+ *    CF_W_PAIRS_SKIPPED, a warning).
+ *
+ * Memory, streams and errors
+ *  - Descriptor arrays are host memory, read during cf_model_create only.
+ *  - State, tau and contact views are caller-owned, contiguous float32/int32
+ *    DEVICE buffers on the device that was current at cf_model_create.
+ *    q_out/v_out may alias q/v exactly (not partially).
+ *  - All compute calls are asynchronous on the given stream (a hipStream_t;
+ *    NULL = default stream) and never synchronise.  The returned status covers
+ *    argument checks and launch errors; device-side conditions (contact
+ *    overflow) are reported through cf_contacts.overflow.
+ *  - A model is not thread-safe (it owns one contact workspace); distinct
+ *    models are independent.  cf_last_error() is per thread.
+ */
+#ifndef CFSIM_H
+#define CFSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CF_ABI_VERSION 1
+
+typedef struct cf_model cf_model;
+typedef int32_t cf_status;
+
+enum {
+  CF_OK = 0,
+  CF_W_PAIRS_SKIPPED = 1, /* warning: some geom pairs have no contact rule     */
+  CF_E_INVALID_ARG = -1,  /* bad descriptor, size, pointer or alignment        */
+  CF_E_DEVICE = -2,       /* HIP runtime error (launch, copy, event)           */
+  CF_E_NOMEM = -3,        /* device allocation failed                          */
+  CF_E_UNSUPPORTED = -4   /* valid model outside what this library implements  */
+};
+
+enum { CF_PLANE = 0, CF_SPHERE = 1, CF_CAPSULE = 2, CF_BOX = 3 };
+enum { CF_JNT_FREE = 0, CF_JNT_HINGE = 1, CF_JNT_SLIDE = 2 };
+
+/* Model description (host memory, copied at create).  nworld worlds share the
+ * tree and geom types; masses, inertias and geom data may differ per world.
+ * Sizes: geom sizes are (radius) for spheres, (radius, half-length along local
+ * z) for capsules, half-sizes for boxes; planes use their local z as normal. */
+typedef struct {
+  int32_t nworld, nbody, ngeom, ncon_max, condim;  /* condim in {1,3,4,6}               */
+  const int32_t *body_parent;   /* [nbody] -1 = world; must be < own index            */
+  const int32_t *body_jnt;      /* [nbody] one joint per body (CF_JNT_*)              */
+  const double *body_pos;       /* [nbody][3] body frame in parent frame at q = 0      */
+  const double *body_quat;      /* [nbody][4]                                          */
+  const double *body_ipos;      /* [nbody][3] COM in the body frame (0 for free)       */
+  const double *jnt_axis;       /* [nbody][3] hinge/slide axis in the body frame       */
+  const double *body_mass;      /* [nworld][nbody]                                     */
+  const double *body_inertia;   /* [nworld][nbody][3] principal, about the COM         */
+  const int32_t *geom_type;     /* [ngeom] CF_PLANE..CF_BOX                            */
+  const int32_t *geom_body;     /* [ngeom] -1 = static                                 */
+  const double *geom_size;      /* [nworld][ngeom][3]                                  */
+  const double *geom_pos;       /* [nworld][ngeom][3] in the body (or world) frame     */
+  const double *geom_quat;      /* [nworld][ngeom][4]                                  */
+  const double *geom_friction;  /* [nworld][ngeom][3] (mu_t, mu_tor, mu_rol)           */
+  double h;                     /* time step > 0                                       */
+  double gravity[3];
+  double k_user, d_user;        /* >= 0; k_user in 1/s, d_user dimensionless           */
+  double solimp[5];             /* r_min, r_max, width, midpoint, power (Eq. r_scaling) */
+  double margin;                /* contact when phi < margin                           */
+} cf_model_desc;
+
+/* Optional contact outputs of a step (device memory, caller-owned; any
+ * pointer may be NULL).  Rows past ncon[w] are left untouched. */
+typedef struct {
+  int32_t *ncon;      /* [nworld] contacts kept                                  */
+  int32_t *overflow;  /* [nworld] contacts dropped beyond ncon_max               */
+  int32_t *geom;      /* [nworld][ncon_max][2] geom a, geom b                    */
+  int32_t *sub;       /* [nworld][ncon_max] sub-contact index (corner / end)     */
+  float *dist;        /* [nworld][ncon_max] phi                                  */
+  float *pos;         /* [nworld][ncon_max][3] contact point                     */
+  float *frame;       /* [nworld][ncon_max][9] rows n, t1, t2                    */
+  float *impulse;     /* [nworld][ncon_max][nfacet] lambda*h per facet           */
+} cf_contacts;
+
+/* Validate the descriptor, upload per-world constants and size the contact
+ * workspace (nworld * ncon_max records) on the current HIP device.  Returns
+ * CF_OK or CF_W_PAIRS_SKIPPED with *out set, else an error with *out = NULL.
+ * This version implements free joints only (hinge/slide: CF_E_UNSUPPORTED);
+ * free bodies need mass > 0 and inertia > 0. */
+cf_status cf_model_create(const cf_model_desc *desc, cf_model **out);
+
+/* Free the model's device memory (synchronises the device first).  NULL is a no-op. */
+void cf_model_destroy(cf_model *m);
+
+/* nq, nv per world and facets per contact; any pointer may be NULL. */
+cf_status cf_model_dims(const cf_model *m, int32_t *nq, int32_t *nv, int32_t *nfacet);
+
+/* One step of every world (Algorithm 1 preceded by collision detection and
+ * followed by integration).  q [nworld][nq], v and tau [nworld][nv] (tau NULL
+ * = zero applied force), q_out/v_out same shapes.  All float32, 16-byte
+ * aligned device pointers.  out may be NULL. */
+cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
+                  float *q_out, float *v_out, const cf_contacts *out);
+
+/* T consecutive steps: q_traj/v_traj [T+1][nworld][nq|nv] receive the initial
+ * state (copied from q0/v0 unless they already alias row 0) and every step's
+ * result; tau_seq [T][nworld][nv] or NULL.  T >= 0. */
+cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
+                     const float *tau_seq, float *q_traj, float *v_traj);
+
+/* Kernel timing.  When enabled, every cf_step records HIP events around its
+ * collision and resolution kernels on the step's stream.  cf_model_kernel_times
+ * waits for the recorded events, returns the summed milliseconds of each
+ * kernel and the number of steps since the last call, and resets the sums. */
+cf_status cf_model_set_profiling(cf_model *m, int32_t enable);
+cf_status cf_model_kernel_times(cf_model *m, double *ms_collide, double *ms_resolve,
+                                int64_t *nsteps);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *cf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,387 @@
+// cf_api.hip - host side of the C ABI declared in include/cfsim.h.
+//
+// Validates the model description, builds the canonical candidate-slot table,
+// uploads per-world constants as float32 and owns the contact workspace.
+// cf_step enqueues the collision kernel then the resolution kernel on the
+// caller's stream; nothing here synchronises except create/destroy and the
+// explicit timing query.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cfsim.h"
+#include "cf_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+cf_status set_err(cf_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+struct EventSet {
+  hipEvent_t e[3];
+};
+
+}  // namespace
+
+struct cf_model {
+  int dev = 0;
+  int nw = 0, nb = 0, ng = 0, nq = 0, nv = 0, ncon_max = 0, condim = 3, nf = 4, nbits = 1;
+  int nslot = 0;
+  cf::Params p{};
+  // device constants
+  uint32_t *d_slots = nullptr;
+  int *d_gbody = nullptr;
+  float4 *d_bmi = nullptr, *d_gdat = nullptr, *d_gpos = nullptr, *d_gquat = nullptr;
+  float2 *d_gfr2 = nullptr;
+  int gpos_ws = 0, gquat_ws = 0;
+  // workspace
+  float4 *d_cnp = nullptr, *d_cpos = nullptr;
+  int *d_ncon = nullptr, *d_over = nullptr;
+  size_t lds_collide = 0, lds_resolve = 0;
+  // timing
+  bool prof = false;
+  std::vector<EventSet> events;
+  size_t ev_used = 0;
+  double ms_collide = 0, ms_resolve = 0;
+  long long prof_steps = 0;
+};
+
+namespace {
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+  size_t bytes = sizeof(T) * (src.empty() ? 1 : src.size());
+  hipError_t e = hipMalloc((void **)dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+void free_model(cf_model *m) {
+  if (!m) return;
+  (void)hipFree(m->d_slots); (void)hipFree(m->d_gbody); (void)hipFree(m->d_bmi); (void)hipFree(m->d_gdat);
+  (void)hipFree(m->d_gpos); (void)hipFree(m->d_gquat); (void)hipFree(m->d_gfr2);
+  (void)hipFree(m->d_cnp); (void)hipFree(m->d_cpos); (void)hipFree(m->d_ncon); (void)hipFree(m->d_over);
+  for (auto &s : m->events)
+    for (auto e : s.e) (void)hipEventDestroy(e);
+  delete m;
+}
+
+bool finite_all(const double *a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// Drain recorded events into the per-kernel sums.
+cf_status drain_events(cf_model *m) {
+  for (size_t i = 0; i < m->ev_used; ++i) {
+    EventSet &s = m->events[i];
+    if (hipEventSynchronize(s.e[2]) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventSynchronize failed");
+    float a = 0, b = 0;
+    if (hipEventElapsedTime(&a, s.e[0], s.e[1]) != hipSuccess ||
+        hipEventElapsedTime(&b, s.e[1], s.e[2]) != hipSuccess)
+      return set_err(CF_E_DEVICE, "hipEventElapsedTime failed");
+    m->ms_collide += a;
+    m->ms_resolve += b;
+  }
+  m->prof_steps += (long long)m->ev_used;
+  m->ev_used = 0;
+  return CF_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *cf_last_error(void) { return g_err.c_str(); }
+
+cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
+  g_err.clear();
+  if (!out) return set_err(CF_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d) return set_err(CF_E_INVALID_ARG, "desc is NULL");
+  const int nw = d->nworld, nb = d->nbody, ng = d->ngeom;
+  if (nw < 1) return set_err(CF_E_INVALID_ARG, "nworld must be >= 1");
+  if (nb < 0 || ng < 0 || d->ncon_max < 0) return set_err(CF_E_INVALID_ARG, "negative size");
+  if (!(d->condim == 1 || d->condim == 3 || d->condim == 4 || d->condim == 6))
+    return set_err(CF_E_INVALID_ARG, "condim must be 1, 3, 4 or 6");
+  if (!(d->h > 0) || !std::isfinite(d->h)) return set_err(CF_E_INVALID_ARG, "h must be finite and > 0");
+  if (!(d->k_user >= 0) || !(d->d_user >= 0) || !std::isfinite(d->k_user) || !std::isfinite(d->d_user))
+    return set_err(CF_E_INVALID_ARG, "k_user and d_user must be finite and >= 0");
+  const double *si = d->solimp;
+  if (!(si[0] > 0 && si[0] <= si[1] && si[1] < 1)) return set_err(CF_E_INVALID_ARG, "need 0 < r_min <= r_max < 1");
+  if (!(si[2] > 0)) return set_err(CF_E_INVALID_ARG, "solimp width must be > 0");
+  if (!(si[3] > 0 && si[3] < 1)) return set_err(CF_E_INVALID_ARG, "solimp midpoint must be in (0, 1)");
+  if (!(si[4] >= 1)) return set_err(CF_E_INVALID_ARG, "solimp power must be >= 1");
+  if (!finite_all(d->gravity, 3) || !std::isfinite(d->margin)) return set_err(CF_E_INVALID_ARG, "non-finite gravity or margin");
+  if (nb > 0 && (!d->body_parent || !d->body_jnt || !d->body_mass || !d->body_inertia || !d->body_ipos))
+    return set_err(CF_E_INVALID_ARG, "missing body arrays");
+  if (ng > 0 && (!d->geom_type || !d->geom_body || !d->geom_size || !d->geom_pos || !d->geom_quat ||
+                 !d->geom_friction))
+    return set_err(CF_E_INVALID_ARG, "missing geom arrays");
+  for (int b = 0; b < nb; ++b) {
+    const int par = d->body_parent[b], t = d->body_jnt[b];
+    if (par < -1 || par >= b) return set_err(CF_E_INVALID_ARG, "body_parent must be -1 or a lower index");
+    if (t != CF_JNT_FREE && t != CF_JNT_HINGE && t != CF_JNT_SLIDE) return set_err(CF_E_INVALID_ARG, "bad joint type");
+    if (t == CF_JNT_FREE) {
+      if (par != -1) return set_err(CF_E_INVALID_ARG, "free joints only on bodies whose parent is the world");
+      const double *ip = d->body_ipos + 3 * b;
+      if (ip[0] != 0 || ip[1] != 0 || ip[2] != 0) return set_err(CF_E_INVALID_ARG, "free bodies need body_ipos = 0");
+    }
+  }
+  for (int b = 0; b < nb; ++b)
+    if (d->body_jnt[b] != CF_JNT_FREE)
+      return set_err(CF_E_UNSUPPORTED, "this version implements free joints only (hinge/slide unsupported)");
+  for (int w = 0; w < nw; ++w)
+    for (int b = 0; b < nb; ++b) {
+      const double m = d->body_mass[(size_t)w * nb + b];
+      const double *I = d->body_inertia + ((size_t)w * nb + b) * 3;
+      if (!(m > 0) || !(I[0] > 0) || !(I[1] > 0) || !(I[2] > 0) || !std::isfinite(m) || !finite_all(I, 3))
+        return set_err(CF_E_INVALID_ARG, "free bodies need finite mass > 0 and inertia > 0");
+    }
+  if (ng > cf::kMaxGeom) return set_err(CF_E_UNSUPPORTED, "ngeom exceeds 8191");
+  for (int g = 0; g < ng; ++g) {
+    const int t = d->geom_type[g], b = d->geom_body[g];
+    if (t < CF_PLANE || t > CF_BOX) return set_err(CF_E_INVALID_ARG, "bad geom type");
+    if (b < -1 || b >= nb) return set_err(CF_E_INVALID_ARG, "bad geom_body");
+  }
+  const size_t wg = (size_t)nw * ng;
+  if (ng > 0 && (!finite_all(d->geom_size, 3 * wg) || !finite_all(d->geom_pos, 3 * wg) ||
+                 !finite_all(d->geom_quat, 4 * wg) || !finite_all(d->geom_friction, 3 * wg)))
+    return set_err(CF_E_INVALID_ARG, "non-finite geom data");
+  for (size_t i = 0; i < wg; ++i) {
+    const double *q = d->geom_quat + 4 * i;
+    if (!(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] > 0)) return set_err(CF_E_INVALID_ARG, "zero geom_quat");
+  }
+  for (size_t i = 0; i < 3 * wg; ++i)
+    if (d->geom_friction[i] < 0) return set_err(CF_E_INVALID_ARG, "negative friction");
+
+  // ---- candidate slots in canonical order
+  std::vector<uint32_t> slots;
+  bool skipped = false;
+  for (int i = 0; i < ng; ++i)
+    for (int j = i + 1; j < ng; ++j) {
+      const int bi = d->geom_body[i], bj = d->geom_body[j];
+      if (bi < 0 && bj < 0) continue;
+      if (bi == bj) continue;
+      if (bi >= 0 && bj >= 0 && (d->body_parent[bi] == bj || d->body_parent[bj] == bi)) continue;
+      const int ti = d->geom_type[i], tj = d->geom_type[j];
+      int ga = i, gb = j;
+      if (tj == CF_PLANE && ti != CF_PLANE) { ga = j; gb = i; }
+      const int ta = d->geom_type[ga], tb = d->geom_type[gb];
+      if (ta == CF_PLANE && tb == CF_SPHERE) slots.push_back(cf::slot_pack(ga, gb, 0, cf::kPlaneSphere));
+      else if (ta == CF_PLANE && tb == CF_CAPSULE)
+        for (int e = 0; e < 2; ++e) slots.push_back(cf::slot_pack(ga, gb, e, cf::kPlaneCapsule));
+      else if (ta == CF_PLANE && tb == CF_BOX)
+        for (int c = 0; c < 8; ++c) slots.push_back(cf::slot_pack(ga, gb, c, cf::kPlaneBox));
+      else if (ta == CF_SPHERE && tb == CF_SPHERE) slots.push_back(cf::slot_pack(ga, gb, 0, cf::kSphereSphere));
+      else skipped = true;
+    }
+
+  cf_model *m = new cf_model();
+  m->nw = nw; m->nb = nb; m->ng = ng; m->ncon_max = d->ncon_max; m->condim = d->condim;
+  m->nf = d->condim == 1 ? 1 : d->condim == 3 ? 4 : d->condim == 4 ? 6 : 10;
+  m->nq = 7 * nb; m->nv = 6 * nb;
+  m->nslot = (int)slots.size();
+  m->nbits = 1;
+  while ((1 << m->nbits) <= nb) ++m->nbits;  // keys 0..nb (nb = no body)
+  m->p.h = (float)d->h; m->p.k_user = (float)d->k_user; m->p.d_user = (float)d->d_user;
+  m->p.margin = (float)d->margin;
+  m->p.gx = (float)d->gravity[0]; m->p.gy = (float)d->gravity[1]; m->p.gz = (float)d->gravity[2];
+  m->p.r_min = (float)si[0]; m->p.r_max = (float)si[1]; m->p.width = (float)si[2];
+  m->p.mid = (float)si[3]; m->p.power = (float)si[4];
+  m->lds_collide = cf::collide_lds_bytes(m->nq, ng);
+  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng);
+  const size_t lds_limit = 64 * 1024;
+  if (m->lds_collide > lds_limit || m->lds_resolve > lds_limit) {
+    delete m;
+    return set_err(CF_E_UNSUPPORTED, "world too large for one workgroup's LDS (reduce bodies or geoms)");
+  }
+  if (hipGetDevice(&m->dev) != hipSuccess) { delete m; return set_err(CF_E_DEVICE, "no HIP device"); }
+
+  // ---- per-world constants (float32); shared arrays get world stride 0
+  std::vector<float4> bmi((size_t)nw * nb), gdat(wg), gpos, gquat;
+  std::vector<float2> gfr2;
+  for (size_t i = 0; i < (size_t)nw * nb; ++i) {
+    const double *I = d->body_inertia + 3 * i;
+    bmi[i] = make_float4((float)d->body_mass[i], (float)I[0], (float)I[1], (float)I[2]);
+  }
+  for (size_t i = 0; i < wg; ++i) {
+    const double *s = d->geom_size + 3 * i, *f = d->geom_friction + 3 * i;
+    gdat[i] = make_float4((float)s[0], (float)s[1], (float)s[2], (float)f[0]);
+  }
+  auto uniform = [&](const double *a, int width) {
+    for (int w = 1; w < nw; ++w)
+      if (std::memcmp(a, a + (size_t)w * ng * width, sizeof(double) * ng * width) != 0) return false;
+    return true;
+  };
+  m->gpos_ws = (ng > 0 && uniform(d->geom_pos, 3)) ? 0 : ng;
+  m->gquat_ws = (ng > 0 && uniform(d->geom_quat, 4)) ? 0 : ng;
+  const size_t npw = m->gpos_ws ? wg : (size_t)ng, nqw = m->gquat_ws ? wg : (size_t)ng;
+  gpos.resize(npw);
+  gquat.resize(nqw);
+  for (size_t i = 0; i < npw; ++i) {
+    const double *p = d->geom_pos + 3 * i;
+    gpos[i] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
+  }
+  for (size_t i = 0; i < nqw; ++i) {
+    const double *q = d->geom_quat + 4 * i;
+    gquat[i] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);  // (w,x,y,z) in (x,y,z,w)
+  }
+  if (m->condim >= 4) {
+    gfr2.resize(wg);
+    for (size_t i = 0; i < wg; ++i)
+      gfr2[i] = make_float2((float)d->geom_friction[3 * i + 1], (float)d->geom_friction[3 * i + 2]);
+  }
+  std::vector<int> gbody(ng);
+  for (int g = 0; g < ng; ++g) gbody[g] = d->geom_body[g];
+
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+  chk(upload(&m->d_slots, slots));
+  chk(upload(&m->d_gbody, gbody));
+  chk(upload(&m->d_bmi, bmi));
+  chk(upload(&m->d_gdat, gdat));
+  chk(upload(&m->d_gpos, gpos));
+  chk(upload(&m->d_gquat, gquat));
+  if (m->condim >= 4) chk(upload(&m->d_gfr2, gfr2));
+  const size_t ncap = (size_t)nw * (m->ncon_max > 0 ? m->ncon_max : 1);
+  chk(hipMalloc((void **)&m->d_cnp, sizeof(float4) * ncap));
+  chk(hipMalloc((void **)&m->d_cpos, sizeof(float4) * ncap));
+  chk(hipMalloc((void **)&m->d_ncon, sizeof(int) * nw));
+  chk(hipMalloc((void **)&m->d_over, sizeof(int) * nw));
+  if (e == hipSuccess) chk(hipMemset(m->d_ncon, 0, sizeof(int) * nw));
+  if (e != hipSuccess) {
+    const bool oom = e == hipErrorOutOfMemory;
+    std::string msg = std::string("device setup failed: ") + hipGetErrorString(e);
+    free_model(m);
+    return set_err(oom ? CF_E_NOMEM : CF_E_DEVICE, msg);
+  }
+  *out = m;
+  if (skipped) {
+    g_err = "some geom pairs have no contact rule and never collide";
+    return CF_W_PAIRS_SKIPPED;
+  }
+  return CF_OK;
+}
+
+void cf_model_destroy(cf_model *m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  free_model(m);
+}
+
+cf_status cf_model_dims(const cf_model *m, int32_t *nq, int32_t *nv, int32_t *nf) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (nq) *nq = m->nq;
+  if (nv) *nv = m->nv;
+  if (nf) *nf = m->nf;
+  return CF_OK;
+}
+
+cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
+                  float *q_out, float *v_out, const cf_contacts *out) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (!q || !v || !q_out || !v_out) return set_err(CF_E_INVALID_ARG, "q, v, q_out, v_out must be non-NULL");
+  if (!aligned16(q) || !aligned16(v) || !aligned16(q_out) || !aligned16(v_out) || (tau && !aligned16(tau)))
+    return set_err(CF_E_INVALID_ARG, "state buffers must be 16-byte aligned");
+  if ((q_out != q && q_out < q + (size_t)m->nw * m->nq && q < q_out + (size_t)m->nw * m->nq) ||
+      (v_out != v && v_out < v + (size_t)m->nw * m->nv && v < v_out + (size_t)m->nw * m->nv))
+    return set_err(CF_E_INVALID_ARG, "outputs may alias inputs only exactly");
+  hipStream_t s = (hipStream_t)stream;
+  EventSet *ev = nullptr;
+  if (m->prof) {
+    if (m->ev_used == m->events.size()) {
+      if (m->events.size() >= 4096) {
+        cf_status st = drain_events(m);
+        if (st != CF_OK) return st;
+      } else {
+        EventSet es;
+        for (auto &x : es.e)
+          if (hipEventCreate(&x) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventCreate failed");
+        m->events.push_back(es);
+      }
+    }
+    ev = &m->events[m->ev_used++];
+    if (hipEventRecord(ev->e[0], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
+  }
+  cf::CollideArgs ca{};
+  ca.q = q; ca.gpos = m->d_gpos; ca.gquat = m->d_gquat; ca.gdat = m->d_gdat; ca.gbody = m->d_gbody;
+  ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
+  ca.ncon_out = out ? out->ncon : nullptr;
+  ca.overflow_out = out ? out->overflow : nullptr;
+  ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
+  ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
+  hipError_t e = cf::launch_collide(ca, m->nw, m->lds_collide, s);
+  if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("collide launch: ") + hipGetErrorString(e));
+  if (ev && hipEventRecord(ev->e[1], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
+
+  cf::ResolveArgs ra{};
+  ra.q = q; ra.v = v; ra.tau = tau; ra.q_out = q_out; ra.v_out = v_out;
+  ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
+  ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
+  if (out) {
+    ra.x_geom = out->geom; ra.x_sub = out->sub; ra.x_dist = out->dist; ra.x_pos = out->pos;
+    ra.x_frame = out->frame; ra.x_imp = out->impulse;
+  }
+  ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
+  ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p;
+  e = cf::launch_resolve(ra, m->nw, m->lds_resolve, s);
+  if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("resolve launch: ") + hipGetErrorString(e));
+  if (ev && hipEventRecord(ev->e[2], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
+  return CF_OK;
+}
+
+cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
+                     const float *tau_seq, float *q_traj, float *v_traj) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (T < 0) return set_err(CF_E_INVALID_ARG, "T must be >= 0");
+  if (!q0 || !v0 || !q_traj || !v_traj) return set_err(CF_E_INVALID_ARG, "NULL state pointer");
+  const size_t sq = (size_t)m->nw * m->nq, sv = (size_t)m->nw * m->nv;
+  hipStream_t s = (hipStream_t)stream;
+  if (q0 != q_traj && hipMemcpyAsync(q_traj, q0, sizeof(float) * sq, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return set_err(CF_E_DEVICE, "hipMemcpyAsync failed");
+  if (v0 != v_traj && hipMemcpyAsync(v_traj, v0, sizeof(float) * sv, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return set_err(CF_E_DEVICE, "hipMemcpyAsync failed");
+  for (int t = 0; t < T; ++t) {
+    cf_status st = cf_step(m, stream, q_traj + t * sq, v_traj + t * sv, tau_seq ? tau_seq + t * sv : nullptr,
+                           q_traj + (t + 1) * sq, v_traj + (t + 1) * sv, nullptr);
+    if (st != CF_OK) return st;
+  }
+  return CF_OK;
+}
+
+cf_status cf_model_set_profiling(cf_model *m, int32_t enable) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (!enable && m->prof) {
+    cf_status st = drain_events(m);
+    if (st != CF_OK) return st;
+  }
+  m->prof = enable != 0;
+  return CF_OK;
+}
+
+cf_status cf_model_kernel_times(cf_model *m, double *ms_collide, double *ms_resolve, int64_t *nsteps) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  cf_status st = drain_events(m);
+  if (st != CF_OK) return st;
+  if (ms_collide) *ms_collide = m->ms_collide;
+  if (ms_resolve) *ms_resolve = m->ms_resolve;
+  if (nsteps) *nsteps = m->prof_steps;
+  m->ms_collide = m->ms_resolve = 0;
+  m->prof_steps = 0;
+  return CF_OK;
+}
+
+}  // extern "C"

@@ -411,15 +411,19 @@ def mixed_shapes(nworld=4, seed=0, condim=3, k_user=0.1, d_user=0.001, ncon_max=
         b.geom(k, bi, size=sizes[:, i], friction=fr)
     s = b.build(condim=condim, k_user=k_user, d_user=d_user, ncon_max=ncon_max,
                 name="mixed_shapes")
+    # bounding radius of each body; bodies start at most 1 cm into the ground
+    bound = np.where(np.array(kinds) == SPHERE, sizes[:, :, 0],
+                     np.where(np.array(kinds) == CAPSULE, sizes[:, :, 0] + sizes[:, :, 1],
+                              np.linalg.norm(sizes, axis=2)))
     for w in range(nworld):
         q = s["q0"][w].reshape(nb, 7)
         v = s["v0"][w].reshape(nb, 6)
         for i in range(nb):
             q[i, 0:3] = (rng.uniform(-0.22, 0.22), rng.uniform(-0.15, 0.15),
-                         rng.uniform(0.0, 0.12))
+                         bound[w, i] + rng.uniform(-0.01, 0.08))
             q[i, 3:7] = _random_quat(rng)
             v[i, 0:3] = rng.normal(0, 0.3, 3)
-            v[i, 3:6] = rng.normal(0, 3.0, 3)
+            v[i, 3:6] = rng.normal(0, 2.0, 3)
     return s
 
 

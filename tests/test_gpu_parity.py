@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Per-step parity feeds both sides the same float32 state; tolerances and the
+guard band are stated in tests/parity.py.  All tests here need an MI355X.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle.cfo import Oracle
+from paper_2603_12185_amd import scenes
+
+from parity import compare_step, tdev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_12185_amd import cfsim
+    cfsim.load()
+    return torch
+
+
+def applied_wrench(s, rng, lin_acc=2.0, ang_acc=20.0, shape=()):
+    """Random applied force/torque per free body, scaled by its mass and inertia
+    (accelerations of order lin_acc m/s^2 and ang_acc rad/s^2)."""
+    nw, nb = s["nworld"], s["nbody"]
+    t = rng.normal(0.0, 1.0, shape + (nw, nb, 6))
+    t[..., :3] *= lin_acc * s["body_mass"][:, :, None]
+    t[..., 3:] *= ang_acc * s["body_inertia"]
+    return t.reshape(shape + (nw, 6 * nb)).astype(np.float32)
+
+
+def _run_steps(torch, model, scene, nsteps, tau=None, record_every=1):
+    """Run nsteps on the GPU, keeping the input state and contact outputs of every
+    recorded step.  Returns list of (t, q_in, v_in, q_out, v_out, contacts)."""
+    q = tdev(scene["q0"])
+    v = tdev(scene["v0"])
+    recs = []
+    for t in range(nsteps):
+        keep = (t % record_every == 0) or t == nsteps - 1
+        con = model.alloc_contacts() if keep else None
+        q1, v1 = model.step(q, v, tau=tau, contacts=con)
+        if keep:
+            recs.append((t, q.cpu().numpy(), v.cpu().numpy(), q1.cpu().numpy(), v1.cpu().numpy(),
+                         to_np(con)))
+        q, v = q1, v1
+    torch.cuda.synchronize()
+    return recs
+
+
+def test_boxes_drop_per_step_parity_1000_steps(torch_cuda):
+    """Config: 1 world, 8 free boxes dropped on a plane, 1000 steps.  Every step:
+    contact set bit-exact, velocities within 1e-5 relative."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.boxes_drop(seed=0)
+    model = cfsim.Model(s)
+    assert model.warning  # box-box pairs have no rule
+    print("case: boxes_drop seed 0, 1000 steps", flush=True)
+    recs = _run_steps(torch_cuda, model, s, 1000)
+    o = Oracle(s)
+    stats = None
+    for t, qi, vi, qg, vg, con in recs:
+        stats = compare_step(s, o, qi, vi, None, qg, vg, con, stats=stats)
+    print("boxes_drop parity", stats)
+    assert stats["checked"] >= 990 and stats["contacts"] > 1000
+
+
+def test_boxes_drop_drift_report(torch_cuda):
+    """Independent 1000-step runs: report per-step state divergence (not bounded)
+    and the first step at which the contact sets differ."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.boxes_drop(seed=0)
+    model = cfsim.Model(s)
+    recs = _run_steps(torch_cuda, model, s, 1000)
+    o = Oracle(s)
+    q, v = s["q0"].astype(np.float64), s["v0"].astype(np.float64)
+    first_div, maxerr = None, []
+    for t, qi, vi, qg, vg, con in recs:
+        q, v, out = o.step(q, v)
+        maxerr.append(float(np.abs(vg.astype(np.float64) - v).max()))
+        if first_div is None and (con["ncon"][0] != out["ncon"][0] or
+                                  (con["geom"][0, :out["ncon"][0]] != out["geom"][0, :out["ncon"][0]]).any()):
+            first_div = t
+    print(f"drift: max|dv| at steps 1/10/100/1000: {maxerr[0]:.2e} {maxerr[9]:.2e} "
+          f"{maxerr[99]:.2e} {maxerr[-1]:.2e}; first contact-set divergence: {first_div}")
+    assert np.isfinite(maxerr).all()
+
+
+@pytest.mark.parametrize("condim", [1, 3, 4, 6])
+def test_mixed_shapes_parity(torch_cuda, condim):
+    """All pair rules (plane-sphere/capsule/box, sphere-sphere, static sphere),
+    tilted planes, per-world sizes, random applied forces; 150 steps."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.mixed_shapes(nworld=5, seed=condim, condim=condim)
+    model = cfsim.Model(s)
+    tau_np = applied_wrench(s, np.random.default_rng(condim))
+    tau = tdev(tau_np)
+    print(f"case: mixed_shapes condim {condim}", flush=True)
+    recs = _run_steps(torch_cuda, model, s, 150, tau=tau, record_every=3)
+    o = Oracle(s)
+    stats = None
+    for t, qi, vi, qg, vg, con in recs:
+        assert np.abs(vg).max() < 1000.0, f"scene left the bounded regime at step {t}"
+        stats = compare_step(s, o, qi, vi, tau_np, qg, vg, con, stats=stats)
+    print("mixed parity", condim, stats)
+    assert stats["contacts"] > 50
+
+
+def test_dense_pile_small_parity(torch_cuda):
+    """16 worlds x 64 spheres in the walled box: 2336 candidate slots per world
+    (10 compaction chunks, ragged tail); compared every 40 steps over 600."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.dense_pile(nworld=16, nsphere=64, seed=7)
+    model = cfsim.Model(s)
+    print("case: dense_pile 16x64", flush=True)
+    recs = _run_steps(torch_cuda, model, s, 600, record_every=40)
+    o = Oracle(s)
+    stats = None
+    for t, qi, vi, qg, vg, con in recs:
+        stats = compare_step(s, o, qi, vi, None, qg, vg, con, stats=stats)
+    print("pile parity", stats)
+    assert stats["contacts"] > 16 * 40
+
+
+def test_dense_pile_many_contacts_parity(torch_cuda):
+    """4 worlds x 128 spheres: more than 256 contacts per world (several
+    reduction chunks per world)."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.dense_pile(nworld=4, nsphere=128, seed=3)
+    model = cfsim.Model(s)
+    print("case: dense_pile 4x128", flush=True)
+    recs = _run_steps(torch_cuda, model, s, 700, record_every=175)
+    o = Oracle(s)
+    stats = None
+    for t, qi, vi, qg, vg, con in recs:
+        stats = compare_step(s, o, qi, vi, None, qg, vg, con, stats=stats)
+    last_ncon = recs[-1][5]["ncon"]
+    print("pile128 parity", stats, "ncon last", last_ncon)
+    assert last_ncon.max() > 256
+
+
+def test_dense_pile_full_size_sampled(torch_cuda):
+    """The benchmark workload (4096 worlds x 64 spheres) in the benchmark's launch
+    configuration: sampled worlds checked against the oracle at steps 150 and
+    400; every world checked for finite state and ncon <= ncon_max."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    s = scenes.dense_pile(nworld=4096, nsphere=64, seed=0)
+    model = cfsim.Model(s)
+    print("case: dense_pile 4096x64 full size", flush=True)
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    sample = [0, 1, 777, 2048, 4095]
+    o = Oracle(scenes.select_worlds(s, sample))
+    stats = None
+    for t in range(401):
+        con = model.alloc_contacts() if t in (150, 400) else None
+        q1, v1 = model.step(q, v, contacts=con)
+        if con is not None:
+            c = to_np(con)
+            assert (c["ncon"] <= s["ncon_max"]).all() and (c["overflow"] == 0).all()
+            qn, vn = q1.cpu().numpy(), v1.cpu().numpy()
+            assert np.isfinite(qn).all() and np.isfinite(vn).all()
+            sub = {k: val[sample] for k, val in c.items()}
+            stats = compare_step(scenes.select_worlds(s, sample), o, q.cpu().numpy()[sample],
+                                 v.cpu().numpy()[sample], None, qn[sample], vn[sample], sub,
+                                 stats=stats)
+            print(f"step {t}: mean contacts/world {c['ncon'].mean():.1f} max {c['ncon'].max()}")
+        q, v = q1, v1
+    torch.cuda.synchronize()
+    print("full-size sampled parity", stats)
+    assert stats["checked"] >= 8
+
+
+def test_empty_and_overflow_edge_cases(torch_cuda):
+    """No contacts (bodies in the air), ncon_max = 0 and a small ncon_max that
+    truncates: counts, kept contacts and dynamics match the oracle."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.dense_pile(nworld=3, nsphere=16, seed=1)
+    s["q0"].reshape(3, 16, 7)[:, :, 2] += 5.0
+    for cm in (1024, 0, 5):
+        sc = scenes.with_params(s, ncon_max=cm)
+        model = cfsim.Model(sc)
+        recs = _run_steps(torch_cuda, model, sc, 3)
+        o = Oracle(sc)
+        for t, qi, vi, qg, vg, con in recs:
+            compare_step(sc, o, qi, vi, None, qg, vg, con)
+            assert con["ncon"].sum() == 0
+    # sunk spheres: many contacts, truncated
+    s2 = scenes.dense_pile(nworld=3, nsphere=32, seed=2)
+    s2["q0"].reshape(3, 32, 7)[:, :, 2] = 0.01
+    for cm in (0, 5, 40):
+        sc = scenes.with_params(s2, ncon_max=cm)
+        model = cfsim.Model(sc)
+        recs = _run_steps(torch_cuda, model, sc, 2)
+        o = Oracle(sc)
+        for t, qi, vi, qg, vg, con in recs:
+            compare_step(sc, o, qi, vi, None, qg, vg, con)
+            assert (con["overflow"] > 0).all()
+
+
+def test_in_place_update_and_determinism(torch_cuda):
+    """q_out/v_out aliasing q/v gives the same bits as separate outputs; two
+    runs from the same state are bitwise identical."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    s = scenes.dense_pile(nworld=64, nsphere=64, seed=5)
+    model = cfsim.Model(s)
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    for _ in range(300):
+        q, v = model.step(q, v)
+    qa, va = q.clone(), v.clone()
+    ref = [model.step(q, v) for _ in range(1)][0]
+    model.step(qa, va, q_out=qa, v_out=va)
+    torch.cuda.synchronize()
+    assert torch.equal(ref[0], qa) and torch.equal(ref[1], va)
+    runs = []
+    for _ in range(2):
+        qq, vv = q.clone(), v.clone()
+        for _ in range(50):
+            qq, vv = model.step(qq, vv)
+        runs.append((qq, vv))
+    torch.cuda.synchronize()
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+
+
+def test_rollout_matches_repeated_steps(torch_cuda):
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    s = scenes.mixed_shapes(nworld=4, seed=11, condim=4)
+    model = cfsim.Model(s)
+    T = 40
+    tau = tdev(applied_wrench(s, np.random.default_rng(0), shape=(T,)))
+    q0, v0 = tdev(s["q0"]), tdev(s["v0"])
+    qt, vt = model.rollout(T, q0, v0, tau_seq=tau)
+    q, v = q0, v0
+    for t in range(T):
+        q, v = model.step(q, v, tau=tau[t].contiguous())
+        assert torch.equal(q, qt[t + 1]) and torch.equal(v, vt[t + 1])
+    assert torch.equal(qt[0], q0)
+
+
+def test_kernel_timing_query(torch_cuda):
+    from paper_2603_12185_amd import cfsim
+    s = scenes.dense_pile(nworld=256, nsphere=64, seed=0)
+    model = cfsim.Model(s)
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    model.set_profiling(True)
+    t0 = time.time()
+    for _ in range(20):
+        q, v = model.step(q, v)
+    a, b, n = model.kernel_times()
+    print(f"collide {a / n * 1e3:.1f} us, resolve {b / n * 1e3:.1f} us per step; wall {time.time() - t0:.3f}s")
+    assert n == 20 and a > 0 and b > 0

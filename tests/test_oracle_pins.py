@@ -624,6 +624,7 @@ def test_geometry_pair_swap_and_rigid_motion():
     np.testing.assert_allclose(a["frame"][0, 0, :3], -b["frame"][0, 0, :3], atol=1e-15)
     # rigid motion of the mixed scene (planes, static sphere and bodies)
     s = scenes.mixed_shapes(nworld=1, seed=5)
+    s["q0"].reshape(-1, 7)[:, 2] -= 0.03  # press every body into the ground
     _, _, base = Oracle(s).step(s["q0"], s["v0"])
     ang = 0.7
     Rz = np.array([[math.cos(ang), -math.sin(ang), 0], [math.sin(ang), math.cos(ang), 0],
