@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Throughput of the plain complementarity-free contact step on one MI355X.
+
+Workload: the dense pile (4096 worlds x 64 free spheres in a 0.5 m walled box,
+radius U(0.02, 0.05) m, density 1000 kg/m^3, condim 3 / 4-facet cone, h = 2 ms,
+k_user = 0.1, d_user = 0.001), seeded and synthetic.  A step is one full pass of
+the hot path (narrow phase, smooth prediction, facet impulses, per-body
+reduction, velocity correction, integration) over all worlds.  W untimed
+warm-up steps let the pile fall and settle, then K steps are timed with the
+state resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "env-steps/s & contact-impulses/s (+% HBM peak) vs plain form, 1 MI355X"
+HBM_PEAK = 8.0e12  # B/s, MI355X published HBM3E bandwidth
+
+
+def alg_bytes(nq, nv, nb, ng, contacts):
+    """Algorithmic HBM bytes per world-step of each kernel (contacts = C_w).
+
+    collide: read q and per-world geom data (size, friction: 16 B/geom), write
+             the contact records (32 B each) and the count.
+    resolve: read q, v, per-body mass/inertia (16 B/body), per-world geom data,
+             the contact records and count; write q and v.
+    Shared tables (candidate slots, static geom poses) are read from L2 by every
+    world and are not counted."""
+    collide = 4 * nq + 16 * ng + 32 * contacts + 8
+    resolve = 8 * nq + 8 * nv + 16 * nb + 16 * ng + 32 * contacts + 4
+    return collide, resolve
+
+
+def cpu_baseline(scene, q, v, worlds, steps, threads):
+    """Time the FP64 oracle (as it stands) on a bounded sample of the same workload."""
+    from oracle.cfo import Oracle
+    from paper_2603_12185_amd import scenes
+    sub = scenes.select_worlds(scene, worlds)
+    o = Oracle(sub)
+    qs, vs = q[worlds].astype(np.float64), v[worlds].astype(np.float64)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        qs, vs = o.step_threads(qs, vs, threads)
+    dt = time.perf_counter() - t0
+    return len(worlds) * steps / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--nworld", type=int, default=4096)
+    ap.add_argument("--nsphere", type=int, default=64)
+    ap.add_argument("--condim", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-worlds", type=int, default=384,
+                    help="worlds in the CPU-baseline sample (0 disables it)")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
+              "worlds shard across GPUs with no exchange, so this build reports the one-GPU "
+              "throughput and runs no multi-GPU configuration.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_12185_amd import cfsim, scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    scene = scenes.dense_pile(nworld=args.nworld, nsphere=args.nsphere, seed=args.seed,
+                              condim=args.condim)
+    model = cfsim.Model(scene)
+    nw, nq, nv, nb, ng = model.nworld, model.nq, model.nv, model.nbody, model.ngeom
+    lib = cfsim.load()
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+
+    q = [torch.from_numpy(scene["q0"]).to(dev), torch.empty((nw, nq), device=dev)]
+    v = [torch.from_numpy(scene["v0"]).to(dev), torch.empty((nw, nv), device=dev)]
+    K, W = args.steps, args.warmup
+    ncon_log = torch.zeros((max(K, 1), nw), dtype=torch.int32, device=dev)
+    over_log = torch.zeros((max(K, 1), nw), dtype=torch.int32, device=dev)
+    cons = [cfsim.Contacts(C.c_void_p(ncon_log[t].data_ptr()), C.c_void_p(over_log[t].data_ptr()),
+                           None, None, None, None, None, None) for t in range(K)]
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    args_pp = [(model._h, sp, ptr(q[i]), ptr(v[i]), None, ptr(q[1 - i]), ptr(v[1 - i])) for i in (0, 1)]
+
+    def run(n, logged):
+        for t in range(n):
+            a = args_pp[t & 1]
+            st = lib.cf_step(*a, C.byref(cons[t]) if logged else None)
+            if st != 0:
+                raise cfsim.CFError(st, cfsim.last_error())
+
+    run(W, False)
+    if W % 2:  # keep the live state in buffer 0
+        q[0].copy_(q[1])
+        v[0].copy_(v[1])
+    torch.cuda.synchronize()
+    state_q, state_v = q[0].cpu().numpy(), v[0].cpu().numpy()
+
+    model.set_profiling(True)
+    model.kernel_times()  # reset
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    run(K, True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_col, ms_res, nsteps = model.kernel_times()
+    model.set_profiling(False)
+    gpu_ms = e0.elapsed_time(e1)
+
+    ncon = ncon_log[:K].double()
+    assert int(over_log[:K].sum()) == 0, "contact capacity overflowed"
+    contacts_per_step = float(ncon.sum(1).mean())
+    c_w = contacts_per_step / nw
+    ms_step = wall * 1e3 / K
+    env_steps = nw * K / wall
+    imp = contacts_per_step * K / wall
+    b_col, b_res = alg_bytes(nq, nv, nb, ng, c_w)
+    t_col, t_res = ms_col / nsteps * 1e-3, ms_res / nsteps * 1e-3
+    if t_col >= t_res:
+        dom, t_dom, b_dom = "collide_kernel", t_col, b_col
+    else:
+        dom, t_dom, b_dom = "resolve_kernel", t_res, b_res
+    achieved = b_dom * nw / t_dom
+    step_bytes = (b_col + b_res) * nw
+
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        from paper_2603_12185_amd import build as _b
+        import hashlib
+        src = b"".join(open(os.path.join(_b.CSRC, s), "rb").read() for s in _b.SOURCES)
+        rec = json.load(open(tfile))
+        if rec.get("source_sha256") == hashlib.sha256(src).hexdigest() and dom in rec.get("kernels", {}):
+            traffic = rec["kernels"][dom]["bytes_per_launch"]
+
+    result = {
+        "metric": METRIC, "value": env_steps, "unit": "env-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"dense_pile_{nw}x{args.nsphere}", "nworld": nw,
+                   "bodies_per_world": nb, "condim": args.condim, "nfacet": model.nfacet,
+                   "h": scene["h"], "k_user": scene["k_user"], "d_user": scene["d_user"],
+                   "ncon_max": model.ncon_max, "mean_contacts_per_world": c_w, "form": "plain",
+                   "parallelism": "single GPU, one workgroup per world"},
+        "contact_impulses_per_s": imp,
+        "facet_impulses_per_s": imp * model.nfacet,
+        "gpu_event_ms_per_step": gpu_ms / K,
+        "kernel_us": {"collide_kernel": t_col * 1e6, "resolve_kernel": t_res * 1e6},
+        "whole_step_alg_GBps": step_bytes / (wall / K) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                     "traffic": traffic, "alg_bytes_per_launch": b_dom * nw},
+    }
+    if args.cpu_worlds > 0:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        rng = np.random.default_rng(0)
+        sample = np.sort(rng.choice(nw, size=min(args.cpu_worlds, nw), replace=False))
+        rate, dt = cpu_baseline(scene, state_q, state_v, sample, args.cpu_steps, threads)
+        result["cpu_baseline"] = {
+            "value": rate, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} worlds x {args.cpu_steps} steps of the same settled pile "
+                      f"(FP64 oracle, {dt:.1f} s wall)"}
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()
