@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--nsphere", type=int, default=64)
     ap.add_argument("--condim", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-worlds", type=int, default=384,
+    ap.add_argument("--cpu-worlds", type=int, default=768,
                     help="worlds in the CPU-baseline sample (0 disables it)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     args = ap.parse_args()

@@ -118,8 +118,11 @@ typedef struct {
 /* Validate the descriptor, upload per-world constants and size the contact
  * workspace (nworld * ncon_max records) on the current HIP device.  Returns
  * CF_OK or CF_W_PAIRS_SKIPPED with *out set, else an error with *out = NULL.
- * This version implements free joints only (hinge/slide: CF_E_UNSUPPORTED);
- * free bodies need mass > 0 and inertia > 0. */
+ * Free joints are allowed only on bodies whose parent is the world.  A free
+ * body without children needs mass > 0 and inertia > 0; every other root with
+ * its descendants (hinge/slide chains, floating bases) must be contiguous in
+ * body order and hold at most 32 dofs (else CF_E_UNSUPPORTED); its mass matrix
+ * must be positive definite. */
 cf_status cf_model_create(const cf_model_desc *desc, cf_model **out);
 
 /* Free the model's device memory (synchronises the device first).  NULL is a no-op. */
@@ -140,6 +143,14 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
  * result; tau_seq [T][nworld][nv] or NULL.  T >= 0. */
 cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
                      const float *tau_seq, float *q_traj, float *v_traj);
+
+/* Workgroup size (64, 128 or 256 threads, one world per workgroup) of the
+ * collision and the resolution kernel.  Defaults are set by cf_model_create;
+ * results do not depend on the choice (same arithmetic, same summation order
+ * within a wave; the per-body sums are ordered by wave, so the last bits of
+ * v+ may differ between sizes). */
+cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolve_block);
+cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t *resolve_block);
 
 /* Kernel timing.  When enabled, every cf_step records HIP events around its
  * collision and resolution kernels on the step's stream.  cf_model_kernel_times

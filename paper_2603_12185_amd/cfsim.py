@@ -59,6 +59,8 @@ SIGNATURES = {
     "cf_model_dims": ([C.c_void_p, _ip, _ip, _ip], C.c_int32),
     "cf_step": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, C.POINTER(Contacts)], C.c_int32),
     "cf_rollout": ([C.c_void_p, C.c_void_p, C.c_int32, _fp, _fp, _fp, _fp, _fp], C.c_int32),
+    "cf_model_set_launch": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int32),
+    "cf_model_get_launch": ([C.c_void_p, _ip, _ip], C.c_int32),
     "cf_model_set_profiling": ([C.c_void_p, C.c_int32], C.c_int32),
     "cf_model_kernel_times": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_int64)], C.c_int32),
@@ -209,6 +211,15 @@ class Model:
         _check(load().cf_rollout(self._h, C.c_void_p(s.cuda_stream), int(T), _ptr(q0), _ptr(v0),
                                  _ptr(tau_seq), _ptr(q_traj), _ptr(v_traj)))
         return q_traj, v_traj
+
+    # ------------------------------------------------------------ launch shape
+    def set_launch(self, collide_block, resolve_block):
+        _check(load().cf_model_set_launch(self._h, int(collide_block), int(resolve_block)))
+
+    def get_launch(self):
+        a, b = C.c_int32(), C.c_int32()
+        _check(load().cf_model_get_launch(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     # ------------------------------------------------------------ timing
     def set_profiling(self, on: bool):

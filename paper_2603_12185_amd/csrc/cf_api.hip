@@ -38,7 +38,11 @@ struct cf_model {
   cf::Params p{};
   // device constants
   uint32_t *d_slots = nullptr;
-  int *d_gbody = nullptr;
+  int *d_gbody = nullptr, *d_gorient = nullptr;
+  cf::BodyC *d_body = nullptr;
+  cf::SubTree *d_sub = nullptr;
+  int norient = 0, nsub = 0, art_floats = 0;
+  int block_collide = 256, block_resolve = 256;
   float4 *d_bmi = nullptr, *d_gdat = nullptr, *d_gpos = nullptr, *d_gquat = nullptr;
   float2 *d_gfr2 = nullptr;
   int gpos_ws = 0, gquat_ws = 0;
@@ -67,7 +71,8 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 
 void free_model(cf_model *m) {
   if (!m) return;
-  (void)hipFree(m->d_slots); (void)hipFree(m->d_gbody); (void)hipFree(m->d_bmi); (void)hipFree(m->d_gdat);
+  (void)hipFree(m->d_slots); (void)hipFree(m->d_gbody); (void)hipFree(m->d_gorient);
+  (void)hipFree(m->d_body); (void)hipFree(m->d_sub); (void)hipFree(m->d_bmi); (void)hipFree(m->d_gdat);
   (void)hipFree(m->d_gpos); (void)hipFree(m->d_gquat); (void)hipFree(m->d_gfr2);
   (void)hipFree(m->d_cnp); (void)hipFree(m->d_cpos); (void)hipFree(m->d_ncon); (void)hipFree(m->d_over);
   for (auto &s : m->events)
@@ -99,6 +104,8 @@ cf_status drain_events(cf_model *m) {
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+constexpr size_t kLdsLimit = 64 * 1024;  // per workgroup
 
 }  // namespace
 
@@ -140,15 +147,62 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       if (ip[0] != 0 || ip[1] != 0 || ip[2] != 0) return set_err(CF_E_INVALID_ARG, "free bodies need body_ipos = 0");
     }
   }
-  for (int b = 0; b < nb; ++b)
-    if (d->body_jnt[b] != CF_JNT_FREE)
-      return set_err(CF_E_UNSUPPORTED, "this version implements free joints only (hinge/slide unsupported)");
+  // Tree structure: a free body without children takes the closed-form path;
+  // every other root with its descendants forms an articulated subtree, which
+  // must be contiguous in body order and hold at most kMaxSubDof dofs.
+  std::vector<int> nchild(nb, 0), root(nb), qadr(nb), dadr(nb);
+  int nq = 0, nv = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (d->body_parent[b] >= 0) nchild[d->body_parent[b]]++;
+    root[b] = d->body_parent[b] < 0 ? b : root[d->body_parent[b]];
+    qadr[b] = nq; dadr[b] = nv;
+    nq += d->body_jnt[b] == CF_JNT_FREE ? 7 : 1;
+    nv += d->body_jnt[b] == CF_JNT_FREE ? 6 : 1;
+  }
+  std::vector<cf::BodyC> bodyc(nb);
+  std::vector<cf::SubTree> subs;
+  int art_floats = 0;
+  for (int b = 0; b < nb;) {
+    int e = b + 1;
+    while (e < nb && root[e] == b) ++e;
+    for (int k = e; k < nb; ++k)
+      if (root[k] == b) return set_err(CF_E_UNSUPPORTED, "each subtree's bodies must be contiguous in body order");
+    const bool fast = d->body_jnt[b] == CF_JNT_FREE && e == b + 1;
+    if (!fast) {
+      cf::SubTree st{};
+      st.b0 = b; st.nb = e - b; st.d0 = dadr[b];
+      st.nd = (e < nb ? dadr[e] : nv) - dadr[b];
+      if (st.nd > cf::kMaxSubDof) return set_err(CF_E_UNSUPPORTED, "articulated subtree with more than 32 dofs");
+      st.lofs = art_floats;
+      art_floats += st.nd * st.nd + 9 * st.nd;
+      subs.push_back(st);
+    }
+    for (int k = b; k < e; ++k) {
+      cf::BodyC &c = bodyc[k];
+      const double *bp = d->body_pos + 3 * k, *bq = d->body_quat + 4 * k, *ax = d->jnt_axis + 3 * k;
+      const double *ip = d->body_ipos + 3 * k;
+      const double an = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+      c.pos = make_float4((float)bp[0], (float)bp[1], (float)bp[2], 0.f);
+      c.quat = make_float4((float)bq[0], (float)bq[1], (float)bq[2], (float)bq[3]);
+      c.axis = an > 0 ? make_float4((float)(ax[0] / an), (float)(ax[1] / an), (float)(ax[2] / an), 0.f)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+      c.ipos = make_float4((float)ip[0], (float)ip[1], (float)ip[2], 0.f);
+      c.parent = d->body_parent[k]; c.jnt = d->body_jnt[k]; c.qadr = qadr[k]; c.dadr = dadr[k];
+      c.fast = fast ? 1 : 0;
+      if (c.jnt != CF_JNT_FREE && !(an > 0)) return set_err(CF_E_INVALID_ARG, "zero joint axis");
+      const double *q = d->body_quat + 4 * k;
+      if (!(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] > 0)) return set_err(CF_E_INVALID_ARG, "zero body_quat");
+    }
+    b = e;
+  }
   for (int w = 0; w < nw; ++w)
     for (int b = 0; b < nb; ++b) {
       const double m = d->body_mass[(size_t)w * nb + b];
       const double *I = d->body_inertia + ((size_t)w * nb + b) * 3;
-      if (!(m > 0) || !(I[0] > 0) || !(I[1] > 0) || !(I[2] > 0) || !std::isfinite(m) || !finite_all(I, 3))
-        return set_err(CF_E_INVALID_ARG, "free bodies need finite mass > 0 and inertia > 0");
+      if (!std::isfinite(m) || !finite_all(I, 3) || m < 0 || I[0] < 0 || I[1] < 0 || I[2] < 0)
+        return set_err(CF_E_INVALID_ARG, "masses and inertias must be finite and >= 0");
+      if (bodyc[b].fast && (!(m > 0) || !(I[0] > 0) || !(I[1] > 0) || !(I[2] > 0)))
+        return set_err(CF_E_INVALID_ARG, "free bodies need mass > 0 and inertia > 0");
     }
   if (ng > cf::kMaxGeom) return set_err(CF_E_UNSUPPORTED, "ngeom exceeds 8191");
   for (int g = 0; g < ng; ++g) {
@@ -192,7 +246,8 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   cf_model *m = new cf_model();
   m->nw = nw; m->nb = nb; m->ng = ng; m->ncon_max = d->ncon_max; m->condim = d->condim;
   m->nf = d->condim == 1 ? 1 : d->condim == 3 ? 4 : d->condim == 4 ? 6 : 10;
-  m->nq = 7 * nb; m->nv = 6 * nb;
+  m->nq = nq; m->nv = nv;
+  m->nsub = (int)subs.size(); m->art_floats = art_floats;
   m->nslot = (int)slots.size();
   m->nbits = 1;
   while ((1 << m->nbits) <= nb) ++m->nbits;  // keys 0..nb (nb = no body)
@@ -201,13 +256,27 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   m->p.gx = (float)d->gravity[0]; m->p.gy = (float)d->gravity[1]; m->p.gz = (float)d->gravity[2];
   m->p.r_min = (float)si[0]; m->p.r_max = (float)si[1]; m->p.width = (float)si[2];
   m->p.mid = (float)si[3]; m->p.power = (float)si[4];
-  m->lds_collide = cf::collide_lds_bytes(m->nq, ng);
-  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng);
-  const size_t lds_limit = 64 * 1024;
-  if (m->lds_collide > lds_limit || m->lds_resolve > lds_limit) {
+  m->p.inv_width = (float)(1.0 / si[2]); m->p.inv_mid = (float)(1.0 / si[3]);
+  m->p.inv_1mmid = (float)(1.0 / (1.0 - si[3])); m->p.power2 = si[4] == 2.0 ? 1 : 0;
+  // Oriented geoms (planes, capsules, boxes, spheres offset from their body
+  // origin) carry a full pose record in the narrow phase.
+  std::vector<int> gorient(ng, -1);
+  for (int g = 0; g < ng; ++g) {
+    bool oriented = d->geom_type[g] != CF_SPHERE || (d->geom_body[g] >= 0 && !bodyc[d->geom_body[g]].fast);
+    if (!oriented && d->geom_body[g] >= 0)
+      for (int w = 0; w < nw && !oriented; ++w) {
+        const double *p = d->geom_pos + 3 * ((size_t)w * ng + g);
+        oriented = p[0] != 0 || p[1] != 0 || p[2] != 0;
+      }
+    if (oriented) gorient[g] = m->norient++;
+  }
+  m->lds_collide = cf::collide_lds_bytes(m->nq, nb, ng, m->norient, m->nsub);
+  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, 256, m->nsub, m->art_floats);
+  if (m->lds_collide > kLdsLimit || m->lds_resolve > kLdsLimit) {
     delete m;
     return set_err(CF_E_UNSUPPORTED, "world too large for one workgroup's LDS (reduce bodies or geoms)");
   }
+  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->block_resolve, m->nsub, m->art_floats);
   if (hipGetDevice(&m->dev) != hipSuccess) { delete m; return set_err(CF_E_DEVICE, "no HIP device"); }
 
   // ---- per-world constants (float32); shared arrays get world stride 0
@@ -251,6 +320,9 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
   chk(upload(&m->d_slots, slots));
   chk(upload(&m->d_gbody, gbody));
+  chk(upload(&m->d_gorient, gorient));
+  chk(upload(&m->d_body, bodyc));
+  chk(upload(&m->d_sub, subs));
   chk(upload(&m->d_bmi, bmi));
   chk(upload(&m->d_gdat, gdat));
   chk(upload(&m->d_gpos, gpos));
@@ -318,18 +390,21 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
   }
   cf::CollideArgs ca{};
   ca.q = q; ca.gpos = m->d_gpos; ca.gquat = m->d_gquat; ca.gdat = m->d_gdat; ca.gbody = m->d_gbody;
+  ca.gorient = m->d_gorient; ca.norient = m->norient;
+  ca.body = m->d_body; ca.sub = m->d_sub; ca.nsub = m->nsub;
   ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
   ca.ncon_out = out ? out->ncon : nullptr;
   ca.overflow_out = out ? out->overflow : nullptr;
   ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
   ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
-  hipError_t e = cf::launch_collide(ca, m->nw, m->lds_collide, s);
+  hipError_t e = cf::launch_collide(ca, m->nw, m->block_collide, m->lds_collide, s);
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("collide launch: ") + hipGetErrorString(e));
   if (ev && hipEventRecord(ev->e[1], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
 
   cf::ResolveArgs ra{};
   ra.q = q; ra.v = v; ra.tau = tau; ra.q_out = q_out; ra.v_out = v_out;
   ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
+  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats;
   ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
   if (out) {
     ra.x_geom = out->geom; ra.x_sub = out->sub; ra.x_dist = out->dist; ra.x_pos = out->pos;
@@ -337,7 +412,7 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
   }
   ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
   ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p;
-  e = cf::launch_resolve(ra, m->nw, m->lds_resolve, s);
+  e = cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("resolve launch: ") + hipGetErrorString(e));
   if (ev && hipEventRecord(ev->e[2], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
   return CF_OK;
@@ -359,6 +434,24 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
                            q_traj + (t + 1) * sq, v_traj + (t + 1) * sv, nullptr);
     if (st != CF_OK) return st;
   }
+  return CF_OK;
+}
+
+cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolve_block) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  auto ok = [](int b) { return b == 64 || b == 128 || b == 256; };
+  if (!ok(collide_block) || !ok(resolve_block))
+    return set_err(CF_E_INVALID_ARG, "workgroup sizes must be 64, 128 or 256");
+  m->block_collide = collide_block;
+  m->block_resolve = resolve_block;
+  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, resolve_block, m->nsub, m->art_floats);
+  return CF_OK;
+}
+
+cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t *resolve_block) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (collide_block) *collide_block = m->block_collide;
+  if (resolve_block) *resolve_block = m->block_resolve;
   return CF_OK;
 }
 

@@ -6,8 +6,9 @@
 
 namespace cf {
 
-constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
-constexpr int kWaves = kBlock / 64;
+// Workgroup sizes the kernels are instantiated for (one world per workgroup).
+constexpr int kBlockSizes[3] = {64, 128, 256};
+constexpr int kCandCap = 1024;         // LDS candidate list of the narrow phase
 
 // Candidate sub-contact ("slot"), packed in 32 bits:
 //   bits  0..12 geom a, 13..25 geom b, 26..28 sub-contact index, 29..30 pair type.
@@ -22,11 +23,35 @@ __host__ __device__ inline int slot_gb(uint32_t s) { return (int)((s >> 13) & 0x
 __host__ __device__ inline int slot_sub(uint32_t s) { return (int)((s >> 26) & 7u); }
 __host__ __device__ inline uint32_t slot_type(uint32_t s) { return (s >> 29) & 3u; }
 
+// Joint types (same values as the C ABI).
+enum JointType : int { kFree = 0, kHinge = 1, kSlide = 2 };
+
+// Per-body constants shared by all worlds.
+struct BodyC {
+  float4 pos;    // body frame origin in the parent frame at q = 0 (x, y, z, -)
+  float4 quat;   // body frame orientation in the parent frame, (w,x,y,z) in (x,y,z,w)
+  float4 axis;   // unit hinge/slide axis in the body frame
+  float4 ipos;   // centre of mass in the body frame
+  int parent, jnt, qadr, dadr;
+  int fast;      // 1: free body without children (closed-form path), 0: articulated subtree member
+  int pad[3];
+};
+
+// Articulated subtree (a root body with its descendants, contiguous in body
+// and dof order): bodies [b0, b0+nb), dofs [d0, d0+nd), float offset of its
+// LDS work block (nd*nd + 9*nd floats).
+struct SubTree {
+  int b0, nb, d0, nd, lofs, pad[3];
+};
+constexpr int kMaxSubDof = 32;
+
 // Per-model solver constants (passed by value).
 struct Params {
   float h, k_user, d_user, margin;
   float gx, gy, gz;
   float r_min, r_max, width, mid, power;
+  float inv_width, inv_mid, inv_1mmid;  // 1/width, 1/mid, 1/(1 - mid)
+  int power2;                           // power == 2: gamma uses squares
 };
 
 // Collision kernel: one workgroup per world.
@@ -36,12 +61,15 @@ struct CollideArgs {
   const float4 *gquat;          // [nw|1][ng] (w, x, y, z)
   const float4 *gdat;           // [nw][ng] (size0, size1, size2, mu_t)
   const int *gbody;             // [ng]
+  const int *gorient;           // [ng] index among oriented geoms, -1 for a plain sphere
+  const BodyC *body;            // [nb]
+  const SubTree *sub;           // [nsub]
   const uint32_t *slots;        // [nslot] canonical order
   float4 *cnp;                  // [nw][ncon_max] (n.x, n.y, n.z, phi)
   float4 *cpos;                 // [nw][ncon_max] (p.x, p.y, p.z, slot bits)
   int *ncon, *overflow;         // [nw] model workspace
   int *ncon_out, *overflow_out; // [nw] caller copies or null
-  int nq, nb, ng, nslot, ncon_max;
+  int nq, nb, ng, norient, nslot, ncon_max, nsub;
   int gpos_ws, gquat_ws;        // world stride in elements (0 = shared by all worlds)
   float margin;
 };
@@ -54,18 +82,20 @@ struct ResolveArgs {
   const float4 *gdat;           // [nw][ng] (size0, size1, size2, mu_t)
   const float2 *gfr2;           // [nw][ng] (mu_tor, mu_rol) or null when condim < 4
   const int *gbody;             // [ng]
+  const BodyC *body;            // [nb]
+  const SubTree *sub;           // [nsub]
   const float4 *cnp, *cpos;     // contact workspace
   const int *ncon;              // [nw]
   // optional exports (device, caller-owned), may be null
   int *x_geom, *x_sub;
   float *x_dist, *x_pos, *x_frame, *x_imp;
-  int nq, nv, nb, ng, ncon_max, condim, nfacet, nbits;
+  int nq, nv, nb, ng, ncon_max, condim, nfacet, nbits, nsub, art_floats;
   Params p;
 };
 
-size_t collide_lds_bytes(int nq, int ng);
-size_t resolve_lds_bytes(int nq, int nv, int nb, int ng);
-hipError_t launch_collide(const CollideArgs &a, int nworld, size_t lds, hipStream_t s);
-hipError_t launch_resolve(const ResolveArgs &a, int nworld, size_t lds, hipStream_t s);
+size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub);
+size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats);
+hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t lds, hipStream_t s);
+hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 
 }  // namespace cf

@@ -1,16 +1,19 @@
 // cf_kernels.hip - gfx950 kernels of the complementarity-free contact step.
 //
-// Two kernels per step, each one workgroup (4 x wave64) per world:
+// Two kernels per step, one workgroup per world (64, 128 or 256 threads):
 //
 //  collide_kernel  analytic narrow phase over the model's candidate slots
-//                  (plane-sphere, plane-capsule, plane-box corner, sphere-sphere),
-//                  in canonical order: float32 test of every slot, float64
-//                  re-evaluation of the slots near contact (decision, gap,
-//                  normal, point); an order-preserving block compaction (wave
-//                  ballots + per-wave counts) writes the contact set to a flat
-//                  structure-of-arrays buffer [world][ncon_max] in HBM.
+//                  (plane-sphere, plane-capsule, plane-box corner, sphere-sphere)
+//                  in canonical order.  Pass 1 tests every slot in float32 on
+//                  16-byte LDS records and keeps, in order, the slots within a
+//                  small band of contact; pass 2 evaluates only those candidates
+//                  (decision, gap, normal, point) from float64 geometry, except
+//                  sphere pairs centred on their bodies (float32).  Both
+//                  passes compact in order with wave ballots plus per-wave
+//                  counts, so contacts land in the flat structure-of-arrays
+//                  buffer [world][ncon_max] without atomics.
 //
-//  resolve_kernel  smooth prediction v_s = v + h M^-1 (tau - c) (Eq. smooth_vel),
+//  resolve_kernel  smooth prediction v_s = v + h M^-1 (tau - c) (Eq. smooth_vel);
 //                  one lane per contact: tangent basis, relative velocity at v_s,
 //                  impedance A = r/(1-r)/(tr_a + tr_b) (Eqs. k_d_setting, r_scaling),
 //                  facet impulses lambda*h = A max(-(k h + d) J~ v_s - k phi, 0)
@@ -22,12 +25,54 @@
 //
 // Free bodies: M is block diagonal (m I3, R diag(I) R^T) and the COM trace of
 // a body is 3/m, so the factorisation of M reduces to the per-body inverse
-// inertia.  Apart from the float64 contact geometry, the step runs in float32.
+// inertia.  Apart from the float64 contact geometry the step runs in float32.
 #include "cf_internal.h"
 
 namespace cf {
 
 static __host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }
+
+__device__ inline unsigned long long lanes_below(int lane) {
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Exclusive prefix of `flag` over the workgroup in thread order; *total gets
+// the workgroup count.  wcnt: shared [2][BS/64]; callers alternate `parity`
+// so that consecutive calls need a single barrier each.
+template <int BS>
+__device__ inline int block_scan(bool flag, int *total, int *wcnt, int parity) {
+  constexpr int NW = BS / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int pre = __popcll(m & lanes_below(lane));
+  if (NW == 1) {
+    *total = __popcll(m);
+    return pre;
+  }
+  if (lane == 0) wcnt[parity * NW + wave] = __popcll(m);
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int c = wcnt[parity * NW + i];
+    off += i < wave ? c : 0;
+    tot += c;
+  }
+  *total = tot;
+  return off + pre;
+}
+
+// Maximum over the workgroup (every thread gets it); wmax: shared [BS/64].
+template <int BS>
+__device__ inline float block_max(float x, float *wmax) {
+  for (int off = 32; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off));
+  if (BS == 64) return x;
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = x;
+  __syncthreads();
+  float m = wmax[0];
+  for (int i = 1; i < BS / 64; ++i) m = fmaxf(m, wmax[i]);
+  return m;
+}
 
 // ---------------------------------------------------------------- helpers
 struct V3 { float x, y, z; };
@@ -40,53 +85,6 @@ __device__ inline V3 cross(V3 a, V3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
-// Rotation matrix rows of the normalised quaternion (w, x, y, z).
-__device__ inline void quat_rows(float qw, float qx, float qy, float qz, V3 &r0, V3 &r1, V3 &r2) {
-  float inv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-  float w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
-  r0 = v3(1.f - 2.f * (y * y + z * z), 2.f * (x * y - z * w), 2.f * (x * z + y * w));
-  r1 = v3(2.f * (x * y + z * w), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - x * w));
-  r2 = v3(2.f * (x * z - y * w), 2.f * (y * z + x * w), 1.f - 2.f * (x * x + y * y));
-}
-
-// ====================================================================
-// collision
-// ====================================================================
-// Every candidate slot is tested in float32; slots within a small band of
-// contact are re-evaluated from float64 geometry, which decides the contact
-// and supplies its gap, normal and point (rounded to float32 on store).  The
-// gap enters the impulse multiplied by the contact stiffness, so its
-// accuracy, not the dynamics', bounds the step's float32 error.
-template <class T>
-struct GeomRec {
-  T p[3];   // world position
-  T r[9];   // world rotation, row-major
-  T s[3];   // size
-  T pad;
-};
-
-size_t collide_lds_bytes(int nq, int ng) {
-  return sizeof(float) * pad4(nq) + (sizeof(GeomRec<float>) + sizeof(GeomRec<double>)) * (size_t)ng;
-}
-
-// Geom pose from (world position, rotation rows) of its body and its local offset.
-template <class T>
-__device__ inline void geom_pose(const T *bp, const T *br, const float4 gp, const float4 gq, GeomRec<T> &o) {
-  // rotation of the geom quaternion (w,x,y,z stored in x,y,z,w)
-  const T qw = gq.x, qx = gq.y, qy = gq.z, qz = gq.w;
-  const T inv = T(1) / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  const T w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
-  const T g[9] = {T(1) - T(2) * (y * y + z * z), T(2) * (x * y - z * w), T(2) * (x * z + y * w),
-                  T(2) * (x * y + z * w), T(1) - T(2) * (x * x + z * z), T(2) * (y * z - x * w),
-                  T(2) * (x * z - y * w), T(2) * (y * z + x * w), T(1) - T(2) * (x * x + y * y)};
-  const T off[3] = {T(gp.x), T(gp.y), T(gp.z)};
-  for (int i = 0; i < 3; ++i) {
-    o.p[i] = bp[i] + br[3 * i] * off[0] + br[3 * i + 1] * off[1] + br[3 * i + 2] * off[2];
-    for (int j = 0; j < 3; ++j)
-      o.r[3 * i + j] = br[3 * i] * g[j] + br[3 * i + 1] * g[3 + j] + br[3 * i + 2] * g[6 + j];
-  }
-}
-
 template <class T>
 __device__ inline void quat_to_rot(T qw, T qx, T qy, T qz, T *R) {
   const T inv = T(1) / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
@@ -96,126 +94,552 @@ __device__ inline void quat_to_rot(T qw, T qx, T qy, T qz, T *R) {
   R[6] = T(2) * (x * z - y * w); R[7] = T(2) * (y * z + x * w); R[8] = T(1) - T(2) * (x * x + y * y);
 }
 
-// Gap, normal (a -> b) and point of one candidate slot.
+// Rotation by angle th about the unit axis (ax, ay, az) (Rodrigues).
 template <class T>
-__device__ inline T eval_slot(uint32_t s, const GeomRec<T> *G, T n[3], T p[3]) {
-  const GeomRec<T> &A = G[slot_ga(s)];
-  const GeomRec<T> &B = G[slot_gb(s)];
+__device__ inline void axis_angle_rot(T ax, T ay, T az, T th, T *R) {
+  const T c = cos(th), s = sin(th), C = T(1) - c;
+  R[0] = c + ax * ax * C; R[1] = ax * ay * C - az * s; R[2] = ax * az * C + ay * s;
+  R[3] = ay * ax * C + az * s; R[4] = c + ay * ay * C; R[5] = ay * az * C - ax * s;
+  R[6] = az * ax * C - ay * s; R[7] = az * ay * C + ax * s; R[8] = c + az * az * C;
+}
+
+template <class T>
+__device__ inline void mul33(const T *A, const T *B, T *O) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) O[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// Forward kinematics of bodies [b0, b0+n) (parents precede children).  Writes
+// each body's frame origin org[4b..], rotation rows rot[12b..] (3 rows of 4)
+// and, when given, its world joint axis ax[4b..] and centre of mass com[4b..].
+template <class T>
+__device__ void fk_range(int b0, int n, const BodyC *B, const float *q, T *org, T *rot, T *ax, T *com) {
+  for (int b = b0; b < b0 + n; ++b) {
+    const BodyC c = B[b];
+    const float *qb = q + c.qadr;
+    T o[3], R[9], aw[3] = {T(0), T(0), T(0)};
+    if (c.jnt == kFree) {
+      o[0] = qb[0]; o[1] = qb[1]; o[2] = qb[2];
+      quat_to_rot<T>(qb[3], qb[4], qb[5], qb[6], R);
+    } else {
+      T po[3] = {T(0), T(0), T(0)}, pR[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
+      if (c.parent >= 0) {
+        for (int i = 0; i < 3; ++i) {
+          po[i] = org[4 * c.parent + i];
+          for (int j = 0; j < 3; ++j) pR[3 * i + j] = rot[12 * c.parent + 4 * i + j];
+        }
+      }
+      T bq[9], R0[9];
+      quat_to_rot<T>(c.quat.x, c.quat.y, c.quat.z, c.quat.w, bq);
+      mul33<T>(pR, bq, R0);
+      const T lp[3] = {c.pos.x, c.pos.y, c.pos.z}, la[3] = {c.axis.x, c.axis.y, c.axis.z};
+      for (int i = 0; i < 3; ++i) {
+        o[i] = po[i] + pR[3 * i] * lp[0] + pR[3 * i + 1] * lp[1] + pR[3 * i + 2] * lp[2];
+        aw[i] = R0[3 * i] * la[0] + R0[3 * i + 1] * la[1] + R0[3 * i + 2] * la[2];
+      }
+      const T th = qb[0];
+      if (c.jnt == kHinge) {
+        T Rj[9];
+        axis_angle_rot<T>(la[0], la[1], la[2], th, Rj);
+        mul33<T>(R0, Rj, R);
+      } else {
+        for (int i = 0; i < 9; ++i) R[i] = R0[i];
+        for (int i = 0; i < 3; ++i) o[i] += aw[i] * th;
+      }
+    }
+    for (int i = 0; i < 3; ++i) {
+      org[4 * b + i] = o[i];
+      for (int j = 0; j < 3; ++j) rot[12 * b + 4 * i + j] = R[3 * i + j];
+      if (ax) ax[4 * b + i] = aw[i];
+    }
+    if (com) {
+      const T ip[3] = {c.ipos.x, c.ipos.y, c.ipos.z};
+      for (int i = 0; i < 3; ++i) com[4 * b + i] = o[i] + R[3 * i] * ip[0] + R[3 * i + 1] * ip[1] + R[3 * i + 2] * ip[2];
+    }
+  }
+}
+
+// ====================================================================
+// articulated subtrees (one lane per subtree, float32, LDS work block)
+// ====================================================================
+// Jacobian columns of body b's COM for every dof on its chain to the root:
+// cols[6x] = (linear, angular) of chain entry x, idx[x] = dof index within the
+// subtree.  free joint dof k: (e_k, 0) for k < 3, (e x (com_b - org_j), e) with
+// e = e_{k-3}; hinge: (a x (com_b - org_j), a); slide: (a, 0).
+__device__ inline int chain_cols(int b, int d0, const BodyC *B, const float4 *bO, const float4 *bAx,
+                                 const float4 *bC, float *cols, int *idx) {
+  int n = 0;
+  const V3 cb = v3(bC[b].x, bC[b].y, bC[b].z);
+  for (int j = b; j >= 0; j = B[j].parent) {
+    const int jt = B[j].jnt, da = B[j].dadr;
+    const V3 r = cb - v3(bO[j].x, bO[j].y, bO[j].z);
+    const V3 aj = v3(bAx[j].x, bAx[j].y, bAx[j].z);
+    if (jt == kFree) {
+      for (int k = 0; k < 6; ++k) {
+        float *c = cols + 6 * n;
+        const V3 e = v3(k % 3 == 0 ? 1.f : 0.f, k % 3 == 1 ? 1.f : 0.f, k % 3 == 2 ? 1.f : 0.f);
+        const V3 lin = k < 3 ? e : cross(e, r), ang = k < 3 ? v3(0.f, 0.f, 0.f) : e;
+        c[0] = lin.x; c[1] = lin.y; c[2] = lin.z; c[3] = ang.x; c[4] = ang.y; c[5] = ang.z;
+        idx[n++] = da + k - d0;
+      }
+    } else {
+      float *c = cols + 6 * n;
+      const V3 lin = jt == kHinge ? cross(aj, r) : aj, ang = jt == kHinge ? aj : v3(0.f, 0.f, 0.f);
+      c[0] = lin.x; c[1] = lin.y; c[2] = lin.z; c[3] = ang.x; c[4] = ang.y; c[5] = ang.z;
+      idx[n++] = da - d0;
+    }
+  }
+  return n;
+}
+
+// World inertia R diag(I) R^T of a body from its rotation rows.
+__device__ inline void world_inertia(const float4 *Rr, float4 mi, float *I /*xx yy zz xy xz yz*/) {
+  const float d[3] = {mi.y, mi.z, mi.w};
+  const float R[9] = {Rr[0].x, Rr[0].y, Rr[0].z, Rr[1].x, Rr[1].y, Rr[1].z, Rr[2].x, Rr[2].y, Rr[2].z};
+  const int ri[6] = {0, 1, 2, 0, 0, 1}, rj[6] = {0, 1, 2, 1, 2, 2};
+  for (int k = 0; k < 6; ++k) {
+    const float *u = R + 3 * ri[k], *v = R + 3 * rj[k];
+    I[k] = u[0] * d[0] * v[0] + u[1] * d[1] * v[1] + u[2] * d[2] * v[2];
+  }
+}
+__device__ inline V3 sym_mul(const float *I, V3 x) {
+  return v3(I[0] * x.x + I[3] * x.y + I[4] * x.z, I[3] * x.x + I[1] * x.y + I[5] * x.z,
+            I[4] * x.x + I[5] * x.y + I[2] * x.z);
+}
+
+__device__ inline void chol_lower(float *M, int n) {
+  for (int j = 0; j < n; ++j) {
+    float s = M[j * n + j];
+    for (int k = 0; k < j; ++k) s -= M[j * n + k] * M[j * n + k];
+    const float l = sqrtf(fmaxf(s, 1e-30f));
+    M[j * n + j] = l;
+    const float il = 1.0f / l;
+    for (int i = j + 1; i < n; ++i) {
+      float t = M[i * n + j];
+      for (int k = 0; k < j; ++k) t -= M[i * n + k] * M[j * n + k];
+      M[i * n + j] = t * il;
+    }
+  }
+}
+__device__ inline void fwd_solve(const float *L, int n, float *x) {
+  for (int i = 0; i < n; ++i) {
+    float s = x[i];
+    for (int k = 0; k < i; ++k) s -= L[i * n + k] * x[k];
+    x[i] = s / L[i * n + i];
+  }
+}
+__device__ inline void bwd_solve(const float *L, int n, float *x) {
+  for (int i = n - 1; i >= 0; --i) {
+    float s = x[i];
+    for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * x[k];
+    x[i] = s / L[i * n + i];
+  }
+}
+
+// Smooth prediction of one articulated subtree: FK, M = sum_b J_b^T diag(m, I_b) J_b,
+// bias c = sum_b J_b^T [m (Jdot_b v - g); I_b (Jdot_b v)_ang + w_b x I_b w_b],
+// Cholesky, v_s = v + h M^-1 (tau - c), body velocities at v_s and COM traces.
+// Work block: M/L [nd*nd] | c [nd] | v_s [nd] | cols [6 nd] | idx [nd].
+__device__ void art_predict(const SubTree S, const BodyC *B, const float4 *bmi, const float *sq, const float *sv,
+                            const float *st, float4 *bC, float4 *bV, float4 *bW, float4 *bO, float4 *bAx,
+                            float4 *bR, float *blk, const Params &P) {
+  const int nd = S.nd, d0 = S.d0;
+  float *M = blk, *cv = M + nd * nd, *vs = cv + nd, *cols = vs + nd;
+  int *idx = reinterpret_cast<int *>(cols + 6 * nd);
+  fk_range<float>(S.b0, S.nb, B, sq, reinterpret_cast<float *>(bO), reinterpret_cast<float *>(bR),
+                  reinterpret_cast<float *>(bAx), reinterpret_cast<float *>(bC));
+  for (int i = 0; i < nd * nd; ++i) M[i] = 0.f;
+  for (int i = 0; i < nd; ++i) cv[i] = 0.f;
+  const float *v = sv + d0;
+  const V3 g = v3(P.gx, P.gy, P.gz);
+  for (int b = S.b0; b < S.b0 + S.nb; ++b) {
+    const int n = chain_cols(b, d0, B, bO, bAx, bC, cols, idx);
+    const float4 mi = bmi[b];
+    float Ib[6];
+    world_inertia(bR + 3 * b, mi, Ib);
+    V3 vc = v3(0.f, 0.f, 0.f), om = vc;
+    for (int x = 0; x < n; ++x) {
+      const float *c = cols + 6 * x, vx = v[idx[x]];
+      vc = vc + vx * v3(c[0], c[1], c[2]);
+      om = om + vx * v3(c[3], c[4], c[5]);
+    }
+    const V3 cb = v3(bC[b].x, bC[b].y, bC[b].z), ob = v3(bO[b].x, bO[b].y, bO[b].z);
+    const V3 vo = vc + cross(om, ob - cb);
+    bW[b] = make_float4(om.x, om.y, om.z, 0.f);  // velocities at v (ancestors first)
+    bV[b] = make_float4(vo.x, vo.y, vo.z, 0.f);
+    // velocity-product accelerations Jdot_b v
+    V3 jl = v3(0.f, 0.f, 0.f), ja = jl;
+    for (int j = b; j >= 0; j = B[j].parent) {
+      const int jt = B[j].jnt, da = B[j].dadr - d0;
+      const V3 wj = v3(bW[j].x, bW[j].y, bW[j].z), voj = v3(bV[j].x, bV[j].y, bV[j].z);
+      const V3 aj = v3(bAx[j].x, bAx[j].y, bAx[j].z), oj = v3(bO[j].x, bO[j].y, bO[j].z);
+      if (jt == kFree) {
+        jl = jl + cross(v3(v[da + 3], v[da + 4], v[da + 5]), vc - voj);
+      } else {
+        const V3 wa = cross(wj, aj);
+        const float td = v[da];
+        if (jt == kHinge) {
+          jl = jl + td * (cross(wa, cb - oj) + cross(aj, vc - voj));
+          ja = ja + td * wa;
+        } else {
+          jl = jl + td * wa;
+        }
+      }
+    }
+    const V3 Flin = mi.x * (jl - g);
+    const V3 Fang = sym_mul(Ib, ja) + cross(om, sym_mul(Ib, om));
+    for (int x = 0; x < n; ++x) {
+      const float *c = cols + 6 * x;
+      const V3 lx = v3(c[0], c[1], c[2]), ax_ = v3(c[3], c[4], c[5]);
+      cv[idx[x]] += dot(lx, Flin) + dot(ax_, Fang);
+      const V3 Ia = sym_mul(Ib, ax_);
+      for (int y = 0; y < n; ++y) {
+        if (idx[y] > idx[x]) continue;
+        const float *e = cols + 6 * y;
+        M[idx[x] * nd + idx[y]] += mi.x * (lx.x * e[0] + lx.y * e[1] + lx.z * e[2]) +
+                                   Ia.x * e[3] + Ia.y * e[4] + Ia.z * e[5];
+      }
+    }
+  }
+  chol_lower(M, nd);
+  for (int i = 0; i < nd; ++i) vs[i] = st[d0 + i] - cv[i];
+  fwd_solve(M, nd, vs);
+  bwd_solve(M, nd, vs);
+  for (int i = 0; i < nd; ++i) vs[i] = v[i] + P.h * vs[i];
+  // body velocities at v_s and traces ||L^-1 J_lin^T||_F^2 (cv is scratch from here on)
+  for (int b = S.b0; b < S.b0 + S.nb; ++b) {
+    const int n = chain_cols(b, d0, B, bO, bAx, bC, cols, idx);
+    V3 vc = v3(0.f, 0.f, 0.f), om = vc;
+    for (int x = 0; x < n; ++x) {
+      const float *c = cols + 6 * x, vx = vs[idx[x]];
+      vc = vc + vx * v3(c[0], c[1], c[2]);
+      om = om + vx * v3(c[3], c[4], c[5]);
+    }
+    float tr = 0.f;
+    for (int r = 0; r < 3; ++r) {
+      for (int i = 0; i < nd; ++i) cv[i] = 0.f;
+      for (int x = 0; x < n; ++x) cv[idx[x]] = cols[6 * x + r];
+      fwd_solve(M, nd, cv);
+      for (int i = 0; i < nd; ++i) tr += cv[i] * cv[i];
+    }
+    bV[b] = make_float4(vc.x, vc.y, vc.z, tr);
+    bW[b] = make_float4(om.x, om.y, om.z, 0.f);
+    bC[b].w = 0.f;
+  }
+}
+
+// Velocity correction and integration of one articulated subtree:
+// p = sum_b J_b^T (F_b, T_b), v+ = v_s + M^-1 p, q+ = q (+) h v+.
+__device__ void art_correct(const SubTree S, const BodyC *B, const float4 *bC, const float4 *bO,
+                            const float4 *bAx, const float4 *accF, const float4 *accT, float *sq, float *sv,
+                            float *blk, const Params &P) {
+  const int nd = S.nd, d0 = S.d0;
+  float *M = blk, *p = M + nd * nd, *vs = p + nd, *cols = vs + nd;
+  int *idx = reinterpret_cast<int *>(cols + 6 * nd);
+  for (int i = 0; i < nd; ++i) p[i] = 0.f;
+  for (int b = S.b0; b < S.b0 + S.nb; ++b) {
+    const int n = chain_cols(b, d0, B, bO, bAx, bC, cols, idx);
+    const V3 F = v3(accF[b].x, accF[b].y, accF[b].z), T = v3(accT[b].x, accT[b].y, accT[b].z);
+    for (int x = 0; x < n; ++x) {
+      const float *c = cols + 6 * x;
+      p[idx[x]] += c[0] * F.x + c[1] * F.y + c[2] * F.z + c[3] * T.x + c[4] * T.y + c[5] * T.z;
+    }
+  }
+  fwd_solve(M, nd, p);
+  bwd_solve(M, nd, p);
+  for (int i = 0; i < nd; ++i) sv[d0 + i] = vs[i] + p[i];
+  for (int b = S.b0; b < S.b0 + S.nb; ++b) {
+    const BodyC c = B[b];
+    float *qb = sq + c.qadr;
+    const float *vb = sv + c.dadr;
+    if (c.jnt != kFree) {
+      qb[0] += P.h * vb[0];
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) qb[k] += P.h * vb[k];
+    const V3 th = P.h * v3(vb[3], vb[4], vb[5]);
+    const float ang = sqrtf(dot(th, th));
+    float ew, ex, ey, ez;
+    if (ang < 1e-8f) {
+      ew = 1.f; ex = 0.5f * th.x; ey = 0.5f * th.y; ez = 0.5f * th.z;
+    } else {
+      const float s = sinf(0.5f * ang) / ang;
+      ew = cosf(0.5f * ang); ex = s * th.x; ey = s * th.y; ez = s * th.z;
+    }
+    const float qw0 = qb[3], qx0 = qb[4], qy0 = qb[5], qz0 = qb[6];
+    const float nw_ = ew * qw0 - ex * qx0 - ey * qy0 - ez * qz0;
+    const float nx_ = ew * qx0 + ex * qw0 + ey * qz0 - ez * qy0;
+    const float ny_ = ew * qy0 - ex * qz0 + ey * qw0 + ez * qx0;
+    const float nz_ = ew * qz0 + ex * qy0 - ey * qx0 + ez * qw0;
+    const float inv = 1.0f / sqrtf(nw_ * nw_ + nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+    qb[3] = nw_ * inv; qb[4] = nx_ * inv; qb[5] = ny_ * inv; qb[6] = nz_ * inv;
+  }
+}
+
+// ====================================================================
+// collision
+// ====================================================================
+// LDS: q row; per geom a float4 (position, size0) and its oriented index;
+// per oriented geom (planes, capsules, boxes, offset spheres) a float32 and a
+// float64 pose record; the ordered candidate list.
+template <class T>
+struct Pose {
+  T p[3];   // world position
+  T r[9];   // world rotation, row-major
+  T s[3];   // size
+  T pad;
+};
+
+size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub) {
+  return sizeof(float) * pad4(nq) + sizeof(float4) * (size_t)ng + sizeof(int) * (size_t)pad4(ng) +
+         (sizeof(Pose<float>) + sizeof(Pose<double>)) * (size_t)norient + sizeof(uint32_t) * kCandCap +
+         (nsub > 0 ? sizeof(double) * 16 * (size_t)nb : 0);
+}
+
+// float32 test: is the slot's gap below `thr` (margin plus the float32 band)?
+__device__ inline bool slot_candidate(uint32_t s, const float4 *Gs, const int *go, const Pose<float> *Of,
+                                      float thr) {
+  const int ga = slot_ga(s), gb = slot_gb(s);
+  const uint32_t t = slot_type(s);
+  if (t == kSphereSphere) {
+    const float4 A = Gs[ga], B = Gs[gb];
+    const float dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
+    const float R = A.w + B.w + thr;
+    return R > 0.f && dx * dx + dy * dy + dz * dz < R * R;
+  }
+  const Pose<float> &P = Of[go[ga]];
+  const float nx = P.r[2], ny = P.r[5], nz = P.r[8];
+  float cx, cy, cz, rad = 0.f;
+  if (t == kPlaneSphere) {
+    const float4 B = Gs[gb];
+    cx = B.x; cy = B.y; cz = B.z; rad = B.w;
+  } else {
+    const Pose<float> &B = Of[go[gb]];
+    cx = B.p[0]; cy = B.p[1]; cz = B.p[2];
+    const int sub = slot_sub(s);
+    if (t == kPlaneCapsule) {
+      const float hl = sub == 0 ? -B.s[1] : B.s[1];
+      cx += hl * B.r[2]; cy += hl * B.r[5]; cz += hl * B.r[8];
+      rad = B.s[0];
+    } else {
+      const float l0 = (sub & 1) ? B.s[0] : -B.s[0];
+      const float l1 = (sub & 2) ? B.s[1] : -B.s[1];
+      const float l2 = (sub & 4) ? B.s[2] : -B.s[2];
+      cx += B.r[0] * l0 + B.r[1] * l1 + B.r[2] * l2;
+      cy += B.r[3] * l0 + B.r[4] * l1 + B.r[5] * l2;
+      cz += B.r[6] * l0 + B.r[7] * l1 + B.r[8] * l2;
+    }
+  }
+  const float phi = nx * (cx - P.p[0]) + ny * (cy - P.p[1]) + nz * (cz - P.p[2]) - rad;
+  return phi < thr;
+}
+
+// float64 centre and radius of a sphere geom.
+__device__ inline void sphere_of(int g, const float4 *Gs, const int *go, const Pose<double> *Od, double c[3],
+                                 double &r) {
+  const int o = go[g];
+  if (o < 0) {
+    const float4 G = Gs[g];
+    c[0] = G.x; c[1] = G.y; c[2] = G.z; r = G.w;
+  } else {
+    c[0] = Od[o].p[0]; c[1] = Od[o].p[1]; c[2] = Od[o].p[2]; r = Od[o].s[0];
+  }
+}
+
+// float64 gap, normal (a -> b) and point of one candidate slot.
+__device__ inline double slot_eval(uint32_t s, const float4 *Gs, const int *go, const Pose<double> *Od,
+                                   double n[3], double p[3]) {
+  const int ga = slot_ga(s), gb = slot_gb(s);
   const uint32_t t = slot_type(s);
   const int sub = slot_sub(s);
-  T phi;
   if (t == kSphereSphere) {
-    const T d[3] = {B.p[0] - A.p[0], B.p[1] - A.p[1], B.p[2] - A.p[2]};
-    const T dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    if (dist >= T(1e-12)) {
+    double ca[3], cb[3], ra, rb;
+    sphere_of(ga, Gs, go, Od, ca, ra);
+    sphere_of(gb, Gs, go, Od, cb, rb);
+    const double d[3] = {cb[0] - ca[0], cb[1] - ca[1], cb[2] - ca[2]};
+    const double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (dist >= 1e-12) {
       n[0] = d[0] / dist; n[1] = d[1] / dist; n[2] = d[2] / dist;
     } else {
-      n[0] = T(0); n[1] = T(0); n[2] = T(1);
+      n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
     }
-    phi = dist - A.s[0] - B.s[0];
-    const T ra = A.s[0] + T(0.5) * phi;
-    for (int i = 0; i < 3; ++i) p[i] = A.p[i] + ra * n[i];
+    const double phi = dist - ra - rb;
+    const double k = ra + 0.5 * phi;
+    for (int i = 0; i < 3; ++i) p[i] = ca[i] + k * n[i];
     return phi;
   }
-  n[0] = A.r[2]; n[1] = A.r[5]; n[2] = A.r[8];  // plane normal: local z
-  T c[3] = {B.p[0], B.p[1], B.p[2]};
-  if (t == kPlaneBox) {
-    const T l0 = (sub & 1) ? B.s[0] : -B.s[0];
-    const T l1 = (sub & 2) ? B.s[1] : -B.s[1];
-    const T l2 = (sub & 4) ? B.s[2] : -B.s[2];
-    for (int i = 0; i < 3; ++i) c[i] += B.r[3 * i] * l0 + B.r[3 * i + 1] * l1 + B.r[3 * i + 2] * l2;
-    phi = n[0] * (c[0] - A.p[0]) + n[1] * (c[1] - A.p[1]) + n[2] * (c[2] - A.p[2]);
-    for (int i = 0; i < 3; ++i) p[i] = c[i] - T(0.5) * phi * n[i];
-    return phi;
+  const Pose<double> &P = Od[go[ga]];
+  n[0] = P.r[2]; n[1] = P.r[5]; n[2] = P.r[8];  // plane normal: local z
+  double c[3], rad = 0.0;
+  if (t == kPlaneSphere) {
+    sphere_of(gb, Gs, go, Od, c, rad);
+  } else {
+    const Pose<double> &B = Od[go[gb]];
+    c[0] = B.p[0]; c[1] = B.p[1]; c[2] = B.p[2];
+    if (t == kPlaneCapsule) {
+      const double hl = sub == 0 ? -B.s[1] : B.s[1];
+      for (int i = 0; i < 3; ++i) c[i] += hl * B.r[3 * i + 2];
+      rad = B.s[0];
+    } else {
+      const double l0 = (sub & 1) ? B.s[0] : -B.s[0];
+      const double l1 = (sub & 2) ? B.s[1] : -B.s[1];
+      const double l2 = (sub & 4) ? B.s[2] : -B.s[2];
+      for (int i = 0; i < 3; ++i) c[i] += B.r[3 * i] * l0 + B.r[3 * i + 1] * l1 + B.r[3 * i + 2] * l2;
+    }
   }
-  if (t == kPlaneCapsule) {
-    const T half = sub == 0 ? -B.s[1] : B.s[1];
-    for (int i = 0; i < 3; ++i) c[i] += half * B.r[3 * i + 2];
-  }
-  phi = n[0] * (c[0] - A.p[0]) + n[1] * (c[1] - A.p[1]) + n[2] * (c[2] - A.p[2]) - B.s[0];
-  const T rr = B.s[0] + T(0.5) * phi;
-  for (int i = 0; i < 3; ++i) p[i] = c[i] - rr * n[i];
+  const double phi = n[0] * (c[0] - P.p[0]) + n[1] * (c[1] - P.p[1]) + n[2] * (c[2] - P.p[2]) - rad;
+  const double k = rad + 0.5 * phi;
+  for (int i = 0; i < 3; ++i) p[i] = c[i] - k * n[i];
   return phi;
 }
 
-__global__ __launch_bounds__(kBlock) void collide_kernel(CollideArgs a) {
+template <int BS, bool ART>
+__global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
+  constexpr int NW = BS / 64;
   extern __shared__ float4 lds[];
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int w = blockIdx.x, tid = threadIdx.x;
   float *sq = reinterpret_cast<float *>(lds);
-  GeomRec<double> *Gd = reinterpret_cast<GeomRec<double> *>(lds + pad4(a.nq) / 4);
-  GeomRec<float> *Gf = reinterpret_cast<GeomRec<float> *>(Gd + a.ng);
-  __shared__ int wave_count[2][kWaves];
+  Pose<double> *Od = reinterpret_cast<Pose<double> *>(lds + pad4(a.nq) / 4);
+  Pose<float> *Of = reinterpret_cast<Pose<float> *>(Od + a.norient);
+  float4 *Gs = reinterpret_cast<float4 *>(Of + a.norient);
+  int *go = reinterpret_cast<int *>(Gs + a.ng);
+  uint32_t *cand = reinterpret_cast<uint32_t *>(go + pad4(a.ng));
+  double *borg = reinterpret_cast<double *>(cand + kCandCap);  // [nb][4] articulated bodies
+  double *brot = borg + 4 * a.nb;                              // [nb][12]
+  __shared__ int wcnt[2 * NW];
+  __shared__ float wmax[NW];
 
+  uint32_t nxt = tid < a.nslot ? a.slots[tid] : 0u;  // prefetch of the first chunk
   const float *qw = a.q + (size_t)w * a.nq;
-  for (int i = tid; i < a.nq; i += kBlock) sq[i] = qw[i];
+  for (int i = tid; i < a.nq; i += BS) sq[i] = qw[i];
   __syncthreads();
-
-  // geom world poses in float64 (free bodies: body origin = COM, q = (x, quat))
-  for (int g = tid; g < a.ng; g += kBlock) {
-    const int b = a.gbody[g];
-    const float4 gp = a.gpos[(size_t)w * a.gpos_ws + g];
-    const float4 gq = a.gquat[(size_t)w * a.gquat_ws + g];
-    const float4 gd = a.gdat[(size_t)w * a.ng + g];
-    double bp[3] = {0.0, 0.0, 0.0}, br[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
-    if (b >= 0) {
-      const float *qb = sq + 7 * b;
-      bp[0] = qb[0]; bp[1] = qb[1]; bp[2] = qb[2];
-      quat_to_rot<double>(qb[3], qb[4], qb[5], qb[6], br);
+  if (ART) {  // forward kinematics of articulated subtrees, float64
+    for (int si = tid; si < a.nsub; si += BS) {
+      const SubTree S = a.sub[si];
+      fk_range<double>(S.b0, S.nb, a.body, sq, borg, brot, nullptr, nullptr);
     }
-    GeomRec<double> rd;
-    geom_pose<double>(bp, br, gp, gq, rd);
-    rd.s[0] = gd.x; rd.s[1] = gd.y; rd.s[2] = gd.z; rd.pad = 0.0;
-    Gd[g] = rd;
-    GeomRec<float> rf;
-    for (int i = 0; i < 3; ++i) { rf.p[i] = (float)rd.p[i]; rf.s[i] = (float)rd.s[i]; }
-    for (int i = 0; i < 9; ++i) rf.r[i] = (float)rd.r[i];
-    rf.pad = 0.f;
-    Gf[g] = rf;
+    __syncthreads();
+  }
+
+  // geom world poses; oriented geoms also get float64 and float32 pose records
+  for (int g = tid; g < a.ng; g += BS) {
+    const int b = a.gbody[g], o = a.gorient[g];
+    const float4 gp = a.gpos[(size_t)w * a.gpos_ws + g];
+    const float4 gd = a.gdat[(size_t)w * a.ng + g];
+    go[g] = o;
+    if (o < 0) {  // sphere at the origin of a free body (or static)
+      const float *qb = b >= 0 ? sq + a.body[b].qadr : nullptr;
+      Gs[g] = b >= 0 ? make_float4(qb[0], qb[1], qb[2], gd.x) : make_float4(gp.x, gp.y, gp.z, gd.x);
+      continue;
+    }
+    const float4 gq = a.gquat[(size_t)w * a.gquat_ws + g];
+    double bp[3] = {0.0, 0.0, 0.0}, br[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0}, gr[9];
+    if (b >= 0) {
+      const BodyC bc = a.body[b];
+      if (!ART || bc.fast) {
+        const float *qb = sq + bc.qadr;
+        bp[0] = qb[0]; bp[1] = qb[1]; bp[2] = qb[2];
+        quat_to_rot<double>(qb[3], qb[4], qb[5], qb[6], br);
+      } else {
+        for (int i = 0; i < 3; ++i) {
+          bp[i] = borg[4 * b + i];
+          for (int j = 0; j < 3; ++j) br[3 * i + j] = brot[12 * b + 4 * i + j];
+        }
+      }
+    }
+    quat_to_rot<double>(gq.x, gq.y, gq.z, gq.w, gr);
+    Pose<double> pd;
+    Pose<float> pf;
+    const double off[3] = {gp.x, gp.y, gp.z};
+    for (int i = 0; i < 3; ++i) {
+      pd.p[i] = bp[i] + br[3 * i] * off[0] + br[3 * i + 1] * off[1] + br[3 * i + 2] * off[2];
+      for (int j = 0; j < 3; ++j)
+        pd.r[3 * i + j] = br[3 * i] * gr[j] + br[3 * i + 1] * gr[3 + j] + br[3 * i + 2] * gr[6 + j];
+    }
+    pd.s[0] = gd.x; pd.s[1] = gd.y; pd.s[2] = gd.z; pd.pad = 0.0;
+    for (int i = 0; i < 3; ++i) { pf.p[i] = (float)pd.p[i]; pf.s[i] = (float)pd.s[i]; }
+    for (int i = 0; i < 9; ++i) pf.r[i] = (float)pd.r[i];
+    pf.pad = 0.f;
+    Od[o] = pd;
+    Of[o] = pf;
+    Gs[g] = make_float4(pf.p[0], pf.p[1], pf.p[2], gd.x);
   }
   __syncthreads();
 
-  // candidate slots in canonical order; order-preserving compaction
+  // Pass-1 band: float32 gaps are accurate to a few ulp of the coordinates and
+  // sizes involved; one band per world, from the largest of them.
+  float band;
+  {
+    float ext = 0.f;
+    for (int g = tid; g < a.ng; g += BS) {
+      const float4 G = Gs[g];
+      ext = fmaxf(ext, fmaxf(fmaxf(fabsf(G.x), fabsf(G.y)), fmaxf(fabsf(G.z), G.w)));
+    }
+    for (int o = tid; o < a.norient; o += BS)
+      ext = fmaxf(ext, fmaxf(fmaxf(Of[o].s[0], Of[o].s[1]), Of[o].s[2]));
+    ext = block_max<BS>(ext, wmax);
+    band = 1e-4f + 8e-6f * ext;
+  }
   const size_t cbase = (size_t)w * a.ncon_max;
-  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  int running = 0;
-  for (int base = 0, it = 0; base < a.nslot; base += kBlock, ++it) {
-    const int s = base + tid;
-    bool hit = false;
-    float4 cn, cp;
-    if (s < a.nslot) {
-      const uint32_t sl = a.slots[s];
-      float nf[3], pf[3];
-      const float phi32 = eval_slot<float>(sl, Gf, nf, pf);
-      const GeomRec<float> &B = Gf[slot_gb(sl)];
-      // float32 gap error is a few ulp of the coordinates involved
-      const float band = 1e-4f + 1e-6f * (fabsf(B.p[0]) + fabsf(B.p[1]) + fabsf(B.p[2]) + B.s[0] + B.s[1] + B.s[2]);
-      if (phi32 < a.margin + band) {
-        double nd[3], pd[3];
-        const double phi = eval_slot<double>(sl, Gd, nd, pd);
-        hit = phi < (double)a.margin;
-        cn = make_float4((float)nd[0], (float)nd[1], (float)nd[2], (float)phi);
-        cp = make_float4((float)pd[0], (float)pd[1], (float)pd[2], __uint_as_float(sl));
-      }
-    }
-    const unsigned long long m = __ballot(hit);
-    if (lane == 0) wave_count[it & 1][wave] = __popcll(m);
+  int running = 0, ncand = 0, par = 0;
+  // Pass 2 over the candidate list: float64 decision, ordered store.
+  auto flush = [&]() {
     __syncthreads();
-    int off = running, tot = 0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) {
-      const int c = wave_count[it & 1][i];
-      off += i < wave ? c : 0;
-      tot += c;
-    }
-    if (hit) {
-      const int idx = off + __popcll(m & below);
-      if (idx < a.ncon_max) {
+    for (int cb = 0; cb < ncand; cb += BS) {
+      const int i = cb + tid;
+      bool hit = false;
+      float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
+      if (i < ncand) {
+        const uint32_t sl = cand[i];
+        const int ga = slot_ga(sl), gb = slot_gb(sl);
+        if (slot_type(sl) == kSphereSphere && go[ga] < 0 && go[gb] < 0) {
+          // two spheres centred on their bodies: the centres are exact float32
+          // state values and the gap needs no rotation, float32 suffices
+          const float4 A = Gs[ga], B = Gs[gb];
+          const V3 d = v3(B.x - A.x, B.y - A.y, B.z - A.z);
+          const float dist = sqrtf(dot(d, d));
+          const V3 n = dist >= 1e-12f ? (1.0f / dist) * d : v3(0.f, 0.f, 1.f);
+          const float phi = dist - A.w - B.w;
+          const float k = A.w + 0.5f * phi;
+          hit = phi < a.margin;
+          cn = make_float4(n.x, n.y, n.z, phi);
+          cp = make_float4(A.x + k * n.x, A.y + k * n.y, A.z + k * n.z, __uint_as_float(sl));
+        } else {
+          double nd[3], pd[3];
+          const double phi = slot_eval(sl, Gs, go, Od, nd, pd);
+          hit = phi < (double)a.margin;
+          cn = make_float4((float)nd[0], (float)nd[1], (float)nd[2], (float)phi);
+          cp = make_float4((float)pd[0], (float)pd[1], (float)pd[2], __uint_as_float(sl));
+        }
+      }
+      int tot;
+      const int idx = running + block_scan<BS>(hit, &tot, wcnt, par);
+      par ^= 1;
+      if (hit && idx < a.ncon_max) {
         a.cnp[cbase + idx] = cn;
         a.cpos[cbase + idx] = cp;
       }
+      running += tot;
     }
-    running += tot;
+    __syncthreads();
+    ncand = 0;
+  };
+
+  // Pass 1 over all slots: float32 test, ordered candidate list.
+  for (int base = 0; base < a.nslot; base += BS) {
+    if (ncand + BS > kCandCap) flush();
+    const int s = base + tid;
+    const uint32_t sl = nxt;
+    nxt = s + BS < a.nslot ? a.slots[s + BS] : 0u;
+    const bool c = s < a.nslot && slot_candidate(sl, Gs, go, Of, a.margin + band);
+    int tot;
+    const int idx = block_scan<BS>(c, &tot, wcnt, par);
+    par ^= 1;
+    if (c) cand[ncand + idx] = sl;
+    ncand += tot;
   }
+  if (ncand > 0) flush();
+
   if (tid == 0) {
     const int kept = running < a.ncon_max ? running : a.ncon_max;
     a.ncon[w] = kept;
@@ -223,11 +647,23 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(CollideArgs a) {
     if (a.ncon_out) a.ncon_out[w] = kept;
     if (a.overflow_out) a.overflow_out[w] = running - kept;
   }
+  (void)NW;
 }
 
-hipError_t launch_collide(const CollideArgs &a, int nworld, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(collide_kernel, dim3(nworld), dim3(kBlock), lds, s, a);
+template <bool ART>
+static hipError_t launch_collide_a(const CollideArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  switch (block) {
+    case 64: hipLaunchKernelGGL((collide_kernel<64, ART>), dim3(nworld), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((collide_kernel<128, ART>), dim3(nworld), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((collide_kernel<256, ART>), dim3(nworld), dim3(256), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  return a.nsub > 0 ? launch_collide_a<true>(a, nworld, block, lds, s)
+                    : launch_collide_a<false>(a, nworld, block, lds, s);
 }
 
 // ====================================================================
@@ -236,15 +672,17 @@ hipError_t launch_collide(const CollideArgs &a, int nworld, size_t lds, hipStrea
 // LDS: q, v, tau rows; per body 7 float4 (com|invm, vs|tr, ws, Iinv a, Iinv b,
 // accumulated force, accumulated torque); per geom float4 friction + int body;
 // per lane the two wrench entries of its contact (float4 + float2 each).
-size_t resolve_lds_bytes(int nq, int nv, int nb, int ng) {
+size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats) {
   return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + sizeof(float4) * 7 * (size_t)nb +
-         sizeof(float4) * (size_t)ng + (sizeof(float4) + sizeof(float2)) * 2 * kBlock +
-         sizeof(int) * (size_t)pad4(ng);
+         sizeof(float4) * (size_t)ng + (sizeof(float4) + sizeof(float2)) * 2 * (size_t)block +
+         sizeof(int) * (size_t)pad4(ng) +
+         (nsub > 0 ? sizeof(float4) * 5 * (size_t)nb + sizeof(float) * (size_t)pad4(art_floats) : 0);
 }
 
-template <int CONDIM>
-__global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
+template <int CONDIM, int BS, bool ART>
+__global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
+  constexpr int NW = BS / 64;
   extern __shared__ float4 lds[];
   const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nq = a.nq, nv = a.nv, nb = a.nb, ng = a.ng;
@@ -255,23 +693,35 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
   float4 *bV = bC + nb, *bW = bV + nb, *bI0 = bW + nb, *bI1 = bI0 + nb;
   float4 *accF = bI1 + nb, *accT = accF + nb;
   float4 *gM = accT + nb;
-  float4 *vA = gM + ng, *vB = vA + kBlock;
-  float2 *vA2 = reinterpret_cast<float2 *>(vB + kBlock), *vB2 = vA2 + kBlock;
-  int *gB = reinterpret_cast<int *>(vB2 + kBlock);
+  float4 *vA = gM + ng, *vB = vA + BS;
+  float2 *vA2 = reinterpret_cast<float2 *>(vB + BS), *vB2 = vA2 + BS;
+  int *gB = reinterpret_cast<int *>(vB2 + BS);
+  float4 *bO = reinterpret_cast<float4 *>(gB + pad4(ng));  // articulated bodies only
+  float4 *bAx = bO + nb, *bR = bAx + nb;                    // bR: 3 rows per body
+  float *art = reinterpret_cast<float *>(bR + 3 * nb);
   const Params P = a.p;
+  const size_t cbase = (size_t)w * a.ncon_max;
 
-  // ---- stage the world's rows (coalesced) and per-geom constants
+  // ---- issue every independent global load up front
+  const int nc = a.ncon[w];
+  float4 c0n = make_float4(0.f, 0.f, 0.f, 0.f), c0p = c0n;
+  if (tid < a.ncon_max) {  // the first chunk's records (only used below ncon)
+    c0n = a.cnp[cbase + tid];
+    c0p = a.cpos[cbase + tid];
+  }
+  float4 mi0 = make_float4(1.f, 1.f, 1.f, 1.f);
+  if (tid < nb) mi0 = a.bmi[(size_t)w * nb + tid];
   {
     const float *qw = a.q + (size_t)w * nq, *vw = a.v + (size_t)w * nv;
-    for (int i = tid; i < nq; i += kBlock) sq[i] = qw[i];
-    for (int i = tid; i < nv; i += kBlock) sv[i] = vw[i];
+    for (int i = tid; i < nq; i += BS) sq[i] = qw[i];
+    for (int i = tid; i < nv; i += BS) sv[i] = vw[i];
     if (a.tau) {
       const float *tw = a.tau + (size_t)w * nv;
-      for (int i = tid; i < nv; i += kBlock) st[i] = tw[i];
+      for (int i = tid; i < nv; i += BS) st[i] = tw[i];
     } else {
-      for (int i = tid; i < nv; i += kBlock) st[i] = 0.f;
+      for (int i = tid; i < nv; i += BS) st[i] = 0.f;
     }
-    for (int g = tid; g < ng; g += kBlock) {
+    for (int g = tid; g < ng; g += BS) {
       gB[g] = a.gbody[g];
       const float mu_t = a.gdat[(size_t)w * ng + g].w;
       float2 fr = make_float2(0.f, 0.f);
@@ -281,29 +731,25 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
   }
   __syncthreads();
 
-  // ---- per body: M blocks, bias, smooth prediction (Eq. smooth_vel), trace 3/m
-  for (int b = tid; b < nb; b += kBlock) {
-    const float4 mi = a.bmi[(size_t)w * nb + b];
-    const float *qb = sq + 7 * b, *vb = sv + 6 * b, *tb = st + 6 * b;
-    V3 r0, r1, r2;
-    quat_rows(qb[3], qb[4], qb[5], qb[6], r0, r1, r2);
+  // ---- per free body: M blocks, bias, smooth prediction (Eq. smooth_vel), trace 3/m
+  for (int b = tid; b < nb; b += BS) {
+    const BodyC bc = a.body[b];
+    if (ART && !bc.fast) continue;
+    const float4 mi = b == tid ? mi0 : a.bmi[(size_t)w * nb + b];
+    const float *qb = sq + bc.qadr, *vb = sv + bc.dadr, *tb = st + bc.dadr;
+    float R[9];
+    quat_to_rot<float>(qb[3], qb[4], qb[5], qb[6], R);
     const float invm = 1.0f / mi.x;
-    const float i0 = mi.y, i1 = mi.z, i2 = mi.w;
-    const float j0 = 1.0f / i0, j1 = 1.0f / i1, j2 = 1.0f / i2;
-    // world inertia Iw = R diag(I) R^T and its inverse R diag(1/I) R^T (symmetric)
-    const V3 c0 = v3(r0.x, r1.x, r2.x), c1 = v3(r0.y, r1.y, r2.y), c2 = v3(r0.z, r1.z, r2.z);
-    (void)c0; (void)c1; (void)c2;
-    auto sym = [&](float d0, float d1, float d2, float *o) {
-      o[0] = r0.x * d0 * r0.x + r0.y * d1 * r0.y + r0.z * d2 * r0.z;  // xx
-      o[1] = r1.x * d0 * r1.x + r1.y * d1 * r1.y + r1.z * d2 * r1.z;  // yy
-      o[2] = r2.x * d0 * r2.x + r2.y * d1 * r2.y + r2.z * d2 * r2.z;  // zz
-      o[3] = r0.x * d0 * r1.x + r0.y * d1 * r1.y + r0.z * d2 * r1.z;  // xy
-      o[4] = r0.x * d0 * r2.x + r0.y * d1 * r2.y + r0.z * d2 * r2.z;  // xz
-      o[5] = r1.x * d0 * r2.x + r1.y * d1 * r2.y + r1.z * d2 * r2.z;  // yz
-    };
+    const float d[3] = {mi.y, mi.z, mi.w}, e[3] = {1.0f / mi.y, 1.0f / mi.z, 1.0f / mi.w};
+    // world inertia R diag(I) R^T and its inverse R diag(1/I) R^T (xx, yy, zz, xy, xz, yz)
     float Iw[6], Ii[6];
-    sym(i0, i1, i2, Iw);
-    sym(j0, j1, j2, Ii);
+    const int ri[6] = {0, 1, 2, 0, 0, 1}, rj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float *u = R + 3 * ri[k], *v = R + 3 * rj[k];
+      Iw[k] = u[0] * d[0] * v[0] + u[1] * d[1] * v[1] + u[2] * d[2] * v[2];
+      Ii[k] = u[0] * e[0] * v[0] + u[1] * e[1] * v[1] + u[2] * e[2] * v[2];
+    }
     const V3 om = v3(vb[3], vb[4], vb[5]);
     const V3 Io = v3(Iw[0] * om.x + Iw[3] * om.y + Iw[4] * om.z,
                      Iw[3] * om.x + Iw[1] * om.y + Iw[5] * om.z,
@@ -322,23 +768,30 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
     bW[b] = make_float4(ws.x, ws.y, ws.z, 0.f);
     bI0[b] = make_float4(Ii[0], Ii[1], Ii[2], Ii[3]);
     bI1[b] = make_float4(Ii[4], Ii[5], 0.f, 0.f);
+  }
+  for (int b = tid; b < nb; b += BS) {
     accF[b] = make_float4(0.f, 0.f, 0.f, 0.f);
     accT[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  // ---- articulated subtrees: one lane each (same equations, dense per-subtree M)
+  if (ART)
+  for (int si = tid; si < a.nsub; si += BS) {
+    const SubTree S = a.sub[si];
+    art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
   }
   __syncthreads();
 
   // ---- contacts: facet impulses, wrenches, deterministic per-body reduction
-  const int nc = a.ncon[w];
-  const size_t cbase = (size_t)w * a.ncon_max;
-  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const unsigned long long below = lanes_below(lane);
   const float aa = P.k_user * P.h + P.d_user;
-  for (int base = 0; base < nc; base += kBlock) {
+  for (int base = 0; base < nc; base += BS) {
     const int k = base + tid;
     int kA = nb, kB = nb;  // key nb = no body (static geom or idle lane)
     float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
     float2 WA2 = make_float2(0.f, 0.f), WB2 = WA2;
     if (k < nc) {
-      const float4 cn = a.cnp[cbase + k], cp = a.cpos[cbase + k];
+      const float4 cn = base == 0 ? c0n : a.cnp[cbase + k];
+      const float4 cp = base == 0 ? c0p : a.cpos[cbase + k];
       const uint32_t sl = __float_as_uint(cp.w);
       const int ga = slot_ga(sl), gb = slot_gb(sl);
       const int ba = gB[ga], bb = gB[gb];
@@ -347,7 +800,7 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
       // tangent basis
       V3 t1 = fabsf(n.x) <= 0.5f ? v3(1.f - n.x * n.x, -n.x * n.y, -n.x * n.z)
                                  : v3(-n.y * n.x, 1.f - n.y * n.y, -n.y * n.z);
-      t1 = (1.0f / sqrtf(dot(t1, t1))) * t1;
+      t1 = rsqrtf(dot(t1, t1)) * t1;
       const V3 t2 = cross(n, t1);
       // relative velocity at v_s (b minus a)
       V3 vrel = v3(0.f, 0.f, 0.f), wrel = vrel;
@@ -372,9 +825,11 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
       const float4 ma = gM[ga], mb = gM[gb];
       const float mut = fmaxf(ma.x, mb.x), mutor = fmaxf(ma.y, mb.y), murol = fmaxf(ma.z, mb.z);
       // impedance (Eqs. k_d_setting, r_scaling), x clamped to [0, 1]
-      const float x = fminf(fabsf(phi) / P.width, 1.0f);
-      const float gam = x < P.mid ? P.mid * powf(x / P.mid, P.power)
-                                  : 1.0f - (1.0f - P.mid) * powf((1.0f - x) / (1.0f - P.mid), P.power);
+      const float x = fminf(fabsf(phi) * P.inv_width, 1.0f);
+      const bool lo = x < P.mid;
+      const float u = lo ? x * P.inv_mid : (1.0f - x) * P.inv_1mmid;
+      const float up = P.power2 ? u * u : powf(u, P.power);
+      const float gam = lo ? P.mid * up : 1.0f - (1.0f - P.mid) * up;
       const float r = P.r_min + (P.r_max - P.r_min) * gam;
       const float A = trs > 0.f ? (r / (1.0f - r)) / trs : 0.f;
       const float c0 = -P.k_user * phi;
@@ -482,7 +937,7 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
     }
     // waves add their partial sums in wave order (keys are distinct within a wave)
 #pragma unroll
-    for (int wv = 0; wv < kWaves; ++wv) {
+    for (int wv = 0; wv < NW; ++wv) {
       if (wave == wv) {
         if (leadA) {
           float4 F = accF[kA], T = accT[kA];
@@ -502,14 +957,21 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
   }
 
   // ---- velocity correction (Eq. vel_correction) and semi-implicit Euler
-  for (int b = tid; b < nb; b += kBlock) {
+  if (ART)
+  for (int si = tid; si < a.nsub; si += BS) {
+    const SubTree S = a.sub[si];
+    art_correct(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
+  }
+  for (int b = tid; b < nb; b += BS) {
+    const BodyC bc = a.body[b];
+    if (ART && !bc.fast) continue;
     const float4 C = bC[b], Vs = bV[b], Ws = bW[b], I0 = bI0[b], I1 = bI1[b];
     const float4 F = accF[b], T = accT[b];
     const V3 vp = v3(Vs.x + C.w * F.x, Vs.y + C.w * F.y, Vs.z + C.w * F.z);
     const V3 wp = v3(Ws.x + I0.x * T.x + I0.w * T.y + I1.x * T.z,
                      Ws.y + I0.w * T.x + I0.y * T.y + I1.y * T.z,
                      Ws.z + I1.x * T.x + I1.y * T.y + I0.z * T.z);
-    float *qb = sq + 7 * b, *vb = sv + 6 * b;
+    float *qb = sq + bc.qadr, *vb = sv + bc.dadr;
     vb[0] = vp.x; vb[1] = vp.y; vb[2] = vp.z; vb[3] = wp.x; vb[4] = wp.y; vb[5] = wp.z;
     qb[0] = C.x + P.h * vp.x;
     qb[1] = C.y + P.h * vp.y;
@@ -535,20 +997,36 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ResolveArgs a) {
   __syncthreads();
   {
     float *qo = a.q_out + (size_t)w * nq, *vo = a.v_out + (size_t)w * nv;
-    for (int i = tid; i < nq; i += kBlock) qo[i] = sq[i];
-    for (int i = tid; i < nv; i += kBlock) vo[i] = sv[i];
+    for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
+    for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
   }
 }
 
-hipError_t launch_resolve(const ResolveArgs &a, int nworld, size_t lds, hipStream_t s) {
-  switch (a.condim) {
-    case 1: hipLaunchKernelGGL(resolve_kernel<1>, dim3(nworld), dim3(kBlock), lds, s, a); break;
-    case 3: hipLaunchKernelGGL(resolve_kernel<3>, dim3(nworld), dim3(kBlock), lds, s, a); break;
-    case 4: hipLaunchKernelGGL(resolve_kernel<4>, dim3(nworld), dim3(kBlock), lds, s, a); break;
-    case 6: hipLaunchKernelGGL(resolve_kernel<6>, dim3(nworld), dim3(kBlock), lds, s, a); break;
+template <int CONDIM, bool ART>
+static hipError_t launch_resolve_b(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  switch (block) {
+    case 64: hipLaunchKernelGGL((resolve_kernel<CONDIM, 64, ART>), dim3(nworld), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((resolve_kernel<CONDIM, 128, ART>), dim3(nworld), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((resolve_kernel<CONDIM, 256, ART>), dim3(nworld), dim3(256), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int CONDIM>
+static hipError_t launch_resolve_c(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  return a.nsub > 0 ? launch_resolve_b<CONDIM, true>(a, nworld, block, lds, s)
+                    : launch_resolve_b<CONDIM, false>(a, nworld, block, lds, s);
+}
+
+hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  switch (a.condim) {
+    case 1: return launch_resolve_c<1>(a, nworld, block, lds, s);
+    case 3: return launch_resolve_c<3>(a, nworld, block, lds, s);
+    case 4: return launch_resolve_c<4>(a, nworld, block, lds, s);
+    case 6: return launch_resolve_c<6>(a, nworld, block, lds, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace cf

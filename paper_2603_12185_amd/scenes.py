@@ -449,3 +449,77 @@ def with_params(scene, **kw):
         else:
             out[k] = v
     return out
+
+
+def articulated_mix(nworld=4, seed=0, condim=3, k_user=0.1, d_user=0.001, ncon_max=96):
+    """Articulated bodies in contact: a 3-link hinge arm hanging from the world
+    (capsule links, tip sphere), a slide-slide-hinge chain carrying a box, a
+    floating base (free box with two hinged capsule fingers) and three free
+    spheres, over a ground plane.  Per-world masses and random joint states."""
+    rng = np.random.default_rng([seed, 5])
+    b = _Builder(nworld)
+    b.geom(PLANE, -1)
+    cap_q = _quat_z_to((1.0, 0.0, 0.0))  # capsule axis along the link (+x)
+
+    def m_(lo, hi):
+        return rng.uniform(lo, hi, nworld)
+
+    def inert(m, a, c):
+        return np.stack([m * a, m * c, m * c], 1)
+
+    # hinge arm from the world at (0.25, 0, 0.2), links along x
+    parent = -1
+    for i in range(3):
+        L = 0.09
+        m = m_(0.1, 0.3)
+        bi = b.body(JNT_HINGE, parent, pos=(0.25, 0.0, 0.2) if i == 0 else (L, 0, 0),
+                    axis=(0, 1, 0), ipos=(L / 2, 0, 0), mass=m, inertia=inert(m, 2e-4, 1e-3))
+        b.geom(CAPSULE, bi, size=(0.015, L / 2 - 0.005, 0), pos=(L / 2, 0, 0), quat=cap_q,
+               friction=(0.6, 0.003, 0.0003))
+        parent = bi
+    b.geom(SPHERE, parent, size=(0.025, 0, 0), pos=(0.09, 0, 0), friction=(0.8, 0.003, 0.0003))
+    # slide x -> slide z -> hinge y carrying a box
+    s0 = b.body(JNT_SLIDE, -1, pos=(-0.2, 0.2, 0.0), axis=(1, 0, 0), mass=0.05, inertia=(1e-5,) * 3)
+    s1 = b.body(JNT_SLIDE, s0, axis=(0, 0, 1), mass=0.05, inertia=(1e-5,) * 3)
+    mb = m_(0.3, 0.6)
+    s2 = b.body(JNT_HINGE, s1, axis=(0, 1, 0), mass=mb, inertia=inert(mb, 6e-4, 6e-4))
+    b.geom(BOX, s2, size=(0.04, 0.03, 0.025), friction=(0.5, 0.002, 0.0002))
+    # floating base with two hinged fingers
+    mp = m_(0.3, 0.5)
+    fb = b.body(JNT_FREE, -1, pos=(-0.15, -0.15, 0.2), mass=mp, inertia=inert(mp, 1e-3, 1e-3))
+    b.geom(BOX, fb, size=(0.05, 0.04, 0.015), friction=(0.7, 0.002, 0.0002))
+    for sgn in (-1, 1):
+        mf = m_(0.05, 0.1)
+        fi = b.body(JNT_HINGE, fb, pos=(0.05, 0.025 * sgn, 0.0), axis=(0, 1, 0), ipos=(0.03, 0, 0),
+                    mass=mf, inertia=inert(mf, 1e-5, 5e-5))
+        b.geom(CAPSULE, fi, size=(0.01, 0.025, 0), pos=(0.03, 0, 0), quat=cap_q,
+               friction=(0.9, 0.003, 0.0003))
+    # free spheres
+    for _ in range(3):
+        r = rng.uniform(0.02, 0.035, nworld)
+        m = 1000 * 4 / 3 * np.pi * r ** 3
+        bi = b.body(JNT_FREE, mass=m, inertia=np.repeat((0.4 * m * r * r)[:, None], 3, 1))
+        b.geom(SPHERE, bi, size=np.stack([r, 0 * r, 0 * r], 1), friction=(0.6, 0.003, 0.0003))
+    s = b.build(condim=condim, k_user=k_user, d_user=d_user, ncon_max=ncon_max,
+                name="articulated_mix")
+    qa = qadr(s)
+    da = dadr(s)
+    for w in range(nworld):
+        q, v = s["q0"][w], s["v0"][w]
+        for i in range(3):                       # arm angles
+            q[qa[i]] = rng.uniform(-0.4, 1.2)
+            v[da[i]] = rng.normal(0, 1.0)
+        q[qa[3]], q[qa[4]], q[qa[5]] = rng.uniform(-0.05, 0.05), rng.uniform(0.03, 0.08), rng.uniform(-0.5, 0.5)
+        v[da[3]], v[da[4]], v[da[5]] = rng.normal(0, 0.2), rng.normal(0, 0.2), rng.normal(0, 1.0)
+        q[qa[6]:qa[6] + 3] = (-0.15 + rng.uniform(-0.03, 0.03), -0.15 + rng.uniform(-0.03, 0.03),
+                              rng.uniform(0.05, 0.12))
+        q[qa[6] + 3:qa[6] + 7] = _random_quat(rng) * 0.2 + np.array([1.0, 0, 0, 0])
+        q[qa[6] + 3:qa[6] + 7] /= np.linalg.norm(q[qa[6] + 3:qa[6] + 7])
+        v[da[6]:da[6] + 6] = rng.normal(0, 0.3, 6)
+        q[qa[7]], q[qa[8]] = rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5)
+        for i in range(3):
+            bi = 9 + i
+            q[qa[bi]:qa[bi] + 3] = (rng.uniform(-0.25, 0.3), rng.uniform(-0.2, 0.2), rng.uniform(0.03, 0.25))
+            q[qa[bi] + 3:qa[bi] + 7] = (1, 0, 0, 0)
+            v[da[bi]:da[bi] + 3] = rng.normal(0, 0.3, 3)
+    return s

@@ -74,10 +74,21 @@ def test_invalid_descriptors_rejected(lib, mutate, expect):
     assert cfsim.last_error()
 
 
-def test_hinge_and_slide_are_reported_unsupported(lib):
-    st, h = _create(scenes.point_mass())
+def test_unsupported_trees_are_reported(lib):
+    """Subtrees must be contiguous in body order and hold at most 32 dofs."""
+    b = scenes._Builder(1)
+    r0 = b.body(scenes.JNT_HINGE, -1, axis=(0, 1, 0))
+    b.body(scenes.JNT_HINGE, -1, axis=(0, 1, 0))
+    b.body(scenes.JNT_HINGE, r0, axis=(0, 1, 0))  # child of body 0 after another root
+    st, h = _create(b.build())
     assert st == cfsim.CF_E_UNSUPPORTED and not h.value
-    assert "free joints" in cfsim.last_error()
+    assert "contiguous" in cfsim.last_error()
+    b = scenes._Builder(1)
+    p = -1
+    for _ in range(33):
+        p = b.body(scenes.JNT_HINGE, p, axis=(0, 1, 0))
+    st, h = _create(b.build())
+    assert st == cfsim.CF_E_UNSUPPORTED and "32" in cfsim.last_error()
 
 
 def test_null_arguments(lib):

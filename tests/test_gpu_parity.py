@@ -257,3 +257,77 @@ def test_kernel_timing_query(torch_cuda):
     a, b, n = model.kernel_times()
     print(f"collide {a / n * 1e3:.1f} us, resolve {b / n * 1e3:.1f} us per step; wall {time.time() - t0:.3f}s")
     assert n == 20 and a > 0 and b > 0
+
+
+# ---------------------------------------------------------------- articulated
+@pytest.mark.parametrize("condim", [3, 6])
+def test_articulated_mix_parity(torch_cuda, condim):
+    """Hinge arm, slide-slide-hinge chain, floating base with hinged fingers and
+    free spheres: per-subtree mass matrix, bias and Cholesky on the GPU; contacts
+    on articulated links; 300 steps compared every 3."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.articulated_mix(nworld=6, seed=condim, condim=condim)
+    model = cfsim.Model(s)
+    print(f"case: articulated_mix condim {condim}", flush=True)
+    recs = _run_steps(torch_cuda, model, s, 300, record_every=3)
+    o = Oracle(s)
+    stats = None
+    for t, qi, vi, qg, vg, con in recs:
+        stats = compare_step(s, o, qi, vi, None, qg, vg, con, stats=stats)
+    print("articulated parity", condim, stats)
+    assert stats["contacts"] > 500
+
+
+def test_pendulum_and_double_pendulum_parity(torch_cuda):
+    """Contact-free hinge chains: per-step parity over 2000 steps and the
+    small-angle period of the GPU trajectory."""
+    from paper_2603_12185_amd import cfsim
+    import math
+    for s in (scenes.pendulum(length=0.5, mass=1.0), scenes.double_pendulum()):
+        s["q0"][0, 0] = 0.3
+        model = cfsim.Model(s)
+        recs = _run_steps(torch_cuda, model, s, 2000, record_every=50)
+        o = Oracle(s)
+        stats = None
+        for t, qi, vi, qg, vg, con in recs:
+            stats = compare_step(s, o, qi, vi, None, qg, vg, con, stats=stats)
+        print(s["name"], stats)
+    # period of a small-amplitude pendulum on the GPU
+    s = scenes.pendulum(length=0.5, mass=1.0, h=0.0005)
+    s["q0"][0, 0] = 0.01
+    model = cfsim.Model(s)
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    th = []
+    for _ in range(4000):
+        q, v = model.step(q, v)
+        th.append(float(q[0, 0]))
+    th = np.array(th)
+    cross = [i + th[i] / (th[i] - th[i + 1]) for i in range(len(th) - 1) if th[i] > 0 >= th[i + 1]]
+    L = 0.5
+    Ipiv = s["body_inertia"][0, 0, 1] + s["body_mass"][0, 0] * L * L
+    T = 2 * math.pi * math.sqrt(Ipiv / (s["body_mass"][0, 0] * 9.81 * L))
+    np.testing.assert_allclose((cross[1] - cross[0]) * s["h"], T, rtol=2e-3)
+
+
+def test_slide_point_mass_stick_decay_on_gpu(torch_cuda):
+    """The stick-regime decay of the sliding point mass (three slide joints), run
+    on the GPU: u_{n+1} = (1 - 2 rho* a mu^2 / 3) u_n."""
+    from paper_2603_12185_amd import cfsim
+    mu = 0.5
+    s = scenes.point_mass(mu=mu)
+    g = 9.81
+    a = s["k_user"] * s["h"] + s["d_user"]
+    rho = s["solimp"][1] / (1 - s["solimp"][1])
+    delta = (g * s["h"] / s["k_user"]) * (3 / (4 * rho) - a)
+    s["q0"][0, 2] = s["geom_size"][0, 1, 0] - delta
+    u1 = 3 * g * s["h"] / (4 * rho * a * mu)
+    s["v0"][0, 0] = 0.5 * u1
+    model = cfsim.Model(s)
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    mu32 = s["geom_friction"][0, 1, 0]
+    fac = 1 - 2 * rho * a * mu32 * mu32 / 3
+    u0 = float(s["v0"][0, 0])
+    for n in range(1, 200):
+        q, v = model.step(q, v)
+        if n % 20 == 0:
+            np.testing.assert_allclose(float(v[0, 0]), fac ** n * u0, rtol=2e-5)
