@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--cpu-worlds", type=int, default=768,
                     help="worlds in the CPU-baseline sample (0 disables it)")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--rollout-steps", type=int, default=1000,
+                    help="steps of the batched-rollout form timed after the plain form (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -173,6 +175,36 @@ def main():
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": traffic, "alg_bytes_per_launch": b_dom * nw},
     }
+    if args.rollout_steps > 0:
+        # Batched-rollout form: the same step, T steps per cf_rollout call (one
+        # persistent kernel per call when the world fits a workgroup's LDS),
+        # from the same settled state, trajectory written to HBM every step.
+        T = args.rollout_steps
+        q0 = torch.from_numpy(state_q).to(dev)
+        v0 = torch.from_numpy(state_v).to(dev)
+        qt = torch.empty((T + 1, nw, nq), device=dev)
+        vt = torch.empty((T + 1, nw, nv), device=dev)
+        nct = torch.zeros((T, nw), dtype=torch.int32, device=dev)
+        model.rollout(min(T, 20), q0, v0, q_traj=qt, v_traj=vt, ncon_traj=nct)  # warm-up
+        torch.cuda.synchronize()
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        r0.record(stream)
+        model.rollout(T, q0, v0, q_traj=qt, v_traj=vt, ncon_traj=nct)
+        r1.record(stream)
+        torch.cuda.synchronize()
+        rwall = time.perf_counter() - t0
+        rc_w = float(nct.double().sum()) / (T * nw)
+        launch = model.get_launch()
+        b_roll = 8 * (nq + nv)  # per world-step: the trajectory rows written
+        result["rollout_form"] = {
+            "value": nw * T / rwall, "unit": "env-steps/s", "steps": T,
+            "ms_per_step": rwall * 1e3 / T, "gpu_event_ms_per_step": r0.elapsed_time(r1) / T,
+            "mean_contacts_per_world": rc_w, "contact_impulses_per_s": rc_w * nw * T / rwall,
+            "persistent_kernel": launch[3], "block": launch[2],
+            "vs_plain_form": (nw * T / rwall) / env_steps,
+            "alg_GBps": b_roll * nw * T / rwall / 1e9,
+        }
     if args.cpu_worlds > 0:
         threads = min(16, len(os.sched_getaffinity(0)))
         rng = np.random.default_rng(0)

@@ -138,19 +138,36 @@ cf_status cf_model_dims(const cf_model *m, int32_t *nq, int32_t *nv, int32_t *nf
 cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                   float *q_out, float *v_out, const cf_contacts *out);
 
-/* T consecutive steps: q_traj/v_traj [T+1][nworld][nq|nv] receive the initial
- * state (copied from q0/v0 unless they already alias row 0) and every step's
- * result; tau_seq [T][nworld][nv] or NULL.  T >= 0. */
+/* T consecutive steps (batched rollouts): q_traj/v_traj [T+1][nworld][nq|nv]
+ * receive the initial state (copied from q0/v0 unless they already alias row 0)
+ * and every step's result; tau_seq [T][nworld][nv] or NULL; ncon_traj
+ * [T][nworld] receives the contacts kept at each step, or NULL.  T >= 0.
+ * The same step as cf_step: when a world's state, contact list (ncon_max
+ * records) and scratch fit one workgroup's LDS, all T steps run in one
+ * persistent kernel launch (one workgroup per world, nothing but the
+ * trajectory crosses HBM; see cf_model_get_launch), else as T cf_step calls.
+ * Allocates nothing, so a stream capture (HIP graph) of the call replays it. */
 cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
-                     const float *tau_seq, float *q_traj, float *v_traj);
+                     const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj);
 
 /* Workgroup size (64, 128 or 256 threads, one world per workgroup) of the
- * collision and the resolution kernel.  Defaults are set by cf_model_create;
+ * collision, the resolution and the rollout kernel (defaults 256 each);
  * results do not depend on the choice (same arithmetic, same summation order
  * within a wave; the per-body sums are ordered by wave, so the last bits of
  * v+ may differ between sizes). */
-cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolve_block);
-cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t *resolve_block);
+cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolve_block, int32_t rollout_block);
+/* Also reports whether cf_rollout uses the persistent kernel (1) or step calls (0). */
+cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t *resolve_block,
+                              int32_t *rollout_block, int32_t *rollout_fused_kernel);
+
+/* Autotuner: times every workgroup size of the two step kernels and of the
+ * rollout kernel over `steps` steps from the state (q, v) (device, not
+ * modified), on this model's worlds, and keeps the fastest of each; cf_rollout
+ * then uses the persistent kernel only where it beat T cf_step calls.  It
+ * allocates temporary device buffers and synchronises the stream.  Optional
+ * outputs: the best microseconds per step of cf_step and of cf_rollout. */
+cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const float *v, int32_t steps,
+                            float *best_step_us, float *best_rollout_step_us);
 
 /* Kernel timing.  When enabled, every cf_step records HIP events around its
  * collision and resolution kernels on the step's stream.  cf_model_kernel_times

@@ -58,9 +58,11 @@ SIGNATURES = {
     "cf_model_destroy": ([C.c_void_p], None),
     "cf_model_dims": ([C.c_void_p, _ip, _ip, _ip], C.c_int32),
     "cf_step": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, C.POINTER(Contacts)], C.c_int32),
-    "cf_rollout": ([C.c_void_p, C.c_void_p, C.c_int32, _fp, _fp, _fp, _fp, _fp], C.c_int32),
-    "cf_model_set_launch": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int32),
-    "cf_model_get_launch": ([C.c_void_p, _ip, _ip], C.c_int32),
+    "cf_rollout": ([C.c_void_p, C.c_void_p, C.c_int32, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
+    "cf_model_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
+    "cf_model_get_launch": ([C.c_void_p, _ip, _ip, _ip, _ip], C.c_int32),
+    "cf_model_autotune": ([C.c_void_p, C.c_void_p, _fp, _fp, C.c_int32, C.POINTER(C.c_float),
+                           C.POINTER(C.c_float)], C.c_int32),
     "cf_model_set_profiling": ([C.c_void_p, C.c_int32], C.c_int32),
     "cf_model_kernel_times": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_int64)], C.c_int32),
@@ -195,8 +197,10 @@ class Model:
                               _ptr(q_out), _ptr(v_out), C.byref(c) if c is not None else None))
         return q_out, v_out
 
-    def rollout(self, T, q0, v0, tau_seq=None, q_traj=None, v_traj=None, stream=None):
-        """T steps; returns trajectories [T+1][nworld][nq|nv]."""
+    def rollout(self, T, q0, v0, tau_seq=None, q_traj=None, v_traj=None, ncon_traj=None,
+                stream=None):
+        """T steps; returns trajectories [T+1][nworld][nq|nv] (ncon_traj [T][nworld]
+        int32 receives per-step contact counts when given)."""
         import torch
         self._check_state(q0, self.nq, "q0")
         self._check_state(v0, self.nv, "v0")
@@ -208,17 +212,36 @@ class Model:
                                     or not tau_seq.is_contiguous()):
             raise ValueError("tau_seq must be contiguous [T][nworld][nv]")
         s = torch.cuda.current_stream() if stream is None else stream
+        if ncon_traj is not None and (ncon_traj.dtype != torch.int32 or
+                                      ncon_traj.numel() < T * self.nworld):
+            raise ValueError("ncon_traj must be int32 [T][nworld]")
         _check(load().cf_rollout(self._h, C.c_void_p(s.cuda_stream), int(T), _ptr(q0), _ptr(v0),
-                                 _ptr(tau_seq), _ptr(q_traj), _ptr(v_traj)))
+                                 _ptr(tau_seq), _ptr(q_traj), _ptr(v_traj), _ptr(ncon_traj)))
         return q_traj, v_traj
 
     # ------------------------------------------------------------ launch shape
-    def set_launch(self, collide_block, resolve_block):
-        _check(load().cf_model_set_launch(self._h, int(collide_block), int(resolve_block)))
+    def set_launch(self, collide_block, resolve_block, rollout_block=None):
+        if rollout_block is None:
+            rollout_block = self.get_launch()[2]
+        _check(load().cf_model_set_launch(self._h, int(collide_block), int(resolve_block),
+                                          int(rollout_block)))
 
     def get_launch(self):
-        a, b = C.c_int32(), C.c_int32()
-        _check(load().cf_model_get_launch(self._h, C.byref(a), C.byref(b)))
+        """(collide_block, resolve_block, rollout_block, rollout_uses_persistent_kernel)."""
+        a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().cf_model_get_launch(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return a.value, b.value, c.value, bool(d.value)
+
+    def autotune(self, q, v, steps=20, stream=None):
+        """Pick the fastest workgroup sizes on state (q, v); returns (us/step of
+        cf_step, us/step of cf_rollout or -1)."""
+        import torch
+        self._check_state(q, self.nq, "q")
+        self._check_state(v, self.nv, "v")
+        s = torch.cuda.current_stream() if stream is None else stream
+        a, b = C.c_float(), C.c_float()
+        _check(load().cf_model_autotune(self._h, C.c_void_p(s.cuda_stream), _ptr(q), _ptr(v),
+                                        int(steps), C.byref(a), C.byref(b)))
         return a.value, b.value
 
     # ------------------------------------------------------------ timing

@@ -42,7 +42,9 @@ struct cf_model {
   cf::BodyC *d_body = nullptr;
   cf::SubTree *d_sub = nullptr;
   int norient = 0, nsub = 0, art_floats = 0;
-  int block_collide = 256, block_resolve = 256;
+  int block_collide = 256, block_resolve = 256, block_rollout = 256;
+  size_t lds_rollout = 0;
+  bool rollout_steps = false;  // autotuner found T cf_step calls faster than the persistent kernel
   float4 *d_bmi = nullptr, *d_gdat = nullptr, *d_gpos = nullptr, *d_gquat = nullptr;
   float2 *d_gfr2 = nullptr;
   int gpos_ws = 0, gquat_ws = 0;
@@ -277,6 +279,8 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
     return set_err(CF_E_UNSUPPORTED, "world too large for one workgroup's LDS (reduce bodies or geoms)");
   }
   m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->block_resolve, m->nsub, m->art_floats);
+  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, nb, ng, m->norient, m->nsub, m->art_floats,
+                                         m->block_rollout, m->ncon_max);
   if (hipGetDevice(&m->dev) != hipSuccess) { delete m; return set_err(CF_E_DEVICE, "no HIP device"); }
 
   // ---- per-world constants (float32); shared arrays get world stride 0
@@ -362,6 +366,29 @@ cf_status cf_model_dims(const cf_model *m, int32_t *nq, int32_t *nv, int32_t *nf
   return CF_OK;
 }
 
+static cf::CollideArgs collide_args(const cf_model *m) {
+  cf::CollideArgs ca{};
+  ca.gpos = m->d_gpos; ca.gquat = m->d_gquat; ca.gdat = m->d_gdat; ca.gbody = m->d_gbody;
+  ca.gorient = m->d_gorient; ca.norient = m->norient;
+  ca.body = m->d_body; ca.sub = m->d_sub; ca.nsub = m->nsub;
+  ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
+  ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
+  ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
+  return ca;
+}
+
+static cf::ResolveArgs resolve_args(const cf_model *m) {
+  cf::ResolveArgs ra{};
+  ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
+  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats;
+  ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
+  ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
+  ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p;
+  return ra;
+}
+
+static bool rollout_fused(const cf_model *m) { return m->lds_rollout <= kLdsLimit && !m->rollout_steps; }
+
 cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                   float *q_out, float *v_out, const cf_contacts *out) {
   if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
@@ -388,30 +415,20 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
     ev = &m->events[m->ev_used++];
     if (hipEventRecord(ev->e[0], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
   }
-  cf::CollideArgs ca{};
-  ca.q = q; ca.gpos = m->d_gpos; ca.gquat = m->d_gquat; ca.gdat = m->d_gdat; ca.gbody = m->d_gbody;
-  ca.gorient = m->d_gorient; ca.norient = m->norient;
-  ca.body = m->d_body; ca.sub = m->d_sub; ca.nsub = m->nsub;
-  ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
+  cf::CollideArgs ca = collide_args(m);
+  ca.q = q;
   ca.ncon_out = out ? out->ncon : nullptr;
   ca.overflow_out = out ? out->overflow : nullptr;
-  ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
-  ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
   hipError_t e = cf::launch_collide(ca, m->nw, m->block_collide, m->lds_collide, s);
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("collide launch: ") + hipGetErrorString(e));
   if (ev && hipEventRecord(ev->e[1], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
 
-  cf::ResolveArgs ra{};
+  cf::ResolveArgs ra = resolve_args(m);
   ra.q = q; ra.v = v; ra.tau = tau; ra.q_out = q_out; ra.v_out = v_out;
-  ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
-  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats;
-  ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
   if (out) {
     ra.x_geom = out->geom; ra.x_sub = out->sub; ra.x_dist = out->dist; ra.x_pos = out->pos;
     ra.x_frame = out->frame; ra.x_imp = out->impulse;
   }
-  ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
-  ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p;
   e = cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("resolve launch: ") + hipGetErrorString(e));
   if (ev && hipEventRecord(ev->e[2], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
@@ -419,40 +436,130 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
 }
 
 cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
-                     const float *tau_seq, float *q_traj, float *v_traj) {
+                     const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj) {
   if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
   if (T < 0) return set_err(CF_E_INVALID_ARG, "T must be >= 0");
   if (!q0 || !v0 || !q_traj || !v_traj) return set_err(CF_E_INVALID_ARG, "NULL state pointer");
+  if (!aligned16(q0) || !aligned16(v0) || !aligned16(q_traj) || !aligned16(v_traj) ||
+      (tau_seq && !aligned16(tau_seq)))
+    return set_err(CF_E_INVALID_ARG, "state buffers must be 16-byte aligned");
   const size_t sq = (size_t)m->nw * m->nq, sv = (size_t)m->nw * m->nv;
   hipStream_t s = (hipStream_t)stream;
   if (q0 != q_traj && hipMemcpyAsync(q_traj, q0, sizeof(float) * sq, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return set_err(CF_E_DEVICE, "hipMemcpyAsync failed");
   if (v0 != v_traj && hipMemcpyAsync(v_traj, v0, sizeof(float) * sv, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return set_err(CF_E_DEVICE, "hipMemcpyAsync failed");
+  if (T == 0) return CF_OK;
+  if (rollout_fused(m)) {
+    cf::RolloutArgs r{};
+    r.c = collide_args(m);
+    r.s = resolve_args(m);
+    r.q0 = q_traj; r.v0 = v_traj; r.tau_seq = tau_seq; r.q_traj = q_traj; r.v_traj = v_traj;
+    r.ncon_traj = ncon_traj; r.T = T; r.nworld = m->nw; r.cap = m->ncon_max;
+    hipError_t e = cf::launch_rollout(r, m->block_rollout, m->lds_rollout, s);
+    if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("rollout launch: ") + hipGetErrorString(e));
+    return CF_OK;
+  }
   for (int t = 0; t < T; ++t) {
+    cf_contacts c{};
+    c.ncon = ncon_traj ? ncon_traj + (size_t)t * m->nw : nullptr;
     cf_status st = cf_step(m, stream, q_traj + t * sq, v_traj + t * sv, tau_seq ? tau_seq + t * sv : nullptr,
-                           q_traj + (t + 1) * sq, v_traj + (t + 1) * sv, nullptr);
+                           q_traj + (t + 1) * sq, v_traj + (t + 1) * sv, ncon_traj ? &c : nullptr);
     if (st != CF_OK) return st;
   }
   return CF_OK;
 }
 
-cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolve_block) {
+cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolve_block, int32_t rollout_block) {
   if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
   auto ok = [](int b) { return b == 64 || b == 128 || b == 256; };
-  if (!ok(collide_block) || !ok(resolve_block))
+  if (!ok(collide_block) || !ok(resolve_block) || !ok(rollout_block))
     return set_err(CF_E_INVALID_ARG, "workgroup sizes must be 64, 128 or 256");
   m->block_collide = collide_block;
   m->block_resolve = resolve_block;
+  m->block_rollout = rollout_block;
+  m->rollout_steps = false;
   m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, resolve_block, m->nsub, m->art_floats);
+  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->art_floats,
+                                         rollout_block, m->ncon_max);
   return CF_OK;
 }
 
-cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t *resolve_block) {
+cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t *resolve_block,
+                              int32_t *rollout_block, int32_t *rollout_fused_kernel) {
   if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
   if (collide_block) *collide_block = m->block_collide;
   if (resolve_block) *resolve_block = m->block_resolve;
+  if (rollout_block) *rollout_block = m->block_rollout;
+  if (rollout_fused_kernel) *rollout_fused_kernel = rollout_fused(m) ? 1 : 0;
   return CF_OK;
+}
+
+cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const float *v, int32_t steps,
+                            float *best_step_us, float *best_rollout_step_us) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (!q || !v || steps < 1) return set_err(CF_E_INVALID_ARG, "need q, v and steps >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t sq = (size_t)m->nw * m->nq, sv = (size_t)m->nw * m->nv;
+  float *buf = nullptr;
+  const size_t nbuf = 2 * (sq + sv) + (size_t)(steps + 1) * (sq + sv);
+  if (hipMalloc((void **)&buf, sizeof(float) * nbuf) != hipSuccess) return set_err(CF_E_NOMEM, "autotune buffers");
+  float *qa = buf, *va = qa + sq, *qb = va + sv, *vb = qb + sq, *qt = vb + sv, *vt = qt + (steps + 1) * sq;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const bool prof = m->prof;
+  m->prof = false;
+  const int sizes[3] = {64, 128, 256};
+  float best = 1e30f, best_r = 1e30f;
+  int bc = m->block_collide, br = m->block_resolve, bo = m->block_rollout;
+  cf_status st = CF_OK;
+  for (int ic = 0; ic < 3 && st == CF_OK; ++ic)
+    for (int ir = 0; ir < 3 && st == CF_OK; ++ir) {
+      m->block_collide = sizes[ic];
+      m->block_resolve = sizes[ir];
+      m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, sizes[ir], m->nsub, m->art_floats);
+      if (m->lds_resolve > kLdsLimit) continue;
+      (void)hipMemcpyAsync(qa, q, sizeof(float) * sq, hipMemcpyDeviceToDevice, s);
+      (void)hipMemcpyAsync(va, v, sizeof(float) * sv, hipMemcpyDeviceToDevice, s);
+      st = cf_step(m, stream, qa, va, nullptr, qb, vb, nullptr);  // warm-up
+      (void)hipEventRecord(e0, s);
+      for (int t = 0; t < steps && st == CF_OK; ++t)
+        st = (t & 1) ? cf_step(m, stream, qb, vb, nullptr, qa, va, nullptr)
+                     : cf_step(m, stream, qa, va, nullptr, qb, vb, nullptr);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; bc = sizes[ic]; br = sizes[ir]; }
+    }
+  m->rollout_steps = false;
+  for (int io = 0; io < 3 && st == CF_OK; ++io) {
+    const size_t lds = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->art_floats,
+                                             sizes[io], m->ncon_max);
+    if (lds > kLdsLimit) continue;
+    m->block_rollout = sizes[io];
+    m->lds_rollout = lds;
+    st = cf_rollout(m, stream, 1, q, v, nullptr, qt, vt, nullptr);  // warm-up
+    (void)hipEventRecord(e0, s);
+    if (st == CF_OK) st = cf_rollout(m, stream, steps, q, v, nullptr, qt, vt, nullptr);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_r) { best_r = ms; bo = sizes[io]; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  m->prof = prof;
+  cf_status st2 = cf_model_set_launch(m, bc, br, bo);
+  // the persistent kernel only when it beats T step calls of the chosen shape
+  m->rollout_steps = !(best_r < best);
+  if (st != CF_OK) return st;
+  if (best_step_us) *best_step_us = best * 1e3f / steps;
+  if (best_rollout_step_us) *best_rollout_step_us = best_r < 1e29f ? best_r * 1e3f / steps : -1.f;
+  return st2;
 }
 
 cf_status cf_model_set_profiling(cf_model *m, int32_t enable) {

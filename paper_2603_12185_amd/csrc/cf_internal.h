@@ -93,7 +93,21 @@ struct ResolveArgs {
   Params p;
 };
 
+// Fused rollout: T steps per launch, one workgroup per world.
+struct RolloutArgs {
+  CollideArgs c;                // q, contact workspace and counts unused
+  ResolveArgs s;                // q, v, tau, outputs, contact inputs and exports unused
+  const float *q0, *v0;         // [nw][nq], [nw][nv]
+  const float *tau_seq;         // [T][nw][nv] or null
+  float *q_traj, *v_traj;       // [T+1][nw][..]; row 0 written by the host
+  int *ncon_traj;               // [T][nw] contacts kept per step, or null
+  int T, nworld, cap;           // cap: contacts held per world per step (= ncon_max)
+};
+
 size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub);
+size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int art_floats, int block,
+                         int cap);
+hipError_t launch_rollout(const RolloutArgs &a, int block, size_t lds, hipStream_t s);
 size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats);
 hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s);

@@ -390,11 +390,6 @@ struct Pose {
   T pad;
 };
 
-size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub) {
-  return sizeof(float) * pad4(nq) + sizeof(float4) * (size_t)ng + sizeof(int) * (size_t)pad4(ng) +
-         (sizeof(Pose<float>) + sizeof(Pose<double>)) * (size_t)norient + sizeof(uint32_t) * kCandCap +
-         (nsub > 0 ? sizeof(double) * 16 * (size_t)nb : 0);
-}
 
 // float32 test: is the slot's gap below `thr` (margin plus the float32 band)?
 __device__ inline bool slot_candidate(uint32_t s, const float4 *Gs, const int *go, const Pose<float> *Of,
@@ -493,13 +488,23 @@ __device__ inline double slot_eval(uint32_t s, const float4 *Gs, const int *go, 
   return phi;
 }
 
+// LDS scratch of the narrow phase of one world (after its q row).
+size_t collide_region_bytes(int nb, int ng, int norient, int nsub) {
+  return sizeof(float4) * (size_t)ng + sizeof(int) * (size_t)pad4(ng) +
+         (sizeof(Pose<float>) + sizeof(Pose<double>)) * (size_t)norient + sizeof(uint32_t) * kCandCap +
+         (nsub > 0 ? sizeof(double) * 16 * (size_t)nb : 0);
+}
+
+// Narrow phase of world w from its q row `sq` (LDS).  Writes the first `cap`
+// contacts of the canonical order to outn/outp (global or LDS) and returns the
+// number found.  `reg` is LDS scratch of collide_region_bytes(); `nxt` is the
+// caller's prefetch of slots[threadIdx.x].  Ends with a workgroup barrier.
 template <int BS, bool ART>
-__global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
+__device__ int collide_world(const CollideArgs &a, int w, const float *sq, float4 *reg, float4 *outn,
+                             float4 *outp, int cap, uint32_t nxt) {
   constexpr int NW = BS / 64;
-  extern __shared__ float4 lds[];
-  const int w = blockIdx.x, tid = threadIdx.x;
-  float *sq = reinterpret_cast<float *>(lds);
-  Pose<double> *Od = reinterpret_cast<Pose<double> *>(lds + pad4(a.nq) / 4);
+  const int tid = threadIdx.x;
+  Pose<double> *Od = reinterpret_cast<Pose<double> *>(reg);
   Pose<float> *Of = reinterpret_cast<Pose<float> *>(Od + a.norient);
   float4 *Gs = reinterpret_cast<float4 *>(Of + a.norient);
   int *go = reinterpret_cast<int *>(Gs + a.ng);
@@ -509,10 +514,6 @@ __global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
   __shared__ int wcnt[2 * NW];
   __shared__ float wmax[NW];
 
-  uint32_t nxt = tid < a.nslot ? a.slots[tid] : 0u;  // prefetch of the first chunk
-  const float *qw = a.q + (size_t)w * a.nq;
-  for (int i = tid; i < a.nq; i += BS) sq[i] = qw[i];
-  __syncthreads();
   if (ART) {  // forward kinematics of articulated subtrees, float64
     for (int si = tid; si < a.nsub; si += BS) {
       const SubTree S = a.sub[si];
@@ -580,7 +581,6 @@ __global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
     ext = block_max<BS>(ext, wmax);
     band = 1e-4f + 8e-6f * ext;
   }
-  const size_t cbase = (size_t)w * a.ncon_max;
   int running = 0, ncand = 0, par = 0;
   // Pass 2 over the candidate list: float64 decision, ordered store.
   auto flush = [&]() {
@@ -615,9 +615,9 @@ __global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
       int tot;
       const int idx = running + block_scan<BS>(hit, &tot, wcnt, par);
       par ^= 1;
-      if (hit && idx < a.ncon_max) {
-        a.cnp[cbase + idx] = cn;
-        a.cpos[cbase + idx] = cp;
+      if (hit && idx < cap) {
+        outn[idx] = cn;
+        outp[idx] = cp;
       }
       running += tot;
     }
@@ -639,15 +639,34 @@ __global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
     ncand += tot;
   }
   if (ncand > 0) flush();
-
-  if (tid == 0) {
-    const int kept = running < a.ncon_max ? running : a.ncon_max;
-    a.ncon[w] = kept;
-    a.overflow[w] = running - kept;
-    if (a.ncon_out) a.ncon_out[w] = kept;
-    if (a.overflow_out) a.overflow_out[w] = running - kept;
-  }
+  else __syncthreads();
   (void)NW;
+  return running;
+}
+
+template <int BS, bool ART>
+__global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
+  extern __shared__ float4 lds[];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  float *sq = reinterpret_cast<float *>(lds);
+  const uint32_t nxt = tid < a.nslot ? a.slots[tid] : 0u;  // prefetch of the first chunk
+  const float *qw = a.q + (size_t)w * a.nq;
+  for (int i = tid; i < a.nq; i += BS) sq[i] = qw[i];
+  __syncthreads();
+  const size_t cbase = (size_t)w * a.ncon_max;
+  const int found = collide_world<BS, ART>(a, w, sq, lds + pad4(a.nq) / 4, a.cnp + cbase, a.cpos + cbase,
+                                           a.ncon_max, nxt);
+  if (tid == 0) {
+    const int kept = found < a.ncon_max ? found : a.ncon_max;
+    a.ncon[w] = kept;
+    a.overflow[w] = found - kept;
+    if (a.ncon_out) a.ncon_out[w] = kept;
+    if (a.overflow_out) a.overflow_out[w] = found - kept;
+  }
+}
+
+size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub) {
+  return sizeof(float) * pad4(nq) + collide_region_bytes(nb, ng, norient, nsub);
 }
 
 template <bool ART>
@@ -672,24 +691,32 @@ hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t ld
 // LDS: q, v, tau rows; per body 7 float4 (com|invm, vs|tr, ws, Iinv a, Iinv b,
 // accumulated force, accumulated torque); per geom float4 friction + int body;
 // per lane the two wrench entries of its contact (float4 + float2 each).
-size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats) {
-  return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + sizeof(float4) * 7 * (size_t)nb +
-         sizeof(float4) * (size_t)ng + (sizeof(float4) + sizeof(float2)) * 2 * (size_t)block +
-         sizeof(int) * (size_t)pad4(ng) +
+// LDS scratch of the resolution of one world (after its q, v and tau rows).
+size_t resolve_region_bytes(int nb, int ng, int block, int nsub, int art_floats) {
+  return sizeof(float4) * 7 * (size_t)nb + sizeof(float4) * (size_t)ng +
+         (sizeof(float4) + sizeof(float2)) * 2 * (size_t)block + sizeof(int) * (size_t)pad4(ng) +
          (nsub > 0 ? sizeof(float4) * 5 * (size_t)nb + sizeof(float) * (size_t)pad4(art_floats) : 0);
 }
 
+size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats) {
+  return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + resolve_region_bytes(nb, ng, block, nsub, art_floats);
+}
+
+// Resolution of world w: its q and v rows (LDS sq, sv) become q+ and v+ in
+// place; st holds the applied forces; the nc contacts are read from inn/inp
+// (global or LDS), the first chunk already loaded by the caller into c0n/c0p
+// (lane tid's record), and mi0 is body tid's mass/inertia.  `reg`: LDS scratch of
+// resolve_region_bytes().  `xbase`: row of the world in the export arrays.
+// Ends with a workgroup barrier.
 template <int CONDIM, int BS, bool ART>
-__global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
+__device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv, const float *st,
+                              const float4 *inn, const float4 *inp, int nc, float4 c0n, float4 c0p,
+                              float4 mi0, float4 *reg, size_t xbase) {
   constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
   constexpr int NW = BS / 64;
-  extern __shared__ float4 lds[];
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nq = a.nq, nv = a.nv, nb = a.nb, ng = a.ng;
-  float *sq = reinterpret_cast<float *>(lds);
-  float *sv = sq + pad4(nq);
-  float *st = sv + pad4(nv);
-  float4 *bC = reinterpret_cast<float4 *>(st + pad4(nv));
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = a.nb, ng = a.ng;
+  float4 *bC = reg;
   float4 *bV = bC + nb, *bW = bV + nb, *bI0 = bW + nb, *bI1 = bI0 + nb;
   float4 *accF = bI1 + nb, *accT = accF + nb;
   float4 *gM = accT + nb;
@@ -700,27 +727,7 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   float4 *bAx = bO + nb, *bR = bAx + nb;                    // bR: 3 rows per body
   float *art = reinterpret_cast<float *>(bR + 3 * nb);
   const Params P = a.p;
-  const size_t cbase = (size_t)w * a.ncon_max;
-
-  // ---- issue every independent global load up front
-  const int nc = a.ncon[w];
-  float4 c0n = make_float4(0.f, 0.f, 0.f, 0.f), c0p = c0n;
-  if (tid < a.ncon_max) {  // the first chunk's records (only used below ncon)
-    c0n = a.cnp[cbase + tid];
-    c0p = a.cpos[cbase + tid];
-  }
-  float4 mi0 = make_float4(1.f, 1.f, 1.f, 1.f);
-  if (tid < nb) mi0 = a.bmi[(size_t)w * nb + tid];
   {
-    const float *qw = a.q + (size_t)w * nq, *vw = a.v + (size_t)w * nv;
-    for (int i = tid; i < nq; i += BS) sq[i] = qw[i];
-    for (int i = tid; i < nv; i += BS) sv[i] = vw[i];
-    if (a.tau) {
-      const float *tw = a.tau + (size_t)w * nv;
-      for (int i = tid; i < nv; i += BS) st[i] = tw[i];
-    } else {
-      for (int i = tid; i < nv; i += BS) st[i] = 0.f;
-    }
     for (int g = tid; g < ng; g += BS) {
       gB[g] = a.gbody[g];
       const float mu_t = a.gdat[(size_t)w * ng + g].w;
@@ -790,8 +797,8 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
     float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
     float2 WA2 = make_float2(0.f, 0.f), WB2 = WA2;
     if (k < nc) {
-      const float4 cn = base == 0 ? c0n : a.cnp[cbase + k];
-      const float4 cp = base == 0 ? c0p : a.cpos[cbase + k];
+      const float4 cn = base == 0 ? c0n : inn[k];
+      const float4 cp = base == 0 ? c0p : inp[k];
       const uint32_t sl = __float_as_uint(cp.w);
       const int ga = slot_ga(sl), gb = slot_gb(sl);
       const int ba = gB[ga], bb = gB[gb];
@@ -878,7 +885,7 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
         WA2 = make_float2(-T.y, -T.z);
       }
       // optional exports
-      const size_t ci = cbase + k;
+      const size_t ci = xbase + k;
       if (a.x_geom) { a.x_geom[2 * ci] = ga; a.x_geom[2 * ci + 1] = gb; }
       if (a.x_sub) a.x_sub[ci] = slot_sub(sl);
       if (a.x_dist) a.x_dist[ci] = phi;
@@ -995,10 +1002,121 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
     qb[3] = nw_ * inv; qb[4] = nx_ * inv; qb[5] = ny_ * inv; qb[6] = nz_ * inv;
   }
   __syncthreads();
+}
+
+template <int CONDIM, int BS, bool ART>
+__global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
+  extern __shared__ float4 lds[];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int nq = a.nq, nv = a.nv, nb = a.nb;
+  float *sq = reinterpret_cast<float *>(lds);
+  float *sv = sq + pad4(nq);
+  float *st = sv + pad4(nv);
+  const size_t cbase = (size_t)w * a.ncon_max;
+  // issue every independent global load up front
+  const int nc = a.ncon[w];
+  float4 c0n = make_float4(0.f, 0.f, 0.f, 0.f), c0p = c0n;
+  if (tid < a.ncon_max) {  // the first chunk's records (only used below ncon)
+    c0n = a.cnp[cbase + tid];
+    c0p = a.cpos[cbase + tid];
+  }
+  float4 mi0 = make_float4(1.f, 1.f, 1.f, 1.f);
+  if (tid < nb) mi0 = a.bmi[(size_t)w * nb + tid];
+  const float *qw = a.q + (size_t)w * nq, *vw = a.v + (size_t)w * nv;
+  for (int i = tid; i < nq; i += BS) sq[i] = qw[i];
+  for (int i = tid; i < nv; i += BS) sv[i] = vw[i];
+  if (a.tau) {
+    const float *tw = a.tau + (size_t)w * nv;
+    for (int i = tid; i < nv; i += BS) st[i] = tw[i];
+  } else {
+    for (int i = tid; i < nv; i += BS) st[i] = 0.f;
+  }
+  resolve_world<CONDIM, BS, ART>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0,
+                                 reinterpret_cast<float4 *>(st + pad4(nv)), cbase);
+  float *qo = a.q_out + (size_t)w * nq, *vo = a.v_out + (size_t)w * nv;
+  for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
+  for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
+}
+
+// ====================================================================
+// rollout: T steps of one world per workgroup, state and contacts in LDS
+// ====================================================================
+size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int art_floats, int block,
+                         int cap) {
+  const size_t c = collide_region_bytes(nb, ng, norient, nsub);
+  const size_t r = resolve_region_bytes(nb, ng, block, nsub, art_floats);
+  return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + 2 * sizeof(float4) * (size_t)cap + (c > r ? c : r);
+}
+
+template <int CONDIM, int BS, bool ART>
+__global__ __launch_bounds__(BS) void rollout_kernel(RolloutArgs r) {
+  extern __shared__ float4 lds[];
+  const CollideArgs &ca = r.c;
+  const ResolveArgs &ra = r.s;
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int nq = ra.nq, nv = ra.nv, nb = ra.nb, nw = r.nworld, cap = r.cap;
+  float *sq = reinterpret_cast<float *>(lds);
+  float *sv = sq + pad4(nq);
+  float *st = sv + pad4(nv);
+  float4 *cn = reinterpret_cast<float4 *>(st + pad4(nv));
+  float4 *cp = cn + cap;
+  float4 *reg = cp + cap;  // shared by the narrow phase and the resolution
   {
-    float *qo = a.q_out + (size_t)w * nq, *vo = a.v_out + (size_t)w * nv;
+    const float *qw = r.q0 + (size_t)w * nq, *vw = r.v0 + (size_t)w * nv;
+    for (int i = tid; i < nq; i += BS) sq[i] = qw[i];
+    for (int i = tid; i < nv; i += BS) sv[i] = vw[i];
+  }
+  const uint32_t nxt = tid < ca.nslot ? ca.slots[tid] : 0u;
+  for (int t = 0; t < r.T; ++t) {
+    if (r.tau_seq) {
+      const float *tw = r.tau_seq + ((size_t)t * nw + w) * nv;
+      for (int i = tid; i < nv; i += BS) st[i] = tw[i];
+    } else {
+      for (int i = tid; i < nv; i += BS) st[i] = 0.f;
+    }
+    float4 mi0 = make_float4(1.f, 1.f, 1.f, 1.f);
+    if (tid < nb) mi0 = ra.bmi[(size_t)w * nb + tid];
+    __syncthreads();
+    const int found = collide_world<BS, ART>(ca, w, sq, reg, cn, cp, cap, nxt);
+    const int nc = found < cap ? found : cap;
+    float4 c0n = make_float4(0.f, 0.f, 0.f, 0.f), c0p = c0n;
+    if (tid < nc) {
+      c0n = cn[tid];
+      c0p = cp[tid];
+    }
+    if (tid == 0 && r.ncon_traj) r.ncon_traj[(size_t)t * nw + w] = nc;
+    __syncthreads();
+    resolve_world<CONDIM, BS, ART>(ra, w, sq, sv, st, cn, cp, nc, c0n, c0p, mi0, reg, 0);
+    float *qo = r.q_traj + ((size_t)(t + 1) * nw + w) * nq, *vo = r.v_traj + ((size_t)(t + 1) * nw + w) * nv;
     for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
     for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
+  }
+}
+
+template <int CONDIM, bool ART>
+static hipError_t launch_rollout_b(const RolloutArgs &a, int block, size_t lds, hipStream_t s) {
+  switch (block) {
+    case 64: hipLaunchKernelGGL((rollout_kernel<CONDIM, 64, ART>), dim3(a.nworld), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((rollout_kernel<CONDIM, 128, ART>), dim3(a.nworld), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((rollout_kernel<CONDIM, 256, ART>), dim3(a.nworld), dim3(256), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int CONDIM>
+static hipError_t launch_rollout_c(const RolloutArgs &a, int block, size_t lds, hipStream_t s) {
+  return a.s.nsub > 0 ? launch_rollout_b<CONDIM, true>(a, block, lds, s)
+                      : launch_rollout_b<CONDIM, false>(a, block, lds, s);
+}
+
+hipError_t launch_rollout(const RolloutArgs &a, int block, size_t lds, hipStream_t s) {
+  switch (a.s.condim) {
+    case 1: return launch_rollout_c<1>(a, block, lds, s);
+    case 3: return launch_rollout_c<3>(a, block, lds, s);
+    case 4: return launch_rollout_c<4>(a, block, lds, s);
+    case 6: return launch_rollout_c<6>(a, block, lds, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -229,20 +229,104 @@ def test_in_place_update_and_determinism(torch_cuda):
     assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
 
 
-def test_rollout_matches_repeated_steps(torch_cuda):
+def _rollout_vs_steps(torch, model, s, T, tau=None):
+    """Rollout trajectory against repeated cf_step from the same start; returns the
+    trajectories and per-step contact counts."""
+    q0, v0 = tdev(s["q0"]), tdev(s["v0"])
+    ncon = torch.zeros((T, s["nworld"]), dtype=torch.int32, device="cuda")
+    qt, vt = model.rollout(T, q0, v0, tau_seq=tau, ncon_traj=ncon)
+    q, v = q0, v0
+    worst = 0.0
+    for t in range(T):
+        con = {"ncon": torch.zeros(s["nworld"], dtype=torch.int32, device="cuda")}
+        q, v = model.step(q, v, tau=None if tau is None else tau[t].contiguous(), contacts=con)
+        assert torch.equal(con["ncon"], ncon[t]), f"contact counts differ at step {t}"
+        d = (v - vt[t + 1]).abs().max().item() / max(vt[t + 1].abs().max().item(), 1e-3)
+        worst = max(worst, d)
+        q, v = qt[t + 1].clone(), vt[t + 1].clone()  # continue from the rollout's state
+    assert torch.equal(qt[0], q0) and torch.equal(vt[0], v0)
+    return qt, vt, ncon, worst
+
+
+@pytest.mark.parametrize("scene_fn", ["mixed", "articulated", "pile"])
+def test_rollout_matches_steps_and_oracle(torch_cuda, scene_fn):
+    """cf_rollout (one persistent kernel) against cf_step from each rollout state
+    (same contact counts, velocities equal to float32 rounding) and against the
+    oracle from sampled trajectory states (parity tolerance)."""
     from paper_2603_12185_amd import cfsim
     torch = torch_cuda
-    s = scenes.mixed_shapes(nworld=4, seed=11, condim=4)
+    if scene_fn == "mixed":
+        s = scenes.mixed_shapes(nworld=4, seed=11, condim=4)
+    elif scene_fn == "articulated":
+        s = scenes.articulated_mix(nworld=4, seed=2, condim=6)
+    else:
+        s = scenes.dense_pile(nworld=8, nsphere=64, seed=4, ncon_max=384)
     model = cfsim.Model(s)
-    T = 40
-    tau = tdev(applied_wrench(s, np.random.default_rng(0), shape=(T,)))
-    q0, v0 = tdev(s["q0"]), tdev(s["v0"])
-    qt, vt = model.rollout(T, q0, v0, tau_seq=tau)
-    q, v = q0, v0
-    for t in range(T):
-        q, v = model.step(q, v, tau=tau[t].contiguous())
-        assert torch.equal(q, qt[t + 1]) and torch.equal(v, vt[t + 1])
-    assert torch.equal(qt[0], q0)
+    assert model.get_launch()[3], "expected the persistent rollout kernel"
+    T = 120 if scene_fn != "pile" else 400
+    tau = tdev(applied_wrench(s, np.random.default_rng(0), shape=(T,))) if scene_fn == "mixed" else None
+    qt, vt, ncon, worst = _rollout_vs_steps(torch, model, s, T, tau)
+    assert worst < 1e-6, f"rollout vs step relative difference {worst:.2e}"
+    o = Oracle(s)
+    stats = None
+    qn, vn = qt.cpu().numpy(), vt.cpu().numpy()
+    tn = None if tau is None else tau.cpu().numpy()
+    for t in range(0, T, max(1, T // 10)):
+        stats = compare_step(s, o, qn[t], vn[t], None if tn is None else tn[t], qn[t + 1], vn[t + 1], None,
+                             stats=stats)
+    print("rollout", scene_fn, stats, "contacts", int(ncon.sum()), "worst vs step", worst)
+
+
+def test_rollout_graph_capture_replays(torch_cuda):
+    """A stream capture of cf_rollout replays correctly: three replays with new
+    initial states, eager work and synchronisations in between, each checked
+    against an eager rollout."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    s = scenes.dense_pile(nworld=32, nsphere=32, seed=8, ncon_max=256)
+    model = cfsim.Model(s)
+    T = 50
+    q_in, v_in = tdev(s["q0"]), tdev(s["v0"])
+    q_traj = torch.empty((T + 1, s["nworld"], model.nq), device="cuda")
+    v_traj = torch.empty((T + 1, s["nworld"], model.nv), device="cuda")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        model.rollout(T, q_in, v_in, q_traj=q_traj, v_traj=v_traj)  # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        model.rollout(T, q_in, v_in, q_traj=q_traj, v_traj=v_traj)
+    rng = np.random.default_rng(1)
+    for rep in range(3):
+        q0 = s["q0"].copy()
+        q0.reshape(s["nworld"], -1, 7)[:, :, 2] += rng.uniform(0.0, 0.05)
+        q_in.copy_(tdev(q0))
+        v_in.copy_(tdev(s["v0"]))
+        g.replay()
+        torch.cuda.synchronize()
+        qe, ve = model.rollout(T, tdev(q0), tdev(s["v0"]))
+        torch.cuda.synchronize()
+        assert torch.equal(qe, q_traj) and torch.equal(ve, v_traj), f"replay {rep} differs"
+        _ = (q_in * 2).sum().item()  # unrelated eager work between replays
+
+
+def test_autotune_picks_valid_launch(torch_cuda):
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    s = scenes.dense_pile(nworld=512, nsphere=64, seed=0)
+    model = cfsim.Model(s)
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    for _ in range(200):
+        q, v = model.step(q, v)
+    us_step, us_roll = model.autotune(q, v, steps=10)
+    cb, rb, ob, fused = model.get_launch()
+    print(f"autotune: step {us_step:.1f} us ({cb}/{rb}), rollout {us_roll:.1f} us/step ({ob}, fused={fused})")
+    assert us_step > 0 and cb in (64, 128, 256) and rb in (64, 128, 256) and ob in (64, 128, 256)
+    q1, v1 = model.step(q, v)
+    torch.cuda.synchronize()
+    assert torch.isfinite(v1).all()
 
 
 def test_kernel_timing_query(torch_cuda):
