@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--rollout-steps", type=int, default=1000,
                     help="steps of the batched-rollout form timed after the plain form (0: skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain elementwise copy of this many MiB five times (a "
+                         "known-traffic kernel that calibrates HBM byte counters under a profiler)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -117,8 +120,7 @@ def main():
     torch.cuda.synchronize()
     state_q, state_v = q[0].cpu().numpy(), v[0].cpu().numpy()
 
-    model.set_profiling(True)
-    model.kernel_times()  # reset
+    # Timed region: K steps, nothing recorded between the launches.
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,9 +129,16 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_col, ms_res, nsteps = model.kernel_times()
-    model.set_profiling(False)
     gpu_ms = e0.elapsed_time(e1)
+    if K % 2:
+        q[0].copy_(q[1])
+        v[0].copy_(v[1])
+
+    # Kernel durations, live on the state the timed region ended in: each
+    # kernel launched K times back to back on the same stream, one pair of HIP
+    # events around each group (events between the two kernels of every step
+    # would add their own gaps to both).
+    us_col, us_res = model.time_kernels(q[0], v[0], q[1], v[1], reps=K)
 
     ncon = ncon_log[:K].double()
     assert int(over_log[:K].sum()) == 0, "contact capacity overflowed"
@@ -139,7 +148,7 @@ def main():
     env_steps = nw * K / wall
     imp = contacts_per_step * K / wall
     b_col, b_res = alg_bytes(nq, nv, nb, ng, c_w)
-    t_col, t_res = ms_col / nsteps * 1e-3, ms_res / nsteps * 1e-3
+    t_col, t_res = us_col * 1e-6, us_res * 1e-6
     if t_col >= t_res:
         dom, t_dom, b_dom = "collide_kernel", t_col, b_col
     else:
@@ -169,7 +178,9 @@ def main():
         "contact_impulses_per_s": imp,
         "facet_impulses_per_s": imp * model.nfacet,
         "gpu_event_ms_per_step": gpu_ms / K,
-        "kernel_us": {"collide_kernel": t_col * 1e6, "resolve_kernel": t_res * 1e6},
+        "kernel_us": {"collide_kernel": t_col * 1e6, "resolve_kernel": t_res * 1e6,
+                      "timing": f"HIP events around {K} back-to-back launches of each kernel on the "
+                                "launch stream, from the state the timed region ended in"},
         "whole_step_alg_GBps": step_bytes / (wall / K) / 1e9,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
@@ -185,25 +196,36 @@ def main():
         qt = torch.empty((T + 1, nw, nq), device=dev)
         vt = torch.empty((T + 1, nw, nv), device=dev)
         nct = torch.zeros((T, nw), dtype=torch.int32, device=dev)
-        model.rollout(min(T, 20), q0, v0, q_traj=qt, v_traj=vt, ncon_traj=nct)  # warm-up
-        torch.cuda.synchronize()
-        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        r0.record(stream)
-        model.rollout(T, q0, v0, q_traj=qt, v_traj=vt, ncon_traj=nct)
-        r1.record(stream)
-        torch.cuda.synchronize()
-        rwall = time.perf_counter() - t0
+
+        def time_rollout():
+            model.rollout(min(T, 20), q0, v0, q_traj=qt, v_traj=vt, ncon_traj=nct)  # warm-up
+            torch.cuda.synchronize()
+            r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            r0.record(stream)
+            model.rollout(T, q0, v0, q_traj=qt, v_traj=vt, ncon_traj=nct)
+            r1.record(stream)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, r0.elapsed_time(r1) / T
+
+        # the persistent kernel at the default launch shape, then whatever the
+        # autotuner picks for this model (persistent kernel or step launches)
+        first = model.get_launch()
+        rwall_p, _ = time_rollout()
+        model.autotune(q0, v0, steps=50)
+        rwall, rgpu = time_rollout()
         rc_w = float(nct.double().sum()) / (T * nw)
         launch = model.get_launch()
         b_roll = 8 * (nq + nv)  # per world-step: the trajectory rows written
         result["rollout_form"] = {
             "value": nw * T / rwall, "unit": "env-steps/s", "steps": T,
-            "ms_per_step": rwall * 1e3 / T, "gpu_event_ms_per_step": r0.elapsed_time(r1) / T,
+            "ms_per_step": rwall * 1e3 / T, "gpu_event_ms_per_step": rgpu,
             "mean_contacts_per_world": rc_w, "contact_impulses_per_s": rc_w * nw * T / rwall,
-            "persistent_kernel": launch[3], "block": launch[2],
+            "persistent_kernel": launch[3], "blocks": list(launch[:3]),
             "vs_plain_form": (nw * T / rwall) / env_steps,
             "alg_GBps": b_roll * nw * T / rwall / 1e9,
+            "persistent_kernel_default_shape": {"block": first[2], "used": first[3],
+                                                "ms_per_step": rwall_p * 1e3 / T},
         }
     if args.cpu_worlds > 0:
         threads = min(16, len(os.sched_getaffinity(0)))
@@ -214,6 +236,14 @@ def main():
             "value": rate, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(sample)} worlds x {args.cpu_steps} steps of the same settled pile "
                       f"(FP64 oracle, {dt:.1f} s wall)"}
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty(n, device=dev)
+        for _ in range(5):
+            torch.neg(src, out=dst)  # reads and writes copy_mib MiB
+        torch.cuda.synchronize()
+        result["copy_calibration_mib"] = args.copy_mib
     print(json.dumps(result))
 
 

@@ -138,6 +138,26 @@ cf_status cf_model_dims(const cf_model *m, int32_t *nq, int32_t *nv, int32_t *nf
 cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                   float *q_out, float *v_out, const cf_contacts *out);
 
+/* Adjoint of one cf_step (reverse mode).  With (q+, v+) = cf_step(q, v, tau)
+ * and L = <gq_out, q+> + <gv_out, v+>, writes gq = dL/dq [nworld][nq],
+ * gv = dL/dv and gtau = dL/dtau [nworld][nv] (gtau may be NULL; tau NULL =
+ * zero applied force; gq_out or gv_out NULL = zero).  The step is piecewise
+ * smooth: the derivative is that of the piece containing (q, v, tau), with the
+ * contact set, each facet's activity (the max(., 0) of Eq. cf_wrench), the
+ * clamp of the impedance argument (Eq. r_scaling) and the tangent-helper
+ * choice held as the forward step took them; contact gaps, normals and points
+ * are differentiated through the narrow phase's geometry.  Quaternion entries
+ * of gq are derivatives with respect to the stored (not necessarily unit)
+ * values.  Chaining the call backwards over a stored trajectory gives the
+ * gradient of a rollout (per-step checkpointing: each call recomputes its
+ * step's forward pass from (q, v, tau)).  Float32 device buffers, 16-byte
+ * aligned; gq/gv may alias gq_out/gv_out exactly.  Asynchronous on stream;
+ * uses the model's contact workspace (so it must not overlap a cf_step of the
+ * same model on another stream).  Models with articulated subtrees (hinge or
+ * slide joints) return CF_E_UNSUPPORTED. */
+cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
+                           const float *gq_out, const float *gv_out, float *gq, float *gv, float *gtau);
+
 /* T consecutive steps (batched rollouts): q_traj/v_traj [T+1][nworld][nq|nv]
  * receive the initial state (copied from q0/v0 unless they already alias row 0)
  * and every step's result; tau_seq [T][nworld][nv] or NULL; ncon_traj
@@ -176,6 +196,15 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
 cf_status cf_model_set_profiling(cf_model *m, int32_t enable);
 cf_status cf_model_kernel_times(cf_model *m, double *ms_collide, double *ms_resolve,
                                 int64_t *nsteps);
+
+/* Isolated kernel durations: on `stream`, one warm-up collision launch from
+ * q, then `reps` collision launches back to back, then `reps` resolution
+ * launches back to back (from q, v into q_out, v_out, which must not alias
+ * them), each group bracketed by one pair of HIP events; returns the average
+ * microseconds per launch of each kernel.  Synchronises the stream; allocates
+ * nothing.  The contact workspace holds the contacts of q afterwards. */
+cf_status cf_model_time_kernels(cf_model *m, void *stream, const float *q, const float *v, float *q_out,
+                                float *v_out, int32_t reps, float *us_collide, float *us_resolve);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *cf_last_error(void);

@@ -59,6 +59,7 @@ SIGNATURES = {
     "cf_model_dims": ([C.c_void_p, _ip, _ip, _ip], C.c_int32),
     "cf_step": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, C.POINTER(Contacts)], C.c_int32),
     "cf_rollout": ([C.c_void_p, C.c_void_p, C.c_int32, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
+    "cf_step_backward": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
     "cf_model_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
     "cf_model_get_launch": ([C.c_void_p, _ip, _ip, _ip, _ip], C.c_int32),
     "cf_model_autotune": ([C.c_void_p, C.c_void_p, _fp, _fp, C.c_int32, C.POINTER(C.c_float),
@@ -66,6 +67,8 @@ SIGNATURES = {
     "cf_model_set_profiling": ([C.c_void_p, C.c_int32], C.c_int32),
     "cf_model_kernel_times": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_int64)], C.c_int32),
+    "cf_model_time_kernels": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, C.c_int32, C.POINTER(C.c_float),
+                               C.POINTER(C.c_float)], C.c_int32),
     "cf_last_error": ([], C.c_char_p),
 }
 
@@ -197,6 +200,30 @@ class Model:
                               _ptr(q_out), _ptr(v_out), C.byref(c) if c is not None else None))
         return q_out, v_out
 
+    def step_backward(self, q, v, tau, gq_out, gv_out, gq=None, gv=None, gtau=None, stream=None):
+        """Adjoint of step(q, v, tau): returns (gq, gv, gtau) = the gradients of
+        <gq_out, q+> + <gv_out, v+> with respect to q, v and tau (contact set
+        and facet activity held at the forward point)."""
+        import torch
+        self._check_state(q, self.nq, "q")
+        self._check_state(v, self.nv, "v")
+        if tau is not None:
+            self._check_state(tau, self.nv, "tau")
+        if gq_out is not None:
+            self._check_state(gq_out, self.nq, "gq_out")
+        if gv_out is not None:
+            self._check_state(gv_out, self.nv, "gv_out")
+        gq = torch.empty_like(q) if gq is None else gq
+        gv = torch.empty_like(v) if gv is None else gv
+        gtau = torch.empty_like(v) if gtau is None else gtau
+        self._check_state(gq, self.nq, "gq")
+        self._check_state(gv, self.nv, "gv")
+        self._check_state(gtau, self.nv, "gtau")
+        s = torch.cuda.current_stream() if stream is None else stream
+        _check(load().cf_step_backward(self._h, C.c_void_p(s.cuda_stream), _ptr(q), _ptr(v), _ptr(tau),
+                                       _ptr(gq_out), _ptr(gv_out), _ptr(gq), _ptr(gv), _ptr(gtau)))
+        return gq, gv, gtau
+
     def rollout(self, T, q0, v0, tau_seq=None, q_traj=None, v_traj=None, ncon_traj=None,
                 stream=None):
         """T steps; returns trajectories [T+1][nworld][nq|nv] (ncon_traj [T][nworld]
@@ -247,6 +274,19 @@ class Model:
     # ------------------------------------------------------------ timing
     def set_profiling(self, on: bool):
         _check(load().cf_model_set_profiling(self._h, 1 if on else 0))
+
+    def time_kernels(self, q, v, q_out, v_out, reps=200, stream=None):
+        """Average microseconds per launch of the collision and the resolution
+        kernel, each launched `reps` times back to back from (q, v)."""
+        import torch
+        for t, n, name in ((q, self.nq, "q"), (v, self.nv, "v"), (q_out, self.nq, "q_out"),
+                           (v_out, self.nv, "v_out")):
+            self._check_state(t, n, name)
+        s = torch.cuda.current_stream() if stream is None else stream
+        a, b = C.c_float(), C.c_float()
+        _check(load().cf_model_time_kernels(self._h, C.c_void_p(s.cuda_stream), _ptr(q), _ptr(v), _ptr(q_out),
+                                            _ptr(v_out), int(reps), C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def kernel_times(self):
         """(ms_collide, ms_resolve, steps) summed since the last call."""

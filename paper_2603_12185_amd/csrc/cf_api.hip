@@ -44,6 +44,8 @@ struct cf_model {
   int norient = 0, nsub = 0, art_floats = 0;
   int block_collide = 256, block_resolve = 256, block_rollout = 256;
   size_t lds_rollout = 0;
+  int block_backward = 0;  // 0: the adjoint's LDS does not fit any workgroup size
+  size_t lds_backward = 0;
   bool rollout_steps = false;  // autotuner found T cf_step calls faster than the persistent kernel
   float4 *d_bmi = nullptr, *d_gdat = nullptr, *d_gpos = nullptr, *d_gquat = nullptr;
   float2 *d_gfr2 = nullptr;
@@ -281,6 +283,10 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->block_resolve, m->nsub, m->art_floats);
   m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, nb, ng, m->norient, m->nsub, m->art_floats,
                                          m->block_rollout, m->ncon_max);
+  for (int bs : {256, 128, 64}) {
+    const size_t l = cf::backward_lds_bytes(m->nq, m->nv, nb, ng, bs);
+    if (l <= kLdsLimit) { m->block_backward = bs; m->lds_backward = l; break; }
+  }
   if (hipGetDevice(&m->dev) != hipSuccess) { delete m; return set_err(CF_E_DEVICE, "no HIP device"); }
 
   // ---- per-world constants (float32); shared arrays get world stride 0
@@ -435,6 +441,44 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
   return CF_OK;
 }
 
+cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
+                           const float *gq_out, const float *gv_out, float *gq, float *gv, float *gtau) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (!q || !v || !gq || !gv) return set_err(CF_E_INVALID_ARG, "q, v, gq, gv must be non-NULL");
+  const float *ptrs[] = {q, v, tau, gq_out, gv_out, gq, gv, gtau};
+  for (const float *p : ptrs)
+    if (p && !aligned16(p)) return set_err(CF_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  const size_t sq = (size_t)m->nw * m->nq, sv = (size_t)m->nw * m->nv;
+  auto overlap = [](const float *x, size_t nx, const float *y, size_t ny) {
+    return x && y && x < y + ny && y < x + nx;
+  };
+  // outputs may alias the incoming adjoints exactly, nothing else
+  if (overlap(gq, sq, q, sq) || overlap(gq, sq, v, sv) || overlap(gq, sq, tau, sv) ||
+      (gq != gq_out && overlap(gq, sq, gq_out, sq)) || overlap(gq, sq, gv_out, sv) ||
+      overlap(gv, sv, q, sq) || overlap(gv, sv, v, sv) || overlap(gv, sv, tau, sv) ||
+      overlap(gv, sv, gq_out, sq) || (gv != gv_out && overlap(gv, sv, gv_out, sv)) ||
+      overlap(gv, sv, gq, sq) || overlap(gtau, sv, gq, sq) || overlap(gtau, sv, gv, sv) ||
+      overlap(gtau, sv, q, sq) || overlap(gtau, sv, v, sv) || overlap(gtau, sv, tau, sv) ||
+      overlap(gtau, sv, gq_out, sq) || overlap(gtau, sv, gv_out, sv))
+    return set_err(CF_E_INVALID_ARG, "gq/gv may alias gq_out/gv_out only exactly; no other overlap");
+  if (m->nsub > 0)
+    return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers models of free bodies only");
+  if (!m->block_backward) return set_err(CF_E_UNSUPPORTED, "world too large for the adjoint's LDS");
+  hipStream_t s = (hipStream_t)stream;
+  cf::CollideArgs ca = collide_args(m);
+  ca.q = q;
+  hipError_t e = cf::launch_collide(ca, m->nw, m->block_collide, m->lds_collide, s);
+  if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("collide launch: ") + hipGetErrorString(e));
+  cf::BackwardArgs b{};
+  b.s = resolve_args(m);
+  b.s.q = q; b.s.v = v; b.s.tau = tau;
+  b.gpos = m->d_gpos; b.gpos_ws = m->gpos_ws;
+  b.gq_out = gq_out; b.gv_out = gv_out; b.gq = gq; b.gv = gv; b.gtau = gtau;
+  e = cf::launch_backward(b, m->nw, m->block_backward, m->lds_backward, s);
+  if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("backward launch: ") + hipGetErrorString(e));
+  return CF_OK;
+}
+
 cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
                      const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj) {
   if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
@@ -569,6 +613,40 @@ cf_status cf_model_set_profiling(cf_model *m, int32_t enable) {
     if (st != CF_OK) return st;
   }
   m->prof = enable != 0;
+  return CF_OK;
+}
+
+cf_status cf_model_time_kernels(cf_model *m, void *stream, const float *q, const float *v, float *q_out,
+                                float *v_out, int32_t reps, float *us_collide, float *us_resolve) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (!q || !v || !q_out || !v_out || reps < 1) return set_err(CF_E_INVALID_ARG, "need q, v, q_out, v_out and reps >= 1");
+  if (!aligned16(q) || !aligned16(v) || !aligned16(q_out) || !aligned16(v_out))
+    return set_err(CF_E_INVALID_ARG, "state buffers must be 16-byte aligned");
+  if (q_out == q || v_out == v) return set_err(CF_E_INVALID_ARG, "q_out/v_out must not alias q/v here");
+  hipStream_t s = (hipStream_t)stream;
+  cf::CollideArgs ca = collide_args(m);
+  ca.q = q;
+  cf::ResolveArgs ra = resolve_args(m);
+  ra.q = q; ra.v = v; ra.tau = nullptr; ra.q_out = q_out; ra.v_out = v_out;
+  hipEvent_t e[3];
+  for (auto &x : e)
+    if (hipEventCreate(&x) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventCreate failed");
+  hipError_t err = cf::launch_collide(ca, m->nw, m->block_collide, m->lds_collide, s);
+  if (err == hipSuccess) err = hipEventRecord(e[0], s);
+  for (int i = 0; i < reps && err == hipSuccess; ++i)
+    err = cf::launch_collide(ca, m->nw, m->block_collide, m->lds_collide, s);
+  if (err == hipSuccess) err = hipEventRecord(e[1], s);
+  for (int i = 0; i < reps && err == hipSuccess; ++i)
+    err = cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
+  if (err == hipSuccess) err = hipEventRecord(e[2], s);
+  if (err == hipSuccess) err = hipEventSynchronize(e[2]);
+  float t0 = 0.f, t1 = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t0, e[0], e[1]);
+  if (err == hipSuccess) err = hipEventElapsedTime(&t1, e[1], e[2]);
+  for (auto &x : e) (void)hipEventDestroy(x);
+  if (err != hipSuccess) return set_err(CF_E_DEVICE, std::string("kernel timing: ") + hipGetErrorString(err));
+  if (us_collide) *us_collide = t0 * 1e3f / reps;
+  if (us_resolve) *us_resolve = t1 * 1e3f / reps;
   return CF_OK;
 }
 

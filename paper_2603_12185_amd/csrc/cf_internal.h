@@ -104,6 +104,18 @@ struct RolloutArgs {
   int T, nworld, cap;           // cap: contacts held per world per step (= ncon_max)
 };
 
+// Adjoint of one step (free bodies): one workgroup per world.
+struct BackwardArgs {
+  ResolveArgs s;                // the step's inputs (q, v, tau), contacts; exports unused
+  const float4 *gpos;           // [nw|1][ng] geom offsets in the body frame
+  int gpos_ws;
+  const float *gq_out, *gv_out; // [nw][nq], [nw][nv] adjoints of q+, v+ (null = 0)
+  float *gq, *gv, *gtau;        // [nw][nq], [nw][nv], [nw][nv] (gtau may be null)
+};
+
+size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block);
+hipError_t launch_backward(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s);
+
 size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub);
 size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int art_floats, int block,
                          int cap);

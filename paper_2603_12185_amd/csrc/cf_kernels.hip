@@ -27,6 +27,7 @@
 // a body is 3/m, so the factorisation of M reduces to the per-body inverse
 // inertia.  Apart from the float64 contact geometry the step runs in float32.
 #include "cf_internal.h"
+#include "cf_adjoint.h"
 
 namespace cf {
 
@@ -692,7 +693,7 @@ hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t ld
 // accumulated force, accumulated torque); per geom float4 friction + int body;
 // per lane the two wrench entries of its contact (float4 + float2 each).
 // LDS scratch of the resolution of one world (after its q, v and tau rows).
-size_t resolve_region_bytes(int nb, int ng, int block, int nsub, int art_floats) {
+__host__ __device__ size_t resolve_region_bytes(int nb, int ng, int block, int nsub, int art_floats) {
   return sizeof(float4) * 7 * (size_t)nb + sizeof(float4) * (size_t)ng +
          (sizeof(float4) + sizeof(float2)) * 2 * (size_t)block + sizeof(int) * (size_t)pad4(ng) +
          (nsub > 0 ? sizeof(float4) * 5 * (size_t)nb + sizeof(float) * (size_t)pad4(art_floats) : 0);
@@ -700,6 +701,36 @@ size_t resolve_region_bytes(int nb, int ng, int block, int nsub, int art_floats)
 
 size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats) {
   return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + resolve_region_bytes(nb, ng, block, nsub, art_floats);
+}
+
+// Arrays of the resolution's LDS scratch (layout of resolve_region_bytes()).
+struct ResolveRegion {
+  float4 *bC;            // per body: COM position, 1/m
+  float4 *bV, *bW;       // v_s | trace, w_s
+  float4 *bI0, *bI1;     // inverse world inertia (xx yy zz xy | xz yz)
+  float4 *accF, *accT;   // accumulated contact force and torque
+  float4 *gM;            // per geom (mu_t, mu_tor, mu_rol)
+  float4 *vA, *vB;       // per lane wrench entries, sides a and b
+  float2 *vA2, *vB2;
+  int *gB;               // per geom body
+  float4 *bO, *bAx, *bR; // articulated bodies: origin, joint axis, rotation rows
+  float *art;            // articulated subtree work blocks
+};
+
+template <int BS>
+__device__ inline ResolveRegion resolve_region(float4 *reg, int nb, int ng) {
+  ResolveRegion r;
+  r.bC = reg;
+  r.bV = r.bC + nb; r.bW = r.bV + nb; r.bI0 = r.bW + nb; r.bI1 = r.bI0 + nb;
+  r.accF = r.bI1 + nb; r.accT = r.accF + nb;
+  r.gM = r.accT + nb;
+  r.vA = r.gM + ng; r.vB = r.vA + BS;
+  r.vA2 = reinterpret_cast<float2 *>(r.vB + BS); r.vB2 = r.vA2 + BS;
+  r.gB = reinterpret_cast<int *>(r.vB2 + BS);
+  r.bO = reinterpret_cast<float4 *>(r.gB + pad4(ng));
+  r.bAx = r.bO + nb; r.bR = r.bAx + nb;
+  r.art = reinterpret_cast<float *>(r.bR + 3 * nb);
+  return r;
 }
 
 // Resolution of world w: its q and v rows (LDS sq, sv) become q+ and v+ in
@@ -716,16 +747,13 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   constexpr int NW = BS / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = a.nb, ng = a.ng;
-  float4 *bC = reg;
-  float4 *bV = bC + nb, *bW = bV + nb, *bI0 = bW + nb, *bI1 = bI0 + nb;
-  float4 *accF = bI1 + nb, *accT = accF + nb;
-  float4 *gM = accT + nb;
-  float4 *vA = gM + ng, *vB = vA + BS;
-  float2 *vA2 = reinterpret_cast<float2 *>(vB + BS), *vB2 = vA2 + BS;
-  int *gB = reinterpret_cast<int *>(vB2 + BS);
-  float4 *bO = reinterpret_cast<float4 *>(gB + pad4(ng));  // articulated bodies only
-  float4 *bAx = bO + nb, *bR = bAx + nb;                    // bR: 3 rows per body
-  float *art = reinterpret_cast<float *>(bR + 3 * nb);
+  const ResolveRegion RR = resolve_region<BS>(reg, nb, ng);
+  float4 *bC = RR.bC, *bV = RR.bV, *bW = RR.bW, *bI0 = RR.bI0, *bI1 = RR.bI1;
+  float4 *accF = RR.accF, *accT = RR.accT, *gM = RR.gM, *vA = RR.vA, *vB = RR.vB;
+  float2 *vA2 = RR.vA2, *vB2 = RR.vB2;
+  int *gB = RR.gB;
+  float4 *bO = RR.bO, *bAx = RR.bAx, *bR = RR.bR;  // articulated bodies only
+  float *art = RR.art;
   const Params P = a.p;
   {
     for (int g = tid; g < ng; g += BS) {
@@ -843,7 +871,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       const float vn = dot(n, vrel);
       float lam[NF];
       V3 f, tc = v3(0.f, 0.f, 0.f);
-      if (CONDIM == 1) {
+      if constexpr (CONDIM == 1) {
         lam[0] = A * fmaxf(-aa * vn + c0, 0.f);
         f = lam[0] * n;
       } else {
@@ -854,14 +882,14 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
         lam[3] = A * fmaxf(-aa * (vn + mut * u2) + c0, 0.f);
         float N = lam[0] + lam[1] + lam[2] + lam[3];
         const float e1 = -mut * (lam[0] - lam[2]), e2 = -mut * (lam[1] - lam[3]);
-        if (CONDIM >= 4) {
+        if constexpr (CONDIM >= 4) {
           const float wt = dot(n, wrel);
           lam[4] = A * fmaxf(-aa * (vn - mutor * wt) + c0, 0.f);
           lam[5] = A * fmaxf(-aa * (vn + mutor * wt) + c0, 0.f);
           N += lam[4] + lam[5];
           tc = (-mutor * (lam[4] - lam[5])) * n;
         }
-        if (CONDIM == 6) {
+        if constexpr (CONDIM == 6) {
           const float o1 = dot(t1, wrel), o2 = dot(t2, wrel);
           lam[6] = A * fmaxf(-aa * (vn - murol * o1) + c0, 0.f);
           lam[7] = A * fmaxf(-aa * (vn - murol * o2) + c0, 0.f);
@@ -1143,6 +1171,297 @@ hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t ld
     case 3: return launch_resolve_c<3>(a, nworld, block, lds, s);
     case 4: return launch_resolve_c<4>(a, nworld, block, lds, s);
     case 6: return launch_resolve_c<6>(a, nworld, block, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ====================================================================
+// adjoint of one step (free bodies)
+// ====================================================================
+// Segmented per-body sum of NV4 float4 per lane and side.  Lane tid holds
+// keys kA, kB (nb = none) and payloads pa[i * BS + tid], pb[i * BS + tid] in
+// LDS; each key's entries are summed by one leader lane in lane order (side a
+// before side b) and the waves add their sums to acc[i * nb + key] in wave
+// order: a fixed summation order, no atomics.  All threads call it; it ends
+// with a barrier.
+template <int BS, int NV4>
+__device__ void body_segment_sum(int kA, int kB, const float4 *pa, const float4 *pb, float4 *acc, int nb,
+                                 int nbits) {
+  constexpr int NW = BS / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned long long below = lanes_below(lane);
+  unsigned long long eAA = ~0ull, eAB = ~0ull, eBA = ~0ull, eBB = ~0ull;
+  for (int i = 0; i < nbits; ++i) {
+    const bool a1 = (kA >> i) & 1, b1 = (kB >> i) & 1;
+    const unsigned long long bA = __ballot(a1), bBv = __ballot(b1);
+    eAA &= a1 ? bA : ~bA;
+    eAB &= a1 ? bBv : ~bBv;
+    eBA &= b1 ? bA : ~bA;
+    eBB &= b1 ? bBv : ~bBv;
+  }
+  const bool leadA = kA < nb && !(eAA & below);
+  const bool leadB = kB < nb && !eBA && !(eBB & below);
+  const int wb0 = wave * 64;
+  float4 SA[NV4], SB[NV4];
+#pragma unroll
+  for (int i = 0; i < NV4; ++i) SA[i] = SB[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto add = [](float4 &x, float4 y) { x.x += y.x; x.y += y.y; x.z += y.z; x.w += y.w; };
+  if (leadA) {
+    for (unsigned long long m = eAA; m; m &= m - 1) {
+      const int l = wb0 + __ffsll((unsigned long long)m) - 1;
+#pragma unroll
+      for (int i = 0; i < NV4; ++i) add(SA[i], pa[i * BS + l]);
+    }
+    for (unsigned long long m = eAB; m; m &= m - 1) {
+      const int l = wb0 + __ffsll((unsigned long long)m) - 1;
+#pragma unroll
+      for (int i = 0; i < NV4; ++i) add(SA[i], pb[i * BS + l]);
+    }
+  }
+  if (leadB) {
+    for (unsigned long long m = eBB; m; m &= m - 1) {
+      const int l = wb0 + __ffsll((unsigned long long)m) - 1;
+#pragma unroll
+      for (int i = 0; i < NV4; ++i) add(SB[i], pb[i * BS + l]);
+    }
+  }
+#pragma unroll
+  for (int wv = 0; wv < NW; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int i = 0; i < NV4; ++i) {
+        if (leadA) add(acc[i * nb + kA], SA[i]);
+        if (leadB) add(acc[i * nb + kB], SB[i]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// LDS beyond the resolution's: the q row before the step; per body the
+// accumulated adjoints (3 float4: x_bar | psi_bar | v_s bar | w_s bar packed),
+// the adjoints of the contact force and torque sums and the direct quaternion
+// adjoint; per lane two packed 3-float4 payloads.
+size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block) {
+  return resolve_lds_bytes(nq, nv, nb, ng, block, 0, 0) + sizeof(float) * pad4(nq) +
+         sizeof(float4) * (6 * (size_t)nb + 6 * (size_t)block);
+}
+
+// Reverse of one step of world w: the forward step is recomputed in LDS
+// (same code as the resolution kernel, so the same contact set, facet
+// activity and branches), then the adjoints run backwards through
+// integration and correction (per body), the contacts' impulses, wrenches and
+// geometry (lane per contact, per-body segmented sums) and the smooth
+// prediction (per body).  Contacts come from the collision kernel's workspace.
+template <int CONDIM, int BS>
+__global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
+  using adj::Vec;
+  using adj::vec;
+  constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
+  const ResolveArgs &a = b.s;
+  extern __shared__ float4 lds[];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int nq = a.nq, nv = a.nv, nb = a.nb, ng = a.ng;
+  float *sq = reinterpret_cast<float *>(lds);
+  float *sv = sq + pad4(nq);
+  float *st = sv + pad4(nv);
+  float4 *reg = reinterpret_cast<float4 *>(st + pad4(nv));
+  float *sq0 = reinterpret_cast<float *>(reg + resolve_region_bytes(nb, ng, BS, 0, 0) / sizeof(float4));
+  float4 *acc = reinterpret_cast<float4 *>(sq0 + pad4(nq));  // [3][nb]
+  float4 *bFb = acc + 3 * nb, *bTb = bFb + nb, *bQb = bTb + nb;
+  float4 *pay = bQb + nb;  // [2][3][BS]
+
+  // ---- forward step, kept in LDS
+  const size_t cbase = (size_t)w * a.ncon_max;
+  const int nc = a.ncon[w];
+  float4 c0n = make_float4(0.f, 0.f, 0.f, 0.f), c0p = c0n;
+  if (tid < a.ncon_max) {
+    c0n = a.cnp[cbase + tid];
+    c0p = a.cpos[cbase + tid];
+  }
+  float4 mi0 = make_float4(1.f, 1.f, 1.f, 1.f);
+  if (tid < nb) mi0 = a.bmi[(size_t)w * nb + tid];
+  const float *qw = a.q + (size_t)w * nq, *vw = a.v + (size_t)w * nv;
+  for (int i = tid; i < nq; i += BS) sq[i] = sq0[i] = qw[i];
+  for (int i = tid; i < nv; i += BS) sv[i] = vw[i];
+  if (a.tau) {
+    const float *tw = a.tau + (size_t)w * nv;
+    for (int i = tid; i < nv; i += BS) st[i] = tw[i];
+  } else {
+    for (int i = tid; i < nv; i += BS) st[i] = 0.f;
+  }
+  resolve_world<CONDIM, BS, false>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg,
+                                   cbase);
+  const ResolveRegion RR = resolve_region<BS>(reg, nb, ng);
+  const Params P = a.p;
+  auto xyz = [](float4 f) { return vec(f.x, f.y, f.z); };
+
+  // ---- reverse of integration and correction, per body
+  for (int bi = tid; bi < nb; bi += BS) {
+    const BodyC bc = a.body[bi];
+    const float4 mi = a.bmi[(size_t)w * nb + bi];
+    adj::BodyUpdate<float> U;
+    U.m = mi.x; U.d[0] = mi.y; U.d[1] = mi.z; U.d[2] = mi.w;
+    for (int i = 0; i < 4; ++i) U.q[i] = sq0[bc.qadr + 3 + i];
+    U.x = xyz(RR.bC[bi]); U.vs = xyz(RR.bV[bi]); U.ws = xyz(RR.bW[bi]);
+    U.F = xyz(RR.accF[bi]); U.Tq = xyz(RR.accT[bi]); U.h = P.h;
+    Vec<float> xpb = vec(0.f, 0.f, 0.f), vpb = xpb, wpb = xpb;
+    float qpb[4] = {0.f, 0.f, 0.f, 0.f};
+    if (b.gq_out) {
+      const float *g = b.gq_out + (size_t)w * nq + bc.qadr;
+      xpb = vec(g[0], g[1], g[2]);
+      for (int i = 0; i < 4; ++i) qpb[i] = g[3 + i];
+    }
+    if (b.gv_out) {
+      const float *g = b.gv_out + (size_t)w * nv + bc.dadr;
+      vpb = vec(g[0], g[1], g[2]);
+      wpb = vec(g[3], g[4], g[5]);
+    }
+    Vec<float> xb, vsb, wsb, Fb, Tb, psi = vec(0.f, 0.f, 0.f);
+    float qb[4] = {0.f, 0.f, 0.f, 0.f};
+    adj::update_vjp(U, xpb, qpb, vpb, wpb, xb, qb, vsb, wsb, Fb, Tb, psi);
+    acc[bi] = make_float4(xb.x, xb.y, xb.z, psi.x);
+    acc[nb + bi] = make_float4(psi.y, psi.z, vsb.x, vsb.y);
+    acc[2 * nb + bi] = make_float4(vsb.z, wsb.x, wsb.y, wsb.z);
+    bFb[bi] = make_float4(Fb.x, Fb.y, Fb.z, 0.f);
+    bTb[bi] = make_float4(Tb.x, Tb.y, Tb.z, 0.f);
+    bQb[bi] = make_float4(qb[0], qb[1], qb[2], qb[3]);
+  }
+  __syncthreads();
+
+  // ---- reverse of the contacts: lane per contact, per-body sums
+  const adj::Impedance<float> I{P.r_min, P.r_max, P.width, P.mid, P.power};
+  for (int base = 0; base < nc; base += BS) {
+    const int k = base + tid;
+    int kA = nb, kB = nb;
+    float4 pA[3], pB[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pA[i] = pB[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k < nc) {
+      const float4 cn = a.cnp[cbase + k], cp = a.cpos[cbase + k];
+      const uint32_t sl = __float_as_uint(cp.w);
+      const int ga = slot_ga(sl), gb = slot_gb(sl);
+      const uint32_t type = slot_type(sl);
+      const int ba = RR.gB[ga], bbd = RR.gB[gb];
+      adj::ContactIn<float> C;
+      const Vec<float> Z = vec(0.f, 0.f, 0.f);
+      C.n = vec(cn.x, cn.y, cn.z); C.p = vec(cp.x, cp.y, cp.z); C.phi = cn.w;
+      C.xa = C.va = C.wa = C.xb = C.vb = C.wb = Z;
+      C.has_a = ba >= 0; C.has_b = bbd >= 0;
+      C.trs = 0.f;
+      if (ba >= 0) { C.xa = xyz(RR.bC[ba]); C.va = xyz(RR.bV[ba]); C.wa = xyz(RR.bW[ba]); C.trs += RR.bV[ba].w; }
+      if (bbd >= 0) { C.xb = xyz(RR.bC[bbd]); C.vb = xyz(RR.bV[bbd]); C.wb = xyz(RR.bW[bbd]); C.trs += RR.bV[bbd].w; }
+      const float4 ma = RR.gM[ga], mb = RR.gM[gb];
+      C.mut = fmaxf(ma.x, mb.x); C.mutor = fmaxf(ma.y, mb.y); C.murol = fmaxf(ma.z, mb.z);
+      C.h = P.h; C.k = P.k_user; C.d = P.d_user;
+      const Vec<float> Fab = ba >= 0 ? xyz(bFb[ba]) : Z, Tab = ba >= 0 ? xyz(bTb[ba]) : Z;
+      const Vec<float> Fbb = bbd >= 0 ? xyz(bFb[bbd]) : Z, Tbb = bbd >= 0 ? xyz(bTb[bbd]) : Z;
+      adj::ContactBar<float> o;
+      adj::contact_vjp<NF>(C, I, Fab, Tab, Fbb, Tbb, o);
+      // geometry: contact (n, phi, p) from the two geoms' poses
+      Vec<float> xab = o.xa, xbb = o.xb, psa = Z, psb = Z;
+      const float4 gda = a.gdat[(size_t)w * ng + ga], gdb = a.gdat[(size_t)w * ng + gb];
+      const Vec<float> n = C.n, p = C.p;
+      const float phi = C.phi;
+      if (type == kSphereSphere) {
+        const float ra = gda.x, rb = gdb.x;
+        Vec<float> cab, cbb;
+        adj::sphere_pair_vjp(n, phi, ra, rb, o.n, o.phi, o.p, cab, cbb);
+        const Vec<float> ca = p - (ra + 0.5f * phi) * n;
+        const Vec<float> cb = ca + (phi + ra + rb) * n;
+        xab = xab + cab; psa = adj::cross(ca - C.xa, cab);
+        xbb = xbb + cbb; psb = adj::cross(cb - C.xb, cbb);
+      } else {
+        const float rad = type == kPlaneBox ? 0.f : gdb.x;
+        const Vec<float> c = p + (rad + 0.5f * phi) * n;
+        Vec<float> pp = c - (phi + rad) * n;  // a point of the plane (static plane: n is fixed)
+        if (ba >= 0) {
+          float R[9];
+          adj::rot_of_quat(sq0 + a.body[ba].qadr + 3, R);
+          const float4 o4 = b.gpos[(size_t)w * b.gpos_ws + ga];
+          pp = C.xa + vec(R[0] * o4.x + R[1] * o4.y + R[2] * o4.z, R[3] * o4.x + R[4] * o4.y + R[5] * o4.z,
+                          R[6] * o4.x + R[7] * o4.y + R[8] * o4.z);
+        }
+        Vec<float> cbar, ppb, nnb;
+        adj::plane_point_vjp(pp, n, c, rad, phi, o.n, o.phi, o.p, cbar, ppb, nnb);
+        xbb = xbb + cbar; psb = adj::cross(c - C.xb, cbar);
+        if (ba >= 0) { xab = xab + ppb; psa = adj::cross(pp - C.xa, ppb) + adj::cross(n, nnb); }
+      }
+      if (ba >= 0) {
+        kA = ba;
+        pA[0] = make_float4(xab.x, xab.y, xab.z, psa.x);
+        pA[1] = make_float4(psa.y, psa.z, o.va.x, o.va.y);
+        pA[2] = make_float4(o.va.z, o.wa.x, o.wa.y, o.wa.z);
+      }
+      if (bbd >= 0) {
+        kB = bbd;
+        pB[0] = make_float4(xbb.x, xbb.y, xbb.z, psb.x);
+        pB[1] = make_float4(psb.y, psb.z, o.vb.x, o.vb.y);
+        pB[2] = make_float4(o.vb.z, o.wb.x, o.wb.y, o.wb.z);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      pay[i * BS + tid] = pA[i];
+      pay[(3 + i) * BS + tid] = pB[i];
+    }
+    __syncthreads();
+    body_segment_sum<BS, 3>(kA, kB, pay, pay + 3 * BS, acc, nb, a.nbits);
+  }
+
+  // ---- reverse of the smooth prediction, per body; adjoint rows staged in LDS
+  for (int bi = tid; bi < nb; bi += BS) {
+    const BodyC bc = a.body[bi];
+    const float4 mi = a.bmi[(size_t)w * nb + bi];
+    adj::BodyPredict<float> B;
+    B.m = mi.x; B.d[0] = mi.y; B.d[1] = mi.z; B.d[2] = mi.w;
+    for (int i = 0; i < 4; ++i) B.q[i] = sq0[bc.qadr + 3 + i];
+    const float *v0 = vw + bc.dadr, *t0 = st + bc.dadr;
+    B.v = vec(v0[0], v0[1], v0[2]); B.w = vec(v0[3], v0[4], v0[5]);
+    B.f = vec(t0[0], t0[1], t0[2]); B.t = vec(t0[3], t0[4], t0[5]);
+    B.g = vec(P.gx, P.gy, P.gz); B.h = P.h;
+    const float4 A0 = acc[bi], A1 = acc[nb + bi], A2 = acc[2 * nb + bi];
+    const Vec<float> xb = vec(A0.x, A0.y, A0.z), vsb = vec(A1.z, A1.w, A2.x), wsb = vec(A2.y, A2.z, A2.w);
+    Vec<float> psi = vec(A0.w, A1.x, A1.y);
+    Vec<float> vb, wb, fb, tb;
+    adj::predict_vjp(B, vsb, wsb, vb, wb, fb, tb, psi);
+    const float4 Q = bQb[bi];
+    float qb[4] = {Q.x, Q.y, Q.z, Q.w};
+    adj::quat_grad_from_psi(B.q, psi, qb);
+    float *gqr = sq + bc.qadr, *gvr = sv + bc.dadr, *gtr = st + bc.dadr;
+    gqr[0] = xb.x; gqr[1] = xb.y; gqr[2] = xb.z;
+    for (int i = 0; i < 4; ++i) gqr[3 + i] = qb[i];
+    gvr[0] = vb.x; gvr[1] = vb.y; gvr[2] = vb.z; gvr[3] = wb.x; gvr[4] = wb.y; gvr[5] = wb.z;
+    gtr[0] = fb.x; gtr[1] = fb.y; gtr[2] = fb.z; gtr[3] = tb.x; gtr[4] = tb.y; gtr[5] = tb.z;
+  }
+  __syncthreads();
+  float *gqw = b.gq + (size_t)w * nq, *gvw = b.gv + (size_t)w * nv;
+  for (int i = tid; i < nq; i += BS) gqw[i] = sq[i];
+  for (int i = tid; i < nv; i += BS) gvw[i] = sv[i];
+  if (b.gtau) {
+    float *gtw = b.gtau + (size_t)w * nv;
+    for (int i = tid; i < nv; i += BS) gtw[i] = st[i];
+  }
+}
+
+template <int CONDIM>
+static hipError_t launch_backward_c(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  switch (block) {
+    case 64: hipLaunchKernelGGL((backward_kernel<CONDIM, 64>), dim3(nworld), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((backward_kernel<CONDIM, 128>), dim3(nworld), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((backward_kernel<CONDIM, 256>), dim3(nworld), dim3(256), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  if (a.s.nsub > 0) return hipErrorInvalidValue;
+  switch (a.s.condim) {
+    case 1: return launch_backward_c<1>(a, nworld, block, lds, s);
+    case 3: return launch_backward_c<3>(a, nworld, block, lds, s);
+    case 4: return launch_backward_c<4>(a, nworld, block, lds, s);
+    case 6: return launch_backward_c<6>(a, nworld, block, lds, s);
     default: return hipErrorInvalidValue;
   }
 }

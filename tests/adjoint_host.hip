@@ -1,0 +1,292 @@
+// Host-side check of the reverse-mode pieces in cf_adjoint.h: each vector-
+// Jacobian product, instantiated in float64, against central differences of
+// the matching forward piece.  Built by tests/test_adjoint_host.py with hipcc
+// and run on the CPU (no device code is launched).
+#include <cstdio>
+#include <cstdlib>
+#include <cmath>
+#include <random>
+#include <vector>
+
+#include "../paper_2603_12185_amd/csrc/cf_adjoint.h"
+
+using namespace cf::adj;
+typedef double D;
+typedef Vec<D> V;
+
+static std::mt19937_64 rng(12345);
+static D U(D a, D b) { return std::uniform_real_distribution<D>(a, b)(rng); }
+static V rv(D s) { return vec(U(-s, s), U(-s, s), U(-s, s)); }
+static D nrm(const std::vector<D> &x) {
+  D s = 0;
+  for (D v : x) s += v * v;
+  return std::sqrt(s);
+}
+
+static int failures = 0;
+static void report(const char *name, const std::vector<D> &an, const std::vector<D> &fd, D tol) {
+  std::vector<D> d(an.size());
+  for (size_t i = 0; i < an.size(); ++i) d[i] = an[i] - fd[i];
+  const D rel = nrm(d) / (nrm(fd) + 1e-300);
+  const bool ok = rel < tol;
+  if (!ok) ++failures;
+  printf("%-34s n=%2zu |g|=%.3e rel=%.2e %s\n", name, an.size(), nrm(fd), rel, ok ? "ok" : "FAIL");
+  if (!ok)
+    for (size_t i = 0; i < an.size(); ++i) printf("   %2zu  an %+.9e  fd %+.9e\n", i, an[i], fd[i]);
+}
+
+// central differences of scalar L(x) over every component of x
+template <class F>
+static std::vector<D> fd_grad(std::vector<D> x, F L, D eps = 1e-6) {
+  std::vector<D> g(x.size());
+  for (size_t i = 0; i < x.size(); ++i) {
+    const D x0 = x[i];
+    x[i] = x0 + eps;
+    const D lp = L(x);
+    x[i] = x0 - eps;
+    const D lm = L(x);
+    x[i] = x0;
+    g[i] = (lp - lm) / (2 * eps);
+  }
+  return g;
+}
+
+static void put(std::vector<D> &x, V v) { x.push_back(v.x); x.push_back(v.y); x.push_back(v.z); }
+static V get(const std::vector<D> &x, size_t i) { return vec(x[i], x[i + 1], x[i + 2]); }
+static D vdot(V a, V b) { return dot(a, b); }
+
+// ----------------------------------------------------------------------------
+static void check_predict(int trial) {
+  BodyPredict<D> B;
+  B.m = U(0.05, 2.0);
+  for (int i = 0; i < 3; ++i) B.d[i] = U(1e-4, 1e-2);
+  for (int i = 0; i < 4; ++i) B.q[i] = U(-1, 1);
+  B.v = rv(1.0); B.w = rv(20.0); B.f = rv(5.0); B.t = rv(0.05); B.g = vec(0.0, 0.0, -9.81); B.h = 0.002;
+  const V vsb = rv(1.0), wsb = rv(1.0);
+  // pack inputs: q(4) v w f t
+  std::vector<D> x(B.q, B.q + 4);
+  put(x, B.v); put(x, B.w); put(x, B.f); put(x, B.t);
+  auto L = [&](const std::vector<D> &y) {
+    BodyPredict<D> C = B;
+    for (int i = 0; i < 4; ++i) C.q[i] = y[i];
+    C.v = get(y, 4); C.w = get(y, 7); C.f = get(y, 10); C.t = get(y, 13);
+    V vs, ws;
+    predict_forward(C, vs, ws);
+    return vdot(vs, vsb) + vdot(ws, wsb);
+  };
+  V vb, wb, fb, tb, psi = vec(0.0, 0.0, 0.0);
+  predict_vjp(B, vsb, wsb, vb, wb, fb, tb, psi);
+  D qb[4] = {0, 0, 0, 0};
+  quat_grad_from_psi(B.q, psi, qb);
+  std::vector<D> an(qb, qb + 4);
+  put(an, vb); put(an, wb); put(an, fb); put(an, tb);
+  char name[64];
+  snprintf(name, sizeof name, "predict #%d", trial);
+  report(name, an, fd_grad(x, L), 1e-7);
+}
+
+static void check_update(int trial, D wscale) {
+  BodyUpdate<D> B;
+  B.m = U(0.05, 2.0);
+  for (int i = 0; i < 3; ++i) B.d[i] = U(1e-4, 1e-2);
+  for (int i = 0; i < 4; ++i) B.q[i] = U(-1, 1);
+  B.x = rv(0.3); B.vs = rv(1.0); B.ws = rv(wscale); B.F = rv(0.01); B.Tq = rv(1e-4); B.h = 0.002;
+  const V xpb = rv(1.0), vpb = rv(1.0), wpb = rv(1.0);
+  const D qpb[4] = {U(-1, 1), U(-1, 1), U(-1, 1), U(-1, 1)};
+  std::vector<D> x(B.q, B.q + 4);
+  put(x, B.x); put(x, B.vs); put(x, B.ws); put(x, B.F); put(x, B.Tq);
+  auto L = [&](const std::vector<D> &y) {
+    BodyUpdate<D> C = B;
+    for (int i = 0; i < 4; ++i) C.q[i] = y[i];
+    C.x = get(y, 4); C.vs = get(y, 7); C.ws = get(y, 10); C.F = get(y, 13); C.Tq = get(y, 16);
+    V xp, vp, wp;
+    D qp[4];
+    update_forward(C, xp, qp, vp, wp);
+    return vdot(xp, xpb) + vdot(vp, vpb) + vdot(wp, wpb) + qp[0] * qpb[0] + qp[1] * qpb[1] + qp[2] * qpb[2] +
+           qp[3] * qpb[3];
+  };
+  V xb, vsb, wsb, Fb, Tb, psi = vec(0.0, 0.0, 0.0);
+  D qb[4] = {0, 0, 0, 0};
+  update_vjp(B, xpb, qpb, vpb, wpb, xb, qb, vsb, wsb, Fb, Tb, psi);
+  quat_grad_from_psi(B.q, psi, qb);
+  std::vector<D> an(qb, qb + 4);
+  put(an, xb); put(an, vsb); put(an, wsb); put(an, Fb); put(an, Tb);
+  char name[64];
+  snprintf(name, sizeof name, "update |w|~%g #%d", wscale, trial);
+  report(name, an, fd_grad(x, L), 1e-6);
+}
+
+static Impedance<D> imp() { return {0.9, 0.95, 0.001, 0.5, 2.0}; }
+
+// Which branch each non-smooth operation of the contact takes: facet
+// activity, the clamp of x, the sign of phi, the tangent helper.
+template <int NF>
+static unsigned pattern(const ContactIn<D> &C) {
+  D lam[NF];
+  V f, ta, tb;
+  contact_forward<NF>(C, imp(), lam, f, ta, tb);
+  unsigned m = 0;
+  for (int i = 0; i < NF; ++i) m |= (lam[i] > 0.0 ? 1u : 0u) << i;
+  m |= (std::fabs(C.phi) >= imp().width ? 1u : 0u) << 12;
+  m |= (C.phi > 0.0 ? 1u : 0u) << 13;
+  m |= (std::fabs(C.n.x) <= 0.5 ? 1u : 0u) << 14;
+  return m;
+}
+
+template <int NF>
+static void make_contact(ContactIn<D> &C, bool has_a, bool has_b, D phi_scale) {
+  for (;;) {
+    C.n = rv(1.0);
+    const D l = std::sqrt(dot(C.n, C.n));
+    C.n = (1.0 / l) * C.n;
+    C.phi = U(-phi_scale, phi_scale * 0.2);
+    C.p = rv(0.3);
+    C.xa = C.p + rv(0.05); C.xb = C.p + rv(0.05);
+    C.va = rv(0.05); C.vb = rv(0.05); C.wa = rv(2.0); C.wb = rv(2.0);
+    C.has_a = has_a; C.has_b = has_b;
+    C.trs = (has_a ? 3.0 / U(0.05, 1) : 0.0) + (has_b ? 3.0 / U(0.05, 1) : 0.0);
+    C.mut = U(0.3, 1.0); C.mutor = U(0.001, 0.005); C.murol = U(1e-4, 5e-4);
+    C.h = 0.002; C.k = 0.1; C.d = 0.001;
+    // keep it only if no branch changes within 1e-5 of any input
+    const unsigned p0 = pattern<NF>(C);
+    bool same = true;
+    D *fields[] = {&C.n.x, &C.n.y, &C.n.z, &C.phi, &C.p.x, &C.p.y, &C.p.z, &C.xa.x, &C.xa.y, &C.xa.z,
+                   &C.va.x, &C.va.y, &C.va.z, &C.wa.x, &C.wa.y, &C.wa.z, &C.xb.x, &C.xb.y, &C.xb.z,
+                   &C.vb.x, &C.vb.y, &C.vb.z, &C.wb.x, &C.wb.y, &C.wb.z};
+    for (D *f : fields)
+      for (D e : {-1e-5, 1e-5}) {
+        const D f0 = *f;
+        *f = f0 + e;
+        same = same && pattern<NF>(C) == p0;
+        *f = f0;
+      }
+    if (same && (p0 & ((1u << NF) - 1))) return;  // at least one facet active
+  }
+}
+
+template <int NF>
+static void check_contact(int trial, bool has_a, bool has_b, D phi_scale) {
+  ContactIn<D> C;
+  make_contact<NF>(C, has_a, has_b, phi_scale);
+  const V Fab = rv(1.0), Tab = rv(1.0), Fbb = rv(1.0), Tbb = rv(1.0);
+  std::vector<D> x;
+  put(x, C.n); x.push_back(C.phi); put(x, C.p);
+  put(x, C.xa); put(x, C.va); put(x, C.wa); put(x, C.xb); put(x, C.vb); put(x, C.wb);
+  auto L = [&](const std::vector<D> &y) {
+    ContactIn<D> K = C;
+    K.n = get(y, 0); K.phi = y[3]; K.p = get(y, 4);
+    K.xa = get(y, 7); K.va = get(y, 10); K.wa = get(y, 13); K.xb = get(y, 16); K.vb = get(y, 19); K.wb = get(y, 22);
+    D lam[NF];
+    V f, ta, tb;
+    contact_forward<NF>(K, imp(), lam, f, ta, tb);
+    D s = 0;
+    if (K.has_a) s += -vdot(f, Fab) + vdot(ta, Tab);
+    if (K.has_b) s += vdot(f, Fbb) + vdot(tb, Tbb);
+    return s;
+  };
+  ContactBar<D> o;
+  contact_vjp<NF>(C, imp(), Fab, Tab, Fbb, Tbb, o);
+  std::vector<D> an;
+  put(an, o.n); an.push_back(o.phi); put(an, o.p);
+  put(an, o.xa); put(an, o.va); put(an, o.wa); put(an, o.xb); put(an, o.vb); put(an, o.wb);
+  char name[64];
+  snprintf(name, sizeof name, "contact nf=%d a=%d b=%d phi~%g #%d", NF, has_a, has_b, phi_scale, trial);
+  report(name, an, fd_grad(x, L, 1e-7), 2e-6);
+}
+
+static void check_sphere_pair(int trial) {
+  const V ca = rv(0.3), cb = ca + rv(0.06);
+  const D ra = U(0.02, 0.05), rb = U(0.02, 0.05);
+  const V nb = rv(1.0), pb = rv(1.0);
+  const D phib = U(-1, 1);
+  std::vector<D> x;
+  put(x, ca); put(x, cb);
+  auto L = [&](const std::vector<D> &y) {
+    V n, p;
+    D phi;
+    sphere_pair_forward(get(y, 0), get(y, 3), ra, rb, n, phi, p);
+    return vdot(n, nb) + phi * phib + vdot(p, pb);
+  };
+  V n, p;
+  D phi;
+  sphere_pair_forward(ca, cb, ra, rb, n, phi, p);
+  V cab, cbb;
+  sphere_pair_vjp(n, phi, ra, rb, nb, phib, pb, cab, cbb);
+  std::vector<D> an;
+  put(an, cab); put(an, cbb);
+  char name[64];
+  snprintf(name, sizeof name, "sphere pair #%d", trial);
+  report(name, an, fd_grad(x, L), 1e-7);
+}
+
+// plane attached to a rotating body: pp = x + R(q) o, n = R(q) R0 e_z; the
+// point c = y + R(qc) oc on another body.  Checks plane_point_vjp and the
+// conversion of point and direction adjoints to body pose adjoints.
+static void check_plane_point(int trial) {
+  D q[4], qc[4];
+  for (int i = 0; i < 4; ++i) { q[i] = U(-1, 1); qc[i] = U(-1, 1); }
+  const V x = rv(0.3), o = rv(0.1), y = rv(0.3), oc = rv(0.05);
+  const D rad = U(0.0, 0.05);
+  const V nb = rv(1.0), pb = rv(1.0);
+  const D phib = U(-1, 1);
+  auto geom = [&](const D *qq, V xx, const D *qqc, V yy, V &pp, V &n, V &c) {
+    D R[9], Rc[9];
+    rot_of_quat(qq, R);
+    rot_of_quat(qqc, Rc);
+    pp = xx + vec(R[0] * o.x + R[1] * o.y + R[2] * o.z, R[3] * o.x + R[4] * o.y + R[5] * o.z,
+                  R[6] * o.x + R[7] * o.y + R[8] * o.z);
+    n = vec(R[2], R[5], R[8]);
+    c = yy + vec(Rc[0] * oc.x + Rc[1] * oc.y + Rc[2] * oc.z, Rc[3] * oc.x + Rc[4] * oc.y + Rc[5] * oc.z,
+                 Rc[6] * oc.x + Rc[7] * oc.y + Rc[8] * oc.z);
+  };
+  std::vector<D> X(q, q + 4);
+  put(X, x);
+  for (int i = 0; i < 4; ++i) X.push_back(qc[i]);
+  put(X, y);
+  auto L = [&](const std::vector<D> &z) {
+    V pp, n, c, p;
+    D phi;
+    geom(&z[0], get(z, 4), &z[7], get(z, 11), pp, n, c);
+    plane_point_forward(pp, n, c, rad, phi, p);
+    return vdot(n, nb) + phi * phib + vdot(p, pb);
+  };
+  V pp, n, c, p;
+  D phi;
+  geom(q, x, qc, y, pp, n, c);
+  plane_point_forward(pp, n, c, rad, phi, p);
+  V cb, ppb, nnb;
+  plane_point_vjp(pp, n, c, rad, phi, nb, phib, pb, cb, ppb, nnb);
+  // point on a body: x_bar += c_bar, psi += (c - x) x c_bar; direction: psi += n x n_bar
+  const V psi_a = cross(pp - x, ppb) + cross(n, nnb);
+  const V psi_b = cross(c - y, cb);
+  D qa[4] = {0, 0, 0, 0}, qbb[4] = {0, 0, 0, 0};
+  quat_grad_from_psi(q, psi_a, qa);
+  quat_grad_from_psi(qc, psi_b, qbb);
+  std::vector<D> an(qa, qa + 4);
+  put(an, ppb);
+  for (int i = 0; i < 4; ++i) an.push_back(qbb[i]);
+  put(an, cb);
+  char name[64];
+  snprintf(name, sizeof name, "plane-point on bodies #%d", trial);
+  report(name, an, fd_grad(X, L), 1e-7);
+}
+
+int main() {
+  for (int t = 0; t < 4; ++t) check_predict(t);
+  for (int t = 0; t < 3; ++t) check_update(t, 20.0);
+  for (int t = 0; t < 2; ++t) check_update(t, 1e-4);  // series branch of exp
+  for (int t = 0; t < 2; ++t) check_update(t, 1e-9);  // small-angle branch
+  for (int t = 0; t < 3; ++t) {
+    check_contact<1>(t, true, true, 0.01);
+    check_contact<4>(t, true, true, 0.01);
+    check_contact<6>(t, true, true, 0.01);
+    check_contact<10>(t, true, true, 0.01);
+    check_contact<4>(t, false, true, 0.01);
+    check_contact<10>(t, false, true, 0.0005);  // x below the clamp: rho varies with phi
+    check_contact<4>(t, true, false, 0.0005);
+  }
+  for (int t = 0; t < 3; ++t) check_sphere_pair(t);
+  for (int t = 0; t < 3; ++t) check_plane_point(t);
+  printf("%s (%d failures)\n", failures ? "FAILED" : "ALL OK", failures);
+  return failures ? 1 : 0;
+}

@@ -341,6 +341,17 @@ def test_kernel_timing_query(torch_cuda):
     a, b, n = model.kernel_times()
     print(f"collide {a / n * 1e3:.1f} us, resolve {b / n * 1e3:.1f} us per step; wall {time.time() - t0:.3f}s")
     assert n == 20 and a > 0 and b > 0
+    model.set_profiling(False)
+    # isolated back-to-back timing leaves the state untouched and gives the
+    # same step as cf_step
+    q0, v0 = q.clone(), v.clone()
+    qo, vo = torch_cuda.empty_like(q), torch_cuda.empty_like(v)
+    uc, ur = model.time_kernels(q, v, qo, vo, reps=10)
+    torch_cuda.cuda.synchronize()
+    assert uc > 0 and ur > 0
+    assert torch_cuda.equal(q, q0) and torch_cuda.equal(v, v0)
+    q1, v1 = model.step(q, v)
+    assert torch_cuda.equal(q1, qo) and torch_cuda.equal(v1, vo)
 
 
 # ---------------------------------------------------------------- articulated
