@@ -427,6 +427,43 @@ def mixed_shapes(nworld=4, seed=0, condim=3, k_user=0.1, d_user=0.001, ncon_max=
     return s
 
 
+def pusher_ball(nworld=4, seed=0, condim=6, k_user=0.1, d_user=0.001, ncon_max=32):
+    """A 3 cm free ball on the ground with four actuated 1 cm free spheres
+    (fingertips driven by applied forces) pressed against it from four sides: a
+    free-body stand-in for in-hand manipulation with the pair rules of the
+    narrow phase (plane-sphere, sphere-sphere).  Per-world friction and pose
+    jitter.  The ball's dofs are 0..5; fingertip f's force dofs are 6 + 6 f ..
+    8 + 6 f."""
+    rng = np.random.default_rng([seed, 6])
+    b = _Builder(nworld)
+    b.geom(PLANE, -1, friction=np.stack([rng.uniform(0.5, 0.9, nworld),
+                                         np.full(nworld, 0.002), np.full(nworld, 0.0002)], 1))
+    rb, mb = 0.03, 0.1
+    ball = b.body(JNT_FREE, mass=mb, inertia=(0.4 * mb * rb * rb,) * 3)
+    b.geom(SPHERE, ball, size=(rb, 0, 0),
+           friction=np.stack([rng.uniform(0.4, 0.8, nworld), np.full(nworld, 0.002),
+                              np.full(nworld, 0.0002)], 1))
+    rf, mf = 0.01, 0.02
+    for _ in range(4):
+        t = b.body(JNT_FREE, mass=mf, inertia=(0.4 * mf * rf * rf,) * 3)
+        b.geom(SPHERE, t, size=(rf, 0, 0),
+               friction=np.stack([rng.uniform(0.6, 1.0, nworld), np.full(nworld, 0.002),
+                                  np.full(nworld, 0.0002)], 1))
+    s = b.build(condim=condim, k_user=k_user, d_user=d_user, ncon_max=ncon_max, name="pusher_ball")
+    for w in range(nworld):
+        q = s["q0"][w].reshape(5, 7)
+        c = np.array([rng.uniform(-0.005, 0.005), rng.uniform(-0.005, 0.005), rb - 0.0005])
+        q[0, 0:3] = c
+        q[0, 3:7] = _random_quat(rng)
+        for i in range(4):
+            ang = 0.5 * np.pi * i + rng.uniform(-0.2, 0.2)
+            el = rng.uniform(0.1, 0.4)  # elevation of the fingertip above the ball's equator
+            d = np.array([np.cos(ang) * np.cos(el), np.sin(ang) * np.cos(el), np.sin(el)])
+            q[1 + i, 0:3] = c + (rb + rf - 0.0005) * d
+            q[1 + i, 3:7] = _random_quat(rng)
+    return s
+
+
 def select_worlds(scene, idx):
     """A copy of the scene restricted to the worlds in idx (any int sequence)."""
     idx = np.asarray(idx, np.int64)
