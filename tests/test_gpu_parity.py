@@ -3,6 +3,7 @@
 Per-step parity feeds both sides the same float32 state; tolerances and the
 guard band are stated in tests/parity.py.  All tests here need an MI355X.
 """
+import os
 import time
 
 import numpy as np
@@ -36,20 +37,34 @@ def applied_wrench(s, rng, lin_acc=2.0, ang_acc=20.0, shape=()):
     return t.reshape(shape + (nw, 6 * nb)).astype(np.float32)
 
 
-def _run_steps(torch, model, scene, nsteps, tau=None, record_every=1):
-    """Run nsteps on the GPU, keeping the input state and contact outputs of every
-    recorded step.  Returns list of (t, q_in, v_in, q_out, v_out, contacts)."""
-    q = tdev(scene["q0"])
-    v = tdev(scene["v0"])
-    recs = []
+def _oracle_states(scene, nsteps, tau=None, record_every=1):
+    """The oracle's own trajectory from the scene's initial state; returns
+    [(t, q_t, v_t)] at the recorded steps, cast to float32 (the shared input of
+    both sides).  tau: [nw][nv] held constant, or None."""
+    o = Oracle(scene)
+    q, v = scene["q0"].astype(np.float64), scene["v0"].astype(np.float64)
+    tau64 = None if tau is None else np.asarray(tau, np.float64)
+    threads = max(1, min(16, len(os.sched_getaffinity(0)), scene["nworld"]))
+    out = []
     for t in range(nsteps):
-        keep = (t % record_every == 0) or t == nsteps - 1
-        con = model.alloc_contacts() if keep else None
-        q1, v1 = model.step(q, v, tau=tau, contacts=con)
-        if keep:
-            recs.append((t, q.cpu().numpy(), v.cpu().numpy(), q1.cpu().numpy(), v1.cpu().numpy(),
-                         to_np(con)))
-        q, v = q1, v1
+        if (t % record_every == 0) or t == nsteps - 1:
+            out.append((t, q.astype(np.float32), v.astype(np.float32)))
+        if t + 1 < nsteps:
+            q, v = o.step_threads(q, v, threads, tau64)
+        if t % 200 == 199:
+            print(f"  oracle trajectory at step {t + 1}", flush=True)
+    return out
+
+
+def _run_steps(torch, model, scene, nsteps, tau=None, record_every=1):
+    """One GPU step from each recorded state of the oracle's trajectory (see
+    _oracle_states).  Returns list of (t, q_in, v_in, q_out, v_out, contacts)."""
+    tau_d = None if tau is None else tdev(tau)
+    recs = []
+    for t, qi, vi in _oracle_states(scene, nsteps, tau, record_every):
+        con = model.alloc_contacts()
+        q1, v1 = model.step(tdev(qi), tdev(vi), tau=tau_d, contacts=con)
+        recs.append((t, qi, vi, q1.cpu().numpy(), v1.cpu().numpy(), to_np(con)))
     torch.cuda.synchronize()
     return recs
 
@@ -77,15 +92,18 @@ def test_boxes_drop_drift_report(torch_cuda):
     from paper_2603_12185_amd import cfsim
     s = scenes.boxes_drop(seed=0)
     model = cfsim.Model(s)
-    recs = _run_steps(torch_cuda, model, s, 1000)
     o = Oracle(s)
     q, v = s["q0"].astype(np.float64), s["v0"].astype(np.float64)
+    qg, vg = tdev(s["q0"]), tdev(s["v0"])
     first_div, maxerr = None, []
-    for t, qi, vi, qg, vg, con in recs:
+    for t in range(1000):
+        con = model.alloc_contacts()
+        qg, vg = model.step(qg, vg, contacts=con)
+        c = to_np(con)
         q, v, out = o.step(q, v)
-        maxerr.append(float(np.abs(vg.astype(np.float64) - v).max()))
-        if first_div is None and (con["ncon"][0] != out["ncon"][0] or
-                                  (con["geom"][0, :out["ncon"][0]] != out["geom"][0, :out["ncon"][0]]).any()):
+        maxerr.append(float(np.abs(vg.cpu().numpy().astype(np.float64) - v).max()))
+        if first_div is None and (c["ncon"][0] != out["ncon"][0] or
+                                  (c["geom"][0, :out["ncon"][0]] != out["geom"][0, :out["ncon"][0]]).any()):
             first_div = t
     print(f"drift: max|dv| at steps 1/10/100/1000: {maxerr[0]:.2e} {maxerr[9]:.2e} "
           f"{maxerr[99]:.2e} {maxerr[-1]:.2e}; first contact-set divergence: {first_div}")
@@ -100,9 +118,8 @@ def test_mixed_shapes_parity(torch_cuda, condim):
     s = scenes.mixed_shapes(nworld=5, seed=condim, condim=condim)
     model = cfsim.Model(s)
     tau_np = applied_wrench(s, np.random.default_rng(condim))
-    tau = tdev(tau_np)
     print(f"case: mixed_shapes condim {condim}", flush=True)
-    recs = _run_steps(torch_cuda, model, s, 150, tau=tau, record_every=3)
+    recs = _run_steps(torch_cuda, model, s, 150, tau=tau_np, record_every=3)
     o = Oracle(s)
     stats = None
     for t, qi, vi, qg, vg, con in recs:
@@ -129,20 +146,31 @@ def test_dense_pile_small_parity(torch_cuda):
 
 
 def test_dense_pile_many_contacts_parity(torch_cuda):
-    """4 worlds x 128 spheres: more than 256 contacts per world (several
-    reduction chunks per world)."""
+    """4 worlds x 128 spheres packed in two overlapping layers on the ground:
+    more than 256 contacts per world (several compaction and reduction
+    chunks); the packed state and the oracle's next three states compared."""
     from paper_2603_12185_amd import cfsim
     s = scenes.dense_pile(nworld=4, nsphere=128, seed=3)
+    rng = np.random.default_rng(3)
+    q = s["q0"].reshape(4, 128, 7)
+    rad = s["geom_size"][:, 5:, 0]  # spheres follow the ground and four walls
+    for w in range(4):
+        for i in range(128):
+            layer, j = divmod(i, 64)
+            gx, gy = divmod(j, 8)
+            q[w, i, 0] = (gx - 3.5) * 0.06 + rng.uniform(-0.002, 0.002)
+            q[w, i, 1] = (gy - 3.5) * 0.06 + rng.uniform(-0.002, 0.002)
+            q[w, i, 2] = rad[w, i] + layer * 0.055
     model = cfsim.Model(s)
-    print("case: dense_pile 4x128", flush=True)
-    recs = _run_steps(torch_cuda, model, s, 700, record_every=175)
+    print("case: dense_pile 4x128 packed", flush=True)
+    recs = _run_steps(torch_cuda, model, s, 4)
     o = Oracle(s)
     stats = None
     for t, qi, vi, qg, vg, con in recs:
         stats = compare_step(s, o, qi, vi, None, qg, vg, con, stats=stats)
     last_ncon = recs[-1][5]["ncon"]
-    print("pile128 parity", stats, "ncon last", last_ncon)
-    assert last_ncon.max() > 256
+    print("pile128 parity", stats, "ncon", [r[5]["ncon"].tolist() for r in recs])
+    assert last_ncon.min() > 256
 
 
 def test_dense_pile_full_size_sampled(torch_cuda):
@@ -156,10 +184,17 @@ def test_dense_pile_full_size_sampled(torch_cuda):
     print("case: dense_pile 4096x64 full size", flush=True)
     q, v = tdev(s["q0"]), tdev(s["v0"])
     sample = [0, 1, 777, 2048, 4095]
-    o = Oracle(scenes.select_worlds(s, sample))
+    ss = scenes.select_worlds(s, sample)
+    o = Oracle(ss)
+    # the sampled worlds' inputs at steps 150 and 400 come from the oracle's own trajectory
+    ostates = {t: (qo, vo) for t, qo, vo in _oracle_states(ss, 401, record_every=50) if t in (150, 400)}
+    idx = torch.tensor(sample, device="cuda")
     stats = None
     for t in range(401):
-        con = model.alloc_contacts() if t in (150, 400) else None
+        con = None
+        if t in (150, 400):
+            con = model.alloc_contacts()
+            q[idx], v[idx] = tdev(ostates[t][0]), tdev(ostates[t][1])
         q1, v1 = model.step(q, v, contacts=con)
         if con is not None:
             c = to_np(con)
@@ -167,8 +202,7 @@ def test_dense_pile_full_size_sampled(torch_cuda):
             qn, vn = q1.cpu().numpy(), v1.cpu().numpy()
             assert np.isfinite(qn).all() and np.isfinite(vn).all()
             sub = {k: val[sample] for k, val in c.items()}
-            stats = compare_step(scenes.select_worlds(s, sample), o, q.cpu().numpy()[sample],
-                                 v.cpu().numpy()[sample], None, qn[sample], vn[sample], sub,
+            stats = compare_step(ss, o, ostates[t][0], ostates[t][1], None, qn[sample], vn[sample], sub,
                                  stats=stats)
             print(f"step {t}: mean contacts/world {c['ncon'].mean():.1f} max {c['ncon'].max()}")
         q, v = q1, v1
@@ -267,12 +301,15 @@ def test_rollout_matches_steps_and_oracle(torch_cuda, scene_fn):
     tau = tdev(applied_wrench(s, np.random.default_rng(0), shape=(T,))) if scene_fn == "mixed" else None
     qt, vt, ncon, worst = _rollout_vs_steps(torch, model, s, T, tau)
     assert worst < 1e-6, f"rollout vs step relative difference {worst:.2e}"
+    # against the oracle: two-step rollouts (persistent kernel) from states of
+    # the oracle's own trajectory, first step compared
     o = Oracle(s)
     stats = None
-    qn, vn = qt.cpu().numpy(), vt.cpu().numpy()
-    tn = None if tau is None else tau.cpu().numpy()
-    for t in range(0, T, max(1, T // 10)):
-        stats = compare_step(s, o, qn[t], vn[t], None if tn is None else tn[t], qn[t + 1], vn[t + 1], None,
+    tau0 = None if tau is None else tau[0].cpu().numpy()
+    for t, qi, vi in _oracle_states(s, T, tau0, record_every=max(1, T // 10)):
+        tau2 = None if tau is None else tdev(np.stack([tau0, tau0]))
+        q2, v2 = model.rollout(2, tdev(qi), tdev(vi), tau_seq=tau2)
+        stats = compare_step(s, o, qi, vi, tau0, q2[1].cpu().numpy(), v2[1].cpu().numpy(), None,
                              stats=stats)
     print("rollout", scene_fn, stats, "contacts", int(ncon.sum()), "worst vs step", worst)
 
