@@ -34,6 +34,12 @@
  *    pair types outside {plane-sphere, plane-capsule, plane-box, sphere-sphere}.
  *  - Degenerate sphere-sphere (centres closer than 1e-12) uses n = +z; a
  *    contact whose two traces sum to 0 is skipped.
+ *  - Exact diagonal impedance (impedance = 1, the alternative the paper states
+ *    before its heuristic, Sec. III.B): per facet f, K h + D equals
+ *    (1/h) (J~_f M^-1 J~_f^T)^-1, split between K and D in the ratio
+ *    k_user : d_user / h of Eq. k_d_setting, so the scalar A of the impulse
+ *    becomes A_f = 1 / ((k_user h + d_user) g_f), g_f = J~_f M^-1 J~_f^T; r(|phi|)
+ *    does not enter.  With k_user h + d_user = 0 or g_f = 0 the impulse is 0.
  *  - Integration: semi-implicit Euler; free-joint orientation is updated by the
  *    exact exponential of h*omega (world frame, left-multiplied) then
  *    normalised; a state quaternion denotes the rotation of its normalised value.
@@ -137,6 +143,7 @@ int cfo_create(const cfo_desc *d, cfo_model **out, char *err, int errlen) {
   if (!(d->condim == 1 || d->condim == 3 || d->condim == 4 || d->condim == 6))
     return fail(err, errlen, "condim must be 1, 3, 4 or 6");
   if (!(d->h > 0)) return fail(err, errlen, "h must be > 0");
+  if (d->impedance != 0 && d->impedance != 1) return fail(err, errlen, "impedance must be 0 or 1");
   if (!(d->k_user >= 0) || !(d->d_user >= 0)) return fail(err, errlen, "k_user, d_user must be >= 0");
   const double *si = d->solimp;
   if (!(si[0] > 0 && si[0] <= si[1] && si[1] < 1)) return fail(err, errlen, "need 0 < r_min <= r_max < 1");
@@ -755,6 +762,18 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
       for (int i = 0; i < nv; i++) s += Jf[i] * vs[i];
       double arg = -(kk * h + dd) * s - kk * C->phi;
       double lh = trs > 0 && arg > 0 ? A * arg : 0.0;
+      if (d->impedance == 1) {
+        /* exact diagonal impedance: K h + D = (1/h) (J~_f M^-1 J~_f^T)^-1 per facet,
+           split between K and D in the ratio k_user : d_user/h, so that
+           A_f = 1 / ((k h + d) g_f) with g_f = J~_f M^-1 J~_f^T = |L^-1 J~_f^T|^2 */
+        double *y = rows + 15 * nv;
+        memcpy(y, Jf, sizeof(double) * nv);
+        fwd_sub(M, nv, y);
+        double g = 0;
+        for (int i = 0; i < nv; i++) g += y[i] * y[i];
+        double aa = kk * h + dd;
+        lh = (g > 0 && aa > 0 && arg > 0) ? arg / (aa * g) : 0.0;
+      }
       lam[fi] = lh;
       for (int i = 0; i < nv; i++) p[i] += Jf[i] * lh;
     }

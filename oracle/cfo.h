@@ -50,6 +50,7 @@ typedef struct {
   const double *geom_size, *geom_pos;              /* [nworld][ngeom][3]           */
   const double *geom_quat, *geom_friction;         /* [nworld][ngeom][4], [..][3]  */
   double h, gravity[3], k_user, d_user, solimp[5], margin;
+  int impedance;                                   /* 0: heuristic M(phi); 1: exact diagonal */
 } cfo_desc;
 
 typedef struct cfo_model cfo_model;

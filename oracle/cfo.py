@@ -34,6 +34,7 @@ class _Desc(C.Structure):
         ("geom_size", _dp), ("geom_pos", _dp), ("geom_quat", _dp), ("geom_friction", _dp),
         ("h", C.c_double), ("gravity", C.c_double * 3), ("k_user", C.c_double),
         ("d_user", C.c_double), ("solimp", C.c_double * 5), ("margin", C.c_double),
+        ("impedance", C.c_int),
     ]
 
 
@@ -129,6 +130,7 @@ class Oracle:
         d.k_user, d.d_user = float(scene["k_user"]), float(scene["d_user"])
         d.solimp[:] = [float(x) for x in scene["solimp"]]
         d.margin = float(scene["margin"])
+        d.impedance = int(scene.get("impedance", 0))
         self._keep = keep
         h = C.c_void_p()
         err = C.create_string_buffer(256)

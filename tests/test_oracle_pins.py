@@ -700,3 +700,85 @@ def test_invalid_descriptors_rejected():
     bad["solimp"] = np.array([0.95, 0.9, 0.001, 0.5, 2.0])
     with pytest.raises(OracleError):
         Oracle(bad)
+
+
+# ---------------------------------------------------------------- exact diagonal impedance
+def test_exact_impedance_normal_row_single_facet():
+    """Exact diagonal impedance (Sec. III.B, K h + D = (1/h)(J~ M^-1 J~^T)^-1 per
+    facet): a frictionless sphere on a plane with one facet (condim 1) has
+    J~ M^-1 J~^T = 1/m (the row passes through the centre), so an active
+    contact leaves the normal velocity at exactly -k phi / (k h + d), whatever
+    the incoming velocity."""
+    for vz in (-0.3, -0.01, 0.0, 0.002):
+        s = scenes.sphere_on_plane(radius=0.05, mass=0.7, mu=(0.0, 0.0, 0.0), condim=1)
+        s["impedance"] = 1
+        q = s["q0"].astype(np.float64).copy()
+        v = s["v0"].astype(np.float64).copy()
+        depth = 0.002
+        q[0, 2] = 0.05 - depth
+        v[0, 2] = vz
+        v[0, 3:6] = (1.0, -2.0, 0.5)  # spin does not enter the normal row
+        o = Oracle(s)
+        q1, v1, out = o.step(q, v)
+        a = s["k_user"] * s["h"] + s["d_user"]
+        phi = float(out["dist"][0, 0])
+        np.testing.assert_allclose(phi, q[0, 2] - float(s["geom_size"][0, 1, 0]), rtol=1e-12)
+        np.testing.assert_allclose(v1[0, 2], -s["k_user"] * phi / a, rtol=1e-12)
+        np.testing.assert_allclose(v1[0, 3:6], v[0, 3:6], rtol=1e-12)
+
+
+def test_exact_impedance_stick_decay_point_mass():
+    """Point mass on three slide joints, four tangential facets of rows n -/+ mu t:
+    each has J~ M^-1 J~^T = (1 + mu^2)/m, so with every facet active the
+    tangential velocity contracts by exactly (1 - mu^2)/(1 + mu^2) per step,
+    independent of k_user and d_user and of the sliding direction."""
+    mu = 0.5
+    for k, d in ((0.1, 0.001), (0.5, 0.005)):
+        for ang in (0.0, 0.7):
+            s = scenes.point_mass(mu=mu, k_user=k, d_user=d)
+            s["impedance"] = 1
+            q = s["q0"].astype(np.float64).copy()
+            v = s["v0"].astype(np.float64).copy()
+            q[0, 2] = s["geom_size"][0, 1, 0] - 0.003
+            u0 = 0.01
+            v[0, 0:2] = (u0 * math.cos(ang), u0 * math.sin(ang))
+            o = Oracle(s)
+            _, v1, out = o.step(q, v)
+            assert (out["impulse"][0, 0] > 0).all()
+            mu32 = float(s["geom_friction"][0, 1, 0])
+            fac = (1 - mu32 ** 2) / (1 + mu32 ** 2)
+            np.testing.assert_allclose(v1[0, 0:2], fac * v[0, 0:2], rtol=1e-11, atol=1e-16)
+
+
+def test_exact_impedance_sphere_tangential_row():
+    """Free solid sphere on a plane (I = 0.4 m R^2): a tangential facet row
+    (n - mu d.t at the contact point, the middle of the overlap, lever arm
+    -(R + phi/2) n) gives J~ M^-1 J~^T = (1 + mu^2)/m + mu^2 (R + phi/2)^2 / I
+    (= (1 + 3.5 mu^2)/m at phi = 0), so each facet impulse is
+    max(-(k h + d) s - k phi, 0) / ((k h + d) J~ M^-1 J~^T); s is read from the
+    smooth velocity in the contact's own frame."""
+    s = scenes.sphere_on_plane(radius=0.04, mass=0.3, mu=(0.6, 0.0, 0.0), condim=3)
+    s["impedance"] = 1
+    q = s["q0"].astype(np.float64).copy()
+    v = s["v0"].astype(np.float64).copy()
+    q[0, 2] = 0.04 - 0.001
+    v[0, 0:6] = (0.02, -0.01, -0.05, 0.3, 0.2, -1.0)
+    o = Oracle(s)
+    _, _, out = o.step(q, v)
+    m, R = float(s["body_mass"][0, 0]), float(s["geom_size"][0, 1, 0])
+    inertia = float(s["body_inertia"][0, 0, 0])
+    mu = float(s["geom_friction"][0, 1, 0])
+    np.testing.assert_allclose((1 + mu * mu) / m + mu * mu * R * R / inertia, (1 + 3.5 * mu * mu) / m,
+                               rtol=1e-6)
+    phi = float(out["dist"][0, 0])
+    arm = R + 0.5 * phi
+    g = (1 + mu * mu) / m + mu * mu * arm * arm / inertia
+    vs = out["v_smooth"][0]
+    n, t1, t2 = out["frame"][0, 0, 0:3], out["frame"][0, 0, 3:6], out["frame"][0, 0, 6:9]
+    r = -arm * n
+    vp = vs[0:3] + np.cross(vs[3:6], r)  # contact point velocity, plane static
+    a = s["k_user"] * s["h"] + s["d_user"]
+    for f, (d1, d2) in enumerate(((1, 0), (0, 1), (-1, 0), (0, -1))):
+        sf = n @ vp - mu * (d1 * (t1 @ vp) + d2 * (t2 @ vp))
+        lam = max(-a * sf - s["k_user"] * phi, 0.0) / (a * g)
+        np.testing.assert_allclose(out["impulse"][0, 0, f], lam, rtol=1e-10)
