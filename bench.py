@@ -161,7 +161,7 @@ def main():
     if os.path.exists(tfile):
         from paper_2603_12185_amd import build as _b
         import hashlib
-        src = b"".join(open(os.path.join(_b.CSRC, s), "rb").read() for s in _b.SOURCES)
+        src = b"".join(open(os.path.join(_b.CSRC, s), "rb").read() for s in sorted(os.listdir(_b.CSRC)))
         rec = json.load(open(tfile))
         if rec.get("source_sha256") == hashlib.sha256(src).hexdigest() and dom in rec.get("kernels", {}):
             traffic = rec["kernels"][dom]["bytes_per_launch"]

@@ -74,6 +74,7 @@ enum {
 
 enum { CF_PLANE = 0, CF_SPHERE = 1, CF_CAPSULE = 2, CF_BOX = 3 };
 enum { CF_JNT_FREE = 0, CF_JNT_HINGE = 1, CF_JNT_SLIDE = 2 };
+enum { CF_IMPEDANCE_HEURISTIC = 0, CF_IMPEDANCE_DIAGONAL = 1 };
 
 /* Model description (host memory, copied at create).  nworld worlds share the
  * tree and geom types; masses, inertias and geom data may differ per world.
@@ -170,8 +171,19 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
 cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
                      const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj);
 
+/* Impedance of the facet impulses (Sec. III.B).  CF_IMPEDANCE_HEURISTIC (the
+ * default): A = r(|phi|)/(1 - r(|phi|)) / (tr_a + tr_b), one scalar per contact
+ * (Eqs. k_d_setting, r_scaling).  CF_IMPEDANCE_DIAGONAL: the diagonal form the
+ * paper gives before its heuristic, K h + D = (1/h) (J~_f M^-1 J~_f^T)^-1 per
+ * facet f, split between K and D in the ratio k_user : d_user / h, so
+ * lambda_f h = max(-(k_user h + d_user) s_f - k_user phi, 0) / ((k_user h + d_user) g_f)
+ * with g_f = J~_f M^-1 J~_f^T (0 when k_user h + d_user = 0).  The diagonal form
+ * is available for models of free bodies only (else CF_E_UNSUPPORTED), and
+ * cf_step_backward does not cover it. */
+cf_status cf_model_set_impedance(cf_model *m, int32_t mode);
+
 /* Workgroup size (64, 128 or 256 threads, one world per workgroup) of the
- * collision, the resolution and the rollout kernel (defaults 256 each);
+ * collision, the resolution and the rollout kernel (defaults 64, 256, 256);
  * results do not depend on the choice (same arithmetic, same summation order
  * within a wave; the per-body sums are ordered by wave, so the last bits of
  * v+ may differ between sizes). */

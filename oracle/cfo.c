@@ -741,7 +741,7 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
     /* M(phi) scalar: r/(1-r) / (tr_a + tr_b) */
     double A = trs > 0 ? cfo_impedance_ratio(m, C->phi) / trs : 0.0;
     static const double dir4[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
-    double lam[10];
+    double lam[10], gain[10];
     for (int fi = 0; fi < nf; fi++) {
       /* facet row J~ = J_n - mu_s d^T J_s */
       for (int i = 0; i < nv; i++) {
@@ -762,6 +762,7 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
       for (int i = 0; i < nv; i++) s += Jf[i] * vs[i];
       double arg = -(kk * h + dd) * s - kk * C->phi;
       double lh = trs > 0 && arg > 0 ? A * arg : 0.0;
+      gain[fi] = trs > 0 ? A : 0.0;
       if (d->impedance == 1) {
         /* exact diagonal impedance: K h + D = (1/h) (J~_f M^-1 J~_f^T)^-1 per facet,
            split between K and D in the ratio k_user : d_user/h, so that
@@ -772,7 +773,8 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
         double g = 0;
         for (int i = 0; i < nv; i++) g += y[i] * y[i];
         double aa = kk * h + dd;
-        lh = (g > 0 && aa > 0 && arg > 0) ? arg / (aa * g) : 0.0;
+        gain[fi] = (g > 0 && aa > 0) ? 1.0 / (aa * g) : 0.0;
+        lh = arg > 0 ? gain[fi] * arg : 0.0;
       }
       lam[fi] = lh;
       for (int i = 0; i < nv; i++) p[i] += Jf[i] * lh;
@@ -789,6 +791,7 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
         memcpy(out->frame + 9 * ci + 6, t2, 3 * sizeof(double));
       }
       if (out->impulse) memcpy(out->impulse + (size_t)nf * ci, lam, sizeof(double) * nf);
+      if (out->facet_gain) memcpy(out->facet_gain + (size_t)nf * ci, gain, sizeof(double) * nf);
     }
   }
 

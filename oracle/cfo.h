@@ -68,6 +68,7 @@ typedef struct {
   double *v_smooth;                 /* [nworld][nv]                               */
   double *gen_impulse;              /* [nworld][nv] p = sum J~^T lambda h         */
   double *trace;                    /* [nworld][nbody] tr(J_b M^-1 J_b^T)          */
+  double *facet_gain;               /* [..][nfacet] A_f with lambda_f h = A_f max(arg_f, 0) */
 } cfo_out;
 
 int  cfo_create(const cfo_desc *d, cfo_model **out, char *err, int errlen);

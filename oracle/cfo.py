@@ -43,7 +43,7 @@ class _Out(C.Structure):
         ("ncon", _ip), ("overflow", _ip), ("geom", _ip), ("sub", _ip),
         ("dist", _dp), ("pos", _dp), ("frame", _dp), ("impulse", _dp),
         ("guard_phi", _dp), ("guard_frame", _dp), ("v_smooth", _dp), ("gen_impulse", _dp),
-        ("trace", _dp),
+        ("trace", _dp), ("facet_gain", _dp),
     ]
 
 
@@ -171,12 +171,13 @@ class Oracle:
                 dist=np.zeros((nw, cm)), pos=np.zeros((nw, cm, 3)), frame=np.zeros((nw, cm, 9)),
                 impulse=np.zeros((nw, cm, nf)), guard_phi=np.full(nw, np.inf),
                 guard_frame=np.full(nw, np.inf), v_smooth=np.zeros((nw, nv)),
-                gen_impulse=np.zeros((nw, nv)), trace=np.zeros((nw, self.nbody)))
+                gen_impulse=np.zeros((nw, nv)), trace=np.zeros((nw, self.nbody)),
+                facet_gain=np.zeros((nw, cm, nf)))
             o = _Out()
             for k in ("ncon", "overflow", "geom", "sub"):
                 setattr(o, k, _i(out[k]))
             for k in ("dist", "pos", "frame", "impulse", "guard_phi", "guard_frame", "v_smooth",
-                      "gen_impulse", "trace"):
+                      "gen_impulse", "trace", "facet_gain"):
                 setattr(o, k, _d(out[k]))
         if worlds is None:
             ranges = [(0, nw)]

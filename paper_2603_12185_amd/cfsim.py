@@ -61,6 +61,7 @@ SIGNATURES = {
     "cf_rollout": ([C.c_void_p, C.c_void_p, C.c_int32, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
     "cf_step_backward": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
     "cf_model_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
+    "cf_model_set_impedance": ([C.c_void_p, C.c_int32], C.c_int32),
     "cf_model_get_launch": ([C.c_void_p, _ip, _ip, _ip, _ip], C.c_int32),
     "cf_model_autotune": ([C.c_void_p, C.c_void_p, _fp, _fp, C.c_int32, C.POINTER(C.c_float),
                            C.POINTER(C.c_float)], C.c_int32),
@@ -145,6 +146,8 @@ class Model:
         self.nworld = int(scene["nworld"])
         self.ncon_max = int(scene["ncon_max"])
         self.nbody, self.ngeom = int(scene["nbody"]), int(scene["ngeom"])
+        if int(scene.get("impedance", 0)):
+            self.set_impedance(int(scene["impedance"]))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -247,6 +250,10 @@ class Model:
         return q_traj, v_traj
 
     # ------------------------------------------------------------ launch shape
+    def set_impedance(self, mode):
+        """0: heuristic impedance (default); 1: exact diagonal impedance per facet."""
+        _check(load().cf_model_set_impedance(self._h, int(mode)))
+
     def set_launch(self, collide_block, resolve_block, rollout_block=None):
         if rollout_block is None:
             rollout_block = self.get_launch()[2]

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/cfsim.h"
@@ -35,6 +36,7 @@ struct cf_model {
   int dev = 0;
   int nw = 0, nb = 0, ng = 0, nq = 0, nv = 0, ncon_max = 0, condim = 3, nf = 4, nbits = 1;
   int nslot = 0;
+  int nslot_pre = 0, sph0 = 0, nsph = 0;  // sphere block of the narrow phase (see below)
   cf::Params p{};
   // device constants
   uint32_t *d_slots = nullptr;
@@ -42,7 +44,7 @@ struct cf_model {
   cf::BodyC *d_body = nullptr;
   cf::SubTree *d_sub = nullptr;
   int norient = 0, nsub = 0, art_floats = 0;
-  int block_collide = 256, block_resolve = 256, block_rollout = 256;
+  int block_collide = 64, block_resolve = 256, block_rollout = 256;
   size_t lds_rollout = 0;
   int block_backward = 0;  // 0: the adjoint's LDS does not fit any workgroup size
   size_t lds_backward = 0;
@@ -274,6 +276,27 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       }
     if (oriented) gorient[g] = m->norient++;
   }
+  // Sphere block: the longest run of trailing geoms that are spheres centred on
+  // free bodies (or static).  When the slot table ends with exactly their
+  // pairs of different bodies in row-major order, the narrow phase tests those
+  // rows in bulk instead of slot by slot.
+  {
+    m->nslot_pre = m->nslot;
+    int g0 = ng;
+    while (g0 > 0 && d->geom_type[g0 - 1] == CF_SPHERE && gorient[g0 - 1] < 0) --g0;
+    const int S = ng - g0;
+    if (S >= 2 && S <= 256) {
+      std::vector<uint32_t> tail;
+      for (int i = g0; i < ng; ++i)
+        for (int j = i + 1; j < ng; ++j)
+          if (d->geom_body[i] != d->geom_body[j]) tail.push_back(cf::slot_pack(i, j, 0, cf::kSphereSphere));
+      if (tail.size() <= slots.size() && std::equal(tail.begin(), tail.end(), slots.end() - tail.size())) {
+        m->sph0 = g0;
+        m->nsph = S;
+        m->nslot_pre = m->nslot - (int)tail.size();
+      }
+    }
+  }
   m->lds_collide = cf::collide_lds_bytes(m->nq, nb, ng, m->norient, m->nsub);
   m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, 256, m->nsub, m->art_floats);
   if (m->lds_collide > kLdsLimit || m->lds_resolve > kLdsLimit) {
@@ -380,6 +403,7 @@ static cf::CollideArgs collide_args(const cf_model *m) {
   ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
   ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
   ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
+  ca.nslot_pre = m->nslot_pre; ca.sph0 = m->sph0; ca.nsph = m->nsph;
   return ca;
 }
 
@@ -463,6 +487,8 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
     return set_err(CF_E_INVALID_ARG, "gq/gv may alias gq_out/gv_out only exactly; no other overlap");
   if (m->nsub > 0)
     return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers models of free bodies only");
+  if (m->p.imp_diag)
+    return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers the heuristic impedance only");
   if (!m->block_backward) return set_err(CF_E_UNSUPPORTED, "world too large for the adjoint's LDS");
   hipStream_t s = (hipStream_t)stream;
   cf::CollideArgs ca = collide_args(m);
@@ -511,6 +537,16 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
                            q_traj + (t + 1) * sq, v_traj + (t + 1) * sv, ncon_traj ? &c : nullptr);
     if (st != CF_OK) return st;
   }
+  return CF_OK;
+}
+
+cf_status cf_model_set_impedance(cf_model *m, int32_t mode) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (mode != CF_IMPEDANCE_HEURISTIC && mode != CF_IMPEDANCE_DIAGONAL)
+    return set_err(CF_E_INVALID_ARG, "impedance mode must be CF_IMPEDANCE_HEURISTIC or CF_IMPEDANCE_DIAGONAL");
+  if (mode == CF_IMPEDANCE_DIAGONAL && m->nsub > 0)
+    return set_err(CF_E_UNSUPPORTED, "the diagonal impedance covers models of free bodies only");
+  m->p.imp_diag = mode == CF_IMPEDANCE_DIAGONAL ? 1 : 0;
   return CF_OK;
 }
 

@@ -52,6 +52,7 @@ struct Params {
   float r_min, r_max, width, mid, power;
   float inv_width, inv_mid, inv_1mmid;  // 1/width, 1/mid, 1/(1 - mid)
   int power2;                           // power == 2: gamma uses squares
+  int imp_diag;                         // 1: exact diagonal impedance per facet
 };
 
 // Collision kernel: one workgroup per world.
@@ -70,6 +71,8 @@ struct CollideArgs {
   int *ncon, *overflow;         // [nw] model workspace
   int *ncon_out, *overflow_out; // [nw] caller copies or null
   int nq, nb, ng, norient, nslot, ncon_max, nsub;
+  int nslot_pre;                // slots tested one by one (all of them when nsph = 0)
+  int sph0, nsph;               // sphere block: geoms [sph0, sph0 + nsph), pairs tested row-wise
   int gpos_ws, gquat_ws;        // world stride in elements (0 = shared by all worlds)
   float margin;
 };

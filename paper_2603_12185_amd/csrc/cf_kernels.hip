@@ -63,6 +63,37 @@ __device__ inline int block_scan(bool flag, int *total, int *wcnt, int parity) {
   return off + pre;
 }
 
+// Exclusive prefix of the integers x over the workgroup in thread order;
+// *total gets their sum.  wsum: shared [BS/64].  Ends with a barrier when
+// BS > 64 (wsum may be reused at once).
+template <int BS>
+__device__ inline int block_scan_int(int x, int *total, int *wsum) {
+  constexpr int NW = BS / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = x;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
+  }
+  if (NW == 1) {
+    *total = __shfl(inc, 63);
+    return inc - x;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int c = wsum[i];
+    base += i < wave ? c : 0;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - x;
+}
+
 // Maximum over the workgroup (every thread gets it); wmax: shared [BS/64].
 template <int BS>
 __device__ inline float block_max(float x, float *wmax) {
@@ -74,6 +105,29 @@ __device__ inline float block_max(float x, float *wmax) {
   for (int i = 1; i < BS / 64; ++i) m = fmaxf(m, wmax[i]);
   return m;
 }
+
+// Copy of a row of n floats from global memory to LDS with every load of the
+// first K * BS elements issued before any is waited for (a plain strided loop
+// would wait for each load before issuing the next).
+template <int BS, int K>
+struct RowStage {
+  float r[K];
+  __device__ inline void load(const float *src, int n) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = threadIdx.x + k * BS;
+      r[k] = i < n ? src[i] : 0.f;
+    }
+  }
+  __device__ inline void store(float *dst, const float *src, int n) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = threadIdx.x + k * BS;
+      if (i < n) dst[i] = r[k];
+    }
+    for (int i = threadIdx.x + K * BS; i < n; i += BS) dst[i] = src[i];
+  }
+};
 
 // ---------------------------------------------------------------- helpers
 struct V3 { float x, y, z; };
@@ -491,29 +545,54 @@ __device__ inline double slot_eval(uint32_t s, const float4 *Gs, const int *go, 
 
 // LDS scratch of the narrow phase of one world (after its q row).
 size_t collide_region_bytes(int nb, int ng, int norient, int nsub) {
-  return sizeof(float4) * (size_t)ng + sizeof(int) * (size_t)pad4(ng) +
+  return sizeof(float4) * (size_t)ng + 2 * sizeof(int) * (size_t)pad4(ng) +
          (sizeof(Pose<float>) + sizeof(Pose<double>)) * (size_t)norient + sizeof(uint32_t) * kCandCap +
          (nsub > 0 ? sizeof(double) * 16 * (size_t)nb : 0);
+}
+
+// Per-geom inputs of the narrow phase (loaded ahead of the q row's barrier).
+struct GeomIn {
+  int b, o;          // body (-1 static), index among oriented geoms (-1: plain sphere)
+  float4 gp, gd, gq; // offset in the body frame, (size, mu_t), orientation in the body frame
+};
+
+__device__ inline GeomIn geom_in(const CollideArgs &a, int w, int g) {
+  GeomIn x;
+  x.b = a.gbody[g];
+  x.o = a.gorient[g];
+  x.gp = a.gpos[(size_t)w * a.gpos_ws + g];
+  x.gd = a.gdat[(size_t)w * a.ng + g];
+  x.gq = a.gquat[(size_t)w * a.gquat_ws + g];
+  return x;
 }
 
 // Narrow phase of world w from its q row `sq` (LDS).  Writes the first `cap`
 // contacts of the canonical order to outn/outp (global or LDS) and returns the
 // number found.  `reg` is LDS scratch of collide_region_bytes(); `nxt` is the
-// caller's prefetch of slots[threadIdx.x].  Ends with a workgroup barrier.
+// caller's prefetch of slots[threadIdx.x]; `pre`, when given, the caller's
+// prefetch of geom threadIdx.x (valid when threadIdx.x < ng).  Ends with a
+// workgroup barrier.
 template <int BS, bool ART>
 __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float4 *reg, float4 *outn,
-                             float4 *outp, int cap, uint32_t nxt) {
+                             float4 *outp, int cap, uint32_t nxt, const GeomIn *pre = nullptr) {
   constexpr int NW = BS / 64;
   const int tid = threadIdx.x;
   Pose<double> *Od = reinterpret_cast<Pose<double> *>(reg);
   Pose<float> *Of = reinterpret_cast<Pose<float> *>(Od + a.norient);
   float4 *Gs = reinterpret_cast<float4 *>(Of + a.norient);
   int *go = reinterpret_cast<int *>(Gs + a.ng);
-  uint32_t *cand = reinterpret_cast<uint32_t *>(go + pad4(a.ng));
+  int *gbd = go + pad4(a.ng);  // body of each geom (-1 static)
+  uint32_t *cand = reinterpret_cast<uint32_t *>(gbd + pad4(a.ng));
   double *borg = reinterpret_cast<double *>(cand + kCandCap);  // [nb][4] articulated bodies
   double *brot = borg + 4 * a.nb;                              // [nb][12]
   __shared__ int wcnt[2 * NW];
   __shared__ float wmax[NW];
+
+  // slot words of the next three chunks, in flight during the set-up below
+  const int npre = a.nslot_pre;
+  uint32_t nxt2 = tid + BS < npre ? a.slots[tid + BS] : 0u;
+  uint32_t nxt3 = tid + 2 * BS < npre ? a.slots[tid + 2 * BS] : 0u;
+  uint32_t nxt4 = tid + 3 * BS < npre ? a.slots[tid + 3 * BS] : 0u;
 
   if (ART) {  // forward kinematics of articulated subtrees, float64
     for (int si = tid; si < a.nsub; si += BS) {
@@ -525,21 +604,21 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
 
   // geom world poses; oriented geoms also get float64 and float32 pose records
   for (int g = tid; g < a.ng; g += BS) {
-    const int b = a.gbody[g], o = a.gorient[g];
-    const float4 gp = a.gpos[(size_t)w * a.gpos_ws + g];
-    const float4 gd = a.gdat[(size_t)w * a.ng + g];
+    const GeomIn gi = (pre && g == tid) ? *pre : geom_in(a, w, g);
+    const int b = gi.b, o = gi.o;
+    const float4 gp = gi.gp, gd = gi.gd, gq = gi.gq;
     go[g] = o;
+    gbd[g] = b;
     if (o < 0) {  // sphere at the origin of a free body (or static)
-      const float *qb = b >= 0 ? sq + a.body[b].qadr : nullptr;
+      const float *qb = b >= 0 ? sq + (ART ? a.body[b].qadr : 7 * b) : nullptr;
       Gs[g] = b >= 0 ? make_float4(qb[0], qb[1], qb[2], gd.x) : make_float4(gp.x, gp.y, gp.z, gd.x);
       continue;
     }
-    const float4 gq = a.gquat[(size_t)w * a.gquat_ws + g];
     double bp[3] = {0.0, 0.0, 0.0}, br[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0}, gr[9];
     if (b >= 0) {
-      const BodyC bc = a.body[b];
+      const BodyC bc = ART ? a.body[b] : BodyC{};
       if (!ART || bc.fast) {
-        const float *qb = sq + bc.qadr;
+        const float *qb = sq + (ART ? bc.qadr : 7 * b);
         bp[0] = qb[0]; bp[1] = qb[1]; bp[2] = qb[2];
         quat_to_rot<double>(qb[3], qb[4], qb[5], qb[6], br);
       } else {
@@ -626,13 +705,17 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     ncand = 0;
   };
 
-  // Pass 1 over all slots: float32 test, ordered candidate list.
-  for (int base = 0; base < a.nslot; base += BS) {
+  // Pass 1 over the slots before the sphere block: float32 test, ordered
+  // candidate list; slot words are loaded four chunks ahead.
+  for (int base = 0; base < npre; base += BS) {
     if (ncand + BS > kCandCap) flush();
     const int s = base + tid;
     const uint32_t sl = nxt;
-    nxt = s + BS < a.nslot ? a.slots[s + BS] : 0u;
-    const bool c = s < a.nslot && slot_candidate(sl, Gs, go, Of, a.margin + band);
+    nxt = nxt2;
+    nxt2 = nxt3;
+    nxt3 = nxt4;
+    nxt4 = s + 4 * BS < npre ? a.slots[s + 4 * BS] : 0u;
+    const bool c = s < npre && slot_candidate(sl, Gs, go, Of, a.margin + band);
     int tot;
     const int idx = block_scan<BS>(c, &tot, wcnt, par);
     par ^= 1;
@@ -641,6 +724,77 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
   }
   if (ncand > 0) flush();
   else __syncthreads();
+
+  // Sphere block: the last nsph geoms are spheres centred on free bodies (or
+  // static), and every pair of them on different bodies is a slot, in row-major
+  // order after all other slots.  Lane per row: the columns j > i are tested
+  // against LDS records read at one address by every lane, the hits form a
+  // bit mask per row, rows are placed by a prefix sum of their counts, and the
+  // hits are evaluated densely (float32: the centres are exact state values).
+  // A pair is a contact when |c_b - c_a|^2 < (r_a + r_b + margin)^2.
+  if (a.nsph > 0) {
+    __shared__ int wsum[NW];
+    const int g0 = a.sph0, S = a.nsph, nwd = (S + 63) >> 6;
+    for (int r0 = 0; r0 < S; r0 += BS) {
+      const int i = r0 + tid;
+      const bool row = i < S;
+      const float4 Gi = row ? Gs[g0 + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int bi = row ? gbd[g0 + i] : -2;
+      unsigned long long m[4] = {0ull, 0ull, 0ull, 0ull};
+      int cnt = 0;
+#pragma unroll
+      for (int cw = 0; cw < 4; ++cw) {
+        if (cw >= nwd) break;
+        const int j0 = cw * 64;
+        const int jlo = max(j0, r0 + 1), jhi = min(j0 + 64, S);
+        unsigned long long mw = 0ull;
+        for (int j = jlo; j < jhi; ++j) {
+          const float4 Gj = Gs[g0 + j];
+          const int bj = gbd[g0 + j];
+          const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
+          const float R = Gi.w + Gj.w + a.margin;
+          const bool hit = j > i && bi != bj && R > 0.f && dx * dx + dy * dy + dz * dz < R * R;
+          mw |= (unsigned long long)hit << (j - j0);
+        }
+        m[cw] = mw;
+        cnt += __popcll(mw);
+      }
+      int tot;
+      const int pre = block_scan_int<BS>(cnt, &tot, wsum);
+      for (int lo = 0; lo < tot; lo += kCandCap) {
+        int k = pre;
+#pragma unroll
+        for (int cw = 0; cw < 4; ++cw) {
+          if (cw >= nwd) break;
+          for (unsigned long long mw = m[cw]; mw; mw &= mw - 1, ++k) {
+            if (k >= lo && k < lo + kCandCap) {
+              const int j = cw * 64 + __ffsll((unsigned long long)mw) - 1;
+              cand[k - lo] = slot_pack(g0 + i, g0 + j, 0, kSphereSphere);
+            }
+          }
+        }
+        __syncthreads();
+        const int nwin = min(kCandCap, tot - lo);
+        for (int cb = 0; cb < nwin; cb += BS) {
+          const int idx = cb + tid;
+          const int pos = running + lo + idx;
+          if (idx < nwin && pos < cap) {
+            const uint32_t sl = cand[idx];
+            const float4 A = Gs[slot_ga(sl)], B = Gs[slot_gb(sl)];
+            const V3 d = v3(B.x - A.x, B.y - A.y, B.z - A.z);
+            const float dist = sqrtf(dot(d, d));
+            const V3 n = dist >= 1e-12f ? (1.0f / dist) * d : v3(0.f, 0.f, 1.f);
+            const float phi = dist - A.w - B.w;
+            const float kk = A.w + 0.5f * phi;
+            outn[pos] = make_float4(n.x, n.y, n.z, phi);
+            outp[pos] = make_float4(A.x + kk * n.x, A.y + kk * n.y, A.z + kk * n.z, __uint_as_float(sl));
+          }
+        }
+        __syncthreads();
+      }
+      running += tot;
+    }
+  }
   (void)NW;
   return running;
 }
@@ -650,13 +804,19 @@ __global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
   extern __shared__ float4 lds[];
   const int w = blockIdx.x, tid = threadIdx.x;
   float *sq = reinterpret_cast<float *>(lds);
-  const uint32_t nxt = tid < a.nslot ? a.slots[tid] : 0u;  // prefetch of the first chunk
+  constexpr int K = 512 / BS;
+  // issue the independent global loads (slots, geoms, q row) before the first wait
+  const uint32_t nxt = tid < a.nslot_pre ? a.slots[tid] : 0u;  // prefetch of the first chunk
+  GeomIn pre{};
+  if (tid < a.ng) pre = geom_in(a, w, tid);
   const float *qw = a.q + (size_t)w * a.nq;
-  for (int i = tid; i < a.nq; i += BS) sq[i] = qw[i];
+  RowStage<BS, K> rq;
+  rq.load(qw, a.nq);
+  rq.store(sq, qw, a.nq);
   __syncthreads();
   const size_t cbase = (size_t)w * a.ncon_max;
   const int found = collide_world<BS, ART>(a, w, sq, lds + pad4(a.nq) / 4, a.cnp + cbase, a.cpos + cbase,
-                                           a.ncon_max, nxt);
+                                           a.ncon_max, nxt, &pre);
   if (tid == 0) {
     const int kept = found < a.ncon_max ? found : a.ncon_max;
     a.ncon[w] = kept;
@@ -733,6 +893,78 @@ __device__ inline ResolveRegion resolve_region(float4 *reg, int nb, int ng) {
   return r;
 }
 
+// x^T S y for the symmetric inverse world inertia S stored as (xx yy zz xy | xz yz).
+__device__ inline float inv_inertia_form(float4 I0, float4 I1, V3 x, V3 y) {
+  const V3 Sy = v3(I0.x * y.x + I0.w * y.y + I1.x * y.z, I0.w * y.x + I0.y * y.y + I1.y * y.z,
+                   I1.x * y.x + I1.y * y.y + I0.z * y.z);
+  return dot(x, Sy);
+}
+
+// Exact diagonal impedance of one contact between free bodies (Sec. III.B,
+// K h + D = (1/h) (J~_f M^-1 J~_f^T)^-1 per facet, split between K and D in the
+// ratio k_user : d_user / h): A_f = 1 / ((k h + d) g_f) with
+// g_f = sum over the contact's bodies of |u_f|^2 / m + a_f^T Iw^-1 a_f, where the
+// facet row acts on a body as linear direction u_f and angular direction a_f:
+// tangential d: u = n - mu_t d, a = r x u; torsional sigma: u = n,
+// a = r x n - mu_tor sigma n; rolling d: u = n, a = r x n - mu_rol d.
+template <int NF>
+__device__ inline void diag_impedance(V3 n, V3 t1, V3 t2, int ba, int bb, V3 ra, V3 rb, const float4 *bC,
+                                      const float4 *bI0, const float4 *bI1, float mut, float mutor, float murol,
+                                      float aa, float *Af) {
+  float g[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) g[i] = 0.f;
+  // each facet's angular direction is formed as a vector before its quadratic
+  // form (expanding the form into cross terms would cancel in float32)
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int b = side ? bb : ba;
+    if (b < 0) continue;
+    const V3 r = side ? rb : ra;
+    const float4 I0 = bI0[b], I1 = bI1[b];
+    const float im = bC[b].w;
+    const V3 rn = cross(r, n);
+    if constexpr (NF == 1) {
+      g[0] += im + inv_inertia_form(I0, I1, rn, rn);
+    } else {
+      const V3 r1 = cross(r, t1), r2 = cross(r, t2);
+      const float lin = im * (1.f + mut * mut);
+      const V3 a0 = rn - mut * r1, a1 = rn - mut * r2, a2 = rn + mut * r1, a3 = rn + mut * r2;
+      g[0] += lin + inv_inertia_form(I0, I1, a0, a0);
+      g[1] += lin + inv_inertia_form(I0, I1, a1, a1);
+      g[2] += lin + inv_inertia_form(I0, I1, a2, a2);
+      g[3] += lin + inv_inertia_form(I0, I1, a3, a3);
+      if constexpr (NF >= 6) {
+        const V3 a4 = rn - mutor * n, a5 = rn + mutor * n;
+        g[4] += im + inv_inertia_form(I0, I1, a4, a4);
+        g[5] += im + inv_inertia_form(I0, I1, a5, a5);
+      }
+      if constexpr (NF == 10) {
+        const V3 a6 = rn - murol * t1, a7 = rn - murol * t2, a8 = rn + murol * t1, a9 = rn + murol * t2;
+        g[6] += im + inv_inertia_form(I0, I1, a6, a6);
+        g[7] += im + inv_inertia_form(I0, I1, a7, a7);
+        g[8] += im + inv_inertia_form(I0, I1, a8, a8);
+        g[9] += im + inv_inertia_form(I0, I1, a9, a9);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NF; ++i) Af[i] = (g[i] > 0.f && aa > 0.f) ? 1.0f / (aa * g[i]) : 0.f;
+}
+
+// Per geom: body and pair-friction inputs (mu_t, mu_tor, mu_rol) in LDS, for
+// geoms g0, g0 + BS, ... (callers that prefetched geom threadIdx.x pass g0 = BS).
+template <int CONDIM, int BS>
+__device__ inline void resolve_geoms(const ResolveArgs &a, int w, int *gB, float4 *gM, int g0) {
+  for (int g = g0 + (int)threadIdx.x; g < a.ng; g += BS) {
+    gB[g] = a.gbody[g];
+    const float mu_t = a.gdat[(size_t)w * a.ng + g].w;
+    float2 fr = make_float2(0.f, 0.f);
+    if (CONDIM >= 4) fr = a.gfr2[(size_t)w * a.ng + g];
+    gM[g] = make_float4(mu_t, fr.x, fr.y, 0.f);
+  }
+}
+
 // Resolution of world w: its q and v rows (LDS sq, sv) become q+ and v+ in
 // place; st holds the applied forces; the nc contacts are read from inn/inp
 // (global or LDS), the first chunk already loaded by the caller into c0n/c0p
@@ -742,7 +974,7 @@ __device__ inline ResolveRegion resolve_region(float4 *reg, int nb, int ng) {
 template <int CONDIM, int BS, bool ART>
 __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv, const float *st,
                               const float4 *inn, const float4 *inp, int nc, float4 c0n, float4 c0p,
-                              float4 mi0, float4 *reg, size_t xbase) {
+                              float4 mi0, float4 *reg, size_t xbase, bool geoms_ready = false) {
   constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
   constexpr int NW = BS / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -755,23 +987,21 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   float4 *bO = RR.bO, *bAx = RR.bAx, *bR = RR.bR;  // articulated bodies only
   float *art = RR.art;
   const Params P = a.p;
-  {
-    for (int g = tid; g < ng; g += BS) {
-      gB[g] = a.gbody[g];
-      const float mu_t = a.gdat[(size_t)w * ng + g].w;
-      float2 fr = make_float2(0.f, 0.f);
-      if (CONDIM >= 4) fr = a.gfr2[(size_t)w * ng + g];
-      gM[g] = make_float4(mu_t, fr.x, fr.y, 0.f);
-    }
-  }
+  if (!geoms_ready) resolve_geoms<CONDIM, BS>(a, w, gB, gM, 0);
   __syncthreads();
 
   // ---- per free body: M blocks, bias, smooth prediction (Eq. smooth_vel), trace 3/m
+  // (without articulated subtrees every body is a free root: q and v offsets 7b and 6b)
   for (int b = tid; b < nb; b += BS) {
-    const BodyC bc = a.body[b];
-    if (ART && !bc.fast) continue;
+    int qadr = 7 * b, dadr = 6 * b;
+    if (ART) {
+      const BodyC bc = a.body[b];
+      if (!bc.fast) continue;
+      qadr = bc.qadr;
+      dadr = bc.dadr;
+    }
     const float4 mi = b == tid ? mi0 : a.bmi[(size_t)w * nb + b];
-    const float *qb = sq + bc.qadr, *vb = sv + bc.dadr, *tb = st + bc.dadr;
+    const float *qb = sq + qadr, *vb = sv + dadr, *tb = st + dadr;
     float R[9];
     quat_to_rot<float>(qb[3], qb[4], qb[5], qb[6], R);
     const float invm = 1.0f / mi.x;
@@ -867,34 +1097,38 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       const float gam = lo ? P.mid * up : 1.0f - (1.0f - P.mid) * up;
       const float r = P.r_min + (P.r_max - P.r_min) * gam;
       const float A = trs > 0.f ? (r / (1.0f - r)) / trs : 0.f;
+      float Af[NF];
+#pragma unroll
+      for (int i = 0; i < NF; ++i) Af[i] = A;
+      if (P.imp_diag) diag_impedance<NF>(n, t1, t2, ba, bb, ra, rb, bC, bI0, bI1, mut, mutor, murol, aa, Af);
       const float c0 = -P.k_user * phi;
       const float vn = dot(n, vrel);
       float lam[NF];
       V3 f, tc = v3(0.f, 0.f, 0.f);
       if constexpr (CONDIM == 1) {
-        lam[0] = A * fmaxf(-aa * vn + c0, 0.f);
+        lam[0] = Af[0] * fmaxf(-aa * vn + c0, 0.f);
         f = lam[0] * n;
       } else {
         const float u1 = dot(t1, vrel), u2 = dot(t2, vrel);
-        lam[0] = A * fmaxf(-aa * (vn - mut * u1) + c0, 0.f);
-        lam[1] = A * fmaxf(-aa * (vn - mut * u2) + c0, 0.f);
-        lam[2] = A * fmaxf(-aa * (vn + mut * u1) + c0, 0.f);
-        lam[3] = A * fmaxf(-aa * (vn + mut * u2) + c0, 0.f);
+        lam[0] = Af[0] * fmaxf(-aa * (vn - mut * u1) + c0, 0.f);
+        lam[1] = Af[1] * fmaxf(-aa * (vn - mut * u2) + c0, 0.f);
+        lam[2] = Af[2] * fmaxf(-aa * (vn + mut * u1) + c0, 0.f);
+        lam[3] = Af[3] * fmaxf(-aa * (vn + mut * u2) + c0, 0.f);
         float N = lam[0] + lam[1] + lam[2] + lam[3];
         const float e1 = -mut * (lam[0] - lam[2]), e2 = -mut * (lam[1] - lam[3]);
         if constexpr (CONDIM >= 4) {
           const float wt = dot(n, wrel);
-          lam[4] = A * fmaxf(-aa * (vn - mutor * wt) + c0, 0.f);
-          lam[5] = A * fmaxf(-aa * (vn + mutor * wt) + c0, 0.f);
+          lam[4] = Af[4] * fmaxf(-aa * (vn - mutor * wt) + c0, 0.f);
+          lam[5] = Af[5] * fmaxf(-aa * (vn + mutor * wt) + c0, 0.f);
           N += lam[4] + lam[5];
           tc = (-mutor * (lam[4] - lam[5])) * n;
         }
         if constexpr (CONDIM == 6) {
           const float o1 = dot(t1, wrel), o2 = dot(t2, wrel);
-          lam[6] = A * fmaxf(-aa * (vn - murol * o1) + c0, 0.f);
-          lam[7] = A * fmaxf(-aa * (vn - murol * o2) + c0, 0.f);
-          lam[8] = A * fmaxf(-aa * (vn + murol * o1) + c0, 0.f);
-          lam[9] = A * fmaxf(-aa * (vn + murol * o2) + c0, 0.f);
+          lam[6] = Af[6] * fmaxf(-aa * (vn - murol * o1) + c0, 0.f);
+          lam[7] = Af[7] * fmaxf(-aa * (vn - murol * o2) + c0, 0.f);
+          lam[8] = Af[8] * fmaxf(-aa * (vn + murol * o1) + c0, 0.f);
+          lam[9] = Af[9] * fmaxf(-aa * (vn + murol * o2) + c0, 0.f);
           N += lam[6] + lam[7] + lam[8] + lam[9];
           tc = tc + (-murol * (lam[6] - lam[8])) * t1 + (-murol * (lam[7] - lam[9])) * t2;
         }
@@ -998,15 +1232,20 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     art_correct(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
   }
   for (int b = tid; b < nb; b += BS) {
-    const BodyC bc = a.body[b];
-    if (ART && !bc.fast) continue;
+    int qadr = 7 * b, dadr = 6 * b;
+    if (ART) {
+      const BodyC bc = a.body[b];
+      if (!bc.fast) continue;
+      qadr = bc.qadr;
+      dadr = bc.dadr;
+    }
     const float4 C = bC[b], Vs = bV[b], Ws = bW[b], I0 = bI0[b], I1 = bI1[b];
     const float4 F = accF[b], T = accT[b];
     const V3 vp = v3(Vs.x + C.w * F.x, Vs.y + C.w * F.y, Vs.z + C.w * F.z);
     const V3 wp = v3(Ws.x + I0.x * T.x + I0.w * T.y + I1.x * T.z,
                      Ws.y + I0.w * T.x + I0.y * T.y + I1.y * T.z,
                      Ws.z + I1.x * T.x + I1.y * T.y + I0.z * T.z);
-    float *qb = sq + bc.qadr, *vb = sv + bc.dadr;
+    float *qb = sq + qadr, *vb = sv + dadr;
     vb[0] = vp.x; vb[1] = vp.y; vb[2] = vp.z; vb[3] = wp.x; vb[4] = wp.y; vb[5] = wp.z;
     qb[0] = C.x + P.h * vp.x;
     qb[1] = C.y + P.h * vp.y;
@@ -1034,14 +1273,16 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
 
 template <int CONDIM, int BS, bool ART>
 __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
+  constexpr int K = 512 / BS;  // row elements per lane loaded up front
   extern __shared__ float4 lds[];
   const int w = blockIdx.x, tid = threadIdx.x;
-  const int nq = a.nq, nv = a.nv, nb = a.nb;
+  const int nq = a.nq, nv = a.nv, nb = a.nb, ng = a.ng;
   float *sq = reinterpret_cast<float *>(lds);
   float *sv = sq + pad4(nq);
   float *st = sv + pad4(nv);
+  float4 *reg = reinterpret_cast<float4 *>(st + pad4(nv));
   const size_t cbase = (size_t)w * a.ncon_max;
-  // issue every independent global load up front
+  // issue every independent global load before the first wait
   const int nc = a.ncon[w];
   float4 c0n = make_float4(0.f, 0.f, 0.f, 0.f), c0p = c0n;
   if (tid < a.ncon_max) {  // the first chunk's records (only used below ncon)
@@ -1050,17 +1291,35 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   }
   float4 mi0 = make_float4(1.f, 1.f, 1.f, 1.f);
   if (tid < nb) mi0 = a.bmi[(size_t)w * nb + tid];
+  int gb0 = -1;
+  float mu0 = 0.f;
+  float2 fr0 = make_float2(0.f, 0.f);
+  if (tid < ng) {
+    gb0 = a.gbody[tid];
+    mu0 = a.gdat[(size_t)w * ng + tid].w;
+    if (CONDIM >= 4) fr0 = a.gfr2[(size_t)w * ng + tid];
+  }
   const float *qw = a.q + (size_t)w * nq, *vw = a.v + (size_t)w * nv;
-  for (int i = tid; i < nq; i += BS) sq[i] = qw[i];
-  for (int i = tid; i < nv; i += BS) sv[i] = vw[i];
-  if (a.tau) {
-    const float *tw = a.tau + (size_t)w * nv;
-    for (int i = tid; i < nv; i += BS) st[i] = tw[i];
+  const float *tw = a.tau ? a.tau + (size_t)w * nv : nullptr;
+  RowStage<BS, K> rq, rv, rt;
+  rq.load(qw, nq);
+  rv.load(vw, nv);
+  if (tw) rt.load(tw, nv);
+  rq.store(sq, qw, nq);
+  rv.store(sv, vw, nv);
+  if (tw) {
+    rt.store(st, tw, nv);
   } else {
     for (int i = tid; i < nv; i += BS) st[i] = 0.f;
   }
-  resolve_world<CONDIM, BS, ART>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0,
-                                 reinterpret_cast<float4 *>(st + pad4(nv)), cbase);
+  const ResolveRegion RR = resolve_region<BS>(reg, nb, ng);
+  if (tid < ng) {
+    RR.gB[tid] = gb0;
+    RR.gM[tid] = make_float4(mu0, fr0.x, fr0.y, 0.f);
+  }
+  resolve_geoms<CONDIM, BS>(a, w, RR.gB, RR.gM, BS);
+  resolve_world<CONDIM, BS, ART>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg, cbase,
+                                 true);
   float *qo = a.q_out + (size_t)w * nq, *vo = a.v_out + (size_t)w * nv;
   for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
   for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
@@ -1094,7 +1353,7 @@ __global__ __launch_bounds__(BS) void rollout_kernel(RolloutArgs r) {
     for (int i = tid; i < nq; i += BS) sq[i] = qw[i];
     for (int i = tid; i < nv; i += BS) sv[i] = vw[i];
   }
-  const uint32_t nxt = tid < ca.nslot ? ca.slots[tid] : 0u;
+  const uint32_t nxt = tid < ca.nslot_pre ? ca.slots[tid] : 0u;
   for (int t = 0; t < r.T; ++t) {
     if (r.tau_seq) {
       const float *tw = r.tau_seq + ((size_t)t * nw + w) * nv;

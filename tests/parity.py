@@ -13,7 +13,10 @@ input state):
               allowed by the velocity tolerance)
   contact set count, geom pairs, sub-contact indices and order: bit-exact
   contact data phi, point: 1e-6 m; frame rows: 2e-5
-  facet impulses <= 1e-4 * max facet impulse of the world + 1e-12
+  facet impulses <= 1e-4 * max facet impulse of the world + A_f (k h + d) 1e-5 * scale
+              + 1e-12, A_f the facet's impulse gain (lambda_f h = A_f max(arg_f, 0)):
+              the second term is the impulse a velocity error within the velocity
+              tolerance makes on that facet
 A world-step is "guarded" (excluded from the bit-exact and tolerance checks,
 and counted) when some evaluated candidate has |phi - margin| < 1e-6 m or
 some contact has ||n_x| - 0.5| < 1e-6: there float32 and float64 may take
@@ -140,5 +143,16 @@ def compare_step(scene, oracle, q_in, v_in, tau, q_gpu, v_gpu, con, worlds=None,
         lmax = max(np.abs(lo).max(initial=0.0), 1e-300)
         irel = np.abs(li - lo).max(initial=0.0) / lmax
         stats["max_imp_rel"] = max(stats["max_imp_rel"], irel)
-        assert np.abs(li - lo).max() <= 1e-4 * lmax + 1e-12, f"world {w}: impulse rel err {irel:.3e}"
+        # a facet's impulse is A_f max(arg_f, 0) with arg_f = -(k h + d) s_f - k phi:
+        # besides 1e-4 of the world's largest impulse, allow the impulse that a
+        # velocity error within the velocity tolerance would make on that facet
+        # (arg_f can be a small difference of large terms on a sliding contact)
+        aa = scene["k_user"] * h + scene["d_user"]
+        tol = 1e-4 * lmax + out["facet_gain"][w, :n] * aa * VREL * scale + 1e-12
+        if (np.abs(li - lo) > tol).any():
+            k, f = np.unravel_index(int(np.argmax(np.abs(li - lo))), li.shape)
+            raise AssertionError(f"world {w}: impulse rel err {irel:.3e} at contact {k} facet {f}: gpu "
+                                 f"{li[k, f]:.9e} oracle {lo[k, f]:.9e} (largest {lmax:.3e}); contact "
+                                 f"geoms {out['geom'][w, k].tolist()} phi {out['dist'][w, k]:.3e} "
+                                 f"gpu facets {li[k].tolist()} oracle facets {lo[k].tolist()}")
     return stats

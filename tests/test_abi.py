@@ -97,3 +97,8 @@ def test_null_arguments(lib):
     assert lib.cf_rollout(None, None, 1, None, None, None, None, None, None) == cfsim.CF_E_INVALID_ARG
     assert lib.cf_model_dims(None, None, None, None) == cfsim.CF_E_INVALID_ARG
     lib.cf_model_destroy(None)
+
+
+
+def test_impedance_mode_null_model(lib):
+    assert lib.cf_model_set_impedance(None, 0) == cfsim.CF_E_INVALID_ARG

@@ -463,3 +463,55 @@ def test_slide_point_mass_stick_decay_on_gpu(torch_cuda):
         q, v = model.step(q, v)
         if n % 20 == 0:
             np.testing.assert_allclose(float(v[0, 0]), fac ** n * u0, rtol=2e-5)
+
+
+# ---------------------------------------------------------------- exact diagonal impedance
+@pytest.mark.parametrize("condim", [1, 3, 4, 6])
+def test_diagonal_impedance_parity(torch_cuda, condim):
+    """The exact diagonal impedance option (per-facet J~ M^-1 J~^T) against the
+    oracle's.  The diagonal form resolves every facet as if it were alone, so
+    coupled facets over-correct and frictional scenes leave the bounded regime
+    within tens of steps: mixed shapes are compared on their first three
+    states, the frictionless (condim 1) pile over 400 steps."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.mixed_shapes(nworld=4, seed=30 + condim, condim=condim)
+    s["impedance"] = 1
+    model = cfsim.Model(s)
+    tau_np = applied_wrench(s, np.random.default_rng(condim))
+    print(f"case: diagonal impedance mixed condim {condim}", flush=True)
+    recs = _run_steps(torch_cuda, model, s, 3, tau=tau_np)
+    o = Oracle(s)
+    stats = None
+    for t, qi, vi, qg, vg, con in recs:
+        stats = compare_step(s, o, qi, vi, tau_np, qg, vg, con, stats=stats)
+    print("diagonal impedance mixed", condim, stats)
+    assert stats["contacts"] >= 3
+    if condim == 1:
+        p = scenes.dense_pile(nworld=4, nsphere=64, seed=9, ncon_max=512, condim=1)
+        p["impedance"] = 1
+        model = cfsim.Model(p)
+        print("case: diagonal impedance dense pile condim 1", flush=True)
+        recs = _run_steps(torch_cuda, model, p, 400, record_every=100)
+        o = Oracle(p)
+        stats = None
+        for t, qi, vi, qg, vg, con in recs:
+            stats = compare_step(p, o, qi, vi, None, qg, vg, con, stats=stats)
+        print("diagonal impedance pile", stats)
+        assert stats["contacts"] > 100
+
+
+def test_diagonal_impedance_rules(torch_cuda):
+    """The diagonal impedance is a free-body option: an articulated model refuses
+    it, an invalid mode is rejected, and the adjoint refuses a diagonal model."""
+    from paper_2603_12185_amd import cfsim
+    m = cfsim.Model(scenes.pendulum())
+    with pytest.raises(cfsim.CFError, match="UNSUPPORTED"):
+        m.set_impedance(1)
+    with pytest.raises(cfsim.CFError, match="INVALID"):
+        m.set_impedance(7)
+    s = scenes.mixed_shapes(nworld=1, seed=2)
+    s["impedance"] = 1
+    m = cfsim.Model(s)
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    with pytest.raises(cfsim.CFError, match="UNSUPPORTED"):
+        m.step_backward(q, v, None, q, v)
