@@ -218,6 +218,31 @@ cf_status cf_model_kernel_times(cf_model *m, double *ms_collide, double *ms_reso
 cf_status cf_model_time_kernels(cf_model *m, void *stream, const float *q, const float *v, float *q_out,
                                 float *v_out, int32_t reps, float *us_collide, float *us_resolve);
 
+/* ---- Learned per-contact impedance network (the learned K, D that Sec. III.B
+ * allows in place of the heuristic).  Per contact, 7 features (phi, v_n, u_1,
+ * u_2, m_eff = 1/(tr_a + tr_b), mu_t, h; stored as 8 floats, the 8th ignored)
+ * are normalised, x = (f - mean)/std, and mapped by two SiLU layers of 64
+ * units to 16 outputs y (one per facet used); the facet impulse gain becomes
+ * the heuristic's times exp(clamp(y_f, -ln 16, ln 16)).  Parameters: one flat
+ * float32 device array of cf_mlp_nparam() values, row-major: mean[8], std[8],
+ * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][16], b3[16].  Products run on
+ * bf16 MFMA with float32 accumulation.  All pointers are 16-byte aligned
+ * device memory; calls are asynchronous on `stream`. */
+int32_t cf_mlp_nparam(void);
+/* y [n][16] = network(feats [n][8]). */
+cf_status cf_mlp_forward(void *stream, const float *params, const float *feats, int32_t n, float *out);
+/* Floats of scratch that cf_mlp_gradient needs for n contacts. */
+int64_t cf_mlp_work_floats(int32_t n);
+/* Gradient of the mean squared error over the n contacts and the first nout
+ * outputs, L = sum (y - targets)^2 / (n nout), targets [n][16]: grad
+ * [nparam] (zero for mean and std) and *loss (device scalar, may be NULL).
+ * Deterministic: per-wave partial sums in `work`, added in a fixed order. */
+cf_status cf_mlp_gradient(void *stream, const float *params, const float *feats, const float *targets,
+                          int32_t n, int32_t nout, float *work, int64_t work_floats, float *grad, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) of the
+ * trained parameters (W1 onwards) with moment buffers m, v [nparam]. */
+cf_status cf_mlp_adam(void *stream, float *params, float *m, float *v, const float *grad, int32_t step, float lr);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *cf_last_error(void);
 

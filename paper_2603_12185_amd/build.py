@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libcfsim.so")
-SOURCES = ["cf_api.hip", "cf_kernels.hip"]
+SOURCES = ["cf_api.hip", "cf_kernels.hip", "cf_mlp.hip"]
 HEADERS = [os.path.join(CSRC, "cf_internal.h"), os.path.join(ROOT, "include", "cfsim.h")]
 
 HIPCC_FLAGS = [

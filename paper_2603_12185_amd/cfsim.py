@@ -70,6 +70,11 @@ SIGNATURES = {
                                C.POINTER(C.c_int64)], C.c_int32),
     "cf_model_time_kernels": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, C.c_int32, C.POINTER(C.c_float),
                                C.POINTER(C.c_float)], C.c_int32),
+    "cf_mlp_nparam": ([], C.c_int32),
+    "cf_mlp_forward": ([C.c_void_p, _fp, _fp, C.c_int32, _fp], C.c_int32),
+    "cf_mlp_work_floats": ([C.c_int32], C.c_int64),
+    "cf_mlp_gradient": ([C.c_void_p, _fp, _fp, _fp, C.c_int32, C.c_int32, _fp, C.c_int64, _fp, _fp], C.c_int32),
+    "cf_mlp_adam": ([C.c_void_p, _fp, _fp, _fp, _fp, C.c_int32, C.c_float], C.c_int32),
     "cf_last_error": ([], C.c_char_p),
 }
 
@@ -300,3 +305,63 @@ class Model:
         a, b, n = C.c_double(), C.c_double(), C.c_int64()
         _check(load().cf_model_kernel_times(self._h, C.byref(a), C.byref(b), C.byref(n)))
         return a.value, b.value, n.value
+
+
+# ---------------------------------------------------------------- learned impedance network
+class ImpedanceNet:
+    """Device-side parameters of the learned impedance network and its training
+    state (Adam moments); every computation runs in the library's kernels."""
+
+    def __init__(self, params):
+        import torch
+        L = load()
+        self.nparam = int(L.cf_mlp_nparam())
+        p = torch.as_tensor(params, dtype=torch.float32).reshape(-1)
+        if p.numel() != self.nparam:
+            raise ValueError(f"expected {self.nparam} parameters")
+        self.params = p.cuda().contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self._work = None
+
+    @staticmethod
+    def _check(t, cols, name):
+        import torch
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2 \
+                or t.shape[1] != cols:
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor [n][{cols}]")
+
+    def forward(self, feats, out=None, stream=None):
+        import torch
+        self._check(feats, 8, "feats")
+        n = feats.shape[0]
+        out = torch.empty((n, 16), dtype=torch.float32, device=feats.device) if out is None else out
+        s = torch.cuda.current_stream() if stream is None else stream
+        _check(load().cf_mlp_forward(C.c_void_p(s.cuda_stream), _ptr(self.params), _ptr(feats), n, _ptr(out)))
+        return out
+
+    def gradient(self, feats, targets, nout, stream=None):
+        """(grad [nparam], loss) of the mean squared error; both device tensors."""
+        import torch
+        self._check(feats, 8, "feats")
+        self._check(targets, 16, "targets")
+        n = feats.shape[0]
+        need = int(load().cf_mlp_work_floats(n))
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need, dtype=torch.float32, device=feats.device)
+        grad = torch.empty_like(self.params)
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        s = torch.cuda.current_stream() if stream is None else stream
+        _check(load().cf_mlp_gradient(C.c_void_p(s.cuda_stream), _ptr(self.params), _ptr(feats), _ptr(targets), n,
+                                      int(nout), _ptr(self._work), self._work.numel(), _ptr(grad), _ptr(loss)))
+        return grad, loss
+
+    def train_step(self, feats, targets, nout, lr, stream=None):
+        import torch
+        grad, loss = self.gradient(feats, targets, nout, stream)
+        self.step += 1
+        s = torch.cuda.current_stream() if stream is None else stream
+        _check(load().cf_mlp_adam(C.c_void_p(s.cuda_stream), _ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                  _ptr(grad), self.step, float(lr)))
+        return loss

@@ -30,6 +30,7 @@ struct EventSet {
   hipEvent_t e[3];
 };
 
+
 }  // namespace
 
 struct cf_model {
@@ -699,3 +700,9 @@ cf_status cf_model_kernel_times(cf_model *m, double *ms_collide, double *ms_reso
 }
 
 }  // extern "C"
+
+namespace cf {
+// Error reporting for the other translation units of the library (the
+// network kernels): records the message for cf_last_error().
+cf_status api_error(cf_status st, const std::string &msg) { return set_err(st, msg); }
+}  // namespace cf

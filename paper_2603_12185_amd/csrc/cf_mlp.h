@@ -1,0 +1,144 @@
+// cf_mlp.h - the learned per-contact impedance network on MFMA (bf16 inputs,
+// float32 accumulation): parameter layout and the per-wave forward pass shared
+// by the training kernels and the resolution kernel.
+//
+// Network (per contact): 7 features (phi, v_n, u_1, u_2, m_eff, mu_t, h),
+// normalised x = (f - mean) / std; z1 = W1^T x + b1, a1 = silu(z1) (64);
+// z2 = W2^T a1 + b2, a2 = silu(z2) (64); y = W3^T a2 + b3 (16 outputs, one per
+// facet used).  The facet impulse gain is the heuristic's times
+// exp(clamp(y_f, -ln 16, ln 16)).
+//
+// Flat float32 parameters (row-major): mean[8], std[8], W1[8][64], b1[64],
+// W2[64][64], b2[64], W3[64][16], b3[16].
+//
+// Products are formed transposed, Z^T = W^T A^T, with the 16x16x16 bf16 MFMA:
+// the accumulator of one 16-unit block (lane l holds rows 4 (l / 16) + r,
+// column l % 16) is exactly the B operand of the next layer's matching
+// 16-wide K block, so activations never leave registers.  Weights are staged
+// in LDS as bf16, transposed so each lane reads its four K values at once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cf {
+namespace mlp {
+
+constexpr int NIN = 8, NH = 64, NOUT = 16, NFEAT = 7;
+constexpr int OFF_MEAN = 0, OFF_STD = 8, OFF_W1 = 16, OFF_B1 = OFF_W1 + NIN * NH, OFF_W2 = OFF_B1 + NH,
+              OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NOUT,
+              NPARAM = OFF_B3 + NOUT, TRAIN_FROM = OFF_W1;
+constexpr float CLIP = 2.7725887222397811f;  // ln 16
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bf16 bits, round to nearest even (finite inputs)
+__device__ inline short to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float dsilu(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ inline f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Weights in LDS (bf16 bits): W1^T [64][16] (K padded with zeros), W2^T [64][64],
+// W3^T [16][64]; biases and normalisation in float32.
+struct Weights {
+  short w1t[NH * 16];
+  short w2t[NH * NH];
+  short w3t[NOUT * NH];
+  float b1[NH], b2[NH], b3[NOUT], mean[NIN], istd[NIN];
+};
+
+// Stage the parameters into LDS (all threads of the block; ends with a barrier).
+template <int BS>
+__device__ inline void stage_weights(const float *p, Weights *W) {
+  for (int i = threadIdx.x; i < NH * 16; i += BS) {
+    const int h = i >> 4, k = i & 15;
+    W->w1t[i] = to_bf16(k < NIN ? p[OFF_W1 + k * NH + h] : 0.f);
+  }
+  for (int i = threadIdx.x; i < NH * NH; i += BS) {
+    const int o = i >> 6, k = i & 63;
+    W->w2t[i] = to_bf16(p[OFF_W2 + k * NH + o]);
+  }
+  for (int i = threadIdx.x; i < NOUT * NH; i += BS) {
+    const int o = i >> 6, k = i & 63;
+    W->w3t[i] = to_bf16(p[OFF_W3 + k * NOUT + o]);
+  }
+  for (int i = threadIdx.x; i < NH; i += BS) {
+    W->b1[i] = p[OFF_B1 + i];
+    W->b2[i] = p[OFF_B2 + i];
+  }
+  for (int i = threadIdx.x; i < NOUT; i += BS) W->b3[i] = p[OFF_B3 + i];
+  for (int i = threadIdx.x; i < NIN; i += BS) {
+    W->mean[i] = p[OFF_MEAN + i];
+    W->istd[i] = 1.0f / p[OFF_STD + i];
+  }
+  __syncthreads();
+}
+
+__device__ inline bf16x4 lds4(const short *s) { return *reinterpret_cast<const bf16x4 *>(s); }
+
+// Activations of one tile of 16 contacts, kept for the backward pass.
+struct Tile {
+  f32x4 z1[4], z2[4];  // pre-activations, block m: rows 16 m + 4 (l / 16) + r, column l % 16
+  f32x4 y;             // outputs: rows 4 (l / 16) + r, column l % 16
+  bf16x4 x;            // input operand: x[contact l % 16][4 (l / 16) + t]
+};
+
+// Forward pass of one wave over 16 contacts.  `f4(t)` returns raw feature
+// 4 (l / 16) + t of the lane's contact l % 16 (features >= NFEAT are ignored).
+template <class F>
+__device__ inline void forward_tile(const Weights *W, F f4, Tile &T) {
+  const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
+  (void)c;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = 4 * q + t;
+    const float v = k < NFEAT ? (f4(t) - W->mean[k]) * W->istd[k] : 0.f;
+    T.x[t] = to_bf16(v);
+  }
+  bf16x4 a1[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    z = mfma(lds4(W->w1t + (16 * m + c) * 16 + 4 * q), T.x, z);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      z[r] += W->b1[16 * m + 4 * q + r];
+      a1[m][r] = to_bf16(silu(z[r]));
+    }
+    T.z1[m] = z;
+  }
+  bf16x4 a2[4];
+#pragma unroll
+  for (int m2 = 0; m2 < 4; ++m2) {
+    f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) z = mfma(lds4(W->w2t + (16 * m2 + c) * NH + 16 * m + 4 * q), a1[m], z);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      z[r] += W->b2[16 * m2 + 4 * q + r];
+      a2[m2][r] = to_bf16(silu(z[r]));
+    }
+    T.z2[m2] = z;
+  }
+  f32x4 y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) y = mfma(lds4(W->w3t + c * NH + 16 * m + 4 * q), a2[m], y);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) y[r] += W->b3[4 * q + r];
+  T.y = y;
+}
+
+}  // namespace mlp
+}  // namespace cf
