@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define CF_ABI_VERSION 1
+#define CF_ABI_VERSION 2
 
 typedef struct cf_model cf_model;
 typedef int32_t cf_status;
@@ -114,6 +114,12 @@ typedef struct {
   float *pos;         /* [nworld][ncon_max][3] contact point                     */
   float *frame;       /* [nworld][ncon_max][9] rows n, t1, t2                    */
   float *impulse;     /* [nworld][ncon_max][nfacet] lambda*h per facet           */
+  /* training data of the learned impedance network (models of free bodies
+   * only, else ignored): the contact's 7 features (8th 0) and, per facet, the
+   * log of the exact diagonal gain over the heuristic's, clipped to
+   * [-ln 256, ln 256] (outputs beyond nfacet 0) */
+  float *features;    /* [nworld][ncon_max][8]                                   */
+  float *target;      /* [nworld][ncon_max][16]                                  */
 } cf_contacts;
 
 /* Validate the descriptor, upload per-world constants and size the contact
@@ -182,6 +188,19 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
  * cf_step_backward does not cover it. */
 cf_status cf_model_set_impedance(cf_model *m, int32_t mode);
 
+/* Learned impedance gains (see the network entry points below): with params
+ * (device, cf_mlp_nparam() floats, read at every step, owned by the caller)
+ * each facet gain of the heuristic is multiplied by exp(clamp(y_f, -ln 256,
+ * ln 256)), y the network's output for the contact, unless that predicts, for
+ * the contact alone along its normal, a next-step penetration larger than the
+ * heuristic's by more than `margin` (m) or a normal kinetic energy larger by
+ * more than that of moving `margin` in one step; then the contact keeps the
+ * heuristic gain.  params NULL switches the network off.  Models of free
+ * bodies with the heuristic impedance only (else CF_E_UNSUPPORTED); the
+ * resolution then runs at most 128 threads per world; cf_rollout uses step
+ * launches; cf_step_backward does not cover it. */
+cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float margin);
+
 /* Workgroup size (64, 128 or 256 threads, one world per workgroup) of the
  * collision, the resolution and the rollout kernel (defaults 64, 256, 256);
  * results do not depend on the choice (same arithmetic, same summation order
@@ -223,7 +242,7 @@ cf_status cf_model_time_kernels(cf_model *m, void *stream, const float *q, const
  * u_2, m_eff = 1/(tr_a + tr_b), mu_t, h; stored as 8 floats, the 8th ignored)
  * are normalised, x = (f - mean)/std, and mapped by two SiLU layers of 64
  * units to 16 outputs y (one per facet used); the facet impulse gain becomes
- * the heuristic's times exp(clamp(y_f, -ln 16, ln 16)).  Parameters: one flat
+ * the heuristic's times exp(clamp(y_f, -ln 256, ln 256)).  Parameters: one flat
  * float32 device array of cf_mlp_nparam() values, row-major: mean[8], std[8],
  * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][16], b3[16].  Products run on
  * bf16 MFMA with float32 accumulation.  All pointers are 16-byte aligned

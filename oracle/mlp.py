@@ -26,7 +26,7 @@ from __future__ import annotations
 import numpy as np
 
 NFEAT, NIN, NH, NOUT = 7, 8, 64, 16
-CLIP = float(np.log(16.0))
+CLIP = float(np.log(256.0))
 
 # offsets in the flat parameter array
 OFF_MEAN = 0

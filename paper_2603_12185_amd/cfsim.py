@@ -41,7 +41,8 @@ class ModelDesc(C.Structure):
 class Contacts(C.Structure):
     _fields_ = [("ncon", C.c_void_p), ("overflow", C.c_void_p), ("geom", C.c_void_p),
                 ("sub", C.c_void_p), ("dist", C.c_void_p), ("pos", C.c_void_p),
-                ("frame", C.c_void_p), ("impulse", C.c_void_p)]
+                ("frame", C.c_void_p), ("impulse", C.c_void_p), ("features", C.c_void_p),
+                ("target", C.c_void_p)]
 
 
 class CFError(RuntimeError):
@@ -62,6 +63,7 @@ SIGNATURES = {
     "cf_step_backward": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
     "cf_model_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
     "cf_model_set_impedance": ([C.c_void_p, C.c_int32], C.c_int32),
+    "cf_model_set_learned_impedance": ([C.c_void_p, _fp, C.c_float], C.c_int32),
     "cf_model_get_launch": ([C.c_void_p, _ip, _ip, _ip, _ip], C.c_int32),
     "cf_model_autotune": ([C.c_void_p, C.c_void_p, _fp, _fp, C.c_int32, C.POINTER(C.c_float),
                            C.POINTER(C.c_float)], C.c_int32),
@@ -173,8 +175,9 @@ class Model:
         if t.numel() != self.nworld * cols:
             raise ValueError(f"{name} must hold nworld*{cols} = {self.nworld * cols} values")
 
-    def alloc_contacts(self, device="cuda"):
-        """Device tensors for every contact output of a step."""
+    def alloc_contacts(self, device="cuda", training=False):
+        """Device tensors for every contact output of a step (with the
+        learned-gain training data when `training`)."""
         import torch
         nw, cm, nf = self.nworld, self.ncon_max, self.nfacet
         i32, f32 = torch.int32, torch.float32
@@ -186,7 +189,9 @@ class Model:
             dist=torch.zeros((nw, cm), dtype=f32, device=device),
             pos=torch.zeros((nw, cm, 3), dtype=f32, device=device),
             frame=torch.zeros((nw, cm, 9), dtype=f32, device=device),
-            impulse=torch.zeros((nw, cm, nf), dtype=f32, device=device))
+            impulse=torch.zeros((nw, cm, nf), dtype=f32, device=device),
+            **({} if not training else dict(features=torch.zeros((nw, cm, 8), dtype=f32, device=device),
+                                            target=torch.zeros((nw, cm, 16), dtype=f32, device=device))))
 
     # ------------------------------------------------------------ compute
     def step(self, q, v, tau=None, q_out=None, v_out=None, contacts=None, stream=None):
@@ -255,6 +260,13 @@ class Model:
         return q_traj, v_traj
 
     # ------------------------------------------------------------ launch shape
+    def set_learned_impedance(self, net, margin=0.0):
+        """Scale the heuristic gains by the network `net` (an ImpedanceNet, or
+        None to switch it off) with the given fallback margin in metres."""
+        self._net = net  # the library reads the parameters at every step
+        _check(load().cf_model_set_learned_impedance(self._h, None if net is None else _ptr(net.params),
+                                                     float(margin)))
+
     def set_impedance(self, mode):
         """0: heuristic impedance (default); 1: exact diagonal impedance per facet."""
         _check(load().cf_model_set_impedance(self._h, int(mode)))

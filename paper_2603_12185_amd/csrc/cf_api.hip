@@ -57,6 +57,7 @@ struct cf_model {
   float4 *d_cnp = nullptr, *d_cpos = nullptr;
   int *d_ncon = nullptr, *d_over = nullptr;
   size_t lds_collide = 0, lds_resolve = 0;
+  const float *mlp = nullptr;  // learned-gain network parameters (caller-owned device memory)
   // timing
   bool prof = false;
   std::vector<EventSet> events;
@@ -418,7 +419,19 @@ static cf::ResolveArgs resolve_args(const cf_model *m) {
   return ra;
 }
 
-static bool rollout_fused(const cf_model *m) { return m->lds_rollout <= kLdsLimit && !m->rollout_steps; }
+static bool rollout_fused(const cf_model *m) {
+  return m->lds_rollout <= kLdsLimit && !m->rollout_steps && !m->mlp;
+}
+
+// The resolution launch of a step: with learned gains the kernel stages the
+// network in LDS and runs at most 128 threads per world.
+static hipError_t launch_resolve_model(const cf_model *m, cf::ResolveArgs ra, hipStream_t s) {
+  if (!m->mlp) return cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
+  const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
+  ra.mlp = m->mlp;
+  const size_t lds = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, block, 0, 0) + cf::resolve_learned_lds_bytes(block);
+  return cf::launch_resolve(ra, m->nw, block, lds, s);
+}
 
 cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                   float *q_out, float *v_out, const cf_contacts *out) {
@@ -459,8 +472,9 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
   if (out) {
     ra.x_geom = out->geom; ra.x_sub = out->sub; ra.x_dist = out->dist; ra.x_pos = out->pos;
     ra.x_frame = out->frame; ra.x_imp = out->impulse;
+    if (m->nsub == 0) { ra.x_feat = out->features; ra.x_target = out->target; }
   }
-  e = cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
+  e = launch_resolve_model(m, ra, s);
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("resolve launch: ") + hipGetErrorString(e));
   if (ev && hipEventRecord(ev->e[2], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
   return CF_OK;
@@ -488,7 +502,7 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
     return set_err(CF_E_INVALID_ARG, "gq/gv may alias gq_out/gv_out only exactly; no other overlap");
   if (m->nsub > 0)
     return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers models of free bodies only");
-  if (m->p.imp_diag)
+  if (m->p.imp_diag || m->mlp)
     return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers the heuristic impedance only");
   if (!m->block_backward) return set_err(CF_E_UNSUPPORTED, "world too large for the adjoint's LDS");
   hipStream_t s = (hipStream_t)stream;
@@ -541,8 +555,28 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
   return CF_OK;
 }
 
+cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float margin) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (!params) {
+    m->mlp = nullptr;
+    return CF_OK;
+  }
+  if (!aligned16(params)) return set_err(CF_E_INVALID_ARG, "params must be 16-byte aligned");
+  if (!(margin >= 0.f)) return set_err(CF_E_INVALID_ARG, "margin must be >= 0");
+  if (m->nsub > 0) return set_err(CF_E_UNSUPPORTED, "learned impedance covers models of free bodies only");
+  if (m->p.imp_diag) return set_err(CF_E_UNSUPPORTED, "learned impedance scales the heuristic, not the diagonal form");
+  const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
+  if (cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, block, 0, 0) + cf::resolve_learned_lds_bytes(block) > kLdsLimit)
+    return set_err(CF_E_UNSUPPORTED, "world too large for the learned resolution's LDS");
+  m->mlp = params;
+  m->p.mlp_margin = margin;
+  return CF_OK;
+}
+
 cf_status cf_model_set_impedance(cf_model *m, int32_t mode) {
   if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (mode == CF_IMPEDANCE_DIAGONAL && m->mlp)
+    return set_err(CF_E_UNSUPPORTED, "switch the learned impedance off first");
   if (mode != CF_IMPEDANCE_HEURISTIC && mode != CF_IMPEDANCE_DIAGONAL)
     return set_err(CF_E_INVALID_ARG, "impedance mode must be CF_IMPEDANCE_HEURISTIC or CF_IMPEDANCE_DIAGONAL");
   if (mode == CF_IMPEDANCE_DIAGONAL && m->nsub > 0)
@@ -674,7 +708,7 @@ cf_status cf_model_time_kernels(cf_model *m, void *stream, const float *q, const
     err = cf::launch_collide(ca, m->nw, m->block_collide, m->lds_collide, s);
   if (err == hipSuccess) err = hipEventRecord(e[1], s);
   for (int i = 0; i < reps && err == hipSuccess; ++i)
-    err = cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
+    err = launch_resolve_model(m, ra, s);
   if (err == hipSuccess) err = hipEventRecord(e[2], s);
   if (err == hipSuccess) err = hipEventSynchronize(e[2]);
   float t0 = 0.f, t1 = 0.f;

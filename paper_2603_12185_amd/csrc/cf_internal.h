@@ -53,6 +53,7 @@ struct Params {
   float inv_width, inv_mid, inv_1mmid;  // 1/width, 1/mid, 1/(1 - mid)
   int power2;                           // power == 2: gamma uses squares
   int imp_diag;                         // 1: exact diagonal impedance per facet
+  float mlp_margin;                     // fallback margin of the learned gains (m)
 };
 
 // Collision kernel: one workgroup per world.
@@ -92,6 +93,8 @@ struct ResolveArgs {
   // optional exports (device, caller-owned), may be null
   int *x_geom, *x_sub;
   float *x_dist, *x_pos, *x_frame, *x_imp;
+  float *x_feat, *x_target;     // learned-gain training data (free-body models)
+  const float *mlp;             // learned-gain network parameters, or null
   int nq, nv, nb, ng, ncon_max, condim, nfacet, nbits, nsub, art_floats;
   Params p;
 };
@@ -124,6 +127,7 @@ size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, 
                          int cap);
 hipError_t launch_rollout(const RolloutArgs &a, int block, size_t lds, hipStream_t s);
 size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats);
+size_t resolve_learned_lds_bytes(int block);  // extra LDS of the resolution with learned gains
 hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 

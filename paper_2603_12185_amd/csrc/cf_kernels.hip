@@ -28,6 +28,7 @@
 // inertia.  Apart from the float64 contact geometry the step runs in float32.
 #include "cf_internal.h"
 #include "cf_adjoint.h"
+#include "cf_mlp.h"
 
 namespace cf {
 
@@ -952,6 +953,94 @@ __device__ inline void diag_impedance(V3 n, V3 t1, V3 t2, int ba, int bb, V3 ra,
   for (int i = 0; i < NF; ++i) Af[i] = (g[i] > 0.f && aa > 0.f) ? 1.0f / (aa * g[i]) : 0.f;
 }
 
+// Kinematics of one contact record at the smooth velocities: frame, lever
+// arms, relative velocity (b minus a), trace sum and pair friction.
+struct ContactKin {
+  V3 n, p, t1, t2, vrel, wrel, ra, rb;
+  float phi, trs, mut, mutor, murol;
+  int ga, gb, ba, bb;
+  uint32_t sl;
+};
+
+__device__ inline ContactKin contact_kin(float4 cn, float4 cp, const int *gB, const float4 *gM, const float4 *bC,
+                                         const float4 *bV, const float4 *bW) {
+  ContactKin K;
+  K.sl = __float_as_uint(cp.w);
+  K.ga = slot_ga(K.sl);
+  K.gb = slot_gb(K.sl);
+  K.ba = gB[K.ga];
+  K.bb = gB[K.gb];
+  K.n = v3(cn.x, cn.y, cn.z);
+  K.p = v3(cp.x, cp.y, cp.z);
+  K.phi = cn.w;
+  const V3 n = K.n;
+  V3 t1 = fabsf(n.x) <= 0.5f ? v3(1.f - n.x * n.x, -n.x * n.y, -n.x * n.z) : v3(-n.y * n.x, 1.f - n.y * n.y, -n.y * n.z);
+  K.t1 = rsqrtf(dot(t1, t1)) * t1;
+  K.t2 = cross(n, K.t1);
+  K.vrel = v3(0.f, 0.f, 0.f);
+  K.wrel = K.vrel;
+  K.ra = K.vrel;
+  K.rb = K.vrel;
+  K.trs = 0.f;
+  if (K.bb >= 0) {
+    const float4 C = bC[K.bb], Vb = bV[K.bb], Wb = bW[K.bb];
+    K.rb = K.p - v3(C.x, C.y, C.z);
+    const V3 wb = v3(Wb.x, Wb.y, Wb.z);
+    K.vrel = v3(Vb.x, Vb.y, Vb.z) + cross(wb, K.rb);
+    K.wrel = wb;
+    K.trs += Vb.w;
+  }
+  if (K.ba >= 0) {
+    const float4 C = bC[K.ba], Va = bV[K.ba], Wa = bW[K.ba];
+    K.ra = K.p - v3(C.x, C.y, C.z);
+    const V3 wa = v3(Wa.x, Wa.y, Wa.z);
+    K.vrel = K.vrel - (v3(Va.x, Va.y, Va.z) + cross(wa, K.ra));
+    K.wrel = K.wrel - wa;
+    K.trs += Va.w;
+  }
+  const float4 ma = gM[K.ga], mb = gM[K.gb];
+  K.mut = fmaxf(ma.x, mb.x);
+  K.mutor = fmaxf(ma.y, mb.y);
+  K.murol = fmaxf(ma.z, mb.z);
+  return K;
+}
+
+// The network's 7 features (8th zero): phi, v_n, u_1, u_2, m_eff = 1/(tr_a + tr_b), mu_t, h.
+__device__ inline void contact_features(const ContactKin &K, float h, float *fe) {
+  fe[0] = K.phi;
+  fe[1] = dot(K.n, K.vrel);
+  fe[2] = dot(K.t1, K.vrel);
+  fe[3] = dot(K.t2, K.vrel);
+  fe[4] = K.trs > 0.f ? 1.0f / K.trs : 0.f;
+  fe[5] = K.mut;
+  fe[6] = h;
+  fe[7] = 0.f;
+}
+
+// Fallback rule of the learned gains: with the contact alone along its normal
+// (inverse mass tr_s / 3 = 1/m_a + 1/m_b for free bodies), the facet impulses
+// change the normal velocity by (tr_s / 3) sum_f lambda_f; the learned
+// impulses are kept unless they predict a next-step penetration larger than
+// the heuristic's by more than `margin`, or a normal kinetic energy larger by
+// more than that of moving `margin` in one step.
+template <int NF>
+__device__ inline bool learned_ok(const float *lh, const float *ll, float vn, float phi, float trs, float h,
+                                  float margin) {
+  if (!(trs > 0.f)) return false;
+  const float winv = trs * (1.0f / 3.0f);
+  float Sh = 0.f, Sl = 0.f;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    Sh += lh[i];
+    Sl += ll[i];
+  }
+  const float vh = vn + winv * Sh, vl = vn + winv * Sl;
+  const float ph = fmaxf(-(phi + h * vh), 0.f), pl = fmaxf(-(phi + h * vl), 0.f);
+  const float eh = 0.5f * vh * vh / winv, el = 0.5f * vl * vl / winv;
+  const float em = 0.5f * (margin / h) * (margin / h) / winv;
+  return pl <= ph + margin && el <= eh + em && isfinite(vl);
+}
+
 // Per geom: body and pair-friction inputs (mu_t, mu_tor, mu_rol) in LDS, for
 // geoms g0, g0 + BS, ... (callers that prefetched geom threadIdx.x pass g0 = BS).
 template <int CONDIM, int BS>
@@ -971,10 +1060,11 @@ __device__ inline void resolve_geoms(const ResolveArgs &a, int w, int *gB, float
 // (lane tid's record), and mi0 is body tid's mass/inertia.  `reg`: LDS scratch of
 // resolve_region_bytes().  `xbase`: row of the world in the export arrays.
 // Ends with a workgroup barrier.
-template <int CONDIM, int BS, bool ART>
+template <int CONDIM, int BS, bool ART, bool LEARN = false>
 __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv, const float *st,
                               const float4 *inn, const float4 *inp, int nc, float4 c0n, float4 c0p,
-                              float4 mi0, float4 *reg, size_t xbase, bool geoms_ready = false) {
+                              float4 mi0, float4 *reg, size_t xbase, bool geoms_ready = false,
+                              const mlp::Weights *lnet = nullptr, float *lfeat = nullptr, float *lout = nullptr) {
   constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
   constexpr int NW = BS / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1054,41 +1144,34 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     int kA = nb, kB = nb;  // key nb = no body (static geom or idle lane)
     float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
     float2 WA2 = make_float2(0.f, 0.f), WB2 = WA2;
+    if constexpr (LEARN) {
+      // learned gains: features of the wave's contacts to LDS, the network on
+      // MFMA (all lanes of the wave), outputs back to LDS
+      float fe[mlp::NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (k < nc) {
+        const ContactKin K = contact_kin(base == 0 ? c0n : inn[k], base == 0 ? c0p : inp[k], gB, gM, bC, bV, bW);
+        contact_features(K, P.h, fe);
+      }
+#pragma unroll
+      for (int i = 0; i < mlp::NIN; ++i) lfeat[tid * mlp::NIN + i] = fe[i];
+      __builtin_amdgcn_wave_barrier();
+      const int q = lane >> 4, cc = lane & 15;
+#pragma unroll
+      for (int tile = 0; tile < 4; ++tile) {
+        const int row = wave * 64 + tile * 16 + cc;
+        mlp::Tile T;
+        mlp::forward_tile(lnet, [&](int t) { return lfeat[row * mlp::NIN + 4 * q + t]; }, T);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lout[row * mlp::NOUT + 4 * q + r] = T.y[r];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
     if (k < nc) {
-      const float4 cn = base == 0 ? c0n : inn[k];
-      const float4 cp = base == 0 ? c0p : inp[k];
-      const uint32_t sl = __float_as_uint(cp.w);
-      const int ga = slot_ga(sl), gb = slot_gb(sl);
-      const int ba = gB[ga], bb = gB[gb];
-      const V3 n = v3(cn.x, cn.y, cn.z), p = v3(cp.x, cp.y, cp.z);
-      const float phi = cn.w;
-      // tangent basis
-      V3 t1 = fabsf(n.x) <= 0.5f ? v3(1.f - n.x * n.x, -n.x * n.y, -n.x * n.z)
-                                 : v3(-n.y * n.x, 1.f - n.y * n.y, -n.y * n.z);
-      t1 = rsqrtf(dot(t1, t1)) * t1;
-      const V3 t2 = cross(n, t1);
-      // relative velocity at v_s (b minus a)
-      V3 vrel = v3(0.f, 0.f, 0.f), wrel = vrel;
-      float trs = 0.f;
-      V3 ra = vrel, rb = vrel;
-      if (bb >= 0) {
-        const float4 C = bC[bb], Vb = bV[bb], Wb = bW[bb];
-        rb = p - v3(C.x, C.y, C.z);
-        const V3 wb = v3(Wb.x, Wb.y, Wb.z);
-        vrel = v3(Vb.x, Vb.y, Vb.z) + cross(wb, rb);
-        wrel = wb;
-        trs += Vb.w;
-      }
-      if (ba >= 0) {
-        const float4 C = bC[ba], Va = bV[ba], Wa = bW[ba];
-        ra = p - v3(C.x, C.y, C.z);
-        const V3 wa = v3(Wa.x, Wa.y, Wa.z);
-        vrel = vrel - (v3(Va.x, Va.y, Va.z) + cross(wa, ra));
-        wrel = wrel - wa;
-        trs += Va.w;
-      }
-      const float4 ma = gM[ga], mb = gM[gb];
-      const float mut = fmaxf(ma.x, mb.x), mutor = fmaxf(ma.y, mb.y), murol = fmaxf(ma.z, mb.z);
+      const ContactKin K = contact_kin(base == 0 ? c0n : inn[k], base == 0 ? c0p : inp[k], gB, gM, bC, bV, bW);
+      const uint32_t sl = K.sl;
+      const int ga = K.ga, gb = K.gb, ba = K.ba, bb = K.bb;
+      const V3 n = K.n, p = K.p, t1 = K.t1, t2 = K.t2, vrel = K.vrel, wrel = K.wrel, ra = K.ra, rb = K.rb;
+      const float phi = K.phi, trs = K.trs, mut = K.mut, mutor = K.mutor, murol = K.murol;
       // impedance (Eqs. k_d_setting, r_scaling), x clamped to [0, 1]
       const float x = fminf(fabsf(phi) * P.inv_width, 1.0f);
       const bool lo = x < P.mid;
@@ -1104,31 +1187,54 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       const float c0 = -P.k_user * phi;
       const float vn = dot(n, vrel);
       float lam[NF];
+      // facet impulses lambda_f h = gain_f * max(arg_f, 0) (Eq. cf_wrench)
+      auto facets = [&](const float *G, float *L) {
+        if constexpr (CONDIM == 1) {
+          L[0] = G[0] * fmaxf(-aa * vn + c0, 0.f);
+        } else {
+          const float u1 = dot(t1, vrel), u2 = dot(t2, vrel);
+          L[0] = G[0] * fmaxf(-aa * (vn - mut * u1) + c0, 0.f);
+          L[1] = G[1] * fmaxf(-aa * (vn - mut * u2) + c0, 0.f);
+          L[2] = G[2] * fmaxf(-aa * (vn + mut * u1) + c0, 0.f);
+          L[3] = G[3] * fmaxf(-aa * (vn + mut * u2) + c0, 0.f);
+          if constexpr (CONDIM >= 4) {
+            const float wt = dot(n, wrel);
+            L[4] = G[4] * fmaxf(-aa * (vn - mutor * wt) + c0, 0.f);
+            L[5] = G[5] * fmaxf(-aa * (vn + mutor * wt) + c0, 0.f);
+          }
+          if constexpr (CONDIM == 6) {
+            const float o1 = dot(t1, wrel), o2 = dot(t2, wrel);
+            L[6] = G[6] * fmaxf(-aa * (vn - murol * o1) + c0, 0.f);
+            L[7] = G[7] * fmaxf(-aa * (vn - murol * o2) + c0, 0.f);
+            L[8] = G[8] * fmaxf(-aa * (vn + murol * o1) + c0, 0.f);
+            L[9] = G[9] * fmaxf(-aa * (vn + murol * o2) + c0, 0.f);
+          }
+        }
+      };
+      facets(Af, lam);
+      if constexpr (LEARN) {
+        // learned gains, kept unless they predict more penetration or more
+        // kinetic energy along the normal than the heuristic's, beyond the margin
+        float Gl[NF], ll[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) Gl[i] = A * __expf(fminf(fmaxf(lout[tid * mlp::NOUT + i], -mlp::CLIP), mlp::CLIP));
+        facets(Gl, ll);
+        if (learned_ok<NF>(lam, ll, vn, phi, trs, P.h, P.mlp_margin)) {
+#pragma unroll
+          for (int i = 0; i < NF; ++i) lam[i] = ll[i];
+        }
+      }
       V3 f, tc = v3(0.f, 0.f, 0.f);
       if constexpr (CONDIM == 1) {
-        lam[0] = Af[0] * fmaxf(-aa * vn + c0, 0.f);
         f = lam[0] * n;
       } else {
-        const float u1 = dot(t1, vrel), u2 = dot(t2, vrel);
-        lam[0] = Af[0] * fmaxf(-aa * (vn - mut * u1) + c0, 0.f);
-        lam[1] = Af[1] * fmaxf(-aa * (vn - mut * u2) + c0, 0.f);
-        lam[2] = Af[2] * fmaxf(-aa * (vn + mut * u1) + c0, 0.f);
-        lam[3] = Af[3] * fmaxf(-aa * (vn + mut * u2) + c0, 0.f);
         float N = lam[0] + lam[1] + lam[2] + lam[3];
         const float e1 = -mut * (lam[0] - lam[2]), e2 = -mut * (lam[1] - lam[3]);
         if constexpr (CONDIM >= 4) {
-          const float wt = dot(n, wrel);
-          lam[4] = Af[4] * fmaxf(-aa * (vn - mutor * wt) + c0, 0.f);
-          lam[5] = Af[5] * fmaxf(-aa * (vn + mutor * wt) + c0, 0.f);
           N += lam[4] + lam[5];
           tc = (-mutor * (lam[4] - lam[5])) * n;
         }
         if constexpr (CONDIM == 6) {
-          const float o1 = dot(t1, wrel), o2 = dot(t2, wrel);
-          lam[6] = Af[6] * fmaxf(-aa * (vn - murol * o1) + c0, 0.f);
-          lam[7] = Af[7] * fmaxf(-aa * (vn - murol * o2) + c0, 0.f);
-          lam[8] = Af[8] * fmaxf(-aa * (vn + murol * o1) + c0, 0.f);
-          lam[9] = Af[9] * fmaxf(-aa * (vn + murol * o2) + c0, 0.f);
           N += lam[6] + lam[7] + lam[8] + lam[9];
           tc = tc + (-murol * (lam[6] - lam[8])) * t1 + (-murol * (lam[7] - lam[9])) * t2;
         }
@@ -1161,6 +1267,22 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       if (a.x_imp) {
 #pragma unroll
         for (int i = 0; i < NF; ++i) a.x_imp[(size_t)NF * ci + i] = lam[i];
+      }
+      if (!ART && a.x_feat) {  // training data of the learned gains
+        float fe[mlp::NIN];
+        contact_features(K, P.h, fe);
+#pragma unroll
+        for (int i = 0; i < mlp::NIN; ++i) a.x_feat[(size_t)mlp::NIN * ci + i] = fe[i];
+      }
+      if (!ART && a.x_target) {  // log of the exact diagonal gain over the heuristic's, clipped
+        float Ad[NF];
+        diag_impedance<NF>(n, t1, t2, ba, bb, ra, rb, bC, bI0, bI1, mut, mutor, murol, aa, Ad);
+#pragma unroll
+        for (int i = 0; i < mlp::NOUT; ++i) {
+          float t = 0.f;
+          if (i < NF && A > 0.f && Ad[i] > 0.f) t = fminf(fmaxf(__logf(Ad[i] / A), -mlp::CLIP), mlp::CLIP);
+          a.x_target[(size_t)mlp::NOUT * ci + i] = t;
+        }
       }
     }
     vA[tid] = WA; vA2[tid] = WA2;
@@ -1271,7 +1393,11 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   __syncthreads();
 }
 
-template <int CONDIM, int BS, bool ART>
+size_t resolve_learned_lds_bytes(int block) {
+  return (sizeof(mlp::Weights) + 15) / 16 * 16 + sizeof(float) * (size_t)block * (mlp::NIN + mlp::NOUT);
+}
+
+template <int CONDIM, int BS, bool ART, bool LEARN>
 __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   constexpr int K = 512 / BS;  // row elements per lane loaded up front
   extern __shared__ float4 lds[];
@@ -1318,8 +1444,17 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
     RR.gM[tid] = make_float4(mu0, fr0.x, fr0.y, 0.f);
   }
   resolve_geoms<CONDIM, BS>(a, w, RR.gB, RR.gM, BS);
-  resolve_world<CONDIM, BS, ART>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg, cbase,
-                                 true);
+  mlp::Weights *lnet = nullptr;
+  float *lfeat = nullptr, *lout = nullptr;
+  if constexpr (LEARN) {
+    char *base = reinterpret_cast<char *>(reg) + resolve_region_bytes(nb, ng, BS, 0, 0);
+    lnet = reinterpret_cast<mlp::Weights *>(base);
+    lfeat = reinterpret_cast<float *>(base + (sizeof(mlp::Weights) + 15) / 16 * 16);
+    lout = lfeat + BS * mlp::NIN;
+    mlp::stage_weights<BS>(a.mlp, lnet);
+  }
+  resolve_world<CONDIM, BS, ART, LEARN>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg,
+                                        cbase, true, lnet, lfeat, lout);
   float *qo = a.q_out + (size_t)w * nq, *vo = a.v_out + (size_t)w * nv;
   for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
   for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
@@ -1407,12 +1542,12 @@ hipError_t launch_rollout(const RolloutArgs &a, int block, size_t lds, hipStream
   }
 }
 
-template <int CONDIM, bool ART>
+template <int CONDIM, bool ART, bool LEARN>
 static hipError_t launch_resolve_b(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
   switch (block) {
-    case 64: hipLaunchKernelGGL((resolve_kernel<CONDIM, 64, ART>), dim3(nworld), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((resolve_kernel<CONDIM, 128, ART>), dim3(nworld), dim3(128), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((resolve_kernel<CONDIM, 256, ART>), dim3(nworld), dim3(256), lds, s, a); break;
+    case 64: hipLaunchKernelGGL((resolve_kernel<CONDIM, 64, ART, LEARN>), dim3(nworld), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((resolve_kernel<CONDIM, 128, ART, LEARN>), dim3(nworld), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((resolve_kernel<CONDIM, 256, ART, LEARN>), dim3(nworld), dim3(256), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1420,8 +1555,9 @@ static hipError_t launch_resolve_b(const ResolveArgs &a, int nworld, int block, 
 
 template <int CONDIM>
 static hipError_t launch_resolve_c(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
-  return a.nsub > 0 ? launch_resolve_b<CONDIM, true>(a, nworld, block, lds, s)
-                    : launch_resolve_b<CONDIM, false>(a, nworld, block, lds, s);
+  if (a.mlp) return a.nsub > 0 ? hipErrorInvalidValue : launch_resolve_b<CONDIM, false, true>(a, nworld, block, lds, s);
+  return a.nsub > 0 ? launch_resolve_b<CONDIM, true, false>(a, nworld, block, lds, s)
+                    : launch_resolve_b<CONDIM, false, false>(a, nworld, block, lds, s);
 }
 
 hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s) {

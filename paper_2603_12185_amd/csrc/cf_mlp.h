@@ -6,7 +6,7 @@
 // normalised x = (f - mean) / std; z1 = W1^T x + b1, a1 = silu(z1) (64);
 // z2 = W2^T a1 + b2, a2 = silu(z2) (64); y = W3^T a2 + b3 (16 outputs, one per
 // facet used).  The facet impulse gain is the heuristic's times
-// exp(clamp(y_f, -ln 16, ln 16)).
+// exp(clamp(y_f, -ln 256, ln 256)).
 //
 // Flat float32 parameters (row-major): mean[8], std[8], W1[8][64], b1[64],
 // W2[64][64], b2[64], W3[64][16], b3[16].
@@ -28,7 +28,7 @@ constexpr int NIN = 8, NH = 64, NOUT = 16, NFEAT = 7;
 constexpr int OFF_MEAN = 0, OFF_STD = 8, OFF_W1 = 16, OFF_B1 = OFF_W1 + NIN * NH, OFF_W2 = OFF_B1 + NH,
               OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NOUT,
               NPARAM = OFF_B3 + NOUT, TRAIN_FROM = OFF_W1;
-constexpr float CLIP = 2.7725887222397811f;  // ln 16
+constexpr float CLIP = 5.5451774444795623f;  // ln 256
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
