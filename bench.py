@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--rollout-steps", type=int, default=1000,
                     help="steps of the batched-rollout form timed after the plain form (0: skip)")
+    ap.add_argument("--learned-steps", type=int, default=200,
+                    help="steps of the learned-impedance form timed after the plain form (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB five times (a "
                          "known-traffic kernel that calibrates HBM byte counters under a profiler)")
@@ -226,6 +228,51 @@ def main():
             "alg_GBps": b_roll * nw * T / rwall / 1e9,
             "persistent_kernel_default_shape": {"block": first[2], "used": first[3],
                                                 "ms_per_step": rwall_p * 1e3 / T},
+        }
+    if args.learned_steps > 0:
+        # Learned-impedance form: train the network on the GPU on one step's
+        # contacts of this workload (exported by the step itself), then time K'
+        # steps with the learned gains and compare mean penetration and normal
+        # jitter with the plain form over the same steps from the same state.
+        from paper_2603_12185_amd import learned
+        L = args.learned_steps
+        qs, vs = torch.from_numpy(state_q).to(dev), torch.from_numpy(state_v).to(dev)
+        model.set_launch(64, 256)
+        t0 = time.perf_counter()
+        feats, targets, _, _ = learned.collect(model, qs.clone(), vs.clone(), steps=1)
+        net, losses = learned.train(feats, targets, model.nfacet, steps=300)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        mp, xp, _, vp = learned.penetration_stats(model, qs.clone(), vs.clone(), 100)
+        model.set_learned_impedance(net, margin=1e-4)
+        ml, xl, _, vl = learned.penetration_stats(model, qs.clone(), vs.clone(), 100)
+        lq = [qs.clone(), torch.empty_like(qs)]
+        lv = [vs.clone(), torch.empty_like(vs)]
+        lpp = [(model._h, sp, ptr(lq[i]), ptr(lv[i]), None, ptr(lq[1 - i]), ptr(lv[1 - i])) for i in (0, 1)]
+        for t in range(20):
+            lib.cf_step(*lpp[t & 1], None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(L):
+            st = lib.cf_step(*lpp[t & 1], None)
+            if st != 0:
+                raise cfsim.CFError(st, cfsim.last_error())
+        torch.cuda.synchronize()
+        lwall = time.perf_counter() - t0
+        us_lc, us_lr = model.time_kernels(qs, vs, lq[1], lv[1], reps=100)
+        model.set_learned_impedance(None)
+        ke = lambda vv: float((vv.reshape(nw, -1, 6)[:, :, 0:3] ** 2).sum(-1).mean())
+        result["learned_form"] = {
+            "value": nw * L / lwall, "unit": "env-steps/s", "steps": L, "ms_per_step": lwall * 1e3 / L,
+            "vs_plain_form": (nw * L / lwall) / env_steps,
+            "kernel_us": {"collide_kernel": us_lc, "resolve_kernel_learned": us_lr},
+            "network": "7-64-64-%d SiLU, bf16 MFMA, fp32 accumulation" % model.nfacet,
+            "training": f"{feats.shape[0]} contacts of one step of this workload, 300 Adam steps of 65536, "
+                        f"loss {losses[0]:.3g} -> {losses[-1]:.3g}, {train_s:.1f} s incl. data export",
+            "fallback_margin_m": 1e-4,
+            "mean_penetration_mm": {"plain": mp * 1e3, "learned": ml * 1e3},
+            "max_penetration_mm": {"plain": xp * 1e3, "learned": xl * 1e3},
+            "mean_sq_speed_after_100_steps": {"plain": ke(vp), "learned": ke(vl)},
         }
     if args.cpu_worlds > 0:
         threads = min(16, len(os.sched_getaffinity(0)))
