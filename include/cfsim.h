@@ -202,10 +202,11 @@ cf_status cf_model_set_impedance(cf_model *m, int32_t mode);
 cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float margin);
 
 /* Workgroup size (64, 128 or 256 threads, one world per workgroup) of the
- * collision, the resolution and the rollout kernel (defaults 64, 256, 256);
- * results do not depend on the choice (same arithmetic, same summation order
- * within a wave; the per-body sums are ordered by wave, so the last bits of
- * v+ may differ between sizes). */
+ * collision, the resolution and the rollout kernel (defaults 64, 128, 256);
+ * results do not depend on the choice beyond the last bits of v+ (same
+ * arithmetic; the per-body contact sums are exact integer sums within a chunk
+ * of one contact per thread, and chunks add in order, so the chunk size can
+ * change the rounding). */
 cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolve_block, int32_t rollout_block);
 /* Also reports whether cf_rollout uses the persistent kernel (1) or step calls (0). */
 cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t *resolve_block,

@@ -45,7 +45,7 @@ struct cf_model {
   cf::BodyC *d_body = nullptr;
   cf::SubTree *d_sub = nullptr;
   int norient = 0, nsub = 0, art_floats = 0;
-  int block_collide = 64, block_resolve = 256, block_rollout = 256;
+  int block_collide = 64, block_resolve = 128, block_rollout = 256;
   size_t lds_rollout = 0;
   int block_backward = 0;  // 0: the adjoint's LDS does not fit any workgroup size
   size_t lds_backward = 0;
@@ -300,14 +300,12 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
     }
   }
   m->lds_collide = cf::collide_lds_bytes(m->nq, nb, ng, m->norient, m->nsub);
-  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, 256, m->nsub, m->art_floats);
+  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->nsub, m->art_floats);
   if (m->lds_collide > kLdsLimit || m->lds_resolve > kLdsLimit) {
     delete m;
     return set_err(CF_E_UNSUPPORTED, "world too large for one workgroup's LDS (reduce bodies or geoms)");
   }
-  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->block_resolve, m->nsub, m->art_floats);
-  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, nb, ng, m->norient, m->nsub, m->art_floats,
-                                         m->block_rollout, m->ncon_max);
+  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, nb, ng, m->norient, m->nsub, m->art_floats, m->ncon_max);
   for (int bs : {256, 128, 64}) {
     const size_t l = cf::backward_lds_bytes(m->nq, m->nv, nb, ng, bs);
     if (l <= kLdsLimit) { m->block_backward = bs; m->lds_backward = l; break; }
@@ -429,7 +427,7 @@ static hipError_t launch_resolve_model(const cf_model *m, cf::ResolveArgs ra, hi
   if (!m->mlp) return cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
   const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
   ra.mlp = m->mlp;
-  const size_t lds = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, block, 0, 0) + cf::resolve_learned_lds_bytes(block);
+  const size_t lds = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, 0, 0) + cf::resolve_learned_lds_bytes(block);
   return cf::launch_resolve(ra, m->nw, block, lds, s);
 }
 
@@ -566,7 +564,7 @@ cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float
   if (m->nsub > 0) return set_err(CF_E_UNSUPPORTED, "learned impedance covers models of free bodies only");
   if (m->p.imp_diag) return set_err(CF_E_UNSUPPORTED, "learned impedance scales the heuristic, not the diagonal form");
   const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
-  if (cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, block, 0, 0) + cf::resolve_learned_lds_bytes(block) > kLdsLimit)
+  if (cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, 0, 0) + cf::resolve_learned_lds_bytes(block) > kLdsLimit)
     return set_err(CF_E_UNSUPPORTED, "world too large for the learned resolution's LDS");
   m->mlp = params;
   m->p.mlp_margin = margin;
@@ -594,9 +592,7 @@ cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolv
   m->block_resolve = resolve_block;
   m->block_rollout = rollout_block;
   m->rollout_steps = false;
-  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, resolve_block, m->nsub, m->art_floats);
-  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->art_floats,
-                                         rollout_block, m->ncon_max);
+  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->art_floats, m->ncon_max);
   return CF_OK;
 }
 
@@ -633,8 +629,6 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
     for (int ir = 0; ir < 3 && st == CF_OK; ++ir) {
       m->block_collide = sizes[ic];
       m->block_resolve = sizes[ir];
-      m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, sizes[ir], m->nsub, m->art_floats);
-      if (m->lds_resolve > kLdsLimit) continue;
       (void)hipMemcpyAsync(qa, q, sizeof(float) * sq, hipMemcpyDeviceToDevice, s);
       (void)hipMemcpyAsync(va, v, sizeof(float) * sv, hipMemcpyDeviceToDevice, s);
       st = cf_step(m, stream, qa, va, nullptr, qb, vb, nullptr);  // warm-up
@@ -650,8 +644,7 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
     }
   m->rollout_steps = false;
   for (int io = 0; io < 3 && st == CF_OK; ++io) {
-    const size_t lds = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->art_floats,
-                                             sizes[io], m->ncon_max);
+    const size_t lds = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->art_floats, m->ncon_max);
     if (lds > kLdsLimit) continue;
     m->block_rollout = sizes[io];
     m->lds_rollout = lds;

@@ -851,17 +851,19 @@ hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t ld
 // resolution
 // ====================================================================
 // LDS: q, v, tau rows; per body 7 float4 (com|invm, vs|tr, ws, Iinv a, Iinv b,
-// accumulated force, accumulated torque); per geom float4 friction + int body;
-// per lane the two wrench entries of its contact (float4 + float2 each).
+// accumulated force, accumulated torque) and 9 ints (fixed-point wrench sums
+// of the current contact chunk, the exponents of its force and its torque
+// part and the entry count, stored component-major); per geom float4
+// friction + int body.
 // LDS scratch of the resolution of one world (after its q, v and tau rows).
-__host__ __device__ size_t resolve_region_bytes(int nb, int ng, int block, int nsub, int art_floats) {
-  return sizeof(float4) * 7 * (size_t)nb + sizeof(float4) * (size_t)ng +
-         (sizeof(float4) + sizeof(float2)) * 2 * (size_t)block + sizeof(int) * (size_t)pad4(ng) +
+__host__ __device__ size_t resolve_region_bytes(int nb, int ng, int nsub, int art_floats) {
+  return sizeof(float4) * 7 * (size_t)nb + sizeof(float4) * (size_t)ng + sizeof(int) * 9 * (size_t)pad4(nb) +
+         sizeof(int) * (size_t)pad4(ng) +
          (nsub > 0 ? sizeof(float4) * 5 * (size_t)nb + sizeof(float) * (size_t)pad4(art_floats) : 0);
 }
 
-size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats) {
-  return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + resolve_region_bytes(nb, ng, block, nsub, art_floats);
+size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int nsub, int art_floats) {
+  return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + resolve_region_bytes(nb, ng, nsub, art_floats);
 }
 
 // Arrays of the resolution's LDS scratch (layout of resolve_region_bytes()).
@@ -871,23 +873,20 @@ struct ResolveRegion {
   float4 *bI0, *bI1;     // inverse world inertia (xx yy zz xy | xz yz)
   float4 *accF, *accT;   // accumulated contact force and torque
   float4 *gM;            // per geom (mu_t, mu_tor, mu_rol)
-  float4 *vA, *vB;       // per lane wrench entries, sides a and b
-  float2 *vA2, *vB2;
+  int *fx;               // fixed-point chunk sums: 6 components, 2 exponents, count (pad4(nb) each)
   int *gB;               // per geom body
   float4 *bO, *bAx, *bR; // articulated bodies: origin, joint axis, rotation rows
   float *art;            // articulated subtree work blocks
 };
 
-template <int BS>
 __device__ inline ResolveRegion resolve_region(float4 *reg, int nb, int ng) {
   ResolveRegion r;
   r.bC = reg;
   r.bV = r.bC + nb; r.bW = r.bV + nb; r.bI0 = r.bW + nb; r.bI1 = r.bI0 + nb;
   r.accF = r.bI1 + nb; r.accT = r.accF + nb;
   r.gM = r.accT + nb;
-  r.vA = r.gM + ng; r.vB = r.vA + BS;
-  r.vA2 = reinterpret_cast<float2 *>(r.vB + BS); r.vB2 = r.vA2 + BS;
-  r.gB = reinterpret_cast<int *>(r.vB2 + BS);
+  r.fx = reinterpret_cast<int *>(r.gM + ng);
+  r.gB = r.fx + 9 * pad4(nb);
   r.bO = reinterpret_cast<float4 *>(r.gB + pad4(ng));
   r.bAx = r.bO + nb; r.bR = r.bAx + nb;
   r.art = reinterpret_cast<float *>(r.bR + 3 * nb);
@@ -1041,6 +1040,52 @@ __device__ inline bool learned_ok(const float *lh, const float *ll, float vn, fl
   return pl <= ph + margin && el <= eh + em && isfinite(vl);
 }
 
+// Fixed-point wrench sums of the resolution: exponent slot of a body with no
+// entry yet, exponent of a zero entry (below any float's), and the exponent
+// that flags a non-finite entry.
+constexpr int FX_EMPTY = -1024, FX_ZERO = -1000, FX_BAD = 1 << 20;
+
+// e with |x|, |y|, |z| < 2^e: the binary exponent of the largest, FX_ZERO
+// when all are zero (zero fits any scale) and FX_BAD when one is not finite.
+__device__ inline int fx_exp(float x, float y, float z) {
+  const float m = fmaxf(fmaxf(fabsf(x), fabsf(y)), fabsf(z));
+  if (!(fabsf(x) + fabsf(y) + fabsf(z) <= 3.40282347e38f)) return FX_BAD;  // NaN or infinity
+  return m == 0.f ? FX_ZERO : __builtin_amdgcn_frexp_expf(m);
+}
+
+// Scale exponent of a part with n entries below 2^e: s = 31 - e - ceil(log2 n).
+__device__ inline int fx_shift(int e, int n) {
+  const int L = n > 1 ? 32 - __clz(n - 1) : 0;
+  return 31 - e - L;
+}
+
+// Raises the force and torque exponents at e and e + stride to cover the
+// wrench entry (a.xyz force, a.w b.xy torque) and counts the entry.
+__device__ inline void fx_exponents(int *e, int *n, int stride, float4 a, float2 b) {
+  atomicMax(e, fx_exp(a.x, a.y, a.z));
+  atomicMax(e + stride, fx_exp(a.w, b.x, b.y));
+  atomicAdd(n, 1);
+}
+
+// Adds the entry (a, b), each part scaled by its 2^s and truncated, to the six
+// sums at p, p + stride, ... (exponents at p + 6 stride and p + 7 stride; n
+// entries).
+__device__ inline void fx_add(int *p, int stride, int n, float4 a, float2 b) {
+  const int sf = fx_shift(p[6 * stride], n), st = fx_shift(p[7 * stride], n);
+  atomicAdd(p, __float2int_rz(ldexpf(a.x, sf)));
+  atomicAdd(p + stride, __float2int_rz(ldexpf(a.y, sf)));
+  atomicAdd(p + 2 * stride, __float2int_rz(ldexpf(a.z, sf)));
+  atomicAdd(p + 3 * stride, __float2int_rz(ldexpf(a.w, st)));
+  atomicAdd(p + 4 * stride, __float2int_rz(ldexpf(b.x, st)));
+  atomicAdd(p + 5 * stride, __float2int_rz(ldexpf(b.y, st)));
+}
+
+// Float value of a fixed-point sum with exponent e over n entries (NaN when an
+// entry was not finite).
+__device__ inline float fx_value(int sum, int e, int n) {
+  return e >= FX_BAD ? __builtin_nanf("") : ldexpf((float)sum, -fx_shift(e, n));
+}
+
 // Per geom: body and pair-friction inputs (mu_t, mu_tor, mu_rol) in LDS, for
 // geoms g0, g0 + BS, ... (callers that prefetched geom threadIdx.x pass g0 = BS).
 template <int CONDIM, int BS>
@@ -1066,14 +1111,14 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
                               float4 mi0, float4 *reg, size_t xbase, bool geoms_ready = false,
                               const mlp::Weights *lnet = nullptr, float *lfeat = nullptr, float *lout = nullptr) {
   constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
-  constexpr int NW = BS / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = a.nb, ng = a.ng;
-  const ResolveRegion RR = resolve_region<BS>(reg, nb, ng);
+  const ResolveRegion RR = resolve_region(reg, nb, ng);
   float4 *bC = RR.bC, *bV = RR.bV, *bW = RR.bW, *bI0 = RR.bI0, *bI1 = RR.bI1;
-  float4 *accF = RR.accF, *accT = RR.accT, *gM = RR.gM, *vA = RR.vA, *vB = RR.vB;
-  float2 *vA2 = RR.vA2, *vB2 = RR.vB2;
-  int *gB = RR.gB;
+  float4 *accF = RR.accF, *accT = RR.accT, *gM = RR.gM;
+  int *gB = RR.gB, *fx = RR.fx;
+  const int nbp = pad4(nb);
+  int *fxE = fx + 6 * nbp, *fxN = fx + 8 * nbp;
   float4 *bO = RR.bO, *bAx = RR.bAx, *bR = RR.bR;  // articulated bodies only
   float *art = RR.art;
   const Params P = a.p;
@@ -1128,6 +1173,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     accF[b] = make_float4(0.f, 0.f, 0.f, 0.f);
     accT[b] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
+  for (int i = tid; i < 9 * nbp; i += BS) fx[i] = i >= 6 * nbp && i < 8 * nbp ? FX_EMPTY : 0;
   // ---- articulated subtrees: one lane each (same equations, dense per-subtree M)
   if (ART)
   for (int si = tid; si < a.nsub; si += BS) {
@@ -1137,7 +1183,6 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   __syncthreads();
 
   // ---- contacts: facet impulses, wrenches, deterministic per-body reduction
-  const unsigned long long below = lanes_below(lane);
   const float aa = P.k_user * P.h + P.d_user;
   for (int base = 0; base < nc; base += BS) {
     const int k = base + tid;
@@ -1285,66 +1330,37 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
         }
       }
     }
-    vA[tid] = WA; vA2[tid] = WA2;
-    vB[tid] = WB; vB2[tid] = WB2;
+    // Per-body sums of the chunk's wrench entries in fixed point: integer
+    // additions commute, so the order of the LDS atomics does not change the
+    // result.  The force and the torque part of body k are scaled by 2^s,
+    // s = 31 - e - L, with every entry's components of that part below 2^e in
+    // magnitude and L = ceil(log2(entries)), so no sum reaches 2^31.
+    if (kA < nb) fx_exponents(fxE + kA, fxN + kA, nbp, WA, WA2);
+    if (kB < nb) fx_exponents(fxE + kB, fxN + kB, nbp, WB, WB2);
     __syncthreads();
-
-    // Key matching inside the wave: each lane learns which lanes carry the
-    // same body on side a and on side b (one ballot per key bit and side).
-    unsigned long long eAA = ~0ull, eAB = ~0ull, eBA = ~0ull, eBB = ~0ull;
-    for (int i = 0; i < a.nbits; ++i) {
-      const bool a1 = (kA >> i) & 1, b1 = (kB >> i) & 1;
-      const unsigned long long bA = __ballot(a1), bBv = __ballot(b1);
-      eAA &= a1 ? bA : ~bA;
-      eAB &= a1 ? bBv : ~bBv;
-      eBA &= b1 ? bA : ~bA;
-      eBB &= b1 ? bBv : ~bBv;
-    }
-    // Leader of a key: its first side-a lane, else its first side-b lane.
-    // It sums the key's entries in lane order, side a before side b.
-    const bool leadA = kA < nb && !(eAA & below);
-    const bool leadB = kB < nb && !eBA && !(eBB & below);
-    const int wb0 = wave * 64;
-    float4 SA = make_float4(0.f, 0.f, 0.f, 0.f), SB = SA;
-    float2 SA2 = make_float2(0.f, 0.f), SB2 = SA2;
-    if (leadA) {
-      for (unsigned long long m = eAA; m; m &= m - 1) {
-        const int l = wb0 + __ffsll((unsigned long long)m) - 1;
-        const float4 u = vA[l]; const float2 u2 = vA2[l];
-        SA.x += u.x; SA.y += u.y; SA.z += u.z; SA.w += u.w; SA2.x += u2.x; SA2.y += u2.y;
-      }
-      for (unsigned long long m = eAB; m; m &= m - 1) {
-        const int l = wb0 + __ffsll((unsigned long long)m) - 1;
-        const float4 u = vB[l]; const float2 u2 = vB2[l];
-        SA.x += u.x; SA.y += u.y; SA.z += u.z; SA.w += u.w; SA2.x += u2.x; SA2.y += u2.y;
-      }
-    }
-    if (leadB) {
-      for (unsigned long long m = eBB; m; m &= m - 1) {
-        const int l = wb0 + __ffsll((unsigned long long)m) - 1;
-        const float4 u = vB[l]; const float2 u2 = vB2[l];
-        SB.x += u.x; SB.y += u.y; SB.z += u.z; SB.w += u.w; SB2.x += u2.x; SB2.y += u2.y;
-      }
-    }
-    // waves add their partial sums in wave order (keys are distinct within a wave)
+    if (kA < nb) fx_add(fx + kA, nbp, fxN[kA], WA, WA2);
+    if (kB < nb) fx_add(fx + kB, nbp, fxN[kB], WB, WB2);
+    __syncthreads();
+    // chunk sums into the float accumulators (chunks in order), slots cleared
+    for (int b = tid; b < nb; b += BS) {
+      const int n = fxN[b];
+      if (n == 0) continue;
+      float4 F = accF[b], T = accT[b];
+      const int ef = fxE[b], et = fxE[nbp + b];
+      F.x += fx_value(fx[b], ef, n);
+      F.y += fx_value(fx[nbp + b], ef, n);
+      F.z += fx_value(fx[2 * nbp + b], ef, n);
+      T.x += fx_value(fx[3 * nbp + b], et, n);
+      T.y += fx_value(fx[4 * nbp + b], et, n);
+      T.z += fx_value(fx[5 * nbp + b], et, n);
+      accF[b] = F; accT[b] = T;
 #pragma unroll
-    for (int wv = 0; wv < NW; ++wv) {
-      if (wave == wv) {
-        if (leadA) {
-          float4 F = accF[kA], T = accT[kA];
-          F.x += SA.x; F.y += SA.y; F.z += SA.z;
-          T.x += SA.w; T.y += SA2.x; T.z += SA2.y;
-          accF[kA] = F; accT[kA] = T;
-        }
-        if (leadB) {
-          float4 F = accF[kB], T = accT[kB];
-          F.x += SB.x; F.y += SB.y; F.z += SB.z;
-          T.x += SB.w; T.y += SB2.x; T.z += SB2.y;
-          accF[kB] = F; accT[kB] = T;
-        }
-      }
-      __syncthreads();
+      for (int c = 0; c < 6; ++c) fx[c * nbp + b] = 0;
+      fxE[b] = FX_EMPTY;
+      fxE[nbp + b] = FX_EMPTY;
+      fxN[b] = 0;
     }
+    __syncthreads();
   }
 
   // ---- velocity correction (Eq. vel_correction) and semi-implicit Euler
@@ -1438,7 +1454,7 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   } else {
     for (int i = tid; i < nv; i += BS) st[i] = 0.f;
   }
-  const ResolveRegion RR = resolve_region<BS>(reg, nb, ng);
+  const ResolveRegion RR = resolve_region(reg, nb, ng);
   if (tid < ng) {
     RR.gB[tid] = gb0;
     RR.gM[tid] = make_float4(mu0, fr0.x, fr0.y, 0.f);
@@ -1447,7 +1463,7 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   mlp::Weights *lnet = nullptr;
   float *lfeat = nullptr, *lout = nullptr;
   if constexpr (LEARN) {
-    char *base = reinterpret_cast<char *>(reg) + resolve_region_bytes(nb, ng, BS, 0, 0);
+    char *base = reinterpret_cast<char *>(reg) + resolve_region_bytes(nb, ng, 0, 0);
     lnet = reinterpret_cast<mlp::Weights *>(base);
     lfeat = reinterpret_cast<float *>(base + (sizeof(mlp::Weights) + 15) / 16 * 16);
     lout = lfeat + BS * mlp::NIN;
@@ -1463,10 +1479,9 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
 // ====================================================================
 // rollout: T steps of one world per workgroup, state and contacts in LDS
 // ====================================================================
-size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int art_floats, int block,
-                         int cap) {
+size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int art_floats, int cap) {
   const size_t c = collide_region_bytes(nb, ng, norient, nsub);
-  const size_t r = resolve_region_bytes(nb, ng, block, nsub, art_floats);
+  const size_t r = resolve_region_bytes(nb, ng, nsub, art_floats);
   return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + 2 * sizeof(float4) * (size_t)cap + (c > r ? c : r);
 }
 
@@ -1638,7 +1653,7 @@ __device__ void body_segment_sum(int kA, int kB, const float4 *pa, const float4 
 // the adjoints of the contact force and torque sums and the direct quaternion
 // adjoint; per lane two packed 3-float4 payloads.
 size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block) {
-  return resolve_lds_bytes(nq, nv, nb, ng, block, 0, 0) + sizeof(float) * pad4(nq) +
+  return resolve_lds_bytes(nq, nv, nb, ng, 0, 0) + sizeof(float) * pad4(nq) +
          sizeof(float4) * (6 * (size_t)nb + 6 * (size_t)block);
 }
 
@@ -1661,7 +1676,7 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   float *sv = sq + pad4(nq);
   float *st = sv + pad4(nv);
   float4 *reg = reinterpret_cast<float4 *>(st + pad4(nv));
-  float *sq0 = reinterpret_cast<float *>(reg + resolve_region_bytes(nb, ng, BS, 0, 0) / sizeof(float4));
+  float *sq0 = reinterpret_cast<float *>(reg + resolve_region_bytes(nb, ng, 0, 0) / sizeof(float4));
   float4 *acc = reinterpret_cast<float4 *>(sq0 + pad4(nq));  // [3][nb]
   float4 *bFb = acc + 3 * nb, *bTb = bFb + nb, *bQb = bTb + nb;
   float4 *pay = bQb + nb;  // [2][3][BS]
@@ -1687,7 +1702,7 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   }
   resolve_world<CONDIM, BS, false>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg,
                                    cbase);
-  const ResolveRegion RR = resolve_region<BS>(reg, nb, ng);
+  const ResolveRegion RR = resolve_region(reg, nb, ng);
   const Params P = a.p;
   auto xyz = [](float4 f) { return vec(f.x, f.y, f.z); };
 
