@@ -31,7 +31,20 @@
  *    corner bits x,y,z = bit 0,1,2 set for +half-size; capsule minus end first).
  *    Beyond ncon_max contacts are dropped and counted as overflow.
  *  - Excluded pairs: both geoms static, same body, parent-child bodies, and
- *    pair types outside {plane-sphere, plane-capsule, plane-box, sphere-sphere}.
+ *    pair types outside {plane-sphere, plane-capsule, plane-box, sphere-sphere,
+ *    box-sphere, box-capsule}.
+ *  - Box-sphere: the box is geom a; the sphere centre c, in the box frame, is
+ *    clamped to the box; outside (distance d > 1e-12 from the clamped point)
+ *    the normal is the unit vector from the clamped point to c and phi = d - r;
+ *    otherwise the normal is the outward axis of the face with the smallest
+ *    depth s_k - |c_k| (lowest axis on ties, + side when c_k >= 0) and
+ *    phi = -depth - r.  The point is c - n (r + phi / 2).  Box-capsule: as for
+ *    the plane, the capsule meets the box with its two end spheres (minus end
+ *    first); contact of the box with the capsule's side between the ends is
+ *    not modelled.
+ *  - Position actuators (the hand of the paper's application section): the
+ *    applied force kp (u - theta) - kd theta_dot of an actuated hinge or slide
+ *    dof is explicit (start-of-step state).
  *  - Degenerate sphere-sphere (centres closer than 1e-12) uses n = +z; a
  *    contact whose two traces sum to 0 is skipped.
  *  - Exact diagonal impedance (impedance = 1, the alternative the paper states
@@ -59,6 +72,8 @@ struct cfo_model {
   int *body_parent, *body_jnt, *geom_type, *geom_body;
   double *body_pos, *body_quat, *body_ipos, *jnt_axis, *body_mass, *body_inertia;
   double *geom_size, *geom_pos, *geom_quat, *geom_friction;
+  double *dof_kp, *dof_kd; /* [nv], NULL without actuators */
+  int *dof_q;              /* [nv] q index of an actuated dof, -1 otherwise */
 };
 
 /* ------------------------------------------------------------------ */
@@ -131,6 +146,7 @@ void cfo_destroy(cfo_model *m) {
   free(m->body_pos); free(m->body_quat); free(m->body_ipos); free(m->jnt_axis);
   free(m->body_mass); free(m->body_inertia);
   free(m->geom_size); free(m->geom_pos); free(m->geom_quat); free(m->geom_friction);
+  free(m->dof_kp); free(m->dof_kd); free(m->dof_q);
   free(m);
 }
 
@@ -211,6 +227,25 @@ int cfo_create(const cfo_desc *d, cfo_model **out, char *err, int errlen) {
   }
   m->nq = qa; m->nv = da;
   m->nf = d->condim == 1 ? 1 : d->condim == 3 ? 4 : d->condim == 4 ? 6 : 10;
+  m->d.dof_kp = m->d.dof_kd = NULL;
+  if (d->dof_kp || d->dof_kd) {
+    m->dof_kp = (double *)calloc(da ? da : 1, sizeof(double));
+    m->dof_kd = (double *)calloc(da ? da : 1, sizeof(double));
+    m->dof_q = (int *)malloc(sizeof(int) * (da ? da : 1));
+    if (!m->dof_kp || !m->dof_kd || !m->dof_q) { cfo_destroy(m); return CFO_ENOMEM; }
+    for (int b = 0; b < nb; b++) {
+      int t = m->body_jnt[b];
+      for (int k = 0; k < jnt_nv(t); k++) {
+        int i = m->dadr[b] + k;
+        double kp = d->dof_kp ? d->dof_kp[i] : 0.0, kd = d->dof_kd ? d->dof_kd[i] : 0.0;
+        if (!(kp >= 0 && kd >= 0 && kp < 1e300 && kd < 1e300)) { cfo_destroy(m); return fail(err, errlen, "actuator gains must be finite and >= 0"); }
+        if (t == CFO_FREE && (kp != 0 || kd != 0)) { cfo_destroy(m); return fail(err, errlen, "actuators only on hinge or slide dofs"); }
+        m->dof_kp[i] = kp; m->dof_kd[i] = kd;
+        m->dof_q[i] = (kp != 0 || kd != 0) ? m->qadr[b] : -1;
+      }
+    }
+    m->d.dof_kp = m->dof_kp; m->d.dof_kd = m->dof_kd;
+  }
   m->d.body_parent = m->body_parent; m->d.body_jnt = m->body_jnt;
   m->d.geom_type = m->geom_type; m->d.geom_body = m->geom_body;
   m->d.body_pos = m->body_pos; m->d.body_quat = m->body_quat; m->d.body_ipos = m->body_ipos;
@@ -504,6 +539,10 @@ static int pair_allowed(const cfo_model *m, int i, int j) {
   int ti = d->geom_type[i], tj = d->geom_type[j];
   if (ti == CFO_PLANE && tj == CFO_PLANE) return 0;
   if (ti == CFO_PLANE || tj == CFO_PLANE) return 1;
+  if (ti == CFO_BOX || tj == CFO_BOX) {
+    int o = ti == CFO_BOX ? tj : ti;
+    return o == CFO_SPHERE || o == CFO_CAPSULE;
+  }
   return ti == CFO_SPHERE && tj == CFO_SPHERE;
 }
 
@@ -512,6 +551,7 @@ static int pair_candidates(const cfo_model *m, int w, int i, int j, const frame_
   const cfo_desc *d = &m->d;
   int ga = i, gb = j;
   if (d->geom_type[j] == CFO_PLANE) { ga = j; gb = i; }
+  else if (d->geom_type[j] == CFO_BOX && d->geom_type[i] != CFO_PLANE) { ga = j; gb = i; }
   gpose_t A, B;
   geom_pose(m, w, ga, f, &A);
   geom_pose(m, w, gb, f, &B);
@@ -550,6 +590,43 @@ static int pair_candidates(const cfo_model *m, int w, int i, int j, const frame_
         memcpy(C->n, nrm, sizeof nrm);
         for (int k = 0; k < 3; k++) C->p[k] = x[k] - 0.5 * phi * nrm[k];
       }
+    }
+  } else if (ta == CFO_BOX) { /* box - sphere, box - capsule (end spheres) */
+    const double *sa = gsize(m, w, ga);
+    int nend = tb == CFO_SPHERE ? 1 : 2;
+    for (int e = 0; e < nend; e++) {
+      double ctr[3];
+      memcpy(ctr, B.pos, sizeof ctr);
+      if (tb == CFO_CAPSULE) {
+        double sgn = e == 0 ? -1.0 : 1.0;
+        for (int k = 0; k < 3; k++) ctr[k] += sgn * sb[1] * B.rot[3 * k + 2];
+      }
+      double r = sb[0], dw[3], l[3], diff[3], nl[3] = {0, 0, 0}, nrm[3], phi;
+      sub3(ctr, A.pos, dw);
+      for (int k = 0; k < 3; k++) l[k] = A.rot[k] * dw[0] + A.rot[3 + k] * dw[1] + A.rot[6 + k] * dw[2];
+      for (int k = 0; k < 3; k++) {
+        double cl = l[k] < -sa[k] ? -sa[k] : (l[k] > sa[k] ? sa[k] : l[k]);
+        diff[k] = l[k] - cl;
+      }
+      double dist = sqrt(dot3(diff, diff));
+      if (dist > 1e-12) {
+        for (int k = 0; k < 3; k++) nl[k] = diff[k] / dist;
+        phi = dist - r;
+      } else {
+        int kmin = 0;
+        double dmin = sa[0] - fabs(l[0]);
+        for (int k = 1; k < 3; k++) {
+          double dk = sa[k] - fabs(l[k]);
+          if (dk < dmin) { dmin = dk; kmin = k; }
+        }
+        nl[kmin] = l[kmin] >= 0 ? 1.0 : -1.0;
+        phi = -dmin - r;
+      }
+      mv3(A.rot, nl, nrm);
+      contact_t *C = c + n++;
+      C->ga = ga; C->gb = gb; C->sub = e; C->phi = phi;
+      memcpy(C->n, nrm, sizeof nrm);
+      for (int k = 0; k < 3; k++) C->p[k] = ctr[k] - nrm[k] * (r + 0.5 * phi);
     }
   } else { /* sphere - sphere */
     const double *sa = gsize(m, w, ga);
@@ -663,7 +740,11 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
   if (nv > 0 && cholesky(M, nv)) { rc = CFO_ESINGULAR; goto done; }
 
   /* --- smooth prediction, Eq. smooth_vel: v_s = v + h M^-1 (tau - c) --- */
-  for (int i = 0; i < nv; i++) vs[i] = (tau ? tau[i] : 0.0) - c[i];
+  for (int i = 0; i < nv; i++) {
+    double ti = tau ? tau[i] : 0.0;
+    if (m->dof_q && m->dof_q[i] >= 0) ti = m->dof_kp[i] * (ti - q[m->dof_q[i]]) - m->dof_kd[i] * v[i];
+    vs[i] = ti - c[i];
+  }
   chol_solve(M, nv, vs);
   for (int i = 0; i < nv; i++) vs[i] = v[i] + h * vs[i];
 

@@ -11,9 +11,12 @@
  *   1. kinematics of a tree of free / hinge / slide joints, the body Jacobians,
  *      the joint-space inertia M = sum_b J_b^T diag(m_b I, I_b) J_b and the bias
  *      c(q, v) (gravity + velocity-product terms) of the step dynamics (Eq. sys_dyn);
- *   2. the smooth prediction v_s = v + h M^-1 (tau - c)   (Eq. smooth_vel);
+ *   2. the smooth prediction v_s = v + h M^-1 (tau - c)   (Eq. smooth_vel), tau
+ *      the applied joint forces (optionally from position actuators on hinge
+ *      and slide dofs: tau = kp (u - theta) - kd theta_dot, u the step's input);
  *   3. an analytic narrow phase (plane-sphere, plane-capsule, plane-box,
- *      sphere-sphere) enumerating geom pairs in index order;
+ *      sphere-sphere, box-sphere, box-capsule) enumerating geom pairs in index
+ *      order;
  *   4. for every contact, dense facet rows J~ = J_n - mu_s d^T J_s
  *      (Eqs. dual_polyhedral / tilde_defs), the impedance of Eqs. k_d_setting and
  *      r_scaling, and the facet impulse lambda*h = (-K(J~ v_s h + phi) - D J~ v_s)_+
@@ -51,6 +54,11 @@ typedef struct {
   const double *geom_quat, *geom_friction;         /* [nworld][ngeom][4], [..][3]  */
   double h, gravity[3], k_user, d_user, solimp[5], margin;
   int impedance;                                   /* 0: heuristic M(phi); 1: exact diagonal */
+  /* Position actuators, [nv] each or NULL: on a hinge or slide dof with
+   * kp or kd nonzero the step's input tau_d is the target position u_d and the
+   * applied force is kp_d (u_d - q_d) - kd_d v_d, evaluated at the start of the
+   * step; other dofs take tau_d as a force.  Free-joint dofs must have 0. */
+  const double *dof_kp, *dof_kd;
 } cfo_desc;
 
 typedef struct cfo_model cfo_model;

@@ -35,6 +35,7 @@ class _Desc(C.Structure):
         ("h", C.c_double), ("gravity", C.c_double * 3), ("k_user", C.c_double),
         ("d_user", C.c_double), ("solimp", C.c_double * 5), ("margin", C.c_double),
         ("impedance", C.c_int),
+        ("dof_kp", _dp), ("dof_kd", _dp),
     ]
 
 
@@ -131,6 +132,13 @@ class Oracle:
         d.solimp[:] = [float(x) for x in scene["solimp"]]
         d.margin = float(scene["margin"])
         d.impedance = int(scene.get("impedance", 0))
+        if scene.get("dof_kp") is not None or scene.get("dof_kd") is not None:
+            nv = sum({0: 6, 1: 1, 2: 1}[int(t)] for t in scene["body_jnt"])
+            for key in ("dof_kp", "dof_kd"):
+                val = scene.get(key)
+                a = np.zeros(nv) if val is None else np.ascontiguousarray(val, dtype=np.float64)
+                keep[key] = a
+                setattr(d, key, _d(a))
         self._keep = keep
         h = C.c_void_p()
         err = C.create_string_buffer(256)
