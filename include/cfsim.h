@@ -19,9 +19,15 @@
  *    and v = (COM linear velocity, angular velocity), both in world
  *    coordinates; a state quaternion denotes the rotation of its normalised
  *    value and is re-normalised by every step.
- *  - Contact normal n points from geom a to geom b; a plane is always geom a;
- *    phi > 0 means separated; the contact point is the middle of the overlap;
- *    a contact exists when phi < margin.
+ *  - Contact normal n points from geom a to geom b; a plane is always geom a,
+ *    and a box paired with a sphere or capsule is geom a; phi > 0 means
+ *    separated; the contact point is the middle of the overlap; a contact
+ *    exists when phi < margin.
+ *  - Box-sphere: the sphere centre, in the box frame, clamped to the box;
+ *    outside, n runs from the clamped point to the centre and phi is their
+ *    distance minus the radius; inside, n is the outward axis of the face of
+ *    least depth (lowest axis on ties) and phi = -depth - radius.  A capsule
+ *    meets a plane or a box with its two end spheres.
  *  - Tangent basis: helper e_x if |n_x| <= 0.5 else e_y; t1 = normalised
  *    component of the helper orthogonal to n; t2 = n x t1.
  *  - Facet order per contact: tangential d = (1,0),(0,1),(-1,0),(0,-1) in
@@ -34,8 +40,8 @@
  *    and resolved; the rest are counted in overflow.
  *  - Pairs that never produce contacts: both geoms static, same body,
  *    parent-child bodies, and types other than plane-sphere, plane-capsule,
- *    plane-box and sphere-sphere (cf_model_create then returns
- *    CF_W_PAIRS_SKIPPED, a warning).
+ *    plane-box, sphere-sphere, box-sphere and box-capsule (cf_model_create
+ *    then returns CF_W_PAIRS_SKIPPED, a warning).
  *
  * Memory, streams and errors
  *  - Descriptor arrays are host memory, read during cf_model_create only.
@@ -161,7 +167,8 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
  * aligned; gq/gv may alias gq_out/gv_out exactly.  Asynchronous on stream;
  * uses the model's contact workspace (so it must not overlap a cf_step of the
  * same model on another stream).  Models with articulated subtrees (hinge or
- * slide joints) return CF_E_UNSUPPORTED. */
+ * slide joints) or with box-sphere / box-capsule pairs return
+ * CF_E_UNSUPPORTED. */
 cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                            const float *gq_out, const float *gv_out, float *gq, float *gv, float *gtau);
 
@@ -187,6 +194,18 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
  * is available for models of free bodies only (else CF_E_UNSUPPORTED), and
  * cf_step_backward does not cover it. */
 cf_status cf_model_set_impedance(cf_model *m, int32_t mode);
+
+/* Position actuators on hinge and slide dofs (the actuated hand of the
+ * paper's application section, Sec. V): for a dof with kp[i] or kd[i]
+ * nonzero, the per-step input tau[i] (cf_step's tau, cf_rollout's tau_seq) is
+ * the target position u_i and the applied force of Eq. smooth_vel is
+ * kp[i] (u_i - q_i) - kd[i] v_i, evaluated on the state at the start of the
+ * step; other dofs take tau[i] as a force.  kp, kd: host arrays of nv floats
+ * (either may be NULL = zeros), finite and >= 0; a nonzero gain on a free-joint
+ * dof is CF_E_INVALID_ARG.  Both NULL (or all zero) removes the actuators.
+ * The gains are copied to the device synchronously: call between steps, not
+ * while work of this model is in flight. */
+cf_status cf_model_set_actuators(cf_model *m, const float *kp, const float *kd);
 
 /* Learned impedance gains (see the network entry points below): with params
  * (device, cf_mlp_nparam() floats, read at every step, owned by the caller)

@@ -63,6 +63,7 @@ SIGNATURES = {
     "cf_step_backward": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
     "cf_model_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
     "cf_model_set_impedance": ([C.c_void_p, C.c_int32], C.c_int32),
+    "cf_model_set_actuators": ([C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)], C.c_int32),
     "cf_model_set_learned_impedance": ([C.c_void_p, _fp, C.c_float], C.c_int32),
     "cf_model_get_launch": ([C.c_void_p, _ip, _ip, _ip, _ip], C.c_int32),
     "cf_model_autotune": ([C.c_void_p, C.c_void_p, _fp, _fp, C.c_int32, C.POINTER(C.c_float),
@@ -155,6 +156,8 @@ class Model:
         self.nbody, self.ngeom = int(scene["nbody"]), int(scene["ngeom"])
         if int(scene.get("impedance", 0)):
             self.set_impedance(int(scene["impedance"]))
+        if scene.get("dof_kp") is not None or scene.get("dof_kd") is not None:
+            self.set_actuators(scene.get("dof_kp"), scene.get("dof_kd"))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -266,6 +269,22 @@ class Model:
         self._net = net  # the library reads the parameters at every step
         _check(load().cf_model_set_learned_impedance(self._h, None if net is None else _ptr(net.params),
                                                      float(margin)))
+
+    def set_actuators(self, kp, kd):
+        """Position actuators: per-dof gains (host sequences of nv values, None =
+        zeros; both None removes them).  The step input of an actuated dof is
+        then its target position."""
+        def arr(x):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(x, dtype=np.float32)
+            if a.shape != (self.nv,):
+                raise ValueError(f"actuator gains must have nv = {self.nv} entries")
+            return a
+        a, b = arr(kp), arr(kd)
+        fp = C.POINTER(C.c_float)
+        _check(load().cf_model_set_actuators(self._h, None if a is None else a.ctypes.data_as(fp),
+                                             None if b is None else b.ctypes.data_as(fp)))
 
     def set_impedance(self, mode):
         """0: heuristic impedance (default); 1: exact diagonal impedance per facet."""

@@ -533,6 +533,34 @@ CF_HD void plane_point_vjp(Vec<T> pp, Vec<T> n, Vec<T> c, T rad, T phi, Vec<T> n
   nnb = n2;
 }
 
+// line (point e0, unit direction u; a box edge) against a point c with radius
+// rad: d = c - e0, d_perp = d - (u.d) u, n = d_perp / |d_perp|,
+// phi = |d_perp| - rad, p = c - (rad + phi/2) n.
+template <class T>
+CF_HD void line_point_forward(Vec<T> e0, Vec<T> u, Vec<T> c, T rad, Vec<T> &n, T &phi, Vec<T> &p) {
+  const Vec<T> d = c - e0;
+  const Vec<T> dp = d - dot(u, d) * u;
+  const T dist = sqrt(dot(dp, dp));
+  n = (T(1) / dist) * dp;
+  phi = dist - rad;
+  p = c - (rad + T(0.5) * phi) * n;
+}
+
+// Adjoints of c, of the line point e0 and of the line direction u.
+template <class T>
+CF_HD void line_point_vjp(Vec<T> e0, Vec<T> u, Vec<T> c, T rad, Vec<T> n, T phi, Vec<T> nb, T phib, Vec<T> pb,
+                          Vec<T> &cb, Vec<T> &e0b, Vec<T> &ub) {
+  const Vec<T> d = c - e0;
+  const T dist = phi + rad;
+  const Vec<T> n2 = nb - (rad + T(0.5) * phi) * pb;
+  const T phi2 = phib - T(0.5) * dot(n, pb);
+  const Vec<T> dpb = phi2 * n + (T(1) / dist) * (n2 - dot(n, n2) * n);
+  const Vec<T> db = dpb - dot(u, dpb) * u;
+  ub = -dot(u, d) * dpb - dot(u, dpb) * d;
+  cb = pb + db;
+  e0b = -db;
+}
+
 #undef CF_HD
 
 }  // namespace adj

@@ -58,6 +58,10 @@ struct cf_model {
   int *d_ncon = nullptr, *d_over = nullptr;
   size_t lds_collide = 0, lds_resolve = 0;
   const float *mlp = nullptr;  // learned-gain network parameters (caller-owned device memory)
+  bool box_pairs = false;      // box-sphere or box-capsule slots present
+  std::vector<int> dof_jnt;    // joint type of each dof
+  std::vector<int> dof_q;      // q index of each dof's joint (hinge / slide)
+  float4 *d_act = nullptr;     // [nv] position actuators, or null
   // timing
   bool prof = false;
   std::vector<EventSet> events;
@@ -79,7 +83,7 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 
 void free_model(cf_model *m) {
   if (!m) return;
-  (void)hipFree(m->d_slots); (void)hipFree(m->d_gbody); (void)hipFree(m->d_gorient);
+  (void)hipFree(m->d_slots); (void)hipFree(m->d_gbody); (void)hipFree(m->d_gorient); (void)hipFree(m->d_act);
   (void)hipFree(m->d_body); (void)hipFree(m->d_sub); (void)hipFree(m->d_bmi); (void)hipFree(m->d_gdat);
   (void)hipFree(m->d_gpos); (void)hipFree(m->d_gquat); (void)hipFree(m->d_gfr2);
   (void)hipFree(m->d_cnp); (void)hipFree(m->d_cpos); (void)hipFree(m->d_ncon); (void)hipFree(m->d_over);
@@ -231,7 +235,7 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
 
   // ---- candidate slots in canonical order
   std::vector<uint32_t> slots;
-  bool skipped = false;
+  bool skipped = false, box_pairs = false;
   for (int i = 0; i < ng; ++i)
     for (int j = i + 1; j < ng; ++j) {
       const int bi = d->geom_body[i], bj = d->geom_body[j];
@@ -241,6 +245,7 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       const int ti = d->geom_type[i], tj = d->geom_type[j];
       int ga = i, gb = j;
       if (tj == CF_PLANE && ti != CF_PLANE) { ga = j; gb = i; }
+      else if (tj == CF_BOX && ti != CF_PLANE && ti != CF_BOX) { ga = j; gb = i; }
       const int ta = d->geom_type[ga], tb = d->geom_type[gb];
       if (ta == CF_PLANE && tb == CF_SPHERE) slots.push_back(cf::slot_pack(ga, gb, 0, cf::kPlaneSphere));
       else if (ta == CF_PLANE && tb == CF_CAPSULE)
@@ -248,6 +253,11 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       else if (ta == CF_PLANE && tb == CF_BOX)
         for (int c = 0; c < 8; ++c) slots.push_back(cf::slot_pack(ga, gb, c, cf::kPlaneBox));
       else if (ta == CF_SPHERE && tb == CF_SPHERE) slots.push_back(cf::slot_pack(ga, gb, 0, cf::kSphereSphere));
+      else if (ta == CF_BOX && tb == CF_SPHERE) { slots.push_back(cf::slot_pack(ga, gb, 0, cf::kBoxSphere)); box_pairs = true; }
+      else if (ta == CF_BOX && tb == CF_CAPSULE) {
+        for (int e = 0; e < 2; ++e) slots.push_back(cf::slot_pack(ga, gb, e, cf::kBoxCapsule));
+        box_pairs = true;
+      }
       else skipped = true;
     }
 
@@ -257,6 +267,14 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   m->nq = nq; m->nv = nv;
   m->nsub = (int)subs.size(); m->art_floats = art_floats;
   m->nslot = (int)slots.size();
+  m->box_pairs = box_pairs;
+  m->dof_jnt.resize(nv);
+  m->dof_q.resize(nv);
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < (d->body_jnt[b] == CF_JNT_FREE ? 6 : 1); ++k) {
+      m->dof_jnt[dadr[b] + k] = d->body_jnt[b];
+      m->dof_q[dadr[b] + k] = qadr[b];
+    }
   m->nbits = 1;
   while ((1 << m->nbits) <= nb) ++m->nbits;  // keys 0..nb (nb = no body)
   m->p.h = (float)d->h; m->p.k_user = (float)d->k_user; m->p.d_user = (float)d->d_user;
@@ -413,7 +431,7 @@ static cf::ResolveArgs resolve_args(const cf_model *m) {
   ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats;
   ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
   ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
-  ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p;
+  ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p; ra.act = m->d_act;
   return ra;
 }
 
@@ -500,6 +518,7 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
     return set_err(CF_E_INVALID_ARG, "gq/gv may alias gq_out/gv_out only exactly; no other overlap");
   if (m->nsub > 0)
     return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers models of free bodies only");
+  if (m->d_act) return set_err(CF_E_UNSUPPORTED, "cf_step_backward does not cover actuators");
   if (m->p.imp_diag || m->mlp)
     return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers the heuristic impedance only");
   if (!m->block_backward) return set_err(CF_E_UNSUPPORTED, "world too large for the adjoint's LDS");
@@ -512,6 +531,7 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
   b.s = resolve_args(m);
   b.s.q = q; b.s.v = v; b.s.tau = tau;
   b.gpos = m->d_gpos; b.gpos_ws = m->gpos_ws;
+  b.gquat = m->d_gquat; b.gquat_ws = m->gquat_ws;
   b.gq_out = gq_out; b.gv_out = gv_out; b.gq = gq; b.gv = gv; b.gtau = gtau;
   e = cf::launch_backward(b, m->nw, m->block_backward, m->lds_backward, s);
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("backward launch: ") + hipGetErrorString(e));
@@ -580,6 +600,37 @@ cf_status cf_model_set_impedance(cf_model *m, int32_t mode) {
   if (mode == CF_IMPEDANCE_DIAGONAL && m->nsub > 0)
     return set_err(CF_E_UNSUPPORTED, "the diagonal impedance covers models of free bodies only");
   m->p.imp_diag = mode == CF_IMPEDANCE_DIAGONAL ? 1 : 0;
+  return CF_OK;
+}
+
+cf_status cf_model_set_actuators(cf_model *m, const float *kp, const float *kd) {
+  if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (!kp && !kd) {
+    if (m->d_act) (void)hipFree(m->d_act);
+    m->d_act = nullptr;
+    return CF_OK;
+  }
+  std::vector<float4> act(m->nv);
+  bool any = false;
+  for (int i = 0; i < m->nv; ++i) {
+    const float p = kp ? kp[i] : 0.f, dd = kd ? kd[i] : 0.f;
+    if (!(p >= 0.f && dd >= 0.f && std::isfinite(p) && std::isfinite(dd)))
+      return set_err(CF_E_INVALID_ARG, "actuator gains must be finite and >= 0");
+    const bool on = p != 0.f || dd != 0.f;
+    if (on && m->dof_jnt[i] == CF_JNT_FREE) return set_err(CF_E_INVALID_ARG, "actuators only on hinge or slide dofs");
+    any = any || on;
+    int qi = on ? m->dof_q[i] : -1;
+    float qf;
+    memcpy(&qf, &qi, sizeof qf);
+    act[i] = make_float4(p, dd, qf, 0.f);
+  }
+  if (!any) return cf_model_set_actuators(m, nullptr, nullptr);
+  if (!m->d_act && hipMalloc((void **)&m->d_act, sizeof(float4) * (m->nv ? m->nv : 1)) != hipSuccess) {
+    m->d_act = nullptr;
+    return set_err(CF_E_NOMEM, "actuator table");
+  }
+  if (hipMemcpy(m->d_act, act.data(), sizeof(float4) * m->nv, hipMemcpyHostToDevice) != hipSuccess)
+    return set_err(CF_E_DEVICE, "actuator table upload");
   return CF_OK;
 }
 

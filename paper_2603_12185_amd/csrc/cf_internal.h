@@ -11,8 +11,11 @@ constexpr int kBlockSizes[3] = {64, 128, 256};
 constexpr int kCandCap = 1024;         // LDS candidate list of the narrow phase
 
 // Candidate sub-contact ("slot"), packed in 32 bits:
-//   bits  0..12 geom a, 13..25 geom b, 26..28 sub-contact index, 29..30 pair type.
-enum PairType : uint32_t { kPlaneSphere = 0, kPlaneCapsule = 1, kPlaneBox = 2, kSphereSphere = 3 };
+//   bits  0..12 geom a, 13..25 geom b, 26..28 sub-contact index, 29..31 pair type.
+// Geom a is the plane of a plane pair and the box of a box pair.
+enum PairType : uint32_t {
+  kPlaneSphere = 0, kPlaneCapsule = 1, kPlaneBox = 2, kSphereSphere = 3, kBoxSphere = 4, kBoxCapsule = 5
+};
 constexpr int kMaxGeom = 8191;
 
 __host__ __device__ inline uint32_t slot_pack(int ga, int gb, int sub, uint32_t type) {
@@ -21,7 +24,7 @@ __host__ __device__ inline uint32_t slot_pack(int ga, int gb, int sub, uint32_t 
 __host__ __device__ inline int slot_ga(uint32_t s) { return (int)(s & 0x1FFFu); }
 __host__ __device__ inline int slot_gb(uint32_t s) { return (int)((s >> 13) & 0x1FFFu); }
 __host__ __device__ inline int slot_sub(uint32_t s) { return (int)((s >> 26) & 7u); }
-__host__ __device__ inline uint32_t slot_type(uint32_t s) { return (s >> 29) & 3u; }
+__host__ __device__ inline uint32_t slot_type(uint32_t s) { return (s >> 29) & 7u; }
 
 // Joint types (same values as the C ABI).
 enum JointType : int { kFree = 0, kHinge = 1, kSlide = 2 };
@@ -95,6 +98,7 @@ struct ResolveArgs {
   float *x_dist, *x_pos, *x_frame, *x_imp;
   float *x_feat, *x_target;     // learned-gain training data (free-body models)
   const float *mlp;             // learned-gain network parameters, or null
+  const float4 *act;            // [nv] position actuators (kp, kd, q index bits, -), or null
   int nq, nv, nb, ng, ncon_max, condim, nfacet, nbits, nsub, art_floats;
   Params p;
 };
@@ -114,7 +118,8 @@ struct RolloutArgs {
 struct BackwardArgs {
   ResolveArgs s;                // the step's inputs (q, v, tau), contacts; exports unused
   const float4 *gpos;           // [nw|1][ng] geom offsets in the body frame
-  int gpos_ws;
+  const float4 *gquat;          // [nw|1][ng] geom orientations in the body frame (x, y, z, w) = (w, x, y, z)
+  int gpos_ws, gquat_ws;
   const float *gq_out, *gv_out; // [nw][nq], [nw][nv] adjoints of q+, v+ (null = 0)
   float *gq, *gv, *gtau;        // [nw][nq], [nw][nv], [nw][nv] (gtau may be null)
 };

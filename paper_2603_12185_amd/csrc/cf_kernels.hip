@@ -458,6 +458,29 @@ __device__ inline bool slot_candidate(uint32_t s, const float4 *Gs, const int *g
     const float R = A.w + B.w + thr;
     return R > 0.f && dx * dx + dy * dy + dz * dz < R * R;
   }
+  if (t == kBoxSphere || t == kBoxCapsule) {
+    // sphere centre (or capsule end) against the box: squared distance outside
+    const Pose<float> &X = Of[go[ga]];
+    float cx, cy, cz, rad;
+    if (t == kBoxSphere) {
+      const float4 S = Gs[gb];
+      cx = S.x; cy = S.y; cz = S.z; rad = S.w;
+    } else {
+      const Pose<float> &C = Of[go[gb]];
+      const float hl = slot_sub(s) == 0 ? -C.s[1] : C.s[1];
+      cx = C.p[0] + hl * C.r[2]; cy = C.p[1] + hl * C.r[5]; cz = C.p[2] + hl * C.r[8];
+      rad = C.s[0];
+    }
+    const float dx = cx - X.p[0], dy = cy - X.p[1], dz = cz - X.p[2];
+    float d2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float e = fabsf(X.r[k] * dx + X.r[3 + k] * dy + X.r[6 + k] * dz) - X.s[k];
+      if (e > 0.f) d2 += e * e;
+    }
+    const float R = rad + thr;
+    return R > 0.f && d2 < R * R;
+  }
   const Pose<float> &P = Of[go[ga]];
   const float nx = P.r[2], ny = P.r[5], nz = P.r[8];
   float cx, cy, cz, rad = 0.f;
@@ -517,6 +540,49 @@ __device__ inline double slot_eval(uint32_t s, const float4 *Gs, const int *go, 
     const double phi = dist - ra - rb;
     const double k = ra + 0.5 * phi;
     for (int i = 0; i < 3; ++i) p[i] = ca[i] + k * n[i];
+    return phi;
+  }
+  if (t == kBoxSphere || t == kBoxCapsule) {
+    // sphere centre c (or capsule end) against the box X: c in the box frame,
+    // clamped to the box; outside, n from the clamped point to c; inside, the
+    // outward axis of the face of least depth (lowest axis on ties)
+    const Pose<double> &X = Od[go[ga]];
+    double c[3], rad;
+    if (t == kBoxSphere) {
+      sphere_of(gb, Gs, go, Od, c, rad);
+    } else {
+      const Pose<double> &C = Od[go[gb]];
+      const double hl = sub == 0 ? -C.s[1] : C.s[1];
+      for (int i = 0; i < 3; ++i) c[i] = C.p[i] + hl * C.r[3 * i + 2];
+      rad = C.s[0];
+    }
+    const double d[3] = {c[0] - X.p[0], c[1] - X.p[1], c[2] - X.p[2]};
+    double l[3], e[3], d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      l[k] = X.r[k] * d[0] + X.r[3 + k] * d[1] + X.r[6 + k] * d[2];
+      e[k] = l[k] - fmin(fmax(l[k], -X.s[k]), X.s[k]);
+      d2 += e[k] * e[k];
+    }
+    const double dist = sqrt(d2);
+    double nl[3] = {0.0, 0.0, 0.0}, phi;
+    if (dist > 1e-12) {
+      for (int k = 0; k < 3; ++k) nl[k] = e[k] / dist;
+      phi = dist - rad;
+    } else {
+      int kmin = 0;
+      double dmin = X.s[0] - fabs(l[0]);
+      for (int k = 1; k < 3; ++k) {
+        const double dk = X.s[k] - fabs(l[k]);
+        if (dk < dmin) { dmin = dk; kmin = k; }
+      }
+      nl[kmin] = l[kmin] >= 0.0 ? 1.0 : -1.0;
+      phi = -dmin - rad;
+    }
+    const double k = rad + 0.5 * phi;
+    for (int i = 0; i < 3; ++i) {
+      n[i] = X.r[3 * i] * nl[0] + X.r[3 * i + 1] * nl[1] + X.r[3 * i + 2] * nl[2];
+      p[i] = c[i] - k * n[i];
+    }
     return phi;
   }
   const Pose<double> &P = Od[go[ga]];
@@ -1100,13 +1166,14 @@ __device__ inline void resolve_geoms(const ResolveArgs &a, int w, int *gB, float
 }
 
 // Resolution of world w: its q and v rows (LDS sq, sv) become q+ and v+ in
-// place; st holds the applied forces; the nc contacts are read from inn/inp
+// place; st holds the step input (applied forces; an actuated dof's target is
+// replaced by its actuator force); the nc contacts are read from inn/inp
 // (global or LDS), the first chunk already loaded by the caller into c0n/c0p
 // (lane tid's record), and mi0 is body tid's mass/inertia.  `reg`: LDS scratch of
 // resolve_region_bytes().  `xbase`: row of the world in the export arrays.
 // Ends with a workgroup barrier.
 template <int CONDIM, int BS, bool ART, bool LEARN = false>
-__device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv, const float *st,
+__device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv, float *st,
                               const float4 *inn, const float4 *inp, int nc, float4 c0n, float4 c0p,
                               float4 mi0, float4 *reg, size_t xbase, bool geoms_ready = false,
                               const mlp::Weights *lnet = nullptr, float *lfeat = nullptr, float *lout = nullptr) {
@@ -1124,6 +1191,16 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   const Params P = a.p;
   if (!geoms_ready) resolve_geoms<CONDIM, BS>(a, w, gB, gM, 0);
   __syncthreads();
+  if (a.act) {
+    // position actuators: the input of an actuated dof is its target u, the
+    // applied force kp (u - q) - kd v on the state at the start of the step
+    for (int i = tid; i < a.nv; i += BS) {
+      const float4 c = a.act[i];
+      const int qi = __float_as_int(c.z);
+      if (qi >= 0) st[i] = c.x * (st[i] - sq[qi]) - c.y * sv[i];
+    }
+    __syncthreads();
+  }
 
   // ---- per free body: M blocks, bias, smooth prediction (Eq. smooth_vel), trace 3/m
   // (without articulated subtrees every body is a free root: q and v offsets 7b and 6b)
@@ -1781,6 +1858,63 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
         const Vec<float> cb = ca + (phi + ra + rb) * n;
         xab = xab + cab; psa = adj::cross(ca - C.xa, cab);
         xbb = xbb + cbb; psb = adj::cross(cb - C.xb, cbb);
+      } else if (type == kBoxSphere || type == kBoxCapsule) {
+        // box (geom a) against the sphere centre or capsule end c of geom b; the
+        // region of c (axes outside the box) picks the face plane, the edge
+        // line or the corner the forward gap was measured from
+        const float rad = gdb.x;
+        const Vec<float> c = p + (rad + 0.5f * phi) * n;
+        float Rb[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, Rg[9], RX[9];
+        Vec<float> xo = Z;
+        if (ba >= 0) {
+          adj::rot_of_quat(sq0 + a.body[ba].qadr + 3, Rb);
+          xo = C.xa;
+        }
+        const float4 o4 = b.gpos[(size_t)w * b.gpos_ws + ga], g4 = b.gquat[(size_t)w * b.gquat_ws + ga];
+        quat_to_rot<float>(g4.x, g4.y, g4.z, g4.w, Rg);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) RX[3 * i + j] = Rb[3 * i] * Rg[j] + Rb[3 * i + 1] * Rg[3 + j] + Rb[3 * i + 2] * Rg[6 + j];
+        const Vec<float> X = xo + vec(Rb[0] * o4.x + Rb[1] * o4.y + Rb[2] * o4.z, Rb[3] * o4.x + Rb[4] * o4.y + Rb[5] * o4.z,
+                                      Rb[6] * o4.x + Rb[7] * o4.y + Rb[8] * o4.z);
+        const float hs[3] = {gda.x, gda.y, gda.z};
+        const Vec<float> dc = c - X;
+        Vec<float> corner = X, e0 = X, u = Z;
+        int nout = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const Vec<float> col = vec(RX[k], RX[3 + k], RX[6 + k]);
+          const float l = adj::dot(col, dc);
+          const float sh = (l >= 0.f ? hs[k] : -hs[k]);
+          corner = corner + sh * col;
+          if (fabsf(l) > hs[k]) {
+            ++nout;
+            e0 = e0 + sh * col;
+          } else {
+            u = col;
+          }
+        }
+        Vec<float> cbar, abx, abp;
+        if (nout <= 1) {  // face or inside: the plane of the face
+          const Vec<float> pp = c - (phi + rad) * n;
+          Vec<float> ppb, nnb;
+          adj::plane_point_vjp(pp, n, c, rad, phi, o.n, o.phi, o.p, cbar, ppb, nnb);
+          abx = ppb;
+          abp = adj::cross(pp - C.xa, ppb) + adj::cross(n, nnb);
+        } else if (nout == 2) {  // edge along the axis where c lies within the box
+          Vec<float> e0b, ub;
+          adj::line_point_vjp(e0, u, c, rad, n, phi, o.n, o.phi, o.p, cbar, e0b, ub);
+          abx = e0b;
+          abp = adj::cross(e0 - C.xa, e0b) + adj::cross(u, ub);
+        } else {  // corner: a sphere of radius 0
+          Vec<float> cab;
+          adj::sphere_pair_vjp(n, phi, 0.f, rad, o.n, o.phi, o.p, cab, cbar);
+          abx = cab;
+          abp = adj::cross(corner - C.xa, cab);
+        }
+        xbb = xbb + cbar; psb = adj::cross(c - C.xb, cbar);
+        if (ba >= 0) { xab = xab + abx; psa = abp; }
       } else {
         const float rad = type == kPlaneBox ? 0.f : gdb.x;
         const Vec<float> c = p + (rad + 0.5f * phi) * n;

@@ -560,3 +560,71 @@ def articulated_mix(nworld=4, seed=0, condim=3, k_user=0.1, d_user=0.001, ncon_m
             q[qa[bi] + 3:qa[bi] + 7] = (1, 0, 0, 0)
             v[da[bi]:da[bi] + 3] = rng.normal(0, 0.3, 3)
     return s
+
+
+# Synthetic four-finger hand (16 hinge dofs) around a free 5 cm cube.
+HAND_LINKS = (0.02, 0.04, 0.03, 0.025)     # base (abduction), proximal, middle, distal [m]
+# Position gains per finger joint: omega^2 I and 2 zeta omega I with omega = 120 rad/s,
+# zeta = 0.5 and I the joint's effective inertia at the rest pose (1 / (M^-1)_jj), which
+# keeps h^2 eig(M^-1 Kp) and h eig(M^-1 Kd) at about 0.14 and 0.6 for h = 2 ms.
+HAND_KP = (10.71, 1.509, 0.1875, 0.0511)   # [N m / rad]
+HAND_KD = (0.0893, 0.01257, 0.00156, 0.000426)  # [N m s / rad]
+HAND_Q0 = (0.0, -0.5, 0.8, 0.7)            # rest pose: fingertips 4.2 cm from the cube's axis [rad]
+
+
+def hand_cube(nworld=4, seed=0, condim=6, k_user=0.1, d_user=0.002, h=0.002, ncon_max=64):
+    """Four fingers of four hinges each (abduction about the root's z, then
+    three flexion hinges about y; capsule links, fingertip spheres), rooted on
+    a palm plane around a free 5 cm cube (body 0) resting on it; position
+    actuators on the 16 finger dofs (gains HAND_KP, HAND_KD; the step input of
+    a finger dof is its target angle).  nv = 22.  Per world the cube's yaw and
+    position and the fingers' angles are perturbed (seeded)."""
+    rng = np.random.default_rng([seed, 11])
+    b = _Builder(nworld)
+    b.geom(PLANE, -1, friction=(0.6, 0.005, 0.0002))
+    half = 0.025
+    mc = 0.1
+    ic = mc * (2 * half) ** 2 / 6
+    cube = b.body(JNT_FREE, pos=(0, 0, half), mass=mc, inertia=(ic, ic, ic))
+    b.geom(BOX, cube, size=(half, half, half), friction=(0.8, 0.005, 0.0002))
+    cap_q = _quat_z_to((1.0, 0.0, 0.0))  # capsule axis along the link (+x)
+    r_link, r_tip, m_link = 0.01, 0.011, 0.05
+    for f in range(4):
+        psi = f * math.pi / 2                          # azimuth of the finger root (facing a cube face)
+        root = (0.139 * math.cos(psi), 0.139 * math.sin(psi), 0.03)
+        yaw = psi + math.pi                            # local +x toward the cube
+        parent = -1
+        for j, L in enumerate(HAND_LINKS):
+            ixx = 0.5 * m_link * r_link ** 2
+            iyy = m_link * (L * L / 12 + r_link ** 2 / 4)
+            kw = dict(axis=(0, 0, 1) if j == 0 else (0, 1, 0), ipos=(L / 2, 0, 0), mass=m_link,
+                      inertia=(ixx, iyy, iyy))
+            if j == 0:
+                bi = b.body(JNT_HINGE, -1, pos=root, quat=(math.cos(yaw / 2), 0, 0, math.sin(yaw / 2)), **kw)
+            else:
+                bi = b.body(JNT_HINGE, parent, pos=(HAND_LINKS[j - 1], 0, 0), **kw)
+            b.geom(CAPSULE, bi, size=(r_link, L / 2, 0), pos=(L / 2, 0, 0), quat=cap_q,
+                   friction=(1.0, 0.005, 0.0002))
+            parent = bi
+        b.geom(SPHERE, parent, size=(r_tip, 0, 0), pos=(HAND_LINKS[-1], 0, 0), friction=(1.0, 0.005, 0.0002))
+    s = b.build(condim=condim, k_user=k_user, d_user=d_user, h=h, ncon_max=ncon_max, name="hand_cube")
+    nv = dims(s)[1]
+    kp, kd = np.zeros(nv), np.zeros(nv)
+    kp[6:] = np.tile(HAND_KP, 4)
+    kd[6:] = np.tile(HAND_KD, 4)
+    s["dof_kp"], s["dof_kd"] = f32(kp), f32(kd)
+    for w in range(nworld):
+        q = s["q0"][w]
+        a = rng.uniform(-0.1, 0.1)
+        q[0:3] = (rng.uniform(-0.005, 0.005), rng.uniform(-0.005, 0.005), half + 0.001)
+        q[3:7] = (math.cos(a / 2), 0, 0, math.sin(a / 2))
+        q[7:] = np.tile(HAND_Q0, 4) + rng.uniform(-0.03, 0.03, 16)
+    return s
+
+
+def hand_targets(scene):
+    """[nworld][nv] step input holding every finger at its initial angle (the
+    cube's dofs take zero force)."""
+    tau = np.zeros((scene["nworld"], dims(scene)[1]), np.float32)
+    tau[:, 6:] = scene["q0"][:, 7:]
+    return tau

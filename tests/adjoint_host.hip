@@ -271,6 +271,63 @@ static void check_plane_point(int trial) {
   report(name, an, fd_grad(X, L), 1e-7);
 }
 
+// box edge on a rotating body: e0 = x + R(q) o, u = R(q) a (unit); the point
+// c = y + R(qc) oc on another body.  Checks line_point_vjp and the body
+// conversion (e0 a point of the body, u a direction of the body).
+static void check_line_point(int trial) {
+  D q[4], qc[4];
+  for (int i = 0; i < 4; ++i) { q[i] = U(-1, 1); qc[i] = U(-1, 1); }
+  const V x = rv(0.3), o = rv(0.1), y = rv(0.3), oc = rv(0.05);
+  V a = rv(1.0);
+  a = (D(1) / sqrt(vdot(a, a))) * a;
+  const D rad = U(0.0, 0.05);
+  const V nb = rv(1.0), pb = rv(1.0);
+  const D phib = U(-1, 1);
+  auto rot = [](const D *R, V v) {
+    return vec(R[0] * v.x + R[1] * v.y + R[2] * v.z, R[3] * v.x + R[4] * v.y + R[5] * v.z,
+               R[6] * v.x + R[7] * v.y + R[8] * v.z);
+  };
+  auto geom = [&](const D *qq, V xx, const D *qqc, V yy, V &e0, V &u, V &c) {
+    D R[9], Rc[9];
+    rot_of_quat(qq, R);
+    rot_of_quat(qqc, Rc);
+    e0 = xx + rot(R, o);
+    u = rot(R, a);
+    c = yy + rot(Rc, oc);
+  };
+  // keep c off the line: shift the other body's origin sideways once
+  const V side = rv(0.2);
+  std::vector<D> X(q, q + 4);
+  put(X, x);
+  for (int i = 0; i < 4; ++i) X.push_back(qc[i]);
+  put(X, y + side);
+  auto L = [&](const std::vector<D> &z) {
+    V e0, u, c, n, p;
+    D phi;
+    geom(&z[0], get(z, 4), &z[7], get(z, 11), e0, u, c);
+    line_point_forward(e0, u, c, rad, n, phi, p);
+    return vdot(n, nb) + phi * phib + vdot(p, pb);
+  };
+  V e0, u, c, n, p;
+  D phi;
+  geom(q, x, qc, y + side, e0, u, c);
+  line_point_forward(e0, u, c, rad, n, phi, p);
+  V cb, e0b, ub;
+  line_point_vjp(e0, u, c, rad, n, phi, nb, phib, pb, cb, e0b, ub);
+  const V psi_a = cross(e0 - x, e0b) + cross(u, ub);
+  const V psi_b = cross(c - (y + side), cb);
+  D qa[4] = {0, 0, 0, 0}, qbb[4] = {0, 0, 0, 0};
+  quat_grad_from_psi(q, psi_a, qa);
+  quat_grad_from_psi(qc, psi_b, qbb);
+  std::vector<D> an(qa, qa + 4);
+  put(an, e0b);
+  for (int i = 0; i < 4; ++i) an.push_back(qbb[i]);
+  put(an, cb);
+  char name[64];
+  snprintf(name, sizeof name, "line-point on bodies #%d", trial);
+  report(name, an, fd_grad(X, L), 1e-7);
+}
+
 int main() {
   for (int t = 0; t < 4; ++t) check_predict(t);
   for (int t = 0; t < 3; ++t) check_update(t, 20.0);
@@ -287,6 +344,7 @@ int main() {
   }
   for (int t = 0; t < 3; ++t) check_sphere_pair(t);
   for (int t = 0; t < 3; ++t) check_plane_point(t);
+  for (int t = 0; t < 3; ++t) check_line_point(t);
   printf("%s (%d failures)\n", failures ? "FAILED" : "ALL OK", failures);
   return failures ? 1 : 0;
 }

@@ -102,3 +102,7 @@ def test_null_arguments(lib):
 
 def test_impedance_mode_null_model(lib):
     assert lib.cf_model_set_impedance(None, 0) == cfsim.CF_E_INVALID_ARG
+
+
+def test_actuators_null_model(lib):
+    assert lib.cf_model_set_actuators(None, None, None) == cfsim.CF_E_INVALID_ARG
