@@ -55,6 +55,10 @@ def cpu_baseline(scene, q, v, worlds, steps, threads):
     return len(worlds) * steps / dt, dt
 
 
+def progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,13 +68,17 @@ def main():
     ap.add_argument("--nsphere", type=int, default=64)
     ap.add_argument("--condim", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-worlds", type=int, default=768,
+    ap.add_argument("--cpu-worlds", type=int, default=2048,
                     help="worlds in the CPU-baseline sample (0 disables it)")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--rollout-steps", type=int, default=1000,
                     help="steps of the batched-rollout form timed after the plain form (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=200,
                     help="steps of the learned-impedance form timed after the plain form (0: skip)")
+    ap.add_argument("--hand-rollouts", type=int, default=2048,
+                    help="rollouts per MPPI iteration of the hand-and-cube form (0: skip)")
+    ap.add_argument("--hand-horizon", type=int, default=20)
+    ap.add_argument("--hand-iters", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB five times (a "
                          "known-traffic kernel that calibrates HBM byte counters under a profiler)")
@@ -141,6 +149,7 @@ def main():
     # events around each group (events between the two kernels of every step
     # would add their own gaps to both).
     us_col, us_res = model.time_kernels(q[0], v[0], q[1], v[1], reps=K)
+    progress(f"plain form: {K} steps in {wall:.2f} s; kernels {us_col:.1f} / {us_res:.1f} us")
 
     ncon = ncon_log[:K].double()
     assert int(over_log[:K].sum()) == 0, "contact capacity overflowed"
@@ -219,6 +228,7 @@ def main():
         rc_w = float(nct.double().sum()) / (T * nw)
         launch = model.get_launch()
         b_roll = 8 * (nq + nv)  # per world-step: the trajectory rows written
+        progress(f"rollout form: {T} steps in {rwall:.2f} s")
         result["rollout_form"] = {
             "value": nw * T / rwall, "unit": "env-steps/s", "steps": T,
             "ms_per_step": rwall * 1e3 / T, "gpu_event_ms_per_step": rgpu,
@@ -262,6 +272,7 @@ def main():
         us_lc, us_lr = model.time_kernels(qs, vs, lq[1], lv[1], reps=100)
         model.set_learned_impedance(None)
         ke = lambda vv: float((vv.reshape(nw, -1, 6)[:, :, 0:3] ** 2).sum(-1).mean())
+        progress(f"learned form: {L} steps in {lwall:.2f} s")
         result["learned_form"] = {
             "value": nw * L / lwall, "unit": "env-steps/s", "steps": L, "ms_per_step": lwall * 1e3 / L,
             "vs_plain_form": (nw * L / lwall) / env_steps,
@@ -274,11 +285,81 @@ def main():
             "max_penetration_mm": {"plain": xp * 1e3, "learned": xl * 1e3},
             "mean_sq_speed_after_100_steps": {"plain": ke(vp), "learned": ke(vl)},
         }
+    if args.hand_rollouts > 0:
+        # Batched-MPC form: the actuated four-finger hand with a free cube (6D
+        # contacts), N rollouts of H steps per MPPI iteration with Gaussian
+        # noise of 0.1 rad on the 16 finger targets; one cf_rollout call per
+        # batch (persistent kernel), eager and replayed from a captured graph,
+        # and whole MPPI iterations (sampling, rollouts, costs, weights, update,
+        # one plant step).
+        from paper_2603_12185_amd import mpc
+        N, H, R = args.hand_rollouts, args.hand_horizon, args.hand_iters
+        ctl = mpc.HandMPPI(nroll=N, H=H, sigma=0.1, seed=args.seed)
+        for _ in range(3):
+            ctl.iterate()
+        u, _ = ctl.sample()
+        ctl.tau_seq[:, :, 6:] = u.transpose(0, 1)
+        ctl.q0s.copy_(ctl.q.expand(N, -1))
+        ctl.v0s.copy_(ctl.v.expand(N, -1))
+        ncon_h = torch.zeros((H, N), dtype=torch.int32, device=dev)
+        hs = torch.cuda.current_stream()
+
+        def hand_roll():
+            ctl.model.rollout(H, ctl.q0s, ctl.v0s, tau_seq=ctl.tau_seq, q_traj=ctl.q_traj,
+                              v_traj=ctl.v_traj, ncon_traj=ncon_h)
+
+        hand_roll()
+        torch.cuda.synchronize()
+        h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        h0.record(hs)
+        for _ in range(R):
+            hand_roll()
+        h1.record(hs)
+        torch.cuda.synchronize()
+        hwall = time.perf_counter() - t0
+        hgpu = h0.elapsed_time(h1) / R
+        hc_w = float(ncon_h.double().mean())
+        hmax = int(ncon_h.max())
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(hs)
+        with torch.cuda.stream(side):
+            hand_roll()
+        hs.wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            hand_roll()
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(R):
+            graph.replay()
+        torch.cuda.synchronize()
+        gwall = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(R):
+            ctl.iterate()
+        torch.cuda.synchronize()
+        iwall = time.perf_counter() - t0
+        launch = ctl.model.get_launch()
+        progress(f"hand form: {R} batches of {N} x {H} in {hwall:.2f} s")
+        result["hand_form"] = {
+            "value": N * H * R / hwall, "unit": "env-steps/s", "rollouts": N, "horizon": H,
+            "ms_per_rollout_batch": hwall * 1e3 / R, "gpu_event_ms_per_rollout_batch": hgpu,
+            "graph_replay_ms_per_rollout_batch": gwall * 1e3 / R,
+            "ms_per_mppi_iteration": iwall * 1e3 / R,
+            "mean_contacts_per_world_step": hc_w, "max_contacts_per_world_step": hmax,
+            "persistent_kernel": launch[3], "rollout_block": launch[2], "launch": "autotuned",
+            "scene": "16 hinge dofs in 4 fingers (capsule links, fingertip spheres, position "
+                     "actuators) + free 5 cm cube, nv 22, condim 6, h 2 ms, sigma 0.1 rad",
+        }
     if args.cpu_worlds > 0:
         threads = min(16, len(os.sched_getaffinity(0)))
         rng = np.random.default_rng(0)
         sample = np.sort(rng.choice(nw, size=min(args.cpu_worlds, nw), replace=False))
         rate, dt = cpu_baseline(scene, state_q, state_v, sample, args.cpu_steps, threads)
+        progress(f"cpu baseline: {dt:.1f} s")
         result["cpu_baseline"] = {
             "value": rate, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(sample)} worlds x {args.cpu_steps} steps of the same settled pile "

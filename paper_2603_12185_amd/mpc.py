@@ -31,10 +31,11 @@ class HandMPPI:
 
     nroll rollouts of horizon H; Gaussian noise of standard deviation sigma
     (rad) on the 16 finger targets; temperature lam; targets clipped to
-    +-clip around the rest pose."""
+    +-clip around the rest pose.  autotune: let the library pick the rollout's
+    launch shape for this scene first."""
 
     def __init__(self, nroll=2048, H=20, sigma=0.1, lam=0.01, clip=0.6, target_yaw=0.5, seed=0,
-                 scene_kw=None):
+                 scene_kw=None, autotune=True):
         import torch
         kw = dict(scene_kw or {})
         self.scene = scenes.hand_cube(nworld=nroll, seed=seed, **kw)
@@ -58,6 +59,11 @@ class HandMPPI:
         self.v_traj = torch.empty((H + 1, nroll, self.nv), dtype=torch.float32, device=dev)
         self.q0s = torch.empty((nroll, self.nq), dtype=torch.float32, device=dev)
         self.v0s = torch.empty((nroll, self.nv), dtype=torch.float32, device=dev)
+        if autotune:
+            # workgroup size and persistent kernel vs step launches for this scene
+            self.q0s.copy_(self.q.expand(nroll, -1))
+            self.v0s.copy_(self.v.expand(nroll, -1))
+            self.model.autotune(self.q0s, self.v0s, steps=H)
 
     def costs(self, q_traj):
         """Per-rollout cost of the trajectories [H+1][N][nq]: squared yaw error
