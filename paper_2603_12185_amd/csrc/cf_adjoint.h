@@ -280,6 +280,7 @@ struct ContactBar {  // adjoints
   Vec<T> n, p;
   T phi;
   Vec<T> xa, va, wa, xb, vb, wb;
+  T trs;  // of tr_a + tr_b (constant for free bodies, a function of the joints otherwise)
 };
 
 template <class T>
@@ -434,6 +435,7 @@ CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b
     c0b += zb;
   }
   T phib = -C.k * c0b + (C.trs > T(0) ? Ab * drho / C.trs : T(0));
+  o.trs = C.trs > T(0) ? -Ab * A / C.trs : T(0);  // A = rho / trs
   // s_f in terms of vn, u1, u2, wt, o1, o2
   T vnb = T(0);
   for (int i = 0; i < NF; ++i) vnb += sb[i];

@@ -44,7 +44,9 @@ struct BodyC {
 // and dof order): bodies [b0, b0+nb), dofs [d0, d0+nd), float offset of its
 // LDS work block (nd*nd + 9*nd floats).
 struct SubTree {
-  int b0, nb, d0, nd, lofs, pad[3];
+  int b0, nb, d0, nd, lofs;  // bodies [b0, b0+nb), dofs [d0, d0+nd), forward work block offset
+  int bofs;                  // reverse-pass work block offset (cf_step_backward)
+  int pad[2];
 };
 constexpr int kMaxSubDof = 32;
 
@@ -124,7 +126,9 @@ struct BackwardArgs {
   float *gq, *gv, *gtau;        // [nw][nq], [nw][nv], [nw][nv] (gtau may be null)
 };
 
-size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block);
+size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats, int artb_floats);
+// Floats of the reverse-pass work block of a subtree with nd dofs and nbs bodies.
+int art_backward_floats(int nd, int nbs);
 hipError_t launch_backward(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 
 size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub);

@@ -28,6 +28,7 @@
 // inertia.  Apart from the float64 contact geometry the step runs in float32.
 #include "cf_internal.h"
 #include "cf_adjoint.h"
+#include "cf_artadj.h"
 #include "cf_mlp.h"
 
 namespace cf {
@@ -1726,12 +1727,164 @@ __device__ void body_segment_sum(int kA, int kB, const float4 *pa, const float4 
 }
 
 // LDS beyond the resolution's: the q row before the step; per body the
-// accumulated adjoints (3 float4: x_bar | psi_bar | v_s bar | w_s bar packed),
-// the adjoints of the contact force and torque sums and the direct quaternion
-// adjoint; per lane two packed 3-float4 payloads.
-size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block) {
-  return resolve_lds_bytes(nq, nv, nb, ng, 0, 0) + sizeof(float) * pad4(nq) +
-         sizeof(float4) * (6 * (size_t)nb + 6 * (size_t)block);
+// accumulated adjoints (4 float4: x_bar | psi_bar | v_s bar | w_s bar | trace
+// bar packed), the adjoints of the contact force and torque sums and the
+// direct quaternion adjoint; per lane two packed 4-float4 payloads; the
+// articulated subtrees' reverse-pass work blocks.
+size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats, int artb_floats) {
+  return resolve_lds_bytes(nq, nv, nb, ng, nsub, art_floats) + sizeof(float) * pad4(nq) +
+         sizeof(float4) * (7 * (size_t)nb + 8 * (size_t)block) + sizeof(float) * (size_t)pad4(artb_floats);
+}
+
+// Reverse-pass work block of a subtree (floats): theta bar, v_s bar, y, w,
+// tau bar, theta-dot bar, c bar, u [nd each]; M bar [nd nd]; J bar [nbs][6][nd];
+// dual joint values and rates [2 nd] and the dual workspace of subtree_phi.
+int art_backward_floats(int nd, int nbs) {
+  return nd * nd + 8 * nd + 6 * nd * nbs + 2 * (2 * nd + artadj::phi_work(nbs, nd));
+}
+
+// ---- articulated subtrees in the reverse pass (hinge and slide joints under a
+// fixed base; one lane per subtree).  Forward block (art_predict/art_correct):
+// L [nd nd] | z = M^-1 p [nd] | v_s [nd] | cols [6 nd] | idx [nd].
+struct ArtRev {
+  float *thb, *vsb, *y, *wv, *tb, *thdb, *cb, *u, *Mb, *Jb;
+  artadj::Du<float> *th, *thd, *wk;
+};
+__device__ inline ArtRev art_rev_block(float *bw, int nd, int nbs) {
+  ArtRev r;
+  r.thb = bw; r.vsb = r.thb + nd; r.y = r.vsb + nd; r.wv = r.y + nd; r.tb = r.wv + nd; r.thdb = r.tb + nd;
+  r.cb = r.thdb + nd; r.u = r.cb + nd; r.Mb = r.u + nd; r.Jb = r.Mb + nd * nd;
+  r.th = reinterpret_cast<artadj::Du<float> *>(r.Jb + 6 * nd * nbs);
+  r.thd = r.th + nd; r.wk = r.thd + nd;
+  return r;
+}
+
+// Reverse of the subtree's integration theta+ = theta + h v+ and correction
+// v+ = v_s + M^-1 p, p = sum_b J_b^T W_b: joint adjoints seeded from the
+// outputs' adjoints, y = M^-1 (v+ bar), body wrench adjoints W_b bar = J_b y
+// for the contact reverse, M bar = -y z^T, J_b bar = W_b y^T.
+__device__ void art_rev_correct(const SubTree S, const BodyC *B, const float4 *bC, const float4 *bO,
+                                const float4 *bAx, const float4 *accF, const float4 *accT, float *blk, float *bw,
+                                const float *gqo, const float *gvo, float4 *bFb, float4 *bTb, float4 *bQb,
+                                float4 *acc, int nb, float h) {
+  const int nd = S.nd, d0 = S.d0;
+  float *L = blk, *z = L + nd * nd, *cols = z + 2 * nd;
+  int *idx = reinterpret_cast<int *>(cols + 6 * nd);
+  const ArtRev R = art_rev_block(bw, nd, S.nb);
+  for (int i = 0; i < nd; ++i) {
+    const float tq = gqo ? gqo[B[S.b0 + i].qadr] : 0.f;
+    const float tv = gvo ? gvo[d0 + i] : 0.f;
+    R.thb[i] = tq;
+    R.vsb[i] = tv + h * tq;
+    R.y[i] = R.vsb[i];
+    R.thdb[i] = 0.f;
+  }
+  fwd_solve(L, nd, R.y);
+  bwd_solve(L, nd, R.y);
+  for (int i = 0; i < nd; ++i)
+    for (int j = 0; j < nd; ++j) R.Mb[i * nd + j] = -R.y[i] * z[j];
+  for (int i = 0; i < 6 * nd * S.nb; ++i) R.Jb[i] = 0.f;
+  for (int k = 0; k < S.nb; ++k) {
+    const int b = S.b0 + k;
+    const int n = chain_cols(b, d0, B, bO, bAx, bC, cols, idx);
+    const float W[6] = {accF[b].x, accF[b].y, accF[b].z, accT[b].x, accT[b].y, accT[b].z};
+    float Wb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float *Jb = R.Jb + 6 * nd * k;
+    for (int x = 0; x < n; ++x) {
+      const int i = idx[x];
+      for (int r = 0; r < 6; ++r) {
+        Wb[r] += cols[6 * x + r] * R.y[i];
+        Jb[r * nd + i] += W[r] * R.y[i];
+      }
+    }
+    bFb[b] = make_float4(Wb[0], Wb[1], Wb[2], 0.f);
+    bTb[b] = make_float4(Wb[3], Wb[4], Wb[5], 0.f);
+    bQb[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = 0; i < 4; ++i) acc[i * nb + b] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+// Reverse of the subtree's smooth prediction v_s = thd + h M^-1 (tau - c) and of
+// its bodies' COM poses, velocities at v_s and traces, given the per-body
+// adjoints from the contacts (acc: x bar, rotation-increment bar, v bar, w bar,
+// trace bar).  Writes the joint adjoints to gq/gv/gt (the LDS rows of the
+// outputs).  act: position actuators or null.
+__device__ void art_rev_predict(const SubTree S, const BodyC *B, const float4 *bmi, const float4 *bC,
+                                const float4 *bO, const float4 *bAx, float *blk, float *bw, const float4 *acc, int nb,
+                                const float *q0, const float *v0, const float4 *act, const Params &P, float *gq,
+                                float *gv, float *gt) {
+  const int nd = S.nd, d0 = S.d0;
+  float *L = blk, *vs = L + nd * nd + nd, *cols = vs + nd;
+  int *idx = reinterpret_cast<int *>(cols + 6 * nd);
+  const ArtRev R = art_rev_block(bw, nd, S.nb);
+  for (int k = 0; k < S.nb; ++k) {
+    const int b = S.b0 + k;
+    const int n = chain_cols(b, d0, B, bO, bAx, bC, cols, idx);
+    const float4 A0 = acc[b], A1 = acc[nb + b], A2 = acc[2 * nb + b], A3 = acc[3 * nb + b];
+    const float xb[3] = {A0.x, A0.y, A0.z}, pb[3] = {A0.w, A1.x, A1.y};
+    const float g6[6] = {A1.z, A1.w, A2.x, A2.y, A2.z, A2.w};  // v bar, w bar at v_s
+    const float trb = A3.x;
+    float *Jb = R.Jb + 6 * nd * k;
+    for (int x = 0; x < n; ++x) {
+      const int i = idx[x];
+      const float *c = cols + 6 * x;
+      R.thb[i] += c[0] * xb[0] + c[1] * xb[1] + c[2] * xb[2] + c[3] * pb[0] + c[4] * pb[1] + c[5] * pb[2];
+      float sv = 0.f;
+      for (int r = 0; r < 6; ++r) {
+        sv += c[r] * g6[r];
+        Jb[r * nd + idx[x]] += g6[r] * vs[idx[x]];
+      }
+      R.vsb[i] += sv;
+    }
+    if (trb != 0.f) {
+      // tr_b = sum_r J_r M^-1 J_r^T over the COM rows r
+      for (int r = 0; r < 3; ++r) {
+        for (int i = 0; i < nd; ++i) R.u[i] = 0.f;
+        for (int x = 0; x < n; ++x) R.u[idx[x]] = cols[6 * x + r];
+        fwd_solve(L, nd, R.u);
+        bwd_solve(L, nd, R.u);
+        for (int x = 0; x < n; ++x) Jb[r * nd + idx[x]] += 2.f * trb * R.u[idx[x]];
+        for (int i = 0; i < nd; ++i)
+          for (int j = 0; j < nd; ++j) R.Mb[i * nd + j] -= trb * R.u[i] * R.u[j];
+      }
+    }
+  }
+  // v_s = thd + h s, s = M^-1 (tau - c): w = h M^-1 (v_s bar), M bar -= w s^T, c bar = -w, tau bar = w
+  for (int i = 0; i < nd; ++i) R.wv[i] = P.h * R.vsb[i];
+  fwd_solve(L, nd, R.wv);
+  bwd_solve(L, nd, R.wv);
+  for (int i = 0; i < nd; ++i) {
+    const float si = (vs[i] - v0[d0 + i]) / P.h;
+    for (int j = 0; j < nd; ++j) R.Mb[j * nd + i] -= R.wv[j] * si;
+    R.cb[i] = -R.wv[i];
+    R.thdb[i] += R.vsb[i];
+    float tbar = R.wv[i];
+    if (act) {  // tau = kp (u - theta) - kd theta-dot for an actuated dof
+      const float4 c = act[d0 + i];
+      if (__float_as_int(c.z) >= 0) {
+        R.thb[i] -= c.x * tbar;
+        R.thdb[i] -= c.y * tbar;
+        tbar *= c.x;
+      }
+    }
+    R.tb[i] = tbar;
+  }
+  // M, c and the J_b as functions of the joints: gradient of Phi by dual passes
+  for (int k = 0; k < 2 * nd; ++k) {
+    for (int i = 0; i < nd; ++i) {
+      R.th[i] = artadj::du<float>(q0[B[S.b0 + i].qadr], k == i ? 1.f : 0.f);
+      R.thd[i] = artadj::du<float>(v0[d0 + i], k == nd + i ? 1.f : 0.f);
+    }
+    const float d = artadj::subtree_phi<artadj::Du<float>>(B, S.b0, S.nb, d0, nd, bmi, R.th, R.thd, P.gx, P.gy, P.gz,
+                                                          R.Mb, R.cb, R.Jb, R.wk).d;
+    if (k < nd) R.thb[k] += d;
+    else R.thdb[k - nd] += d;
+  }
+  for (int i = 0; i < nd; ++i) {
+    gq[B[S.b0 + i].qadr] = R.thb[i];
+    gv[d0 + i] = R.thdb[i];
+    gt[d0 + i] = R.tb[i];
+  }
 }
 
 // Reverse of one step of world w: the forward step is recomputed in LDS
@@ -1740,7 +1893,7 @@ size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block) {
 // integration and correction (per body), the contacts' impulses, wrenches and
 // geometry (lane per contact, per-body segmented sums) and the smooth
 // prediction (per body).  Contacts come from the collision kernel's workspace.
-template <int CONDIM, int BS>
+template <int CONDIM, int BS, bool ART>
 __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   using adj::Vec;
   using adj::vec;
@@ -1753,10 +1906,12 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   float *sv = sq + pad4(nq);
   float *st = sv + pad4(nv);
   float4 *reg = reinterpret_cast<float4 *>(st + pad4(nv));
-  float *sq0 = reinterpret_cast<float *>(reg + resolve_region_bytes(nb, ng, 0, 0) / sizeof(float4));
-  float4 *acc = reinterpret_cast<float4 *>(sq0 + pad4(nq));  // [3][nb]
-  float4 *bFb = acc + 3 * nb, *bTb = bFb + nb, *bQb = bTb + nb;
-  float4 *pay = bQb + nb;  // [2][3][BS]
+  float *sq0 = reinterpret_cast<float *>(reg + resolve_region_bytes(nb, ng, ART ? a.nsub : 0, ART ? a.art_floats : 0) /
+                                                      sizeof(float4));
+  float4 *acc = reinterpret_cast<float4 *>(sq0 + pad4(nq));  // [4][nb]
+  float4 *bFb = acc + 4 * nb, *bTb = bFb + nb, *bQb = bTb + nb;
+  float4 *pay = bQb + nb;  // [2][4][BS]
+  float *artb = reinterpret_cast<float *>(pay + 8 * BS);  // subtree reverse blocks
 
   // ---- forward step, kept in LDS
   const size_t cbase = (size_t)w * a.ncon_max;
@@ -1777,15 +1932,22 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   } else {
     for (int i = tid; i < nv; i += BS) st[i] = 0.f;
   }
-  resolve_world<CONDIM, BS, false>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg,
-                                   cbase);
+  resolve_world<CONDIM, BS, ART>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg, cbase);
   const ResolveRegion RR = resolve_region(reg, nb, ng);
   const Params P = a.p;
   auto xyz = [](float4 f) { return vec(f.x, f.y, f.z); };
 
-  // ---- reverse of integration and correction, per body
+  // ---- reverse of integration and correction, per free body and per subtree
+  if (ART)
+  for (int si = tid; si < a.nsub; si += BS) {
+    const SubTree S = a.sub[si];
+    art_rev_correct(S, a.body, RR.bC, RR.bO, RR.bAx, RR.accF, RR.accT, RR.art + S.lofs, artb + S.bofs,
+                    b.gq_out ? b.gq_out + (size_t)w * nq : nullptr, b.gv_out ? b.gv_out + (size_t)w * nv : nullptr,
+                    bFb, bTb, bQb, acc, nb, P.h);
+  }
   for (int bi = tid; bi < nb; bi += BS) {
     const BodyC bc = a.body[bi];
+    if (ART && !bc.fast) continue;
     const float4 mi = a.bmi[(size_t)w * nb + bi];
     adj::BodyUpdate<float> U;
     U.m = mi.x; U.d[0] = mi.y; U.d[1] = mi.z; U.d[2] = mi.w;
@@ -1810,6 +1972,7 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
     acc[bi] = make_float4(xb.x, xb.y, xb.z, psi.x);
     acc[nb + bi] = make_float4(psi.y, psi.z, vsb.x, vsb.y);
     acc[2 * nb + bi] = make_float4(vsb.z, wsb.x, wsb.y, wsb.z);
+    acc[3 * nb + bi] = make_float4(0.f, 0.f, 0.f, 0.f);
     bFb[bi] = make_float4(Fb.x, Fb.y, Fb.z, 0.f);
     bTb[bi] = make_float4(Tb.x, Tb.y, Tb.z, 0.f);
     bQb[bi] = make_float4(qb[0], qb[1], qb[2], qb[3]);
@@ -1821,9 +1984,9 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   for (int base = 0; base < nc; base += BS) {
     const int k = base + tid;
     int kA = nb, kB = nb;
-    float4 pA[3], pB[3];
+    float4 pA[4], pB[4];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) pA[i] = pB[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = 0; i < 4; ++i) pA[i] = pB[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (k < nc) {
       const float4 cn = a.cnp[cbase + k], cp = a.cpos[cbase + k];
       const uint32_t sl = __float_as_uint(cp.w);
@@ -1936,26 +2099,36 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
         pA[0] = make_float4(xab.x, xab.y, xab.z, psa.x);
         pA[1] = make_float4(psa.y, psa.z, o.va.x, o.va.y);
         pA[2] = make_float4(o.va.z, o.wa.x, o.wa.y, o.wa.z);
+        pA[3] = make_float4(o.trs, 0.f, 0.f, 0.f);
       }
       if (bbd >= 0) {
         kB = bbd;
         pB[0] = make_float4(xbb.x, xbb.y, xbb.z, psb.x);
         pB[1] = make_float4(psb.y, psb.z, o.vb.x, o.vb.y);
         pB[2] = make_float4(o.vb.z, o.wb.x, o.wb.y, o.wb.z);
+        pB[3] = make_float4(o.trs, 0.f, 0.f, 0.f);
       }
     }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 4; ++i) {
       pay[i * BS + tid] = pA[i];
-      pay[(3 + i) * BS + tid] = pB[i];
+      pay[(4 + i) * BS + tid] = pB[i];
     }
     __syncthreads();
-    body_segment_sum<BS, 3>(kA, kB, pay, pay + 3 * BS, acc, nb, a.nbits);
+    body_segment_sum<BS, 4>(kA, kB, pay, pay + 4 * BS, acc, nb, a.nbits);
   }
 
-  // ---- reverse of the smooth prediction, per body; adjoint rows staged in LDS
+  // ---- reverse of the smooth prediction, per free body and per subtree;
+  // adjoint rows staged in LDS
+  if (ART)
+  for (int si = tid; si < a.nsub; si += BS) {
+    const SubTree S = a.sub[si];
+    art_rev_predict(S, a.body, a.bmi + (size_t)w * nb, RR.bC, RR.bO, RR.bAx, RR.art + S.lofs, artb + S.bofs, acc, nb,
+                    sq0, vw, a.act, P, sq, sv, st);
+  }
   for (int bi = tid; bi < nb; bi += BS) {
     const BodyC bc = a.body[bi];
+    if (ART && !bc.fast) continue;
     const float4 mi = a.bmi[(size_t)w * nb + bi];
     adj::BodyPredict<float> B;
     B.m = mi.x; B.d[0] = mi.y; B.d[1] = mi.z; B.d[2] = mi.w;
@@ -1988,26 +2161,31 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   }
 }
 
-template <int CONDIM>
+template <int CONDIM, bool ART>
 static hipError_t launch_backward_c(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
   switch (block) {
-    case 64: hipLaunchKernelGGL((backward_kernel<CONDIM, 64>), dim3(nworld), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((backward_kernel<CONDIM, 128>), dim3(nworld), dim3(128), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((backward_kernel<CONDIM, 256>), dim3(nworld), dim3(256), lds, s, a); break;
+    case 64: hipLaunchKernelGGL((backward_kernel<CONDIM, 64, ART>), dim3(nworld), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((backward_kernel<CONDIM, 128, ART>), dim3(nworld), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((backward_kernel<CONDIM, 256, ART>), dim3(nworld), dim3(256), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_backward(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
-  if (a.s.nsub > 0) return hipErrorInvalidValue;
+template <bool ART>
+static hipError_t launch_backward_a(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
   switch (a.s.condim) {
-    case 1: return launch_backward_c<1>(a, nworld, block, lds, s);
-    case 3: return launch_backward_c<3>(a, nworld, block, lds, s);
-    case 4: return launch_backward_c<4>(a, nworld, block, lds, s);
-    case 6: return launch_backward_c<6>(a, nworld, block, lds, s);
+    case 1: return launch_backward_c<1, ART>(a, nworld, block, lds, s);
+    case 3: return launch_backward_c<3, ART>(a, nworld, block, lds, s);
+    case 4: return launch_backward_c<4, ART>(a, nworld, block, lds, s);
+    case 6: return launch_backward_c<6, ART>(a, nworld, block, lds, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_backward(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  return a.s.nsub > 0 ? launch_backward_a<true>(a, nworld, block, lds, s)
+                      : launch_backward_a<false>(a, nworld, block, lds, s);
 }
 
 }  // namespace cf

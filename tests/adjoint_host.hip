@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../paper_2603_12185_amd/csrc/cf_adjoint.h"
+#include "../paper_2603_12185_amd/csrc/cf_artadj.h"
 
 using namespace cf::adj;
 typedef double D;
@@ -172,10 +173,12 @@ static void check_contact(int trial, bool has_a, bool has_b, D phi_scale) {
   std::vector<D> x;
   put(x, C.n); x.push_back(C.phi); put(x, C.p);
   put(x, C.xa); put(x, C.va); put(x, C.wa); put(x, C.xb); put(x, C.vb); put(x, C.wb);
+  x.push_back(C.trs);
   auto L = [&](const std::vector<D> &y) {
     ContactIn<D> K = C;
     K.n = get(y, 0); K.phi = y[3]; K.p = get(y, 4);
     K.xa = get(y, 7); K.va = get(y, 10); K.wa = get(y, 13); K.xb = get(y, 16); K.vb = get(y, 19); K.wb = get(y, 22);
+    K.trs = y[25];
     D lam[NF];
     V f, ta, tb;
     contact_forward<NF>(K, imp(), lam, f, ta, tb);
@@ -189,6 +192,7 @@ static void check_contact(int trial, bool has_a, bool has_b, D phi_scale) {
   std::vector<D> an;
   put(an, o.n); an.push_back(o.phi); put(an, o.p);
   put(an, o.xa); put(an, o.va); put(an, o.wa); put(an, o.xb); put(an, o.vb); put(an, o.wb);
+  an.push_back(o.trs);
   char name[64];
   snprintf(name, sizeof name, "contact nf=%d a=%d b=%d phi~%g #%d", NF, has_a, has_b, phi_scale, trial);
   report(name, an, fd_grad(x, L, 1e-7), 2e-6);
@@ -328,6 +332,63 @@ static void check_line_point(int trial) {
   report(name, an, fd_grad(X, L), 1e-7);
 }
 
+// Phi of an articulated subtree (cf_artadj.h): its derivatives along every
+// joint angle and rate by the dual-number pass (float32) against central
+// differences of the float64 pass.  A chain of four bodies under a fixed base
+// (hinge, hinge, slide, hinge) with random frames, axes, COM offsets and
+// inertias; random Mbar, cbar, Jbar.
+static void check_subtree_phi(int trial) {
+  using cf::BodyC;
+  using namespace cf::artadj;
+  const int nbs = 4, nd = 4;
+  BodyC B[4] = {};
+  const int jt[4] = {cf::kHinge, cf::kHinge, cf::kSlide, cf::kHinge};
+  for (int k = 0; k < nbs; ++k) {
+    BodyC &c = B[k];
+    c.parent = k - 1;
+    c.jnt = jt[k];
+    c.qadr = k;
+    c.dadr = k;
+    c.fast = 0;
+    const V p = rv(0.1), ip = rv(0.05);
+    V ax = rv(1.0);
+    ax = (D(1) / sqrt(vdot(ax, ax))) * ax;
+    c.pos = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+    c.quat = make_float4((float)U(-1, 1), (float)U(-1, 1), (float)U(-1, 1), (float)U(-1, 1));
+    c.axis = make_float4((float)ax.x, (float)ax.y, (float)ax.z, 0.f);
+    c.ipos = make_float4((float)ip.x, (float)ip.y, (float)ip.z, 0.f);
+  }
+  float4 bmi[4];
+  for (int k = 0; k < nbs; ++k) bmi[k] = make_float4((float)U(0.1, 1), (float)U(1e-3, 1e-2), (float)U(1e-3, 1e-2), (float)U(1e-3, 1e-2));
+  std::vector<float> Mb(nd * nd), cb(nd), Jb(6 * nd * nbs);
+  for (auto &x : Mb) x = (float)U(-1, 1);
+  for (auto &x : cb) x = (float)U(-1, 1);
+  for (auto &x : Jb) x = (float)U(-1, 1);
+  std::vector<D> th(nd), thd(nd);
+  for (int i = 0; i < nd; ++i) { th[i] = (float)U(-1, 1); thd[i] = (float)U(-3, 3); }
+  const float g[3] = {0.1f, -0.2f, -9.81f};
+  std::vector<D> x(th);
+  x.insert(x.end(), thd.begin(), thd.end());
+  std::vector<D> wk(phi_work(nbs, nd));
+  auto L = [&](const std::vector<D> &y) {
+    return subtree_phi<D>(B, 0, nbs, 0, nd, bmi, y.data(), y.data() + nd, g[0], g[1], g[2], Mb.data(), cb.data(),
+                          Jb.data(), wk.data());
+  };
+  std::vector<Du<float>> a(nd), ad(nd), wd(phi_work(nbs, nd));
+  std::vector<D> an(2 * nd);
+  for (int k = 0; k < 2 * nd; ++k) {
+    for (int i = 0; i < nd; ++i) {
+      a[i] = du<float>((float)th[i], k == i ? 1.f : 0.f);
+      ad[i] = du<float>((float)thd[i], k == nd + i ? 1.f : 0.f);
+    }
+    an[k] = subtree_phi<Du<float>>(B, 0, nbs, 0, nd, bmi, a.data(), ad.data(), g[0], g[1], g[2], Mb.data(), cb.data(),
+                                   Jb.data(), wd.data()).d;
+  }
+  char name[64];
+  snprintf(name, sizeof name, "subtree phi (dual) #%d", trial);
+  report(name, an, fd_grad(x, L), 2e-4);
+}
+
 int main() {
   for (int t = 0; t < 4; ++t) check_predict(t);
   for (int t = 0; t < 3; ++t) check_update(t, 20.0);
@@ -345,6 +406,7 @@ int main() {
   for (int t = 0; t < 3; ++t) check_sphere_pair(t);
   for (int t = 0; t < 3; ++t) check_plane_point(t);
   for (int t = 0; t < 3; ++t) check_line_point(t);
+  for (int t = 0; t < 3; ++t) check_subtree_phi(t);
   printf("%s (%d failures)\n", failures ? "FAILED" : "ALL OK", failures);
   return failures ? 1 : 0;
 }
