@@ -428,7 +428,7 @@ __device__ void art_correct(const SubTree S, const BodyC *B, const float4 *bC, c
     const float nx_ = ew * qx0 + ex * qw0 + ey * qz0 - ez * qy0;
     const float ny_ = ew * qy0 - ex * qz0 + ey * qw0 + ez * qx0;
     const float nz_ = ew * qz0 + ex * qy0 - ey * qx0 + ez * qw0;
-    const float inv = 1.0f / sqrtf(nw_ * nw_ + nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+    const float inv = rsqrtf(nw_ * nw_ + nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
     qb[3] = nw_ * inv; qb[4] = nx_ * inv; qb[5] = ny_ * inv; qb[6] = nz_ * inv;
   }
 }
@@ -1217,8 +1217,10 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     const float *qb = sq + qadr, *vb = sv + dadr, *tb = st + dadr;
     float R[9];
     quat_to_rot<float>(qb[3], qb[4], qb[5], qb[6], R);
-    const float invm = 1.0f / mi.x;
-    const float d[3] = {mi.y, mi.z, mi.w}, e[3] = {1.0f / mi.y, 1.0f / mi.z, 1.0f / mi.w};
+    // hardware reciprocals (1 ulp) for the per-body inverses
+    const float invm = __builtin_amdgcn_rcpf(mi.x);
+    const float d[3] = {mi.y, mi.z, mi.w},
+                e[3] = {__builtin_amdgcn_rcpf(mi.y), __builtin_amdgcn_rcpf(mi.z), __builtin_amdgcn_rcpf(mi.w)};
     // world inertia R diag(I) R^T and its inverse R diag(1/I) R^T (xx, yy, zz, xy, xz, yz)
     float Iw[6], Ii[6];
     const int ri[6] = {0, 1, 2, 0, 0, 1}, rj[6] = {0, 1, 2, 1, 2, 2};
@@ -1302,7 +1304,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       const float up = P.power2 ? u * u : powf(u, P.power);
       const float gam = lo ? P.mid * up : 1.0f - (1.0f - P.mid) * up;
       const float r = P.r_min + (P.r_max - P.r_min) * gam;
-      const float A = trs > 0.f ? (r / (1.0f - r)) / trs : 0.f;
+      const float A = trs > 0.f ? r * __builtin_amdgcn_rcpf((1.0f - r) * trs) : 0.f;
       float Af[NF];
 #pragma unroll
       for (int i = 0; i < NF; ++i) Af[i] = A;
@@ -1481,7 +1483,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     const float nx_ = ew * qx0 + ex * qw0 + ey * qz0 - ez * qy0;
     const float ny_ = ew * qy0 - ex * qz0 + ey * qw0 + ez * qx0;
     const float nz_ = ew * qz0 + ex * qy0 - ey * qx0 + ez * qw0;
-    const float inv = 1.0f / sqrtf(nw_ * nw_ + nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+    const float inv = rsqrtf(nw_ * nw_ + nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
     qb[3] = nw_ * inv; qb[4] = nx_ * inv; qb[5] = ny_ * inv; qb[6] = nz_ * inv;
   }
   __syncthreads();

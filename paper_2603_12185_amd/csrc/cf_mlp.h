@@ -40,9 +40,13 @@ __device__ inline short to_bf16(float x) {
   return (short)(u >> 16);
 }
 
-__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware exponential and reciprocal
+// (v_exp_f32, v_rcp_f32: about 1 ulp each, far below the bf16 rounding of the
+// activations); a large negative z gives exp = inf, rcp = 0, silu = -0.
+__device__ inline float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu(float z) { return z * sigmoid(z); }
 __device__ inline float dsilu(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
