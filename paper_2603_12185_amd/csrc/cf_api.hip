@@ -323,13 +323,13 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       }
     }
   }
-  m->lds_collide = cf::collide_lds_bytes(m->nq, nb, ng, m->norient, m->nsub);
+  m->lds_collide = cf::collide_lds_bytes(m->nq, nb, ng, m->norient, m->nsub, m->nsph);
   m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->nsub, m->art_floats);
   if (m->lds_collide > kLdsLimit || m->lds_resolve > kLdsLimit) {
     delete m;
     return set_err(CF_E_UNSUPPORTED, "world too large for one workgroup's LDS (reduce bodies or geoms)");
   }
-  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, nb, ng, m->norient, m->nsub, m->art_floats, m->ncon_max);
+  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, nb, ng, m->norient, m->nsub, m->nsph, m->art_floats, m->ncon_max);
   for (int bs : {256, 128, 64}) {
     const size_t l = cf::backward_lds_bytes(m->nq, m->nv, nb, ng, bs, m->nsub, m->art_floats, m->artb_floats);
     if (l <= kLdsLimit) { m->block_backward = bs; m->lds_backward = l; break; }
@@ -648,7 +648,7 @@ cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolv
   m->block_resolve = resolve_block;
   m->block_rollout = rollout_block;
   m->rollout_steps = false;
-  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->art_floats, m->ncon_max);
+  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->nsph, m->art_floats, m->ncon_max);
   return CF_OK;
 }
 
@@ -700,7 +700,7 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
     }
   m->rollout_steps = false;
   for (int io = 0; io < 3 && st == CF_OK; ++io) {
-    const size_t lds = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->art_floats, m->ncon_max);
+    const size_t lds = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->nsph, m->art_floats, m->ncon_max);
     if (lds > kLdsLimit) continue;
     m->block_rollout = sizes[io];
     m->lds_rollout = lds;

@@ -131,8 +131,8 @@ size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, i
 int art_backward_floats(int nd, int nbs);
 hipError_t launch_backward(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 
-size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub);
-size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int art_floats, int cap);
+size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub, int nsph);
+size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int nsph, int art_floats, int cap);
 hipError_t launch_rollout(const RolloutArgs &a, int block, size_t lds, hipStream_t s);
 size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int nsub, int art_floats);
 size_t resolve_learned_lds_bytes(int block);  // extra LDS of the resolution with learned gains

@@ -611,11 +611,13 @@ __device__ inline double slot_eval(uint32_t s, const float4 *Gs, const int *go, 
   return phi;
 }
 
-// LDS scratch of the narrow phase of one world (after its q row).
-size_t collide_region_bytes(int nb, int ng, int norient, int nsub) {
+// LDS scratch of the narrow phase of one world (after its q row); the sphere
+// block's hit masks (nsph rows of ceil(nsph / 64) words) come last.
+size_t collide_region_bytes(int nb, int ng, int norient, int nsub, int nsph) {
   return sizeof(float4) * (size_t)ng + 2 * sizeof(int) * (size_t)pad4(ng) +
          (sizeof(Pose<float>) + sizeof(Pose<double>)) * (size_t)norient + sizeof(uint32_t) * kCandCap +
-         (nsub > 0 ? sizeof(double) * 16 * (size_t)nb : 0);
+         (nsub > 0 ? sizeof(double) * 16 * (size_t)nb : 0) +
+         sizeof(unsigned long long) * (size_t)nsph * (size_t)((nsph + 63) / 64);
 }
 
 // Per-geom inputs of the narrow phase (loaded ahead of the q row's barrier).
@@ -795,37 +797,53 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
 
   // Sphere block: the last nsph geoms are spheres centred on free bodies (or
   // static), and every pair of them on different bodies is a slot, in row-major
-  // order after all other slots.  Lane per row: the columns j > i are tested
-  // against LDS records read at one address by every lane, the hits form a
-  // bit mask per row, rows are placed by a prefix sum of their counts, and the
-  // hits are evaluated densely (float32: the centres are exact state values).
-  // A pair is a contact when |c_b - c_a|^2 < (r_a + r_b + margin)^2.
+  // order after all other slots.  The pairs are tested cyclically: the lane of
+  // sphere i tests (i, i + d mod S) for d = 1 .. S/2 (d = S/2 once per pair), so
+  // every lane makes about S/2 tests against LDS records of consecutive
+  // spheres; a hit sets bit max(i, j) of row min(i, j) in an LDS mask (integer
+  // OR, order-free).  Rows are then placed in canonical order by a prefix sum
+  // of their popcounts, and the hits are evaluated densely (float32: the centres
+  // are exact state values) and stored in order.  A pair is a contact when
+  // |c_b - c_a|^2 < (r_a + r_b + margin)^2 (the same float32 value from either
+  // end of the pair).
   if (a.nsph > 0) {
     __shared__ int wsum[NW];
     const int g0 = a.sph0, S = a.nsph, nwd = (S + 63) >> 6;
+    unsigned long long *rm = reinterpret_cast<unsigned long long *>(
+        a.nsub > 0 ? reinterpret_cast<char *>(brot + 12 * a.nb) : reinterpret_cast<char *>(borg));
+    for (int x = tid; x < S * nwd; x += BS) rm[x] = 0ull;
+    __syncthreads();
+    const int half = S >> 1;
+    for (int r0 = 0; r0 < S; r0 += BS) {
+      const int i = r0 + tid;
+      if (i < S) {
+        const float4 Gi = Gs[g0 + i];
+        const int bi = gbd[g0 + i];
+        const int dmax = (S & 1) ? half : (i < half ? half : half - 1);
+        for (int d = 1; d <= dmax; ++d) {
+          const int j = i + d < S ? i + d : i + d - S;
+          const float4 Gj = Gs[g0 + j];
+          const int bj = gbd[g0 + j];
+          const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
+          const float R = Gi.w + Gj.w + a.margin;
+          if (bi != bj && R > 0.f && dx * dx + dy * dy + dz * dz < R * R) {
+            const int lo = min(i, j), hi = max(i, j);
+            atomicOr(rm + lo * nwd + (hi >> 6), 1ull << (hi & 63));
+          }
+        }
+      }
+    }
+    __syncthreads();
     for (int r0 = 0; r0 < S; r0 += BS) {
       const int i = r0 + tid;
       const bool row = i < S;
-      const float4 Gi = row ? Gs[g0 + i] : make_float4(0.f, 0.f, 0.f, 0.f);
-      const int bi = row ? gbd[g0 + i] : -2;
       unsigned long long m[4] = {0ull, 0ull, 0ull, 0ull};
       int cnt = 0;
 #pragma unroll
       for (int cw = 0; cw < 4; ++cw) {
         if (cw >= nwd) break;
-        const int j0 = cw * 64;
-        const int jlo = max(j0, r0 + 1), jhi = min(j0 + 64, S);
-        unsigned long long mw = 0ull;
-        for (int j = jlo; j < jhi; ++j) {
-          const float4 Gj = Gs[g0 + j];
-          const int bj = gbd[g0 + j];
-          const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
-          const float R = Gi.w + Gj.w + a.margin;
-          const bool hit = j > i && bi != bj && R > 0.f && dx * dx + dy * dy + dz * dz < R * R;
-          mw |= (unsigned long long)hit << (j - j0);
-        }
-        m[cw] = mw;
-        cnt += __popcll(mw);
+        m[cw] = row ? rm[i * nwd + cw] : 0ull;
+        cnt += __popcll(m[cw]);
       }
       int tot;
       const int pre = block_scan_int<BS>(cnt, &tot, wsum);
@@ -894,8 +912,8 @@ __global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
   }
 }
 
-size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub) {
-  return sizeof(float) * pad4(nq) + collide_region_bytes(nb, ng, norient, nsub);
+size_t collide_lds_bytes(int nq, int nb, int ng, int norient, int nsub, int nsph) {
+  return sizeof(float) * pad4(nq) + collide_region_bytes(nb, ng, norient, nsub, nsph);
 }
 
 template <bool ART>
@@ -1559,8 +1577,8 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
 // ====================================================================
 // rollout: T steps of one world per workgroup, state and contacts in LDS
 // ====================================================================
-size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int art_floats, int cap) {
-  const size_t c = collide_region_bytes(nb, ng, norient, nsub);
+size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, int nsph, int art_floats, int cap) {
+  const size_t c = collide_region_bytes(nb, ng, norient, nsub, nsph);
   const size_t r = resolve_region_bytes(nb, ng, nsub, art_floats);
   return sizeof(float) * (pad4(nq) + 2 * (size_t)pad4(nv)) + 2 * sizeof(float4) * (size_t)cap + (c > r ? c : r);
 }
