@@ -218,7 +218,9 @@ cf_status cf_model_set_actuators(cf_model *m, const float *kp, const float *kd);
  * more than that of moving `margin` in one step; then the contact keeps the
  * heuristic gain.  params NULL switches the network off.  Models of free
  * bodies with the heuristic impedance only (else CF_E_UNSUPPORTED); the
- * resolution then runs at most 128 threads per world; cf_rollout uses step
+ * resolution then runs at most 128 threads per world, after a one-workgroup
+ * kernel that writes the network's bf16 LDS image from params (a device buffer
+ * of the model, allocated by the first call with params); cf_rollout uses step
  * launches; cf_step_backward does not cover it. */
 cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float margin);
 

@@ -59,6 +59,7 @@ struct cf_model {
   int *d_ncon = nullptr, *d_over = nullptr;
   size_t lds_collide = 0, lds_resolve = 0;
   const float *mlp = nullptr;  // learned-gain network parameters (caller-owned device memory)
+  float4 *d_mlp_img = nullptr; // their LDS image, rewritten by every step that uses them
   bool box_pairs = false;      // box-sphere or box-capsule slots present
   std::vector<int> dof_jnt;    // joint type of each dof
   std::vector<int> dof_q;      // q index of each dof's joint (hinge / slide)
@@ -85,6 +86,7 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 void free_model(cf_model *m) {
   if (!m) return;
   (void)hipFree(m->d_slots); (void)hipFree(m->d_gbody); (void)hipFree(m->d_gorient); (void)hipFree(m->d_act);
+  (void)hipFree(m->d_mlp_img);
   (void)hipFree(m->d_body); (void)hipFree(m->d_sub); (void)hipFree(m->d_bmi); (void)hipFree(m->d_gdat);
   (void)hipFree(m->d_gpos); (void)hipFree(m->d_gquat); (void)hipFree(m->d_gfr2);
   (void)hipFree(m->d_cnp); (void)hipFree(m->d_cpos); (void)hipFree(m->d_ncon); (void)hipFree(m->d_over);
@@ -445,12 +447,16 @@ static bool rollout_fused(const cf_model *m) {
   return m->lds_rollout <= kLdsLimit && !m->rollout_steps && !m->mlp;
 }
 
-// The resolution launch of a step: with learned gains the kernel stages the
-// network in LDS and runs at most 128 threads per world.
+// The resolution launch of a step: with learned gains the network's LDS image
+// is first written from the current parameters (one small kernel), then the
+// resolution copies it to LDS and runs at most 128 threads per world.
 static hipError_t launch_resolve_model(const cf_model *m, cf::ResolveArgs ra, hipStream_t s) {
   if (!m->mlp) return cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
   const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
   ra.mlp = m->mlp;
+  ra.mlp_img = m->d_mlp_img;
+  const hipError_t e = cf::launch_mlp_pack(m->mlp, m->d_mlp_img, s);
+  if (e != hipSuccess) return e;
   const size_t lds = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, 0, 0) + cf::resolve_learned_lds_bytes(block);
   return cf::launch_resolve(ra, m->nw, block, lds, s);
 }
@@ -591,6 +597,10 @@ cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float
   const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
   if (cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, 0, 0) + cf::resolve_learned_lds_bytes(block) > kLdsLimit)
     return set_err(CF_E_UNSUPPORTED, "world too large for the learned resolution's LDS");
+  if (!m->d_mlp_img && hipMalloc((void **)&m->d_mlp_img, cf::mlp_image_bytes()) != hipSuccess) {
+    m->d_mlp_img = nullptr;
+    return set_err(CF_E_NOMEM, "learned-gain network image");
+  }
   m->mlp = params;
   m->p.mlp_margin = margin;
   return CF_OK;

@@ -100,6 +100,7 @@ struct ResolveArgs {
   float *x_dist, *x_pos, *x_frame, *x_imp;
   float *x_feat, *x_target;     // learned-gain training data (free-body models)
   const float *mlp;             // learned-gain network parameters, or null
+  const float4 *mlp_img;        // their LDS image (launch_mlp_pack), with mlp
   const float4 *act;            // [nv] position actuators (kp, kd, q index bits, -), or null
   int nq, nv, nb, ng, ncon_max, condim, nfacet, nbits, nsub, art_floats;
   Params p;
@@ -125,6 +126,11 @@ struct BackwardArgs {
   const float *gq_out, *gv_out; // [nw][nq], [nw][nv] adjoints of q+, v+ (null = 0)
   float *gq, *gv, *gtau;        // [nw][nq], [nw][nv], [nw][nv] (gtau may be null)
 };
+
+// Learned gains: bytes of the network's LDS image, and the kernel writing it
+// from the float32 parameters (one workgroup).
+size_t mlp_image_bytes();
+hipError_t launch_mlp_pack(const float *params, void *img, hipStream_t s);
 
 size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, int art_floats, int artb_floats);
 // Floats of the reverse-pass work block of a subtree with nd dofs and nbs bodies.

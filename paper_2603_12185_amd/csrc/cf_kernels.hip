@@ -1565,7 +1565,11 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
     lnet = reinterpret_cast<mlp::Weights *>(base);
     lfeat = reinterpret_cast<float *>(base + (sizeof(mlp::Weights) + 15) / 16 * 16);
     lout = lfeat + BS * mlp::NIN;
-    mlp::stage_weights<BS>(a.mlp, lnet);
+    // copy of the network's image, written for this step by launch_mlp_pack
+    static_assert(sizeof(mlp::Weights) % sizeof(float4) == 0, "image copied in float4");
+    float4 *dst = reinterpret_cast<float4 *>(lnet);
+    for (int i = tid; i < (int)(sizeof(mlp::Weights) / sizeof(float4)); i += BS) dst[i] = a.mlp_img[i];
+    __syncthreads();
   }
   resolve_world<CONDIM, BS, ART, LEARN>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg,
                                         cbase, true, lnet, lfeat, lout);

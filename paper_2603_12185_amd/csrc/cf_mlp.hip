@@ -216,7 +216,20 @@ static int grad_waves(int n) {
   return (w + NWAVE - 1) / NWAVE * NWAVE;
 }
 
+// The network's LDS image (layout of Weights: bf16 transposed weights, float32
+// biases and normalisation) written once per step from the float32 parameters,
+// so each workgroup of the resolution copies it instead of converting.
+__global__ __launch_bounds__(256) void pack_kernel(const float *p, Weights *img) { stage_weights<256>(p, img); }
+
 }  // namespace mlp
+
+size_t mlp_image_bytes() { return sizeof(mlp::Weights); }
+
+hipError_t launch_mlp_pack(const float *params, void *img, hipStream_t s) {
+  hipLaunchKernelGGL(mlp::pack_kernel, dim3(1), dim3(256), 0, s, params, reinterpret_cast<mlp::Weights *>(img));
+  return hipGetLastError();
+}
+
 }  // namespace cf
 
 using namespace cf::mlp;
