@@ -166,11 +166,10 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
  * step's forward pass from (q, v, tau)).  Float32 device buffers, 16-byte
  * aligned; gq/gv may alias gq_out/gv_out exactly.  Asynchronous on stream;
  * uses the model's contact workspace (so it must not overlap a cf_step of the
- * same model on another stream).  Articulated subtrees are covered when all
- * their joints are hinges or slides under a fixed base (a subtree rooted at a
- * free joint returns CF_E_UNSUPPORTED), position actuators included (their
- * gtau entries are adjoints of the targets); the diagonal and the learned
- * impedance return CF_E_UNSUPPORTED. */
+ * same model on another stream).  Articulated subtrees (hinge and slide joints
+ * below a fixed or a free root) and position actuators are covered (an
+ * actuated dof's gtau entry is the adjoint of its target); the diagonal and the
+ * learned impedance return CF_E_UNSUPPORTED. */
 cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                            const float *gq_out, const float *gv_out, float *gq, float *gv, float *gtau);
 

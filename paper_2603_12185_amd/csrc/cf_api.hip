@@ -45,7 +45,6 @@ struct cf_model {
   cf::BodyC *d_body = nullptr;
   cf::SubTree *d_sub = nullptr;
   int norient = 0, nsub = 0, art_floats = 0, artb_floats = 0;
-  bool art_backward = false;  // cf_step_backward covers the model's subtrees
   int block_collide = 64, block_resolve = 128, block_rollout = 256;
   size_t lds_rollout = 0;
   int block_backward = 0;  // 0: the adjoint's LDS does not fit any workgroup size
@@ -177,7 +176,6 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   std::vector<cf::BodyC> bodyc(nb);
   std::vector<cf::SubTree> subs;
   int art_floats = 0, artb_floats = 0;
-  bool art_backward = true;  // every subtree: hinge / slide joints under a fixed base
   for (int b = 0; b < nb;) {
     int e = b + 1;
     while (e < nb && root[e] == b) ++e;
@@ -193,7 +191,6 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       art_floats += st.nd * st.nd + 9 * st.nd;
       st.bofs = artb_floats;
       artb_floats += cf::art_backward_floats(st.nd, st.nb);
-      for (int k = b; k < e; ++k) art_backward = art_backward && d->body_jnt[k] != CF_JNT_FREE;
       subs.push_back(st);
     }
     for (int k = b; k < e; ++k) {
@@ -273,7 +270,7 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   m->nf = d->condim == 1 ? 1 : d->condim == 3 ? 4 : d->condim == 4 ? 6 : 10;
   m->nq = nq; m->nv = nv;
   m->nsub = (int)subs.size(); m->art_floats = art_floats;
-  m->artb_floats = artb_floats; m->art_backward = art_backward;
+  m->artb_floats = artb_floats;
   m->nslot = (int)slots.size();
   m->box_pairs = box_pairs;
   m->dof_jnt.resize(nv);
@@ -528,8 +525,6 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
       overlap(gtau, sv, q, sq) || overlap(gtau, sv, v, sv) || overlap(gtau, sv, tau, sv) ||
       overlap(gtau, sv, gq_out, sq) || overlap(gtau, sv, gv_out, sv))
     return set_err(CF_E_INVALID_ARG, "gq/gv may alias gq_out/gv_out only exactly; no other overlap");
-  if (m->nsub > 0 && !m->art_backward)
-    return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers subtrees of hinge and slide joints under a fixed base");
   if (m->p.imp_diag || m->mlp)
     return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers the heuristic impedance only");
   if (!m->block_backward) return set_err(CF_E_UNSUPPORTED, "world too large for the adjoint's LDS");

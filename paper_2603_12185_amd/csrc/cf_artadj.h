@@ -1,5 +1,5 @@
 // cf_artadj.h - pieces of the reverse pass of an articulated subtree (hinge and
-// slide joints under a fixed base) for cf_step_backward.
+// slide joints below a fixed or free root) for cf_step_backward.
 //
 // The subtree's prediction uses M(th), the bias c(th, thd) and the body
 // Jacobians J_b(th) (Eq. smooth_vel and the J~^T lambda scatter of Eq.
@@ -9,7 +9,8 @@
 //   Phi(th, thd) = <Mbar, M(th)> + <cbar, c(th, thd)> + sum_b <Jbar_b, J_b(th)>
 // with Mbar, cbar, Jbar held fixed.  subtree_phi evaluates Phi over any scalar
 // type; with the dual numbers below it gives one directional derivative per
-// call (forward mode, one call per joint angle and one per joint rate).
+// call (forward mode, one call per joint angle and one per joint rate; a free
+// root's pose is varied along a translation or a world-frame rotation increment).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -63,15 +64,19 @@ CF_HD void quat_rot_f(float w, float x, float y, float z, float *R) {
 // Workspace of subtree_phi, in scalars: 24 per body and 6 per dof.
 CF_HD int phi_work(int nbs, int nd) { return 24 * nbs + 6 * nd; }
 
-// Phi over one subtree of hinge / slide joints whose root hangs from the world.
-// B: the model's bodies; the subtree is bodies [b0, b0 + nbs) with dofs
-// [d0, d0 + nd) (one per body); bmi: (m, Ixx, Iyy, Izz) per body of the world
-// (indexed by body); th, thd: joint values and rates [nd]; g: gravity.
-// Mbar [nd][nd], cbar [nd], Jbar [nbs][6][nd] (rows: COM linear x y z, angular
-// x y z).  wk: phi_work(nbs, nd) scalars.
+// Phi over one subtree: hinge / slide joints below a root that hangs from the
+// world by a hinge, a slide or a free joint.  B: the model's bodies; the subtree
+// is bodies [b0, b0 + nbs) with dofs [d0, d0 + nd) (a free root's 6 first, then
+// one per body); bmi: (m, Ixx, Iyy, Izz) per body of the world (indexed by
+// body); th, thd: joint values and rates [nd] (th unused for a free root's
+// dofs, whose pose is rpos / rrot: frame origin and row-major rotation, so a
+// caller can vary it along a translation or a world-frame rotation increment);
+// g: gravity.  Mbar [nd][nd], cbar [nd], Jbar [nbs][6][nd] (rows: COM linear
+// x y z, angular x y z).  wk: phi_work(nbs, nd) scalars.
 template <class S>
 CF_HD S subtree_phi(const BodyC *B, int b0, int nbs, int d0, int nd, const float4 *bmi, const S *th, const S *thd,
-                    float gx, float gy, float gz, const float *Mbar, const float *cbar, const float *Jbar, S *wk) {
+                    const S *rpos, const S *rrot, float gx, float gy, float gz, const float *Mbar,
+                    const float *cbar, const float *Jbar, S *wk) {
   S *org = wk, *rot = org + 3 * nbs, *ax = rot + 9 * nbs, *com = ax + 3 * nbs, *om = com + 3 * nbs,
     *vo = om + 3 * nbs, *J = vo + 3 * nbs;
   const S zero = lift<S>(0.f);
@@ -79,6 +84,16 @@ CF_HD S subtree_phi(const BodyC *B, int b0, int nbs, int d0, int nd, const float
   for (int k = 0; k < nbs; ++k) {
     const BodyC c = B[b0 + k];
     const int pk = c.parent - b0;
+    if (c.jnt == kFree) {  // the root's pose as given
+      const float ip[3] = {c.ipos.x, c.ipos.y, c.ipos.z};
+      for (int i = 0; i < 3; ++i) {
+        org[3 * k + i] = rpos[i];
+        ax[3 * k + i] = zero;
+        com[3 * k + i] = rpos[i] + rrot[3 * i] * ip[0] + rrot[3 * i + 1] * ip[1] + rrot[3 * i + 2] * ip[2];
+        for (int j = 0; j < 3; ++j) rot[9 * k + 3 * i + j] = rrot[3 * i + j];
+      }
+      continue;
+    }
     S po[3], pR[9];
     for (int i = 0; i < 3; ++i) {
       po[i] = pk >= 0 ? org[3 * pk + i] : zero;
@@ -128,7 +143,16 @@ CF_HD S subtree_phi(const BodyC *B, int b0, int nbs, int d0, int nd, const float
     for (int j = b; j >= b0; j = B[j].parent) {
       const int jk = j - b0, x = B[j].dadr - d0;
       const S a[3] = {ax[3 * jk], ax[3 * jk + 1], ax[3 * jk + 2]};
-      if (B[j].jnt == kHinge) {
+      if (B[j].jnt == kFree) {  // (e_k, 0) and (e_k x (c_b - o), e_k)
+        const S r[3] = {cb[0] - org[3 * jk], cb[1] - org[3 * jk + 1], cb[2] - org[3 * jk + 2]};
+        for (int e = 0; e < 3; ++e) {
+          J[e * nd + x + e] = lift<S>(1.f);
+          J[(3 + e) * nd + x + 3 + e] = lift<S>(1.f);
+        }
+        J[1 * nd + x + 3] = -r[2]; J[2 * nd + x + 3] = r[1];   // e_x x r = (0, -r_z, r_y)
+        J[0 * nd + x + 4] = r[2];  J[2 * nd + x + 4] = -r[0];  // e_y x r = (r_z, 0, -r_x)
+        J[0 * nd + x + 5] = -r[1]; J[1 * nd + x + 5] = r[0];   // e_z x r = (-r_y, r_x, 0)
+      } else if (B[j].jnt == kHinge) {
         const S r[3] = {cb[0] - org[3 * jk], cb[1] - org[3 * jk + 1], cb[2] - org[3 * jk + 2]};
         J[0 * nd + x] = a[1] * r[2] - a[2] * r[1];
         J[1 * nd + x] = a[2] * r[0] - a[0] * r[2];
@@ -158,6 +182,16 @@ CF_HD S subtree_phi(const BodyC *B, int b0, int nbs, int d0, int nd, const float
       const S a[3] = {ax[3 * jk], ax[3 * jk + 1], ax[3 * jk + 2]};
       const S wj[3] = {om[3 * jk], om[3 * jk + 1], om[3 * jk + 2]};
       const S wa[3] = {wj[1] * a[2] - wj[2] * a[1], wj[2] * a[0] - wj[0] * a[2], wj[0] * a[1] - wj[1] * a[0]};
+      if (B[j].jnt == kFree) {  // the root's angular rates act on c_b - origin velocity
+        const int x = B[j].dadr - d0;
+        const S wr[3] = {thd[x + 3], thd[x + 4], thd[x + 5]};
+        const S dv[3] = {vc[0] - vo[3 * jk], vc[1] - vo[3 * jk + 1], vc[2] - vo[3 * jk + 2]};
+        jl[0] = jl[0] + (wr[1] * dv[2] - wr[2] * dv[1]);
+        jl[1] = jl[1] + (wr[2] * dv[0] - wr[0] * dv[2]);
+        jl[2] = jl[2] + (wr[0] * dv[1] - wr[1] * dv[0]);
+        if (B[j].parent < b0) break;
+        continue;
+      }
       const S td = thd[B[j].dadr - d0];
       if (B[j].jnt == kHinge) {
         const S rc[3] = {cb[0] - org[3 * jk], cb[1] - org[3 * jk + 1], cb[2] - org[3 * jk + 2]};

@@ -1762,24 +1762,27 @@ size_t backward_lds_bytes(int nq, int nv, int nb, int ng, int block, int nsub, i
 
 // Reverse-pass work block of a subtree (floats): theta bar, v_s bar, y, w,
 // tau bar, theta-dot bar, c bar, u [nd each]; M bar [nd nd]; J bar [nbs][6][nd];
-// dual joint values and rates [2 nd] and the dual workspace of subtree_phi.
+// a free root's direct quaternion adjoint [4]; dual joint values and rates
+// [2 nd], dual root pose [12] and the dual workspace of subtree_phi.
 int art_backward_floats(int nd, int nbs) {
-  return nd * nd + 8 * nd + 6 * nd * nbs + 2 * (2 * nd + artadj::phi_work(nbs, nd));
+  return nd * nd + 8 * nd + 6 * nd * nbs + 4 + 2 * (2 * nd + 12 + artadj::phi_work(nbs, nd));
 }
 
-// ---- articulated subtrees in the reverse pass (hinge and slide joints under a
-// fixed base; one lane per subtree).  Forward block (art_predict/art_correct):
+// ---- articulated subtrees in the reverse pass (hinge and slide joints below a
+// fixed or free root; one lane per subtree).  A free root's 6 dofs (linear and
+// angular velocity, world frame) carry the adjoints of its frame origin and of
+// a world-frame rotation increment.  Forward block (art_predict/art_correct):
 // L [nd nd] | z = M^-1 p [nd] | v_s [nd] | cols [6 nd] | idx [nd].
 struct ArtRev {
-  float *thb, *vsb, *y, *wv, *tb, *thdb, *cb, *u, *Mb, *Jb;
-  artadj::Du<float> *th, *thd, *wk;
+  float *thb, *vsb, *y, *wv, *tb, *thdb, *cb, *u, *Mb, *Jb, *qb;
+  artadj::Du<float> *th, *thd, *rp, *rr, *wk;
 };
 __device__ inline ArtRev art_rev_block(float *bw, int nd, int nbs) {
   ArtRev r;
   r.thb = bw; r.vsb = r.thb + nd; r.y = r.vsb + nd; r.wv = r.y + nd; r.tb = r.wv + nd; r.thdb = r.tb + nd;
-  r.cb = r.thdb + nd; r.u = r.cb + nd; r.Mb = r.u + nd; r.Jb = r.Mb + nd * nd;
-  r.th = reinterpret_cast<artadj::Du<float> *>(r.Jb + 6 * nd * nbs);
-  r.thd = r.th + nd; r.wk = r.thd + nd;
+  r.cb = r.thdb + nd; r.u = r.cb + nd; r.Mb = r.u + nd; r.Jb = r.Mb + nd * nd; r.qb = r.Jb + 6 * nd * nbs;
+  r.th = reinterpret_cast<artadj::Du<float> *>(r.qb + 4);
+  r.thd = r.th + nd; r.rp = r.thd + nd; r.rr = r.rp + 3; r.wk = r.rr + 9;
   return r;
 }
 
@@ -1789,17 +1792,52 @@ __device__ inline ArtRev art_rev_block(float *bw, int nd, int nbs) {
 // for the contact reverse, M bar = -y z^T, J_b bar = W_b y^T.
 __device__ void art_rev_correct(const SubTree S, const BodyC *B, const float4 *bC, const float4 *bO,
                                 const float4 *bAx, const float4 *accF, const float4 *accT, float *blk, float *bw,
-                                const float *gqo, const float *gvo, float4 *bFb, float4 *bTb, float4 *bQb,
-                                float4 *acc, int nb, float h) {
+                                const float *q0, const float *vp, const float *gqo, const float *gvo, float4 *bFb,
+                                float4 *bTb, float4 *bQb, float4 *acc, int nb, float h) {
   const int nd = S.nd, d0 = S.d0;
   float *L = blk, *z = L + nd * nd, *cols = z + 2 * nd;
   int *idx = reinterpret_cast<int *>(cols + 6 * nd);
   const ArtRev R = art_rev_block(bw, nd, S.nb);
+  for (int i = 0; i < 4; ++i) R.qb[i] = 0.f;
+  for (int k = 0; k < S.nb; ++k) {
+    const BodyC bc = B[S.b0 + k];
+    const int x = bc.dadr - d0;
+    if (bc.jnt == kFree) {
+      // q+ = (o + h v+, normalise(exp(h w+) q)): the free-body update with no
+      // wrench (the correction went through M^-1 p)
+      adj::BodyUpdate<float> U;
+      U.m = 1.f; U.d[0] = U.d[1] = U.d[2] = 1.f;
+      for (int i = 0; i < 4; ++i) U.q[i] = q0[bc.qadr + 3 + i];
+      U.x = adj::vec(q0[bc.qadr], q0[bc.qadr + 1], q0[bc.qadr + 2]);
+      U.vs = adj::vec(vp[bc.dadr], vp[bc.dadr + 1], vp[bc.dadr + 2]);
+      U.ws = adj::vec(vp[bc.dadr + 3], vp[bc.dadr + 4], vp[bc.dadr + 5]);
+      U.F = U.Tq = adj::vec(0.f, 0.f, 0.f);
+      U.h = h;
+      adj::Vec<float> xpb = adj::vec(0.f, 0.f, 0.f), vpb = xpb, wpb = xpb;
+      float qpb[4] = {0.f, 0.f, 0.f, 0.f};
+      if (gqo) {
+        xpb = adj::vec(gqo[bc.qadr], gqo[bc.qadr + 1], gqo[bc.qadr + 2]);
+        for (int i = 0; i < 4; ++i) qpb[i] = gqo[bc.qadr + 3 + i];
+      }
+      if (gvo) {
+        vpb = adj::vec(gvo[bc.dadr], gvo[bc.dadr + 1], gvo[bc.dadr + 2]);
+        wpb = adj::vec(gvo[bc.dadr + 3], gvo[bc.dadr + 4], gvo[bc.dadr + 5]);
+      }
+      adj::Vec<float> xb, vsb, wsb, Fb, Tb, psi = adj::vec(0.f, 0.f, 0.f);
+      adj::update_vjp(U, xpb, qpb, vpb, wpb, xb, R.qb, vsb, wsb, Fb, Tb, psi);
+      const float tq[6] = {xb.x, xb.y, xb.z, 0.f, 0.f, 0.f}, tv[6] = {vsb.x, vsb.y, vsb.z, wsb.x, wsb.y, wsb.z};
+      for (int e = 0; e < 6; ++e) {
+        R.thb[x + e] = tq[e];
+        R.vsb[x + e] = tv[e];
+      }
+    } else {
+      const float tq = gqo ? gqo[bc.qadr] : 0.f;
+      const float tv = gvo ? gvo[d0 + x] : 0.f;
+      R.thb[x] = tq;
+      R.vsb[x] = tv + h * tq;
+    }
+  }
   for (int i = 0; i < nd; ++i) {
-    const float tq = gqo ? gqo[B[S.b0 + i].qadr] : 0.f;
-    const float tv = gvo ? gvo[d0 + i] : 0.f;
-    R.thb[i] = tq;
-    R.vsb[i] = tv + h * tq;
     R.y[i] = R.vsb[i];
     R.thdb[i] = 0.f;
   }
@@ -1894,20 +1932,57 @@ __device__ void art_rev_predict(const SubTree S, const BodyC *B, const float4 *b
     R.tb[i] = tbar;
   }
   // M, c and the J_b as functions of the joints: gradient of Phi by dual passes
+  const BodyC rb = B[S.b0];
+  const bool free_root = rb.jnt == kFree;
+  float R0[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, p0[3] = {0.f, 0.f, 0.f};
+  if (free_root) {
+    quat_to_rot<float>(q0[rb.qadr + 3], q0[rb.qadr + 4], q0[rb.qadr + 5], q0[rb.qadr + 6], R0);
+    for (int i = 0; i < 3; ++i) p0[i] = q0[rb.qadr + i];
+  }
   for (int k = 0; k < 2 * nd; ++k) {
-    for (int i = 0; i < nd; ++i) {
-      R.th[i] = artadj::du<float>(q0[B[S.b0 + i].qadr], k == i ? 1.f : 0.f);
-      R.thd[i] = artadj::du<float>(v0[d0 + i], k == nd + i ? 1.f : 0.f);
+    const int kd = k < nd ? k : -1;  // joint direction (a free root: translation, then rotation)
+    for (int i = 0; i < nd; ++i) R.thd[i] = artadj::du<float>(v0[d0 + i], k == nd + i ? 1.f : 0.f);
+    for (int b = S.b0; b < S.b0 + S.nb; ++b) {
+      const BodyC bc = B[b];
+      if (bc.jnt == kFree) continue;
+      const int x = bc.dadr - d0;
+      R.th[x] = artadj::du<float>(q0[bc.qadr], kd == x ? 1.f : 0.f);
     }
-    const float d = artadj::subtree_phi<artadj::Du<float>>(B, S.b0, S.nb, d0, nd, bmi, R.th, R.thd, P.gx, P.gy, P.gz,
-                                                          R.Mb, R.cb, R.Jb, R.wk).d;
+    for (int i = 0; i < 3; ++i) R.rp[i] = artadj::du<float>(p0[i], free_root && kd == i ? 1.f : 0.f);
+    // rotation increment about world axis e: d R = [e]x R
+    const int e = free_root && kd >= 3 && kd < 6 ? kd - 3 : -1;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        float d = 0.f;
+        if (e >= 0) {
+          const int i1 = (e + 1) % 3, i2 = (e + 2) % 3;  // ([e]x R)_ij = e x (column j of R)
+          d = i == i1 ? -R0[3 * i2 + j] : i == i2 ? R0[3 * i1 + j] : 0.f;
+        }
+        R.rr[3 * i + j] = artadj::du<float>(R0[3 * i + j], d);
+      }
+    const float d = artadj::subtree_phi<artadj::Du<float>>(B, S.b0, S.nb, d0, nd, bmi, R.th, R.thd, R.rp, R.rr, P.gx,
+                                                          P.gy, P.gz, R.Mb, R.cb, R.Jb, R.wk).d;
     if (k < nd) R.thb[k] += d;
     else R.thdb[k - nd] += d;
   }
-  for (int i = 0; i < nd; ++i) {
-    gq[B[S.b0 + i].qadr] = R.thb[i];
-    gv[d0 + i] = R.thdb[i];
-    gt[d0 + i] = R.tb[i];
+  for (int b = S.b0; b < S.b0 + S.nb; ++b) {
+    const BodyC bc = B[b];
+    const int x = bc.dadr - d0;
+    if (bc.jnt == kFree) {
+      float qb[4] = {R.qb[0], R.qb[1], R.qb[2], R.qb[3]};
+      const float qq[4] = {q0[bc.qadr + 3], q0[bc.qadr + 4], q0[bc.qadr + 5], q0[bc.qadr + 6]};
+      adj::quat_grad_from_psi(qq, adj::vec(R.thb[x + 3], R.thb[x + 4], R.thb[x + 5]), qb);
+      for (int i = 0; i < 3; ++i) gq[bc.qadr + i] = R.thb[x + i];
+      for (int i = 0; i < 4; ++i) gq[bc.qadr + 3 + i] = qb[i];
+      for (int i = 0; i < 6; ++i) {
+        gv[d0 + x + i] = R.thdb[x + i];
+        gt[d0 + x + i] = R.tb[x + i];
+      }
+    } else {
+      gq[bc.qadr] = R.thb[x];
+      gv[d0 + x] = R.thdb[x];
+      gt[d0 + x] = R.tb[x];
+    }
   }
 }
 
@@ -1960,12 +2035,26 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   const ResolveRegion RR = resolve_region(reg, nb, ng);
   const Params P = a.p;
   auto xyz = [](float4 f) { return vec(f.x, f.y, f.z); };
+  // Rotation and frame origin of body bi at the start of the step (a free body:
+  // its quaternion and COM; an articulated body: the forward kinematics in LDS).
+  auto body_frame = [&](int bi, float *R, Vec<float> &org) {
+    if (ART && !a.body[bi].fast) {
+      for (int r = 0; r < 3; ++r) {
+        const float4 row = RR.bR[3 * bi + r];
+        R[3 * r] = row.x; R[3 * r + 1] = row.y; R[3 * r + 2] = row.z;
+      }
+      org = xyz(RR.bO[bi]);
+    } else {
+      adj::rot_of_quat(sq0 + a.body[bi].qadr + 3, R);
+      org = xyz(RR.bC[bi]);
+    }
+  };
 
   // ---- reverse of integration and correction, per free body and per subtree
   if (ART)
   for (int si = tid; si < a.nsub; si += BS) {
     const SubTree S = a.sub[si];
-    art_rev_correct(S, a.body, RR.bC, RR.bO, RR.bAx, RR.accF, RR.accT, RR.art + S.lofs, artb + S.bofs,
+    art_rev_correct(S, a.body, RR.bC, RR.bO, RR.bAx, RR.accF, RR.accT, RR.art + S.lofs, artb + S.bofs, sq0, sv,
                     b.gq_out ? b.gq_out + (size_t)w * nq : nullptr, b.gv_out ? b.gv_out + (size_t)w * nv : nullptr,
                     bFb, bTb, bQb, acc, nb, P.h);
   }
@@ -2053,10 +2142,7 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
         const Vec<float> c = p + (rad + 0.5f * phi) * n;
         float Rb[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, Rg[9], RX[9];
         Vec<float> xo = Z;
-        if (ba >= 0) {
-          adj::rot_of_quat(sq0 + a.body[ba].qadr + 3, Rb);
-          xo = C.xa;
-        }
+        if (ba >= 0) body_frame(ba, Rb, xo);
         const float4 o4 = b.gpos[(size_t)w * b.gpos_ws + ga], g4 = b.gquat[(size_t)w * b.gquat_ws + ga];
         quat_to_rot<float>(g4.x, g4.y, g4.z, g4.w, Rg);
 #pragma unroll
@@ -2108,10 +2194,11 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
         Vec<float> pp = c - (phi + rad) * n;  // a point of the plane (static plane: n is fixed)
         if (ba >= 0) {
           float R[9];
-          adj::rot_of_quat(sq0 + a.body[ba].qadr + 3, R);
+          Vec<float> xo;
+          body_frame(ba, R, xo);
           const float4 o4 = b.gpos[(size_t)w * b.gpos_ws + ga];
-          pp = C.xa + vec(R[0] * o4.x + R[1] * o4.y + R[2] * o4.z, R[3] * o4.x + R[4] * o4.y + R[5] * o4.z,
-                          R[6] * o4.x + R[7] * o4.y + R[8] * o4.z);
+          pp = xo + vec(R[0] * o4.x + R[1] * o4.y + R[2] * o4.z, R[3] * o4.x + R[4] * o4.y + R[5] * o4.z,
+                        R[6] * o4.x + R[7] * o4.y + R[8] * o4.z);
         }
         Vec<float> cbar, ppb, nnb;
         adj::plane_point_vjp(pp, n, c, rad, phi, o.n, o.phi, o.p, cbar, ppb, nnb);

@@ -371,8 +371,8 @@ static void check_subtree_phi(int trial) {
   x.insert(x.end(), thd.begin(), thd.end());
   std::vector<D> wk(phi_work(nbs, nd));
   auto L = [&](const std::vector<D> &y) {
-    return subtree_phi<D>(B, 0, nbs, 0, nd, bmi, y.data(), y.data() + nd, g[0], g[1], g[2], Mb.data(), cb.data(),
-                          Jb.data(), wk.data());
+    return subtree_phi<D>(B, 0, nbs, 0, nd, bmi, y.data(), y.data() + nd, nullptr, nullptr, g[0], g[1], g[2],
+                          Mb.data(), cb.data(), Jb.data(), wk.data());
   };
   std::vector<Du<float>> a(nd), ad(nd), wd(phi_work(nbs, nd));
   std::vector<D> an(2 * nd);
@@ -381,12 +381,99 @@ static void check_subtree_phi(int trial) {
       a[i] = du<float>((float)th[i], k == i ? 1.f : 0.f);
       ad[i] = du<float>((float)thd[i], k == nd + i ? 1.f : 0.f);
     }
-    an[k] = subtree_phi<Du<float>>(B, 0, nbs, 0, nd, bmi, a.data(), ad.data(), g[0], g[1], g[2], Mb.data(), cb.data(),
-                                   Jb.data(), wd.data()).d;
+    an[k] = subtree_phi<Du<float>>(B, 0, nbs, 0, nd, bmi, a.data(), ad.data(), nullptr, nullptr, g[0], g[1], g[2],
+                                   Mb.data(), cb.data(), Jb.data(), wd.data()).d;
   }
   char name[64];
   snprintf(name, sizeof name, "subtree phi (dual) #%d", trial);
   report(name, an, fd_grad(x, L), 2e-4);
+}
+
+// The same with a free root (6 dofs: translation of its frame origin and a
+// world-frame rotation increment) carrying three hinge / slide children.
+static void check_subtree_phi_free(int trial) {
+  using cf::BodyC;
+  using namespace cf::artadj;
+  const int nbs = 4, nd = 9;
+  BodyC B[4] = {};
+  const int jt[4] = {cf::kFree, cf::kHinge, cf::kSlide, cf::kHinge};
+  const int par[4] = {-1, 0, 1, 0};  // a branch: bodies 1 and 3 both hang from the root
+  for (int k = 0; k < nbs; ++k) {
+    BodyC &c = B[k];
+    c.parent = par[k];
+    c.jnt = jt[k];
+    c.dadr = k == 0 ? 0 : 5 + k;
+    c.qadr = k == 0 ? 0 : 6 + k;
+    const V p = rv(0.1), ip = rv(0.05);
+    V ax = rv(1.0);
+    ax = (D(1) / sqrt(vdot(ax, ax))) * ax;
+    c.pos = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+    c.quat = make_float4((float)U(-1, 1), (float)U(-1, 1), (float)U(-1, 1), (float)U(-1, 1));
+    c.axis = make_float4((float)ax.x, (float)ax.y, (float)ax.z, 0.f);
+    c.ipos = k == 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4((float)ip.x, (float)ip.y, (float)ip.z, 0.f);
+  }
+  float4 bmi[4];
+  for (int k = 0; k < nbs; ++k) bmi[k] = make_float4((float)U(0.1, 1), (float)U(1e-3, 1e-2), (float)U(1e-3, 1e-2), (float)U(1e-3, 1e-2));
+  std::vector<float> Mb(nd * nd), cb(nd), Jb(6 * nd * nbs);
+  for (auto &x : Mb) x = (float)U(-1, 1);
+  for (auto &x : cb) x = (float)U(-1, 1);
+  for (auto &x : Jb) x = (float)U(-1, 1);
+  D q[4] = {U(-1, 1), U(-1, 1), U(-1, 1), U(-1, 1)}, R0[9];
+  rot_of_quat(q, R0);
+  const V p0 = rv(0.3);
+  std::vector<D> th(nd, 0.0), thd(nd);
+  for (int i = 6; i < nd; ++i) th[i] = (float)U(-1, 1);
+  for (int i = 0; i < nd; ++i) thd[i] = (float)U(-3, 3);
+  const float g[3] = {0.1f, -0.2f, -9.81f};
+  // x: translation (3), rotation increment (3), child joints (3), rates (9)
+  std::vector<D> x(6, 0.0);
+  for (int i = 6; i < nd; ++i) x.push_back(th[i]);
+  x.insert(x.end(), thd.begin(), thd.end());
+  std::vector<D> wk(phi_work(nbs, nd));
+  auto L = [&](const std::vector<D> &y) {
+    const V w = vec(y[3], y[4], y[5]);
+    const D a = sqrt(vdot(w, w));
+    D Rr[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, Rn[9];
+    if (a > 0) {
+      const D c = cos(a), s_ = sin(a), t = 1 - c, ux = w.x / a, uy = w.y / a, uz = w.z / a;
+      const D K[9] = {c + ux * ux * t, ux * uy * t - uz * s_, ux * uz * t + uy * s_,
+                      uy * ux * t + uz * s_, c + uy * uy * t, uy * uz * t - ux * s_,
+                      uz * ux * t - uy * s_, uz * uy * t + ux * s_, c + uz * uz * t};
+      for (int i = 0; i < 9; ++i) Rr[i] = K[i];
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Rn[3 * i + j] = Rr[3 * i] * R0[j] + Rr[3 * i + 1] * R0[3 + j] + Rr[3 * i + 2] * R0[6 + j];
+    const D rp[3] = {p0.x + y[0], p0.y + y[1], p0.z + y[2]};
+    std::vector<D> t(nd, 0.0);
+    for (int i = 6; i < nd; ++i) t[i] = y[i];
+    return subtree_phi<D>(B, 0, nbs, 0, nd, bmi, t.data(), y.data() + nd, rp, Rn, g[0], g[1], g[2], Mb.data(),
+                          cb.data(), Jb.data(), wk.data());
+  };
+  std::vector<Du<float>> a(nd), ad(nd), rp(3), rr(9), wd(phi_work(nbs, nd));
+  std::vector<D> an(2 * nd);
+  for (int k = 0; k < 2 * nd; ++k) {
+    for (int i = 0; i < nd; ++i) {
+      a[i] = du<float>((float)th[i], (i >= 6 && k == i) ? 1.f : 0.f);
+      ad[i] = du<float>((float)thd[i], k == nd + i ? 1.f : 0.f);
+    }
+    const D pp[3] = {p0.x, p0.y, p0.z};
+    for (int i = 0; i < 3; ++i) rp[i] = du<float>((float)pp[i], k == i ? 1.f : 0.f);
+    const int e = (k >= 3 && k < 6) ? k - 3 : -1;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        float d = 0.f;
+        if (e >= 0) {
+          const int i1 = (e + 1) % 3, i2 = (e + 2) % 3;
+          d = (float)(i == i1 ? -R0[3 * i2 + j] : i == i2 ? R0[3 * i1 + j] : 0.0);
+        }
+        rr[3 * i + j] = du<float>((float)R0[3 * i + j], d);
+      }
+    an[k] = subtree_phi<Du<float>>(B, 0, nbs, 0, nd, bmi, a.data(), ad.data(), rp.data(), rr.data(), g[0], g[1],
+                                   g[2], Mb.data(), cb.data(), Jb.data(), wd.data()).d;
+  }
+  char name[64];
+  snprintf(name, sizeof name, "subtree phi, free root (dual) #%d", trial);
+  report(name, an, fd_grad(x, L), 5e-4);
 }
 
 int main() {
@@ -407,6 +494,7 @@ int main() {
   for (int t = 0; t < 3; ++t) check_plane_point(t);
   for (int t = 0; t < 3; ++t) check_line_point(t);
   for (int t = 0; t < 3; ++t) check_subtree_phi(t);
+  for (int t = 0; t < 3; ++t) check_subtree_phi_free(t);
   printf("%s (%d failures)\n", failures ? "FAILED" : "ALL OK", failures);
   return failures ? 1 : 0;
 }

@@ -75,6 +75,9 @@ CASES = {
     "hand_c6": lambda: (scenes.hand_cube(nworld=3, seed=2, condim=6), 150, True),
     "hand_c3": lambda: (scenes.hand_cube(nworld=3, seed=3, condim=3), 150, True),
     "double_pendulum": lambda: (scenes.double_pendulum(), 40, True),
+    # hinge arm, slide-slide-hinge chain, floating base with two hinged fingers
+    "articulated_c3": lambda: (scenes.articulated_mix(nworld=3, seed=5, condim=3), 150, True),
+    "articulated_c6": lambda: (scenes.articulated_mix(nworld=3, seed=6, condim=6), 150, True),
     "slide_point": lambda: (scenes.point_mass(mu=0.6, z0=0.049), 20, True),
 }
 
@@ -107,6 +110,8 @@ def test_step_backward_matches_oracle_fd(torch_cuda, case):
         tau = hand_press_targets(s, rng)
     elif case in ("double_pendulum", "slide_point"):
         tau = joint_forces(s, rng)
+    elif case.startswith("articulated"):
+        tau = joint_forces(s, rng, scale=0.05)
     q, v = oracle_state(s, nsteps, None if tau is None else tau.astype(np.float64))
     nw, nq, nv = s["nworld"], q.shape[1], v.shape[1]
     gq_out = rng.normal(size=(nw, nq)).astype(np.float32)
