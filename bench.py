@@ -75,6 +75,8 @@ def main():
                     help="steps of the batched-rollout form timed after the plain form (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=200,
                     help="steps of the learned-impedance form timed after the plain form (0: skip)")
+    ap.add_argument("--learned-big-worlds", type=int, default=8192,
+                    help="worlds of 128 spheres for the learned gains' configured evaluation (0: skip)")
     ap.add_argument("--hand-rollouts", type=int, default=2048,
                     help="rollouts per MPPI iteration of the hand-and-cube form (0: skip)")
     ap.add_argument("--hand-horizon", type=int, default=20)
@@ -285,6 +287,70 @@ def main():
             "max_penetration_mm": {"plain": xp * 1e3, "learned": xl * 1e3},
             "mean_sq_speed_after_100_steps": {"plain": ke(vp), "learned": ke(vl)},
         }
+    if args.learned_steps > 0 and args.learned_big_worlds > 0:
+        # The learned gains' configured evaluation: worlds of 128 spheres (about
+        # twice the contacts per world), a network trained on 1e6 contacts of
+        # one plain step of this workload, then penetration, jitter and
+        # throughput of the learned and the plain form from the same settled state.
+        from paper_2603_12185_amd import learned
+        NB, L = args.learned_big_worlds, args.learned_steps
+        big = scenes.dense_pile(nworld=NB, nsphere=128, seed=args.seed + 1, condim=args.condim, ncon_max=2048)
+        bm = cfsim.Model(big)
+        bq = [torch.from_numpy(big["q0"]).to(dev), torch.empty((NB, bm.nq), device=dev)]
+        bv = [torch.from_numpy(big["v0"]).to(dev), torch.empty((NB, bm.nv), device=dev)]
+        bpp = [(bm._h, sp, ptr(bq[i]), ptr(bv[i]), None, ptr(bq[1 - i]), ptr(bv[1 - i])) for i in (0, 1)]
+
+        def big_steps(n):
+            for t in range(n):
+                st = lib.cf_step(*bpp[t & 1], None)
+                if st != 0:
+                    raise cfsim.CFError(st, cfsim.last_error())
+
+        big_steps(800)  # settle (even count: the state ends in buffer 0)
+        torch.cuda.synchronize()
+        sq0, sv0 = bq[0].clone(), bv[0].clone()
+        feats, targets, _, _ = learned.collect(bm, sq0.clone(), sv0.clone(), steps=1)
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed)
+        pick = torch.randperm(feats.shape[0], generator=g, device=dev)[:1000000]
+        net, losses = learned.train(feats[pick].contiguous(), targets[pick].contiguous(), bm.nfacet, steps=300)
+        nrows = int(feats.shape[0])
+        del feats, targets
+        mp, xp, _, vp = learned.penetration_stats(bm, sq0.clone(), sv0.clone(), 100)
+        timings = {}
+        for form in ("plain", "learned"):
+            bm.set_learned_impedance(net if form == "learned" else None, margin=1e-4)
+            bq[0].copy_(sq0)
+            bv[0].copy_(sv0)
+            big_steps(20)
+            bq[0].copy_(sq0)
+            bv[0].copy_(sv0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            big_steps(L)
+            torch.cuda.synchronize()
+            timings[form] = time.perf_counter() - t0
+        ml, xl, _, vl = learned.penetration_stats(bm, sq0.clone(), sv0.clone(), 100)
+        bm.set_learned_impedance(None)
+        ncon_big = {"ncon": torch.zeros(NB, dtype=torch.int32, device=dev)}
+        bm.step(sq0, sv0, contacts=ncon_big)
+        ke = lambda vv: float((vv.reshape(NB, -1, 6)[:, :, 0:3] ** 2).sum(-1).mean())
+        progress(f"learned form 8192x128: {L} steps plain {timings['plain']:.2f} s, learned {timings['learned']:.2f} s")
+        result["learned_form_128_spheres"] = {
+            "workload": f"dense_pile_{NB}x128", "steps": L,
+            "mean_contacts_per_world": float(ncon_big["ncon"].double().mean()),
+            "value": NB * L / timings["learned"], "unit": "env-steps/s",
+            "plain_value": NB * L / timings["plain"],
+            "vs_plain_form": timings["plain"] / timings["learned"],
+            "training": f"{min(nrows, 1000000)} of {nrows} contacts of one plain step, 300 Adam steps of 65536, "
+                        f"loss {losses[0]:.3g} -> {losses[-1]:.3g}",
+            "fallback_margin_m": 1e-4,
+            "mean_penetration_mm": {"plain": mp * 1e3, "learned": ml * 1e3},
+            "max_penetration_mm": {"plain": xp * 1e3, "learned": xl * 1e3},
+            "mean_sq_speed_after_100_steps": {"plain": ke(vp), "learned": ke(vl)},
+        }
+        del bm, bq, bv, big
+        torch.cuda.empty_cache()
     if args.hand_rollouts > 0:
         # Batched-MPC form: the actuated four-finger hand with a free cube (6D
         # contacts), N rollouts of H steps per MPPI iteration with Gaussian
