@@ -168,8 +168,10 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
  * uses the model's contact workspace (so it must not overlap a cf_step of the
  * same model on another stream).  Articulated subtrees (hinge and slide joints
  * below a fixed or a free root) and position actuators are covered (an
- * actuated dof's gtau entry is the adjoint of its target); the diagonal and the
- * learned impedance return CF_E_UNSUPPORTED. */
+ * actuated dof's gtau entry is the adjoint of its target), and so is the
+ * diagonal impedance (its per-facet gains differentiated through the lever
+ * arms, the contact frame and the bodies' world inverse inertia, i.e. their
+ * orientation); the learned impedance returns CF_E_UNSUPPORTED. */
 cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                            const float *gq_out, const float *gv_out, float *gq, float *gv, float *gtau);
 
@@ -192,8 +194,8 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
  * facet f, split between K and D in the ratio k_user : d_user / h, so
  * lambda_f h = max(-(k_user h + d_user) s_f - k_user phi, 0) / ((k_user h + d_user) g_f)
  * with g_f = J~_f M^-1 J~_f^T (0 when k_user h + d_user = 0).  The diagonal form
- * is available for models of free bodies only (else CF_E_UNSUPPORTED), and
- * cf_step_backward does not cover it. */
+ * is available for models of free bodies only (else CF_E_UNSUPPORTED);
+ * cf_step_backward covers it. */
 cf_status cf_model_set_impedance(cf_model *m, int32_t mode);
 
 /* Position actuators on hinge and slide dofs (the actuated hand of the

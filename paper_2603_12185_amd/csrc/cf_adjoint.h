@@ -273,6 +273,10 @@ struct ContactIn {
   bool has_a, has_b;
   T trs, mut, mutor, murol;
   T h, k, d;  // time step, k_user, d_user
+  // exact diagonal impedance: per side 1/m and the world inverse inertia
+  // (xx, yy, zz, xy, xz, yz); unused with the heuristic
+  bool diag;
+  T ima, imb, Sa[6], Sb[6];
 };
 
 template <class T>
@@ -281,6 +285,7 @@ struct ContactBar {  // adjoints
   T phi;
   Vec<T> xa, va, wa, xb, vb, wb;
   T trs;  // of tr_a + tr_b (constant for free bodies, a function of the joints otherwise)
+  Vec<T> psa, psb;  // of rotation increments of the sides through their inverse inertia (diagonal impedance)
 };
 
 template <class T>
@@ -288,6 +293,100 @@ CF_HD void tangent_basis(Vec<T> n, Vec<T> &u, T &ilen, bool &hx) {
   hx = fabs(n.x) <= T(0.5);
   u = hx ? vec(T(1) - n.x * n.x, -n.x * n.y, -n.x * n.z) : vec(-n.y * n.x, T(1) - n.y * n.y, -n.y * n.z);
   ilen = T(1) / sqrt(dot(u, u));
+}
+
+// Exact diagonal impedance of one contact (the form Sec. III.B gives before its
+// heuristic): g_f = sum over the contact's bodies of im |u_f|^2 + a_f^T S a_f and
+// A_f = 1 / (aa g_f), the facet row acting on a body at lever arm r as linear
+// direction u_f and angular direction a_f: tangential d: u = n - mu_t d, a = r x u;
+// torsional sigma: u = n, a = r x n - mu_tor sigma n; rolling d: u = n,
+// a = r x n - mu_rol d (|u|^2 = 1 + mu_t^2 for the tangential facets).
+template <int NF, class T>
+CF_HD void diag_dirs(Vec<T> r, Vec<T> n, Vec<T> t1, Vec<T> t2, T mut, T mutor, T murol, Vec<T> *a, T *lin) {
+  const Vec<T> rn = cross(r, n);
+  if constexpr (NF == 1) {
+    a[0] = rn; lin[0] = T(1);
+  } else {
+    const Vec<T> r1 = cross(r, t1), r2 = cross(r, t2);
+    a[0] = rn - mut * r1; a[1] = rn - mut * r2; a[2] = rn + mut * r1; a[3] = rn + mut * r2;
+    for (int i = 0; i < 4; ++i) lin[i] = T(1) + mut * mut;
+    if constexpr (NF >= 6) {
+      a[4] = rn - mutor * n; a[5] = rn + mutor * n;
+      lin[4] = lin[5] = T(1);
+    }
+    if constexpr (NF == 10) {
+      a[6] = rn - murol * t1; a[7] = rn - murol * t2; a[8] = rn + murol * t1; a[9] = rn + murol * t2;
+      for (int i = 6; i < 10; ++i) lin[i] = T(1);
+    }
+  }
+}
+
+template <int NF, class T>
+CF_HD void diag_gains(const ContactIn<T> &C, T *A) {
+  T g[NF];
+  for (int i = 0; i < NF; ++i) g[i] = T(0);
+  for (int side = 0; side < 2; ++side) {
+    if (!(side ? C.has_b : C.has_a)) continue;
+    const Vec<T> r = C.p - (side ? C.xb : C.xa);
+    const T im = side ? C.imb : C.ima;
+    const T *S = side ? C.Sb : C.Sa;
+    Vec<T> t1, t2;
+    {
+      Vec<T> u;
+      T il;
+      bool hx;
+      tangent_basis(C.n, u, il, hx);
+      t1 = il * u;
+      t2 = cross(C.n, t1);
+    }
+    Vec<T> a[NF];
+    T lin[NF];
+    diag_dirs<NF>(r, C.n, t1, t2, C.mut, C.mutor, C.murol, a, lin);
+    for (int i = 0; i < NF; ++i) g[i] += im * lin[i] + dot(a[i], sym_mul(S, a[i]));
+  }
+  const T aa = C.k * C.h + C.d;
+  for (int i = 0; i < NF; ++i) A[i] = (g[i] > T(0) && aa > T(0)) ? T(1) / (aa * g[i]) : T(0);
+}
+
+// Reverse of diag_gains for one side: given gb[f] (the adjoints of g_f), adds
+// the adjoints of the lever arm r, of n, t1, t2 and of the side's rotation
+// increment (through S).
+template <int NF, class T>
+CF_HD void diag_side_vjp(Vec<T> r, Vec<T> n, Vec<T> t1, Vec<T> t2, T mut, T mutor, T murol, const T *S,
+                         const T *gb, Vec<T> &rb, Vec<T> &nb, Vec<T> &t1b, Vec<T> &t2b, Vec<T> &psib) {
+  Vec<T> a[NF];
+  T lin[NF];
+  diag_dirs<NF>(r, n, t1, t2, mut, mutor, murol, a, lin);
+  Vec<T> ab[NF];
+  for (int i = 0; i < NF; ++i) {
+    const Vec<T> Sa = sym_mul(S, a[i]);
+    ab[i] = (T(2) * gb[i]) * Sa;
+    psib = psib + (T(2) * gb[i]) * cross(Sa, a[i]);  // d(a^T S a) = 2 dpsi . (S a x a)
+  }
+  // a = r x u (+ a term free of r): r_bar += u x a_bar, u_bar += a_bar x r
+  auto lever = [&](Vec<T> u, Vec<T> abar) {
+    rb = rb + cross(u, abar);
+    return cross(abar, r);
+  };
+  if constexpr (NF == 1) {
+    nb = nb + lever(n, ab[0]);
+  } else {
+    Vec<T> ub;
+    ub = lever(n - mut * t1, ab[0]); nb = nb + ub; t1b = t1b - mut * ub;
+    ub = lever(n - mut * t2, ab[1]); nb = nb + ub; t2b = t2b - mut * ub;
+    ub = lever(n + mut * t1, ab[2]); nb = nb + ub; t1b = t1b + mut * ub;
+    ub = lever(n + mut * t2, ab[3]); nb = nb + ub; t2b = t2b + mut * ub;
+    if constexpr (NF >= 6) {
+      nb = nb + lever(n, ab[4]) - mutor * ab[4];
+      nb = nb + lever(n, ab[5]) + mutor * ab[5];
+    }
+    if constexpr (NF == 10) {
+      nb = nb + lever(n, ab[6]); t1b = t1b - murol * ab[6];
+      nb = nb + lever(n, ab[7]); t2b = t2b - murol * ab[7];
+      nb = nb + lever(n, ab[8]); t1b = t1b + murol * ab[8];
+      nb = nb + lever(n, ab[9]); t2b = t2b + murol * ab[9];
+    }
+  }
 }
 
 // Facet impulses and the wrench on body b (f, tb) and on body a (-f, ta).
@@ -304,34 +403,37 @@ CF_HD void contact_forward(const ContactIn<T> &C, const Impedance<T> &P, T *lam,
   if (C.has_b) { vrel = C.vb + cross(C.wb, rb); wrel = C.wb; }
   if (C.has_a) { vrel = vrel - (C.va + cross(C.wa, ra)); wrel = wrel - C.wa; }
   T drho;
-  const T A = C.trs > T(0) ? impedance_rho(C.phi, P, drho) / C.trs : T(0);
+  const T A0 = C.trs > T(0) ? impedance_rho(C.phi, P, drho) / C.trs : T(0);
+  T Af[NF];
+  if (C.diag) diag_gains<NF>(C, Af);
+  else for (int i = 0; i < NF; ++i) Af[i] = A0;
   const T aa = C.k * C.h + C.d, c0 = -C.k * C.phi;
   const T vn = dot(C.n, vrel);
   Vec<T> tc = vec(T(0), T(0), T(0));
   if constexpr (NF == 1) {
-    lam[0] = A * fmax(-aa * vn + c0, T(0));
+    lam[0] = Af[0] * fmax(-aa * vn + c0, T(0));
     f = lam[0] * C.n;
   } else {
     const T u1 = dot(t1, vrel), u2 = dot(t2, vrel);
-    lam[0] = A * fmax(-aa * (vn - C.mut * u1) + c0, T(0));
-    lam[1] = A * fmax(-aa * (vn - C.mut * u2) + c0, T(0));
-    lam[2] = A * fmax(-aa * (vn + C.mut * u1) + c0, T(0));
-    lam[3] = A * fmax(-aa * (vn + C.mut * u2) + c0, T(0));
+    lam[0] = Af[0] * fmax(-aa * (vn - C.mut * u1) + c0, T(0));
+    lam[1] = Af[1] * fmax(-aa * (vn - C.mut * u2) + c0, T(0));
+    lam[2] = Af[2] * fmax(-aa * (vn + C.mut * u1) + c0, T(0));
+    lam[3] = Af[3] * fmax(-aa * (vn + C.mut * u2) + c0, T(0));
     T N = lam[0] + lam[1] + lam[2] + lam[3];
     const T e1 = -C.mut * (lam[0] - lam[2]), e2 = -C.mut * (lam[1] - lam[3]);
     if constexpr (NF >= 6) {
       const T wt = dot(C.n, wrel);
-      lam[4] = A * fmax(-aa * (vn - C.mutor * wt) + c0, T(0));
-      lam[5] = A * fmax(-aa * (vn + C.mutor * wt) + c0, T(0));
+      lam[4] = Af[4] * fmax(-aa * (vn - C.mutor * wt) + c0, T(0));
+      lam[5] = Af[5] * fmax(-aa * (vn + C.mutor * wt) + c0, T(0));
       N += lam[4] + lam[5];
       tc = (-C.mutor * (lam[4] - lam[5])) * C.n;
     }
     if constexpr (NF == 10) {
       const T o1 = dot(t1, wrel), o2 = dot(t2, wrel);
-      lam[6] = A * fmax(-aa * (vn - C.murol * o1) + c0, T(0));
-      lam[7] = A * fmax(-aa * (vn - C.murol * o2) + c0, T(0));
-      lam[8] = A * fmax(-aa * (vn + C.murol * o1) + c0, T(0));
-      lam[9] = A * fmax(-aa * (vn + C.murol * o2) + c0, T(0));
+      lam[6] = Af[6] * fmax(-aa * (vn - C.murol * o1) + c0, T(0));
+      lam[7] = Af[7] * fmax(-aa * (vn - C.murol * o2) + c0, T(0));
+      lam[8] = Af[8] * fmax(-aa * (vn + C.murol * o1) + c0, T(0));
+      lam[9] = Af[9] * fmax(-aa * (vn + C.murol * o2) + c0, T(0));
       N += lam[6] + lam[7] + lam[8] + lam[9];
       tc = tc + (-C.murol * (lam[6] - lam[8])) * t1 + (-C.murol * (lam[7] - lam[9])) * t2;
     }
@@ -357,9 +459,14 @@ CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b
   Vec<T> vrel = Z, wrel = Z;
   if (C.has_b) { vrel = C.vb + cross(C.wb, rb); wrel = C.wb; }
   if (C.has_a) { vrel = vrel - (C.va + cross(C.wa, ra)); wrel = wrel - C.wa; }
-  T drho;
-  const T rho = impedance_rho(C.phi, P, drho);
-  const T A = C.trs > T(0) ? rho / C.trs : T(0);
+  T drho = T(0);
+  T Af[NF];
+  if (C.diag) {
+    diag_gains<NF>(C, Af);
+  } else {
+    const T rho = impedance_rho(C.phi, P, drho);
+    for (int i = 0; i < NF; ++i) Af[i] = C.trs > T(0) ? rho / C.trs : T(0);
+  }
   const T aa = C.k * C.h + C.d, c0 = -C.k * C.phi;
   const T vn = dot(n, vrel);
   T s[NF], z[NF], lam[NF];
@@ -381,7 +488,7 @@ CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b
   T N = T(0);
   for (int i = 0; i < NF; ++i) {
     z[i] = -aa * s[i] + c0;
-    lam[i] = A * fmax(z[i], T(0));
+    lam[i] = Af[i] * fmax(z[i], T(0));
     N += lam[i];
   }
   Vec<T> f;
@@ -425,17 +532,30 @@ CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b
       lb[7] -= C.murol * g2; lb[9] += C.murol * g2;
     }
   }
-  // lam_f = A max(z_f, 0), z_f = -aa s_f + c0
+  // lam_f = A_f max(z_f, 0), z_f = -aa s_f + c0
   T Ab = T(0), c0b = T(0);
-  T sb[NF];
+  T sb[NF], Afb[NF];
   for (int i = 0; i < NF; ++i) {
-    const T zb = z[i] > T(0) ? A * lb[i] : T(0);
-    if (z[i] > T(0)) Ab += lb[i] * z[i];
+    const T zb = z[i] > T(0) ? Af[i] * lb[i] : T(0);
+    Afb[i] = z[i] > T(0) ? lb[i] * z[i] : T(0);
+    Ab += Afb[i];
     sb[i] = -aa * zb;
     c0b += zb;
   }
-  T phib = -C.k * c0b + (C.trs > T(0) ? Ab * drho / C.trs : T(0));
-  o.trs = C.trs > T(0) ? -Ab * A / C.trs : T(0);  // A = rho / trs
+  T phib = -C.k * c0b;
+  o.trs = T(0);
+  o.psa = o.psb = Z;
+  Vec<T> rab_d = Z, rbb_d = Z;
+  if (C.diag) {
+    // A_f = 1 / (aa g_f): g_bar = -A_bar A_f / g_f = -A_bar aa A_f^2
+    T gb[NF];
+    for (int i = 0; i < NF; ++i) gb[i] = -Afb[i] * aa * Af[i] * Af[i];
+    if (C.has_a) diag_side_vjp<NF>(ra, n, t1, t2, C.mut, C.mutor, C.murol, C.Sa, gb, rab_d, nb, t1b, t2b, o.psa);
+    if (C.has_b) diag_side_vjp<NF>(rb, n, t1, t2, C.mut, C.mutor, C.murol, C.Sb, gb, rbb_d, nb, t1b, t2b, o.psb);
+  } else if (C.trs > T(0)) {  // A = rho(phi) / trs
+    phib += Ab * drho / C.trs;
+    o.trs = -Ab * Af[0] / C.trs;
+  }
   // s_f in terms of vn, u1, u2, wt, o1, o2
   T vnb = T(0);
   for (int i = 0; i < NF; ++i) vnb += sb[i];
@@ -470,6 +590,8 @@ CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b
     o.wa = -(cross(ra, vrelb) + wrelb);
     rab = rab - cross(vrelb, C.wa);
   }
+  rab = rab + rab_d;
+  rbb = rbb + rbb_d;
   // ra = p - xa, rb = p - xb
   o.p = rab + rbb;
   o.xa = -rab;

@@ -525,8 +525,7 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
       overlap(gtau, sv, q, sq) || overlap(gtau, sv, v, sv) || overlap(gtau, sv, tau, sv) ||
       overlap(gtau, sv, gq_out, sq) || overlap(gtau, sv, gv_out, sv))
     return set_err(CF_E_INVALID_ARG, "gq/gv may alias gq_out/gv_out only exactly; no other overlap");
-  if (m->p.imp_diag || m->mlp)
-    return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers the heuristic impedance only");
+  if (m->mlp) return set_err(CF_E_UNSUPPORTED, "cf_step_backward does not cover the learned impedance");
   if (!m->block_backward) return set_err(CF_E_UNSUPPORTED, "world too large for the adjoint's LDS");
   hipStream_t s = (hipStream_t)stream;
   cf::CollideArgs ca = collide_args(m);

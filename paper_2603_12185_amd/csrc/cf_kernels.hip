@@ -2117,6 +2117,16 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
       const float4 ma = RR.gM[ga], mb = RR.gM[gb];
       C.mut = fmaxf(ma.x, mb.x); C.mutor = fmaxf(ma.y, mb.y); C.murol = fmaxf(ma.z, mb.z);
       C.h = P.h; C.k = P.k_user; C.d = P.d_user;
+      C.diag = P.imp_diag != 0;
+      C.ima = C.imb = 0.f;
+      if (C.diag) {  // free bodies only: 1/m and the world inverse inertia at the step's start
+        auto inertia = [&](int bi, float *S) {
+          const float4 I0 = RR.bI0[bi], I1 = RR.bI1[bi];
+          S[0] = I0.x; S[1] = I0.y; S[2] = I0.z; S[3] = I0.w; S[4] = I1.x; S[5] = I1.y;
+        };
+        if (ba >= 0) { C.ima = RR.bC[ba].w; inertia(ba, C.Sa); }
+        if (bbd >= 0) { C.imb = RR.bC[bbd].w; inertia(bbd, C.Sb); }
+      }
       const Vec<float> Fab = ba >= 0 ? xyz(bFb[ba]) : Z, Tab = ba >= 0 ? xyz(bTb[ba]) : Z;
       const Vec<float> Fbb = bbd >= 0 ? xyz(bFb[bbd]) : Z, Tbb = bbd >= 0 ? xyz(bTb[bbd]) : Z;
       adj::ContactBar<float> o;
@@ -2205,6 +2215,8 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
         xbb = xbb + cbar; psb = adj::cross(c - C.xb, cbar);
         if (ba >= 0) { xab = xab + ppb; psa = adj::cross(pp - C.xa, ppb) + adj::cross(n, nnb); }
       }
+      psa = psa + o.psa;
+      psb = psb + o.psb;
       if (ba >= 0) {
         kA = ba;
         pA[0] = make_float4(xab.x, xab.y, xab.z, psa.x);

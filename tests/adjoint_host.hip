@@ -134,8 +134,18 @@ static unsigned pattern(const ContactIn<D> &C) {
   return m;
 }
 
+// World inverse inertia R(q) diag(d) R(q)^T of a body with quaternion q.
+static void inv_inertia(const D *q, const D *d, D *S) {
+  D R[9];
+  rot_of_quat(q, R);
+  rot_diag_rot(R, d, S);
+}
+
 template <int NF>
 static void make_contact(ContactIn<D> &C, bool has_a, bool has_b, D phi_scale) {
+  C.diag = false;
+  C.ima = C.imb = 0;
+  for (int i = 0; i < 6; ++i) C.Sa[i] = C.Sb[i] = 0;
   for (;;) {
     C.n = rv(1.0);
     const D l = std::sqrt(dot(C.n, C.n));
@@ -165,20 +175,39 @@ static void make_contact(ContactIn<D> &C, bool has_a, bool has_b, D phi_scale) {
   }
 }
 
+// diag: the exact diagonal impedance, the sides' inverse inertias rotated by
+// quaternions that are inputs of the check too (their adjoints reach them
+// through the rotation increments psa, psb).
 template <int NF>
-static void check_contact(int trial, bool has_a, bool has_b, D phi_scale) {
+static void check_contact(int trial, bool has_a, bool has_b, D phi_scale, bool diag = false) {
   ContactIn<D> C;
   make_contact<NF>(C, has_a, has_b, phi_scale);
+  D qa[4], qb[4], da[3], db[3];
+  for (int i = 0; i < 4; ++i) { qa[i] = U(-1, 1); qb[i] = U(-1, 1); }
+  for (int i = 0; i < 3; ++i) { da[i] = 1.0 / U(1e-4, 1e-3); db[i] = 1.0 / U(1e-4, 1e-3); }
+  if (diag) {
+    C.diag = true;
+    C.ima = 1.0 / U(0.1, 1.0);
+    C.imb = 1.0 / U(0.1, 1.0);
+    inv_inertia(qa, da, C.Sa);
+    inv_inertia(qb, db, C.Sb);
+  }
   const V Fab = rv(1.0), Tab = rv(1.0), Fbb = rv(1.0), Tbb = rv(1.0);
   std::vector<D> x;
   put(x, C.n); x.push_back(C.phi); put(x, C.p);
   put(x, C.xa); put(x, C.va); put(x, C.wa); put(x, C.xb); put(x, C.vb); put(x, C.wb);
   x.push_back(C.trs);
+  for (int i = 0; i < 4; ++i) x.push_back(qa[i]);
+  for (int i = 0; i < 4; ++i) x.push_back(qb[i]);
   auto L = [&](const std::vector<D> &y) {
     ContactIn<D> K = C;
     K.n = get(y, 0); K.phi = y[3]; K.p = get(y, 4);
     K.xa = get(y, 7); K.va = get(y, 10); K.wa = get(y, 13); K.xb = get(y, 16); K.vb = get(y, 19); K.wb = get(y, 22);
     K.trs = y[25];
+    if (diag) {
+      inv_inertia(&y[26], da, K.Sa);
+      inv_inertia(&y[30], db, K.Sb);
+    }
     D lam[NF];
     V f, ta, tb;
     contact_forward<NF>(K, imp(), lam, f, ta, tb);
@@ -193,8 +222,14 @@ static void check_contact(int trial, bool has_a, bool has_b, D phi_scale) {
   put(an, o.n); an.push_back(o.phi); put(an, o.p);
   put(an, o.xa); put(an, o.va); put(an, o.wa); put(an, o.xb); put(an, o.vb); put(an, o.wb);
   an.push_back(o.trs);
-  char name[64];
-  snprintf(name, sizeof name, "contact nf=%d a=%d b=%d phi~%g #%d", NF, has_a, has_b, phi_scale, trial);
+  D gqa[4] = {0, 0, 0, 0}, gqb[4] = {0, 0, 0, 0};
+  quat_grad_from_psi(qa, o.psa, gqa);
+  quat_grad_from_psi(qb, o.psb, gqb);
+  for (int i = 0; i < 4; ++i) an.push_back(gqa[i]);
+  for (int i = 0; i < 4; ++i) an.push_back(gqb[i]);
+  char name[80];
+  snprintf(name, sizeof name, "contact nf=%d a=%d b=%d phi~%g%s #%d", NF, has_a, has_b, phi_scale,
+           diag ? " diag" : "", trial);
   report(name, an, fd_grad(x, L, 1e-7), 2e-6);
 }
 
@@ -489,6 +524,12 @@ int main() {
     check_contact<4>(t, false, true, 0.01);
     check_contact<10>(t, false, true, 0.0005);  // x below the clamp: rho varies with phi
     check_contact<4>(t, true, false, 0.0005);
+    check_contact<1>(t, true, true, 0.01, true);
+    check_contact<4>(t, true, true, 0.01, true);
+    check_contact<6>(t, true, true, 0.01, true);
+    check_contact<10>(t, true, true, 0.01, true);
+    check_contact<4>(t, false, true, 0.01, true);
+    check_contact<6>(t, true, false, 0.0005, true);
   }
   for (int t = 0; t < 3; ++t) check_sphere_pair(t);
   for (int t = 0; t < 3; ++t) check_plane_point(t);

@@ -79,6 +79,16 @@ CASES = {
     "articulated_c3": lambda: (scenes.articulated_mix(nworld=3, seed=5, condim=3), 150, True),
     "articulated_c6": lambda: (scenes.articulated_mix(nworld=3, seed=6, condim=6), 150, True),
     "slide_point": lambda: (scenes.point_mass(mu=0.6, z0=0.049), 20, True),
+    # exact diagonal impedance (per-facet gains through lever arms, frame and
+    # the bodies' world inverse inertia); the form overshoots where several
+    # facets push together, so the states are taken early
+    "boxes_drop_diag": lambda: (dict(scenes.boxes_drop(seed=1), impedance=1), 120, False),
+    "mixed_c1_diag": lambda: (dict(scenes.mixed_shapes(nworld=3, seed=31, condim=1), impedance=1), 20, True),
+    "mixed_c3_diag": lambda: (dict(scenes.mixed_shapes(nworld=3, seed=31, condim=3), impedance=1), 0, True),
+    "mixed_c4_diag": lambda: (dict(scenes.mixed_shapes(nworld=3, seed=34, condim=4), impedance=1), 0, True),
+    "mixed_c6_diag": lambda: (dict(scenes.mixed_shapes(nworld=3, seed=34, condim=6), impedance=1), 0, True),
+    "cluster_c4_diag": lambda: (dict(scenes.sphere_cluster(nsphere=10, seed=3, condim=4, spread=0.05),
+                                     impedance=1), 2, True),
 }
 
 
