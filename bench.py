@@ -59,6 +59,91 @@ def progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
+def pile_run(nw, nsphere, condim, k_user, d_user, steps, last, seed=0):
+    """One plain-form run of the dense pile from its initial lattice: `steps`
+    cf_step calls, timed as a whole and over the last `last` steps (HIP events
+    on the launch stream at step 0, steps - last and steps), with the contact
+    count of every world-step kept on the device.  Returns a dict of rates and
+    contact statistics (mean and max contacts per world-step over the whole run
+    and over the last steps) and both kernels' durations on the final state."""
+    import torch
+
+    from paper_2603_12185_amd import cfsim, scenes
+    dev = torch.device("cuda:0")
+    scene = scenes.dense_pile(nworld=nw, nsphere=nsphere, seed=seed, condim=condim,
+                              k_user=k_user, d_user=d_user)
+    model = cfsim.Model(scene)
+    lib = cfsim.load()
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+    nq, nv = model.nq, model.nv
+    q = [torch.from_numpy(scene["q0"]).to(dev), torch.empty((nw, nq), device=dev)]
+    v = [torch.from_numpy(scene["v0"]).to(dev), torch.empty((nw, nv), device=dev)]
+    ncon = torch.zeros((steps, nw), dtype=torch.int32, device=dev)
+    over = torch.zeros((steps, nw), dtype=torch.int32, device=dev)
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    cons = [cfsim.Contacts(ptr(ncon[t]), ptr(over[t]), None, None, None, None, None, None)
+            for t in range(steps)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for t in range(steps):
+        if t == steps - last:
+            ev[1].record(stream)
+        i = t & 1
+        st = lib.cf_step(model._h, sp, ptr(q[i]), ptr(v[i]), None, ptr(q[1 - i]), ptr(v[1 - i]),
+                         C.byref(cons[t]))
+        if st != 0:
+            raise cfsim.CFError(st, cfsim.last_error())
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    f = steps & 1
+    us_col, us_res = model.time_kernels(q[f], v[f], q[1 - f], v[1 - f], reps=200)
+    ms_all, ms_last = ev[0].elapsed_time(ev[2]), ev[1].elapsed_time(ev[2])
+    c = ncon.double()
+    cl = c[steps - last:]
+    bad = int(over.sum())
+    finite = bool(torch.isfinite(q[f]).all() and torch.isfinite(v[f]).all())
+    return {
+        "bodies_per_world": model.nbody, "condim": condim, "k_user": k_user, "d_user": d_user,
+        "steps": steps, "wall_s": wall,
+        "whole_run": {"env_steps_per_s": nw * steps / (ms_all * 1e-3), "ms_per_step": ms_all / steps,
+                      "mean_contacts_per_world": float(c.mean()), "max_contacts_per_world": int(c.max()),
+                      "contact_impulses_per_s": float(c.sum()) / (ms_all * 1e-3)},
+        f"last_{last}_steps": {"env_steps_per_s": nw * last / (ms_last * 1e-3), "ms_per_step": ms_last / last,
+                               "mean_contacts_per_world": float(cl.mean()),
+                               "max_contacts_per_world": int(cl.max()),
+                               "contact_impulses_per_s": float(cl.sum()) / (ms_last * 1e-3)},
+        "kernel_us_final_state": {"collide_kernel": us_col, "resolve_kernel": us_res},
+        "capacity_overflows": bad, "state_finite": finite,
+    }
+
+
+def sweep(args):
+    """The pile's variants: bodies per world 16/32/64/128 (condim 3), condim 6
+    and the stiffer (k, d) = (0.5, 0.005) at 64 bodies; each run from the
+    initial lattice for `steps` steps, the whole run and the settled last 100
+    steps reported separately.  Prints one JSON line."""
+    nw, steps, last = args.nworld, args.sweep_steps, min(100, args.sweep_steps)
+    runs = {}
+    for nb in (16, 32, 64, 128):
+        runs[f"bodies_{nb}"] = pile_run(nw, nb, 3, 0.1, 0.001, steps, last)
+        progress(f"sweep bodies {nb}: {runs[f'bodies_{nb}'][f'last_{last}_steps']['env_steps_per_s']:.3e} env-steps/s")
+    runs["condim_6"] = pile_run(nw, 64, 6, 0.1, 0.001, steps, last)
+    progress("sweep condim 6 done")
+    runs["k0.5_d0.005"] = pile_run(nw, 64, 3, 0.5, 0.005, steps, last)
+    progress("sweep stiff gains done")
+    # linearity in bodies per world: body-steps/s of the settled steps
+    lin = {k: r["bodies_per_world"] * r[f"last_{last}_steps"]["env_steps_per_s"]
+           for k, r in runs.items() if k.startswith("bodies_")}
+    print(json.dumps({
+        "metric": METRIC + " (pile variants)", "unit": "env-steps/s", "n_gpus": 1, "nworld": nw,
+        "dtype": "f32", "data": "synthetic", "timing": "HIP events on the launch stream",
+        "runs": runs, "body_steps_per_s_settled": lin}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +169,10 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB five times (a "
                          "known-traffic kernel that calibrates HBM byte counters under a profiler)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the pile's variants (bodies per world 16/32/64/128, condim 6, "
+                         "(k, d) = (0.5, 0.005)) instead of the default measurement")
+    ap.add_argument("--sweep-steps", type=int, default=500)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -100,6 +189,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sweep:
+        sweep(args)
+        return
     scene = scenes.dense_pile(nworld=args.nworld, nsphere=args.nsphere, seed=args.seed,
                               condim=args.condim)
     model = cfsim.Model(scene)

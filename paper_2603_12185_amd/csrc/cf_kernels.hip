@@ -811,9 +811,36 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     const int g0 = a.sph0, S = a.nsph, nwd = (S + 63) >> 6;
     unsigned long long *rm = reinterpret_cast<unsigned long long *>(
         a.nsub > 0 ? reinterpret_cast<char *>(brot + 12 * a.nb) : reinterpret_cast<char *>(borg));
+    const int half = S >> 1;
+    if (S <= 64) {
+      // one row word per sphere, all rows in one pass (S <= 64 <= BS): the
+      // lane's hits with every partner j are collected branch-free as bits of
+      // one register; the bits above i are its own row, stored whole, and each
+      // bit j below i (a pair reached by wrapping round) is ORed into row j
+      unsigned long long hits = 0ull;
+      const int i = tid;
+      if (i < S) {
+        const float4 Gi = Gs[g0 + i];
+        const int bi = gbd[g0 + i];
+        const int dmax = (S & 1) ? half : (i < half ? half : half - 1);
+        int j = i;
+        for (int d = 1; d <= dmax; ++d) {
+          j = j + 1 == S ? 0 : j + 1;
+          const float4 Gj = Gs[g0 + j];
+          const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
+          const float R = Gi.w + Gj.w + a.margin;  // the same rounding from either end of the pair
+          const bool hit = (bi != gbd[g0 + j]) & (R > 0.f) & (dx * dx + dy * dy + dz * dz < R * R);
+          hits |= (unsigned long long)hit << j;
+        }
+        rm[i] = i == 63 ? 0ull : hits & (~0ull << (i + 1));
+      }
+      __syncthreads();
+      if (i < S)
+        for (unsigned long long lo = hits & ((1ull << i) - 1ull); lo; lo &= lo - 1ull)
+          atomicOr(rm + (__ffsll(lo) - 1), 1ull << i);
+    } else {
     for (int x = tid; x < S * nwd; x += BS) rm[x] = 0ull;
     __syncthreads();
-    const int half = S >> 1;
     for (int r0 = 0; r0 < S; r0 += BS) {
       const int i = r0 + tid;
       if (i < S) {
@@ -832,6 +859,7 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
           }
         }
       }
+    }
     }
     __syncthreads();
     for (int r0 = 0; r0 < S; r0 += BS) {

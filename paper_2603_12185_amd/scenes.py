@@ -344,7 +344,7 @@ def two_spheres(r1=0.05, r2=0.04, m1=1.0, m2=0.5, gap=-0.002, vel1=(0.3, 0.05, 0
 
 
 def sphere_cluster(nsphere=6, seed=0, condim=3, gravity=(0, 0, 0), k_user=0.1, d_user=0.001,
-                   spread=0.07, speed=0.5, spin=5.0):
+                   spread=0.07, speed=0.5, spin=5.0, ncon_max=64):
     """Free spheres packed closely with random velocities and spins, no static geoms."""
     rng = np.random.default_rng([seed, 3])
     b = _Builder(1)
@@ -356,7 +356,7 @@ def sphere_cluster(nsphere=6, seed=0, condim=3, gravity=(0, 0, 0), k_user=0.1, d
                friction=(rng.uniform(0.3, 1.0), rng.uniform(0.001, 0.005),
                          rng.uniform(0.0001, 0.0005)))
     s = b.build(condim=condim, k_user=k_user, d_user=d_user, gravity=gravity,
-                ncon_max=64, name="sphere_cluster")
+                ncon_max=ncon_max, name="sphere_cluster")
     q = s["q0"].reshape(nsphere, 7)
     q[:, 0:3] = rng.uniform(-spread, spread, (nsphere, 3))
     q[:, 3:7] = [_random_quat(rng) for _ in range(nsphere)]
