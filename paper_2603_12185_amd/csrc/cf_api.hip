@@ -38,6 +38,7 @@ struct cf_model {
   int nw = 0, nb = 0, ng = 0, nq = 0, nv = 0, ncon_max = 0, condim = 3, nf = 4, nbits = 1;
   int nslot = 0;
   int nslot_pre = 0, sph0 = 0, nsph = 0;  // sphere block of the narrow phase (see below)
+  int npl = 0;                            // static planes tested as rows against the block
   cf::Params p{};
   // device constants
   uint32_t *d_slots = nullptr;
@@ -321,6 +322,19 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
         m->nslot_pre = m->nslot - (int)tail.size();
       }
     }
+    // Plane rows: every geom before the block is a static plane and the slots
+    // before the block are exactly each plane's pairs with every block sphere,
+    // plane-major.
+    if (m->nsph > 0 && m->sph0 > 0) {
+      bool rows = true;
+      for (int g = 0; g < m->sph0 && rows; ++g) rows = d->geom_type[g] == CF_PLANE && d->geom_body[g] < 0;
+      if (rows && m->nslot_pre == m->sph0 * m->nsph) {
+        for (int p = 0, k = 0; p < m->sph0 && rows; ++p)
+          for (int i = 0; i < m->nsph && rows; ++i, ++k)
+            rows = slots[k] == cf::slot_pack(p, m->sph0 + i, 0, cf::kPlaneSphere);
+        if (rows) m->npl = m->sph0;
+      }
+    }
   }
   m->lds_collide = cf::collide_lds_bytes(m->nq, nb, ng, m->norient, m->nsub, m->nsph);
   m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->nsub, m->art_floats);
@@ -426,7 +440,7 @@ static cf::CollideArgs collide_args(const cf_model *m) {
   ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
   ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
   ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
-  ca.nslot_pre = m->nslot_pre; ca.sph0 = m->sph0; ca.nsph = m->nsph;
+  ca.nslot_pre = m->nslot_pre; ca.sph0 = m->sph0; ca.nsph = m->nsph; ca.npl = m->npl;
   return ca;
 }
 

@@ -79,6 +79,7 @@ struct CollideArgs {
   int nq, nb, ng, norient, nslot, ncon_max, nsub;
   int nslot_pre;                // slots tested one by one (all of them when nsph = 0)
   int sph0, nsph;               // sphere block: geoms [sph0, sph0 + nsph), pairs tested row-wise
+  int npl;                      // > 0: geoms [0, npl) are static planes whose slots are their rows against the block
   int gpos_ws, gquat_ws;        // world stride in elements (0 = shared by all worlds)
   float margin;
 };

@@ -659,7 +659,7 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
   __shared__ float wmax[NW];
 
   // slot words of the next three chunks, in flight during the set-up below
-  const int npre = a.nslot_pre;
+  const int npre = a.npl > 0 ? 0 : a.nslot_pre;
   uint32_t nxt2 = tid + BS < npre ? a.slots[tid + BS] : 0u;
   uint32_t nxt3 = tid + 2 * BS < npre ? a.slots[tid + 2 * BS] : 0u;
   uint32_t nxt4 = tid + 3 * BS < npre ? a.slots[tid + 3 * BS] : 0u;
@@ -774,6 +774,42 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     __syncthreads();
     ncand = 0;
   };
+
+  // Plane rows: when the slots before the sphere block are exactly every
+  // (static plane p, sphere i) pair, plane-major, each lane takes a sphere and
+  // decides every plane's pair directly in float64 (the decision and the
+  // record of the per-slot path, without its slot words, type dispatch and
+  // candidate list); hits are stored in slot order by a workgroup scan.
+  if (a.npl > 0) {
+    const int g0 = a.sph0, S = a.nsph;
+    for (int pl = 0; pl < a.npl; ++pl) {
+      const Pose<double> &Pd = Od[go[pl]];
+      const double nx = Pd.r[2], ny = Pd.r[5], nz = Pd.r[8];  // plane normal: local z
+      for (int r0 = 0; r0 < S; r0 += BS) {
+        const int i = r0 + tid;
+        bool hit = false;
+        float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
+        if (i < S) {
+          const float4 G = Gs[g0 + i];
+          const double cx = G.x, cy = G.y, cz = G.z, rad = G.w;
+          const double phi = nx * (cx - Pd.p[0]) + ny * (cy - Pd.p[1]) + nz * (cz - Pd.p[2]) - rad;
+          const double k = rad + 0.5 * phi;
+          hit = phi < (double)a.margin;
+          cn = make_float4((float)nx, (float)ny, (float)nz, (float)phi);
+          cp = make_float4((float)(cx - k * nx), (float)(cy - k * ny), (float)(cz - k * nz),
+                           __uint_as_float(slot_pack(pl, g0 + i, 0, kPlaneSphere)));
+        }
+        int tot;
+        const int idx = running + block_scan<BS>(hit, &tot, wcnt, par);
+        par ^= 1;
+        if (hit && idx < cap) {
+          outn[idx] = cn;
+          outp[idx] = cp;
+        }
+        running += tot;
+      }
+    }
+  }
 
   // Pass 1 over the slots before the sphere block: float32 test, ordered
   // candidate list; slot words are loaded four chunks ahead.
