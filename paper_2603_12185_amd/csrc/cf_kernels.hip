@@ -385,6 +385,24 @@ __device__ void art_predict(const SubTree S, const BodyC *B, const float4 *bmi, 
   }
 }
 
+// Unit quaternion exp(th/2) = (cos x, sin(x) th/|th|), x = |th|/2, of a rotation
+// vector: below x = 1/4 from the Taylor series of cos x and of sin(x)/x (the
+// first omitted terms are below 1e-13 relative, so the float32 result is that
+// of the exact functions), else from sinf, cosf.
+__device__ inline void quat_of_rotvec(V3 th, float &ew, float &ex, float &ey, float &ez) {
+  const float ang = sqrtf(dot(th, th)), x = 0.5f * ang;
+  float s;  // sin(x) / ang
+  if (x < 0.25f) {
+    const float x2 = x * x;
+    s = 0.5f * (1.f - x2 * (1.f / 6.f - x2 * (1.f / 120.f - x2 * (1.f / 5040.f - x2 * (1.f / 362880.f)))));
+    ew = 1.f - x2 * (0.5f - x2 * (1.f / 24.f - x2 * (1.f / 720.f - x2 * (1.f / 40320.f - x2 * (1.f / 3628800.f)))));
+  } else {
+    s = sinf(x) / ang;
+    ew = cosf(x);
+  }
+  ex = s * th.x; ey = s * th.y; ez = s * th.z;
+}
+
 // Velocity correction and integration of one articulated subtree:
 // p = sum_b J_b^T (F_b, T_b), v+ = v_s + M^-1 p, q+ = q (+) h v+.
 __device__ void art_correct(const SubTree S, const BodyC *B, const float4 *bC, const float4 *bO,
@@ -415,14 +433,8 @@ __device__ void art_correct(const SubTree S, const BodyC *B, const float4 *bC, c
     }
     for (int k = 0; k < 3; ++k) qb[k] += P.h * vb[k];
     const V3 th = P.h * v3(vb[3], vb[4], vb[5]);
-    const float ang = sqrtf(dot(th, th));
     float ew, ex, ey, ez;
-    if (ang < 1e-8f) {
-      ew = 1.f; ex = 0.5f * th.x; ey = 0.5f * th.y; ez = 0.5f * th.z;
-    } else {
-      const float s = sinf(0.5f * ang) / ang;
-      ew = cosf(0.5f * ang); ex = s * th.x; ey = s * th.y; ez = s * th.z;
-    }
+    quat_of_rotvec(th, ew, ex, ey, ez);
     const float qw0 = qb[3], qx0 = qb[4], qy0 = qb[5], qz0 = qb[6];
     const float nw_ = ew * qw0 - ex * qx0 - ey * qy0 - ez * qz0;
     const float nx_ = ew * qx0 + ex * qw0 + ey * qz0 - ez * qy0;
@@ -1022,7 +1034,7 @@ struct ResolveRegion {
   float4 *bI0, *bI1;     // inverse world inertia (xx yy zz xy | xz yz)
   float4 *accF, *accT;   // accumulated contact force and torque
   float4 *gM;            // per geom (mu_t, mu_tor, mu_rol)
-  int *fx;               // fixed-point chunk sums: 6 components, 2 exponents, count (pad4(nb) each)
+  int *fx;               // fixed-point chunk sums: 3 packed 64-bit words (6 ints), 2 exponents, count (pad4(nb) each)
   int *gB;               // per geom body
   float4 *bO, *bAx, *bR; // articulated bodies: origin, joint axis, rotation rows
   float *art;            // articulated subtree work blocks
@@ -1216,22 +1228,34 @@ __device__ inline void fx_exponents(int *e, int *n, int stride, float4 a, float2
   atomicAdd(n, 1);
 }
 
-// Adds the entry (a, b), each part scaled by its 2^s and truncated, to the six
-// sums at p, p + stride, ... (exponents at p + 6 stride and p + 7 stride; n
-// entries).
-__device__ inline void fx_add(int *p, int stride, int n, float4 a, float2 b) {
-  const int sf = fx_shift(p[6 * stride], n), st = fx_shift(p[7 * stride], n);
-  atomicAdd(p, __float2int_rz(ldexpf(a.x, sf)));
-  atomicAdd(p + stride, __float2int_rz(ldexpf(a.y, sf)));
-  atomicAdd(p + 2 * stride, __float2int_rz(ldexpf(a.z, sf)));
-  atomicAdd(p + 3 * stride, __float2int_rz(ldexpf(a.w, st)));
-  atomicAdd(p + 4 * stride, __float2int_rz(ldexpf(b.x, st)));
-  atomicAdd(p + 5 * stride, __float2int_rz(ldexpf(b.y, st)));
+// Bias of every scaled entry of a part with n entries: 2^(31 - L), L =
+// ceil(log2 n).  A scaled entry lies strictly between -2^(31 - L) and
+// 2^(31 - L), so entry + bias is in [1, 2^(32 - L)) and the biased sum of n
+// entries stays below 2^32: two such sums share one 64-bit word (one LDS
+// atomic) without a carry from the low half into the high half.
+__device__ inline uint32_t fx_bias(int n) {
+  const int L = n > 1 ? 32 - __clz(n - 1) : 0;
+  return 1u << (31 - L);
 }
 
-// Float value of a fixed-point sum with exponent e over n entries (NaN when an
-// entry was not finite).
-__device__ inline float fx_value(int sum, int e, int n) {
+// Adds the entry (a, b) of body k, each part scaled by its 2^s, truncated and
+// biased, to the body's three packed words (Fx|Fy, Fz|Tx, Ty|Tz; low | high
+// half) at q[k], q[k + stride], q[k + 2 stride]; e: the body's force and torque
+// exponents at e[k] and e[k + stride]; n entries.
+__device__ inline void fx_add(unsigned long long *q, const int *e, int k, int stride, int n, float4 a, float2 b) {
+  const int sf = fx_shift(e[k], n), st = fx_shift(e[stride + k], n);
+  const uint32_t B = fx_bias(n);
+  auto u = [&](float x, int sh) { return (unsigned long long)((uint32_t)__float2int_rz(ldexpf(x, sh)) + B); };
+  atomicAdd(q + k, u(a.x, sf) | (u(a.y, sf) << 32));
+  atomicAdd(q + stride + k, u(a.z, sf) | (u(a.w, st) << 32));
+  atomicAdd(q + 2 * stride + k, u(b.x, st) | (u(b.y, st) << 32));
+}
+
+// Float value of the biased half `h` of a packed sum with exponent e over n
+// entries (NaN when an entry was not finite): the n biases are removed in
+// 32-bit arithmetic, which leaves the true sum (below 2^31 in magnitude).
+__device__ inline float fx_value(uint32_t h, int e, int n) {
+  const int sum = (int)(h - (uint32_t)n * fx_bias(n));
   return e >= FX_BAD ? __builtin_nanf("") : ldexpf((float)sum, -fx_shift(e, n));
 }
 
@@ -1269,6 +1293,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   int *gB = RR.gB, *fx = RR.fx;
   const int nbp = pad4(nb);
   int *fxE = fx + 6 * nbp, *fxN = fx + 8 * nbp;
+  unsigned long long *fxQ = reinterpret_cast<unsigned long long *>(fx);  // [3][nbp] packed sums
   float4 *bO = RR.bO, *bAx = RR.bAx, *bR = RR.bR;  // articulated bodies only
   float *art = RR.art;
   const Params P = a.p;
@@ -1496,12 +1521,13 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     // additions commute, so the order of the LDS atomics does not change the
     // result.  The force and the torque part of body k are scaled by 2^s,
     // s = 31 - e - L, with every entry's components of that part below 2^e in
-    // magnitude and L = ceil(log2(entries)), so no sum reaches 2^31.
+    // magnitude and L = ceil(log2(entries)), so no sum reaches 2^31; biased,
+    // two components share each 64-bit LDS word (three atomics per entry).
     if (kA < nb) fx_exponents(fxE + kA, fxN + kA, nbp, WA, WA2);
     if (kB < nb) fx_exponents(fxE + kB, fxN + kB, nbp, WB, WB2);
     __syncthreads();
-    if (kA < nb) fx_add(fx + kA, nbp, fxN[kA], WA, WA2);
-    if (kB < nb) fx_add(fx + kB, nbp, fxN[kB], WB, WB2);
+    if (kA < nb) fx_add(fxQ, fxE, kA, nbp, fxN[kA], WA, WA2);
+    if (kB < nb) fx_add(fxQ, fxE, kB, nbp, fxN[kB], WB, WB2);
     __syncthreads();
     // chunk sums into the float accumulators (chunks in order), slots cleared
     for (int b = tid; b < nb; b += BS) {
@@ -1509,15 +1535,15 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       if (n == 0) continue;
       float4 F = accF[b], T = accT[b];
       const int ef = fxE[b], et = fxE[nbp + b];
-      F.x += fx_value(fx[b], ef, n);
-      F.y += fx_value(fx[nbp + b], ef, n);
-      F.z += fx_value(fx[2 * nbp + b], ef, n);
-      T.x += fx_value(fx[3 * nbp + b], et, n);
-      T.y += fx_value(fx[4 * nbp + b], et, n);
-      T.z += fx_value(fx[5 * nbp + b], et, n);
+      const unsigned long long q0 = fxQ[b], q1 = fxQ[nbp + b], q2 = fxQ[2 * nbp + b];
+      F.x += fx_value((uint32_t)q0, ef, n);
+      F.y += fx_value((uint32_t)(q0 >> 32), ef, n);
+      F.z += fx_value((uint32_t)q1, ef, n);
+      T.x += fx_value((uint32_t)(q1 >> 32), et, n);
+      T.y += fx_value((uint32_t)q2, et, n);
+      T.z += fx_value((uint32_t)(q2 >> 32), et, n);
       accF[b] = F; accT[b] = T;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) fx[c * nbp + b] = 0;
+      fxQ[b] = 0ull; fxQ[nbp + b] = 0ull; fxQ[2 * nbp + b] = 0ull;
       fxE[b] = FX_EMPTY;
       fxE[nbp + b] = FX_EMPTY;
       fxN[b] = 0;
@@ -1552,14 +1578,8 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     qb[2] = C.z + P.h * vp.z;
     // quat <- normalize(exp(h w) (x) quat), world-frame angular velocity
     const V3 th = P.h * wp;
-    const float ang = sqrtf(dot(th, th));
     float ew, ex, ey, ez;
-    if (ang < 1e-8f) {
-      ew = 1.f; ex = 0.5f * th.x; ey = 0.5f * th.y; ez = 0.5f * th.z;
-    } else {
-      const float s = sinf(0.5f * ang) / ang;
-      ew = cosf(0.5f * ang); ex = s * th.x; ey = s * th.y; ez = s * th.z;
-    }
+    quat_of_rotvec(th, ew, ex, ey, ez);
     const float qw0 = qb[3], qx0 = qb[4], qy0 = qb[5], qz0 = qb[6];
     const float nw_ = ew * qw0 - ex * qx0 - ey * qy0 - ez * qz0;
     const float nx_ = ew * qx0 + ex * qw0 + ey * qz0 - ez * qy0;
