@@ -648,6 +648,53 @@ __device__ inline GeomIn geom_in(const CollideArgs &a, int w, int g) {
   return x;
 }
 
+// Hit masks of a sphere block of S <= 64 NWD spheres (rows of NWD words in rm,
+// zero on entry).  The lane of sphere i tests its partners j = i + d mod S,
+// d = 1 ... S/2 (d = S/2 once per pair), branch-free, collecting the hit bits in
+// NWD registers; the bits above i are ORed into row i and each bit j below i (a
+// pair reached by wrapping round) into row j at bit i (integer OR: the order of
+// the atomics does not matter).  A pair is a hit when |c_j - c_i|^2 <
+// (r_i + r_j + margin)^2 in float32, the same value from either end.
+template <int BS, int NWD>
+__device__ inline void sphere_masks(const float4 *Gs, const int *gbd, int g0, int S, float margin,
+                                    unsigned long long *rm) {
+  const int half = S >> 1;
+  for (int r0 = 0; r0 < S; r0 += BS) {
+    const int i = r0 + (int)threadIdx.x;
+    if (i >= S) continue;
+    const float4 Gi = Gs[g0 + i];
+    const int bi = gbd[g0 + i];
+    const int dmax = (S & 1) ? half : (i < half ? half : half - 1);
+    unsigned long long h[NWD];
+#pragma unroll
+    for (int w = 0; w < NWD; ++w) h[w] = 0ull;
+    int j = i;
+    for (int d = 1; d <= dmax; ++d) {
+      j = j + 1 == S ? 0 : j + 1;
+      const float4 Gj = Gs[g0 + j];
+      const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
+      const float R = Gi.w + Gj.w + margin;
+      const bool hit = (bi != gbd[g0 + j]) & (R > 0.f) & (dx * dx + dy * dy + dz * dz < R * R);
+      const unsigned long long bit = (unsigned long long)hit << (j & 63);
+      if constexpr (NWD == 1) {
+        h[0] |= bit;
+      } else {
+        h[0] |= j < 64 ? bit : 0ull;
+        h[1] |= j < 64 ? 0ull : bit;
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < NWD; ++w) {
+      const int lo = i + 1 - 64 * w;  // first bit of word w above i
+      const unsigned long long above = lo <= 0 ? ~0ull : lo >= 64 ? 0ull : ~0ull << lo;
+      const unsigned long long own = h[w] & above;
+      if (own) atomicOr(rm + i * NWD + w, own);
+      for (unsigned long long b = h[w] & ~above; b; b &= b - 1ull)
+        atomicOr(rm + (64 * w + __ffsll(b) - 1) * NWD + (i >> 6), 1ull << (i & 63));
+    }
+  }
+}
+
 // Narrow phase of world w from its q row `sq` (LDS).  Writes the first `cap`
 // contacts of the canonical order to outn/outp (global or LDS) and returns the
 // number found.  `reg` is LDS scratch of collide_region_bytes(); `nxt` is the
@@ -859,36 +906,14 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     const int g0 = a.sph0, S = a.nsph, nwd = (S + 63) >> 6;
     unsigned long long *rm = reinterpret_cast<unsigned long long *>(
         a.nsub > 0 ? reinterpret_cast<char *>(brot + 12 * a.nb) : reinterpret_cast<char *>(borg));
-    const int half = S >> 1;
-    if (S <= 64) {
-      // one row word per sphere, all rows in one pass (S <= 64 <= BS): the
-      // lane's hits with every partner j are collected branch-free as bits of
-      // one register; the bits above i are its own row, stored whole, and each
-      // bit j below i (a pair reached by wrapping round) is ORed into row j
-      unsigned long long hits = 0ull;
-      const int i = tid;
-      if (i < S) {
-        const float4 Gi = Gs[g0 + i];
-        const int bi = gbd[g0 + i];
-        const int dmax = (S & 1) ? half : (i < half ? half : half - 1);
-        int j = i;
-        for (int d = 1; d <= dmax; ++d) {
-          j = j + 1 == S ? 0 : j + 1;
-          const float4 Gj = Gs[g0 + j];
-          const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
-          const float R = Gi.w + Gj.w + a.margin;  // the same rounding from either end of the pair
-          const bool hit = (bi != gbd[g0 + j]) & (R > 0.f) & (dx * dx + dy * dy + dz * dz < R * R);
-          hits |= (unsigned long long)hit << j;
-        }
-        rm[i] = i == 63 ? 0ull : hits & (~0ull << (i + 1));
-      }
-      __syncthreads();
-      if (i < S)
-        for (unsigned long long lo = hits & ((1ull << i) - 1ull); lo; lo &= lo - 1ull)
-          atomicOr(rm + (__ffsll(lo) - 1), 1ull << i);
-    } else {
     for (int x = tid; x < S * nwd; x += BS) rm[x] = 0ull;
     __syncthreads();
+    if (S <= 64) {
+      sphere_masks<BS, 1>(Gs, gbd, g0, S, a.margin, rm);
+    } else if (S <= 128) {
+      sphere_masks<BS, 2>(Gs, gbd, g0, S, a.margin, rm);
+    } else {
+    const int half = S >> 1;
     for (int r0 = 0; r0 < S; r0 += BS) {
       const int i = r0 + tid;
       if (i < S) {
