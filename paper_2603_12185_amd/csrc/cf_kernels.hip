@@ -761,10 +761,15 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     Pose<double> pd;
     Pose<float> pf;
     const double off[3] = {gp.x, gp.y, gp.z};
-    for (int i = 0; i < 3; ++i) {
-      pd.p[i] = bp[i] + br[3 * i] * off[0] + br[3 * i + 1] * off[1] + br[3 * i + 2] * off[2];
-      for (int j = 0; j < 3; ++j)
-        pd.r[3 * i + j] = br[3 * i] * gr[j] + br[3 * i + 1] * gr[3 + j] + br[3 * i + 2] * gr[6 + j];
+    if (b < 0) {  // static: the body frame is the world frame
+      for (int i = 0; i < 3; ++i) pd.p[i] = off[i];
+      for (int k = 0; k < 9; ++k) pd.r[k] = gr[k];
+    } else {
+      for (int i = 0; i < 3; ++i) {
+        pd.p[i] = bp[i] + br[3 * i] * off[0] + br[3 * i + 1] * off[1] + br[3 * i + 2] * off[2];
+        for (int j = 0; j < 3; ++j)
+          pd.r[3 * i + j] = br[3 * i] * gr[j] + br[3 * i + 1] * gr[3 + j] + br[3 * i + 2] * gr[6 + j];
+      }
     }
     pd.s[0] = gd.x; pd.s[1] = gd.y; pd.s[2] = gd.z; pd.pad = 0.0;
     for (int i = 0; i < 3; ++i) { pf.p[i] = (float)pd.p[i]; pf.s[i] = (float)pd.s[i]; }
@@ -1043,7 +1048,7 @@ hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t ld
 // friction + int body.
 // LDS scratch of the resolution of one world (after its q, v and tau rows).
 __host__ __device__ size_t resolve_region_bytes(int nb, int ng, int nsub, int art_floats) {
-  return sizeof(float4) * 7 * (size_t)nb + sizeof(float4) * (size_t)ng + sizeof(int) * 9 * (size_t)pad4(nb) +
+  return sizeof(float4) * 7 * (size_t)nb + sizeof(float4) * (size_t)ng + sizeof(int) * 8 * (size_t)pad4(nb) +
          sizeof(int) * (size_t)pad4(ng) +
          (nsub > 0 ? sizeof(float4) * 5 * (size_t)nb + sizeof(float) * (size_t)pad4(art_floats) : 0);
 }
@@ -1059,7 +1064,7 @@ struct ResolveRegion {
   float4 *bI0, *bI1;     // inverse world inertia (xx yy zz xy | xz yz)
   float4 *accF, *accT;   // accumulated contact force and torque
   float4 *gM;            // per geom (mu_t, mu_tor, mu_rol)
-  int *fx;               // fixed-point chunk sums: 3 packed 64-bit words (6 ints), 2 exponents, count (pad4(nb) each)
+  int *fx;               // fixed-point chunk sums: 3 packed 64-bit words (6 ints), 2 exponents (pad4(nb) each)
   int *gB;               // per geom body
   float4 *bO, *bAx, *bR; // articulated bodies: origin, joint axis, rotation rows
   float *art;            // articulated subtree work blocks
@@ -1072,7 +1077,7 @@ __device__ inline ResolveRegion resolve_region(float4 *reg, int nb, int ng) {
   r.accF = r.bI1 + nb; r.accT = r.accF + nb;
   r.gM = r.accT + nb;
   r.fx = reinterpret_cast<int *>(r.gM + ng);
-  r.gB = r.fx + 9 * pad4(nb);
+  r.gB = r.fx + 8 * pad4(nb);
   r.bO = reinterpret_cast<float4 *>(r.gB + pad4(ng));
   r.bAx = r.bO + nb; r.bR = r.bAx + nb;
   r.art = reinterpret_cast<float *>(r.bR + 3 * nb);
@@ -1239,49 +1244,47 @@ __device__ inline int fx_exp(float x, float y, float z) {
   return m == 0.f ? FX_ZERO : __builtin_amdgcn_frexp_expf(m);
 }
 
-// Scale exponent of a part with n entries below 2^e: s = 31 - e - ceil(log2 n).
-__device__ inline int fx_shift(int e, int n) {
-  const int L = n > 1 ? 32 - __clz(n - 1) : 0;
-  return 31 - e - L;
+// Headroom bits of a chunk's sums: a body gets at most one entry per lane (a
+// contact's two sides are different bodies), so at most BS entries per chunk.
+template <int BS>
+constexpr int fx_headroom() {
+  return BS <= 64 ? 6 : BS <= 128 ? 7 : 8;
 }
 
 // Raises the force and torque exponents at e and e + stride to cover the
-// wrench entry (a.xyz force, a.w b.xy torque) and counts the entry.
-__device__ inline void fx_exponents(int *e, int *n, int stride, float4 a, float2 b) {
+// wrench entry (a.xyz force, a.w b.xy torque).
+__device__ inline void fx_exponents(int *e, int stride, float4 a, float2 b) {
   atomicMax(e, fx_exp(a.x, a.y, a.z));
   atomicMax(e + stride, fx_exp(a.w, b.x, b.y));
-  atomicAdd(n, 1);
 }
 
-// Bias of every scaled entry of a part with n entries: 2^(31 - L), L =
-// ceil(log2 n).  A scaled entry lies strictly between -2^(31 - L) and
-// 2^(31 - L), so entry + bias is in [1, 2^(32 - L)) and the biased sum of n
-// entries stays below 2^32: two such sums share one 64-bit word (one LDS
-// atomic) without a carry from the low half into the high half.
-__device__ inline uint32_t fx_bias(int n) {
-  const int L = n > 1 ? 32 - __clz(n - 1) : 0;
-  return 1u << (31 - L);
+// Adds the entry (a, b) of body k, each part scaled by 2^s, s = 31 - e - L
+// (L = headroom bits), and truncated, to the body's three packed words (Fx|Fy,
+// Fz|Tx, Ty|Tz) at q[k], q[k + stride], q[k + 2 stride]; e: the body's force
+// and torque exponents at e[k] and e[k + stride].  A word holds lo + 2^32 hi in
+// two's complement: each half's sum stays below 2^31 in magnitude, so the
+// 64-bit sum of the packed entries is exactly (sum of lo) + 2^32 (sum of hi).
+template <int BS>
+__device__ inline void fx_add(unsigned long long *q, const int *e, int k, int stride, float4 a, float2 b) {
+  constexpr int L = fx_headroom<BS>();
+  const int sf = 31 - e[k] - L, st = 31 - e[stride + k] - L;
+  auto u = [&](float x, int sh) { return (unsigned long long)(long long)__float2int_rz(ldexpf(x, sh)); };
+  atomicAdd(q + k, u(a.x, sf) + (u(a.y, sf) << 32));
+  atomicAdd(q + stride + k, u(a.z, sf) + (u(a.w, st) << 32));
+  atomicAdd(q + 2 * stride + k, u(b.x, st) + (u(b.y, st) << 32));
 }
 
-// Adds the entry (a, b) of body k, each part scaled by its 2^s, truncated and
-// biased, to the body's three packed words (Fx|Fy, Fz|Tx, Ty|Tz; low | high
-// half) at q[k], q[k + stride], q[k + 2 stride]; e: the body's force and torque
-// exponents at e[k] and e[k + stride]; n entries.
-__device__ inline void fx_add(unsigned long long *q, const int *e, int k, int stride, int n, float4 a, float2 b) {
-  const int sf = fx_shift(e[k], n), st = fx_shift(e[stride + k], n);
-  const uint32_t B = fx_bias(n);
-  auto u = [&](float x, int sh) { return (unsigned long long)((uint32_t)__float2int_rz(ldexpf(x, sh)) + B); };
-  atomicAdd(q + k, u(a.x, sf) | (u(a.y, sf) << 32));
-  atomicAdd(q + stride + k, u(a.z, sf) | (u(a.w, st) << 32));
-  atomicAdd(q + 2 * stride + k, u(b.x, st) | (u(b.y, st) << 32));
+// The low and the high half's sums of a packed word.
+__device__ inline int fx_lo(unsigned long long t) { return (int)(uint32_t)t; }
+__device__ inline int fx_hi(unsigned long long t) {
+  return (int)(uint32_t)((t - (unsigned long long)(long long)fx_lo(t)) >> 32);
 }
 
-// Float value of the biased half `h` of a packed sum with exponent e over n
-// entries (NaN when an entry was not finite): the n biases are removed in
-// 32-bit arithmetic, which leaves the true sum (below 2^31 in magnitude).
-__device__ inline float fx_value(uint32_t h, int e, int n) {
-  const int sum = (int)(h - (uint32_t)n * fx_bias(n));
-  return e >= FX_BAD ? __builtin_nanf("") : ldexpf((float)sum, -fx_shift(e, n));
+// Float value of a fixed-point sum with exponent e (NaN when an entry was not
+// finite).
+template <int BS>
+__device__ inline float fx_value(int sum, int e) {
+  return e >= FX_BAD ? __builtin_nanf("") : ldexpf((float)sum, -(31 - e - fx_headroom<BS>()));
 }
 
 // Per geom: body and pair-friction inputs (mu_t, mu_tor, mu_rol) in LDS, for
@@ -1317,7 +1320,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   float4 *accF = RR.accF, *accT = RR.accT, *gM = RR.gM;
   int *gB = RR.gB, *fx = RR.fx;
   const int nbp = pad4(nb);
-  int *fxE = fx + 6 * nbp, *fxN = fx + 8 * nbp;
+  int *fxE = fx + 6 * nbp;
   unsigned long long *fxQ = reinterpret_cast<unsigned long long *>(fx);  // [3][nbp] packed sums
   float4 *bO = RR.bO, *bAx = RR.bAx, *bR = RR.bR;  // articulated bodies only
   float *art = RR.art;
@@ -1385,7 +1388,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     accF[b] = make_float4(0.f, 0.f, 0.f, 0.f);
     accT[b] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  for (int i = tid; i < 9 * nbp; i += BS) fx[i] = i >= 6 * nbp && i < 8 * nbp ? FX_EMPTY : 0;
+  for (int i = tid; i < 8 * nbp; i += BS) fx[i] = i >= 6 * nbp ? FX_EMPTY : 0;
   // ---- articulated subtrees: one lane each (same equations, dense per-subtree M)
   if (ART)
   for (int si = tid; si < a.nsub; si += BS) {
@@ -1546,32 +1549,30 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     // additions commute, so the order of the LDS atomics does not change the
     // result.  The force and the torque part of body k are scaled by 2^s,
     // s = 31 - e - L, with every entry's components of that part below 2^e in
-    // magnitude and L = ceil(log2(entries)), so no sum reaches 2^31; biased,
-    // two components share each 64-bit LDS word (three atomics per entry).
-    if (kA < nb) fx_exponents(fxE + kA, fxN + kA, nbp, WA, WA2);
-    if (kB < nb) fx_exponents(fxE + kB, fxN + kB, nbp, WB, WB2);
+    // magnitude and at most 2^L entries, so no sum reaches 2^31; two
+    // components share each 64-bit LDS word (three atomics per entry).
+    if (kA < nb) fx_exponents(fxE + kA, nbp, WA, WA2);
+    if (kB < nb) fx_exponents(fxE + kB, nbp, WB, WB2);
     __syncthreads();
-    if (kA < nb) fx_add(fxQ, fxE, kA, nbp, fxN[kA], WA, WA2);
-    if (kB < nb) fx_add(fxQ, fxE, kB, nbp, fxN[kB], WB, WB2);
+    if (kA < nb) fx_add<BS>(fxQ, fxE, kA, nbp, WA, WA2);
+    if (kB < nb) fx_add<BS>(fxQ, fxE, kB, nbp, WB, WB2);
     __syncthreads();
     // chunk sums into the float accumulators (chunks in order), slots cleared
     for (int b = tid; b < nb; b += BS) {
-      const int n = fxN[b];
-      if (n == 0) continue;
-      float4 F = accF[b], T = accT[b];
       const int ef = fxE[b], et = fxE[nbp + b];
+      if (ef == FX_EMPTY) continue;  // no entry this chunk (an entry raises both exponents)
+      float4 F = accF[b], T = accT[b];
       const unsigned long long q0 = fxQ[b], q1 = fxQ[nbp + b], q2 = fxQ[2 * nbp + b];
-      F.x += fx_value((uint32_t)q0, ef, n);
-      F.y += fx_value((uint32_t)(q0 >> 32), ef, n);
-      F.z += fx_value((uint32_t)q1, ef, n);
-      T.x += fx_value((uint32_t)(q1 >> 32), et, n);
-      T.y += fx_value((uint32_t)q2, et, n);
-      T.z += fx_value((uint32_t)(q2 >> 32), et, n);
+      F.x += fx_value<BS>(fx_lo(q0), ef);
+      F.y += fx_value<BS>(fx_hi(q0), ef);
+      F.z += fx_value<BS>(fx_lo(q1), ef);
+      T.x += fx_value<BS>(fx_hi(q1), et);
+      T.y += fx_value<BS>(fx_lo(q2), et);
+      T.z += fx_value<BS>(fx_hi(q2), et);
       accF[b] = F; accT[b] = T;
       fxQ[b] = 0ull; fxQ[nbp + b] = 0ull; fxQ[2 * nbp + b] = 0ull;
       fxE[b] = FX_EMPTY;
       fxE[nbp + b] = FX_EMPTY;
-      fxN[b] = 0;
     }
     __syncthreads();
   }
