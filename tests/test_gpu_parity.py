@@ -164,6 +164,40 @@ def test_sphere_block_sizes_parity(torch_cuda, nsphere):
     assert stats["checked"] == 1 and stats["contacts"] >= nsphere // 2
 
 
+@pytest.mark.parametrize("case", ["pile64", "pile128", "cluster100"])
+def test_collide_launch_shapes_agree(torch_cuda, case):
+    """The narrow phase at 64, 128 and 256 threads per world (plane rows, the
+    sphere block's one- and two-word register masks, their row loops and
+    workgroup scans) finds the same contacts, bit for bit, in the same order; the
+    resolution at each shape agrees with the default's to float32 rounding (its
+    fixed-point headroom depends on the workgroup size)."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    if case == "cluster100":
+        s, settle = scenes.sphere_cluster(nsphere=100, seed=5, spread=0.15, ncon_max=1024), 0
+    else:
+        s, settle = scenes.dense_pile(nworld=8, nsphere=int(case[4:]), seed=11), 300
+    model = cfsim.Model(s)
+    print(f"case: launch shapes {case}", flush=True)
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    for _ in range(settle):
+        q, v = model.step(q, v)
+    ref = None
+    for blk in (64, 128, 256):
+        model.set_launch(blk, blk)
+        con = model.alloc_contacts()
+        q1, v1 = model.step(q.clone(), v.clone(), contacts=con)
+        rec = (con["ncon"].clone(), con["geom"].clone(), con["dist"].clone(), con["pos"].clone(),
+               con["frame"].clone())
+        if ref is None:
+            ref = (rec, v1)
+            assert int(con["ncon"].min()) > 0
+            continue
+        for x, y in zip(rec, ref[0]):
+            assert torch.equal(x, y), f"contacts differ at {blk} threads per world"
+        assert float((v1 - ref[1]).abs().max()) <= 1e-5 * float(ref[1].abs().max())
+
+
 def test_dense_pile_many_contacts_parity(torch_cuda):
     """4 worlds x 128 spheres packed in two overlapping layers on the ground:
     more than 256 contacts per world (several compaction and reduction
