@@ -1042,10 +1042,10 @@ hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t ld
 // resolution
 // ====================================================================
 // LDS: q, v, tau rows; per body 7 float4 (com|invm, vs|tr, ws, Iinv a, Iinv b,
-// accumulated force, accumulated torque) and 9 ints (fixed-point wrench sums
-// of the current contact chunk, the exponents of its force and its torque
-// part and the entry count, stored component-major); per geom float4
-// friction + int body.
+// accumulated force, accumulated torque) and 8 ints (the fixed-point wrench
+// sums of the current contact chunk as three packed 64-bit words, the
+// exponents of its force and its torque part, stored component-major); per
+// geom float4 friction + int body.
 // LDS scratch of the resolution of one world (after its q, v and tau rows).
 __host__ __device__ size_t resolve_region_bytes(int nb, int ng, int nsub, int art_floats) {
   return sizeof(float4) * 7 * (size_t)nb + sizeof(float4) * (size_t)ng + sizeof(int) * 8 * (size_t)pad4(nb) +
