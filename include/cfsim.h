@@ -226,11 +226,13 @@ cf_status cf_model_set_actuators(cf_model *m, const float *kp, const float *kd);
 cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float margin);
 
 /* Workgroup size (64, 128 or 256 threads, one world per workgroup) of the
- * collision, the resolution and the rollout kernel (defaults 64, 128, 256);
- * results do not depend on the choice beyond the last bits of v+ (same
- * arithmetic; the per-body contact sums are exact integer sums within a chunk
- * of one contact per thread, and chunks add in order, so the chunk size can
- * change the rounding). */
+ * collision, the resolution and the rollout kernel.  Defaults by world size:
+ * collision 64 threads, 128 above 64 and 256 above 128 spheres in the sphere
+ * block (one block row per thread); resolution 128 threads, 256 above 64
+ * bodies; rollout 256.  The contacts do not depend on the choice; v+ only in
+ * its last bits (same arithmetic; the per-body contact sums are exact integer
+ * sums within a chunk of one contact per thread, and chunks add in order, so
+ * the chunk size can change the rounding). */
 cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolve_block, int32_t rollout_block);
 /* Also reports whether cf_rollout uses the persistent kernel (1) or step calls (0). */
 cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t *resolve_block,

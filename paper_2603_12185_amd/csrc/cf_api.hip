@@ -336,6 +336,11 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       }
     }
   }
+  // Default launch shape by world size (cf_model_autotune measures instead):
+  // one sphere-block row per collision thread, and a resolution workgroup of
+  // 256 threads once a world has more than 64 bodies (fewer contact chunks).
+  m->block_collide = m->nsph > 128 ? 256 : m->nsph > 64 ? 128 : 64;
+  m->block_resolve = nb > 64 ? 256 : 128;
   m->lds_collide = cf::collide_lds_bytes(m->nq, nb, ng, m->norient, m->nsub, m->nsph);
   m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->nsub, m->art_floats);
   if (m->lds_collide > kLdsLimit || m->lds_resolve > kLdsLimit) {
