@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define CF_ABI_VERSION 2
+#define CF_ABI_VERSION 3
 
 typedef struct cf_model cf_model;
 typedef int32_t cf_status;
@@ -126,6 +126,10 @@ typedef struct {
    * [-ln 256, ln 256] (outputs beyond nfacet 0) */
   float *features;    /* [nworld][ncon_max][8]                                   */
   float *target;      /* [nworld][ncon_max][16]                                  */
+  /* with the learned impedance on (cf_model_set_learned_impedance): 1 where
+   * the contact fell back to the heuristic gains, 0 where it kept the learned
+   * ones; left untouched otherwise */
+  int32_t *fallback;  /* [nworld][ncon_max]                                      */
 } cf_contacts;
 
 /* Validate the descriptor, upload per-world constants and size the contact
@@ -178,14 +182,19 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
 /* T consecutive steps (batched rollouts): q_traj/v_traj [T+1][nworld][nq|nv]
  * receive the initial state (copied from q0/v0 unless they already alias row 0)
  * and every step's result; tau_seq [T][nworld][nv] or NULL; ncon_traj
- * [T][nworld] receives the contacts kept at each step, or NULL.  T >= 0.
- * The same step as cf_step: when a world's state, contact list (ncon_max
- * records) and scratch fit one workgroup's LDS, all T steps run in one
- * persistent kernel launch (one workgroup per world, nothing but the
- * trajectory crosses HBM; see cf_model_get_launch), else as T cf_step calls.
- * Allocates nothing, so a stream capture (HIP graph) of the call replays it. */
+ * [T][nworld] receives the contacts kept at each step and overflow_traj
+ * [T][nworld] the contacts dropped beyond ncon_max at each step (either may
+ * be NULL).  T >= 0.  The same step as cf_step (Algorithm 1 with collision
+ * and integration, repeated): batched rollouts are the workload of the
+ * paper's throughput-versus-environments and MPC experiments (Sec. IV.E,
+ * Sec. V).  When a world's state, contact list (ncon_max records) and
+ * scratch fit one workgroup's LDS, all T steps run in one persistent kernel
+ * launch (one workgroup per world, nothing but the trajectory crosses HBM;
+ * see cf_model_get_launch), else as T cf_step calls.  Allocates nothing, so a
+ * stream capture (HIP graph) of the call replays it. */
 cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
-                     const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj);
+                     const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj,
+                     int32_t *overflow_traj);
 
 /* Impedance of the facet impulses (Sec. III.B).  CF_IMPEDANCE_HEURISTIC (the
  * default): A = r(|phi|)/(1 - r(|phi|)) / (tr_a + tr_b), one scalar per contact

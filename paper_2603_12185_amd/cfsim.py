@@ -42,7 +42,7 @@ class Contacts(C.Structure):
     _fields_ = [("ncon", C.c_void_p), ("overflow", C.c_void_p), ("geom", C.c_void_p),
                 ("sub", C.c_void_p), ("dist", C.c_void_p), ("pos", C.c_void_p),
                 ("frame", C.c_void_p), ("impulse", C.c_void_p), ("features", C.c_void_p),
-                ("target", C.c_void_p)]
+                ("target", C.c_void_p), ("fallback", C.c_void_p)]
 
 
 class CFError(RuntimeError):
@@ -59,7 +59,7 @@ SIGNATURES = {
     "cf_model_destroy": ([C.c_void_p], None),
     "cf_model_dims": ([C.c_void_p, _ip, _ip, _ip], C.c_int32),
     "cf_step": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, C.POINTER(Contacts)], C.c_int32),
-    "cf_rollout": ([C.c_void_p, C.c_void_p, C.c_int32, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
+    "cf_rollout": ([C.c_void_p, C.c_void_p, C.c_int32, _fp, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
     "cf_step_backward": ([C.c_void_p, C.c_void_p, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp], C.c_int32),
     "cf_model_set_launch": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
     "cf_model_set_impedance": ([C.c_void_p, C.c_int32], C.c_int32),
@@ -241,9 +241,10 @@ class Model:
         return gq, gv, gtau
 
     def rollout(self, T, q0, v0, tau_seq=None, q_traj=None, v_traj=None, ncon_traj=None,
-                stream=None):
-        """T steps; returns trajectories [T+1][nworld][nq|nv] (ncon_traj [T][nworld]
-        int32 receives per-step contact counts when given)."""
+                stream=None, overflow_traj=None):
+        """T steps; returns trajectories [T+1][nworld][nq|nv] (ncon_traj and
+        overflow_traj, int32 [T][nworld], receive per-step contact counts kept
+        and dropped beyond ncon_max when given)."""
         import torch
         self._check_state(q0, self.nq, "q0")
         self._check_state(v0, self.nv, "v0")
@@ -255,11 +256,13 @@ class Model:
                                     or not tau_seq.is_contiguous()):
             raise ValueError("tau_seq must be contiguous [T][nworld][nv]")
         s = torch.cuda.current_stream() if stream is None else stream
-        if ncon_traj is not None and (ncon_traj.dtype != torch.int32 or
-                                      ncon_traj.numel() < T * self.nworld):
-            raise ValueError("ncon_traj must be int32 [T][nworld]")
+        for name, t in (("ncon_traj", ncon_traj), ("overflow_traj", overflow_traj)):
+            if t is not None and (t.dtype != torch.int32 or t.numel() < T * self.nworld
+                                  or not t.is_contiguous()):
+                raise ValueError(f"{name} must be contiguous int32 [T][nworld]")
         _check(load().cf_rollout(self._h, C.c_void_p(s.cuda_stream), int(T), _ptr(q0), _ptr(v0),
-                                 _ptr(tau_seq), _ptr(q_traj), _ptr(v_traj), _ptr(ncon_traj)))
+                                 _ptr(tau_seq), _ptr(q_traj), _ptr(v_traj), _ptr(ncon_traj),
+                                 _ptr(overflow_traj)))
         return q_traj, v_traj
 
     # ------------------------------------------------------------ launch shape

@@ -517,6 +517,7 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
     ra.x_geom = out->geom; ra.x_sub = out->sub; ra.x_dist = out->dist; ra.x_pos = out->pos;
     ra.x_frame = out->frame; ra.x_imp = out->impulse;
     if (m->nsub == 0) { ra.x_feat = out->features; ra.x_target = out->target; }
+    ra.x_fallback = out->fallback;
   }
   e = launch_resolve_model(m, ra, s);
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("resolve launch: ") + hipGetErrorString(e));
@@ -563,7 +564,8 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
 }
 
 cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
-                     const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj) {
+                     const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj,
+                     int32_t *overflow_traj) {
   if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
   if (T < 0) return set_err(CF_E_INVALID_ARG, "T must be >= 0");
   if (!q0 || !v0 || !q_traj || !v_traj) return set_err(CF_E_INVALID_ARG, "NULL state pointer");
@@ -582,7 +584,7 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
     r.c = collide_args(m);
     r.s = resolve_args(m);
     r.q0 = q_traj; r.v0 = v_traj; r.tau_seq = tau_seq; r.q_traj = q_traj; r.v_traj = v_traj;
-    r.ncon_traj = ncon_traj; r.T = T; r.nworld = m->nw; r.cap = m->ncon_max;
+    r.ncon_traj = ncon_traj; r.over_traj = overflow_traj; r.T = T; r.nworld = m->nw; r.cap = m->ncon_max;
     hipError_t e = cf::launch_rollout(r, m->block_rollout, m->lds_rollout, s);
     if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("rollout launch: ") + hipGetErrorString(e));
     return CF_OK;
@@ -590,8 +592,10 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
   for (int t = 0; t < T; ++t) {
     cf_contacts c{};
     c.ncon = ncon_traj ? ncon_traj + (size_t)t * m->nw : nullptr;
+    c.overflow = overflow_traj ? overflow_traj + (size_t)t * m->nw : nullptr;
     cf_status st = cf_step(m, stream, q_traj + t * sq, v_traj + t * sv, tau_seq ? tau_seq + t * sv : nullptr,
-                           q_traj + (t + 1) * sq, v_traj + (t + 1) * sv, ncon_traj ? &c : nullptr);
+                           q_traj + (t + 1) * sq, v_traj + (t + 1) * sv,
+                           (ncon_traj || overflow_traj) ? &c : nullptr);
     if (st != CF_OK) return st;
   }
   return CF_OK;
@@ -727,9 +731,9 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
     if (lds > kLdsLimit) continue;
     m->block_rollout = sizes[io];
     m->lds_rollout = lds;
-    st = cf_rollout(m, stream, 1, q, v, nullptr, qt, vt, nullptr);  // warm-up
+    st = cf_rollout(m, stream, 1, q, v, nullptr, qt, vt, nullptr, nullptr);  // warm-up
     (void)hipEventRecord(e0, s);
-    if (st == CF_OK) st = cf_rollout(m, stream, steps, q, v, nullptr, qt, vt, nullptr);
+    if (st == CF_OK) st = cf_rollout(m, stream, steps, q, v, nullptr, qt, vt, nullptr, nullptr);
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
     float ms = 0;

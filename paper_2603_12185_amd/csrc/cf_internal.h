@@ -100,6 +100,7 @@ struct ResolveArgs {
   int *x_geom, *x_sub;
   float *x_dist, *x_pos, *x_frame, *x_imp;
   float *x_feat, *x_target;     // learned-gain training data (free-body models)
+  int *x_fallback;              // learned gains: 1 where a contact fell back to the heuristic
   const float *mlp;             // learned-gain network parameters, or null
   const float4 *mlp_img;        // their LDS image (launch_mlp_pack), with mlp
   const float4 *act;            // [nv] position actuators (kp, kd, q index bits, -), or null
@@ -115,6 +116,7 @@ struct RolloutArgs {
   const float *tau_seq;         // [T][nw][nv] or null
   float *q_traj, *v_traj;       // [T+1][nw][..]; row 0 written by the host
   int *ncon_traj;               // [T][nw] contacts kept per step, or null
+  int *over_traj;               // [T][nw] contacts dropped beyond cap per step, or null
   int T, nworld, cap;           // cap: contacts held per world per step (= ncon_max)
 };
 

@@ -1479,10 +1479,12 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
 #pragma unroll
         for (int i = 0; i < NF; ++i) Gl[i] = A * __expf(fminf(fmaxf(lout[tid * mlp::NOUT + i], -mlp::CLIP), mlp::CLIP));
         facets(Gl, ll);
-        if (learned_ok<NF>(lam, ll, vn, phi, trs, P.h, P.mlp_margin)) {
+        const bool keep = learned_ok<NF>(lam, ll, vn, phi, trs, P.h, P.mlp_margin);
+        if (keep) {
 #pragma unroll
           for (int i = 0; i < NF; ++i) lam[i] = ll[i];
         }
+        if (a.x_fallback) a.x_fallback[xbase + k] = keep ? 0 : 1;
       }
       V3 f, tc = v3(0.f, 0.f, 0.f);
       if constexpr (CONDIM == 1) {
@@ -1734,6 +1736,7 @@ __global__ __launch_bounds__(BS) void rollout_kernel(RolloutArgs r) {
       c0p = cp[tid];
     }
     if (tid == 0 && r.ncon_traj) r.ncon_traj[(size_t)t * nw + w] = nc;
+    if (tid == 0 && r.over_traj) r.over_traj[(size_t)t * nw + w] = found - nc;
     __syncthreads();
     resolve_world<CONDIM, BS, ART>(ra, w, sq, sv, st, cn, cp, nc, c0n, c0p, mi0, reg, 0);
     float *qo = r.q_traj + ((size_t)(t + 1) * nw + w) * nq, *vo = r.v_traj + ((size_t)(t + 1) * nw + w) * nv;

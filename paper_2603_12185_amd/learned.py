@@ -56,6 +56,9 @@ def collect(model, q, v, steps, every=1, tau=None):
 def train(feats, targets, nout, steps=400, batch=65536, lr=3e-3, seed=0):
     """Adam on minibatches drawn from the rows; returns (net, losses)."""
     import torch
+    if feats.shape[0] == 0:
+        raise ValueError("no training rows: the step that was sampled had no contacts "
+                         "(let the scene settle into contact before collecting)")
     net = cfsim.ImpedanceNet(init_params(feats, seed))
     g = torch.Generator(device=feats.device)
     g.manual_seed(seed)
@@ -71,18 +74,22 @@ def train(feats, targets, nout, steps=400, batch=65536, lr=3e-3, seed=0):
 
 def penetration_stats(model, q, v, steps, tau=None):
     """Steps from (q, v) recording every contact's gap; returns the mean and the
-    maximum penetration (m) over all contacts and steps, the final state, and
-    the mean kinetic energy per world of the last step (for drift checks)."""
+    maximum penetration (m) over all contacts and steps, the final state, the
+    final velocities (for jitter checks) and, with the learned gains on, the
+    fraction of contacts that fell back to the heuristic (else None)."""
     import torch
-    tot, cnt, mx = 0.0, 0, 0.0
+    tot, cnt, mx, nfb = 0.0, 0, 0.0, 0
     for _ in range(steps):
         con = {"ncon": torch.zeros(model.nworld, dtype=torch.int32, device=q.device),
-               "dist": torch.zeros((model.nworld, model.ncon_max), dtype=torch.float32, device=q.device)}
+               "dist": torch.zeros((model.nworld, model.ncon_max), dtype=torch.float32, device=q.device),
+               "fallback": torch.zeros((model.nworld, model.ncon_max), dtype=torch.int32, device=q.device)}
         q, v = model.step(q, v, tau=tau, contacts=con)
         keep = torch.arange(model.ncon_max, device=q.device)[None, :] < con["ncon"].long()[:, None]
         pen = torch.clamp(-con["dist"][keep], min=0.0)
         tot += float(pen.sum())
         cnt += int(pen.numel())
+        nfb += int(con["fallback"][keep].sum())
         if pen.numel():
             mx = max(mx, float(pen.max()))
-    return tot / max(cnt, 1), mx, q, v
+    fb = nfb / max(cnt, 1) if getattr(model, "_net", None) is not None else None
+    return tot / max(cnt, 1), mx, q, v, fb

@@ -94,7 +94,7 @@ def test_unsupported_trees_are_reported(lib):
 def test_null_arguments(lib):
     assert lib.cf_model_create(None, None) == cfsim.CF_E_INVALID_ARG
     assert lib.cf_step(None, None, None, None, None, None, None, None) == cfsim.CF_E_INVALID_ARG
-    assert lib.cf_rollout(None, None, 1, None, None, None, None, None, None) == cfsim.CF_E_INVALID_ARG
+    assert lib.cf_rollout(None, None, 1, None, None, None, None, None, None, None) == cfsim.CF_E_INVALID_ARG
     assert lib.cf_model_dims(None, None, None, None) == cfsim.CF_E_INVALID_ARG
     lib.cf_model_destroy(None)
 

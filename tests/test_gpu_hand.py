@@ -81,7 +81,9 @@ def test_hand_rollout_matches_steps(torch_cuda):
     tau = tdev(_target_schedule(s, T, 10, 0.2, seed=4))
     q0, v0 = tdev(s["q0"]), tdev(s["v0"])
     ncon = torch.zeros((T, s["nworld"]), dtype=torch.int32, device="cuda")
-    qt, vt = model.rollout(T, q0, v0, tau_seq=tau, ncon_traj=ncon)
+    over = torch.full((T, s["nworld"]), -1, dtype=torch.int32, device="cuda")
+    qt, vt = model.rollout(T, q0, v0, tau_seq=tau, ncon_traj=ncon, overflow_traj=over)
+    assert int(over.abs().sum()) == 0, "contact capacity overflowed in the rollout"
     worst = 0.0
     for t in range(T):
         con = {"ncon": torch.zeros(s["nworld"], dtype=torch.int32, device="cuda")}

@@ -173,9 +173,9 @@ def test_trained_network_quiets_the_pile(torch_cuda):
     qe, ve = tdev(se["q0"]), tdev(se["v0"])
     for _ in range(400):
         qe, ve = me.step(qe, ve)
-    mp, xp, _, va = learned.penetration_stats(me, qe.clone(), ve.clone(), 200)
+    mp, xp, _, va, _ = learned.penetration_stats(me, qe.clone(), ve.clone(), 200)
     me.set_learned_impedance(net, margin=1e-4)
-    ml, xl, _, vb = learned.penetration_stats(me, qe.clone(), ve.clone(), 200)
+    ml, xl, _, vb, _ = learned.penetration_stats(me, qe.clone(), ve.clone(), 200)
     kp = float((va.reshape(256, 64, 6)[:, :, 0:3] ** 2).sum(-1).mean())
     kl = float((vb.reshape(256, 64, 6)[:, :, 0:3] ** 2).sum(-1).mean())
     print(f"mean penetration plain {mp * 1e3:.4f} mm learned {ml * 1e3:.4f} mm; "

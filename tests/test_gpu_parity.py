@@ -291,6 +291,37 @@ def test_empty_and_overflow_edge_cases(torch_cuda):
             assert (con["overflow"] > 0).all()
 
 
+def test_rollout_reports_overflow(torch_cuda):
+    """cf_rollout counts, per step and world, the contacts dropped beyond
+    ncon_max exactly as cf_step does: sunk spheres with a small capacity, on
+    the persistent kernel and on step launches (a capacity too large for the
+    persistent kernel's LDS)."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    s2 = scenes.dense_pile(nworld=3, nsphere=32, seed=2)
+    s2["q0"].reshape(3, 32, 7)[:, :, 2] = 0.01
+    T = 4
+    for cm, fused in ((5, True), (40, True), (4000, False)):
+        sc = scenes.with_params(s2, ncon_max=cm)
+        if cm == 4000:
+            sc["q0"].reshape(3, 32, 7)[:, :, 2] = 0.01  # same sunk state, capacity never reached
+        model = cfsim.Model(sc)
+        assert model.get_launch()[3] == fused
+        q0, v0 = tdev(sc["q0"]), tdev(sc["v0"])
+        nct = torch.full((T, 3), -1, dtype=torch.int32, device="cuda")
+        ovt = torch.full((T, 3), -1, dtype=torch.int32, device="cuda")
+        qt, vt = model.rollout(T, q0, v0, ncon_traj=nct, overflow_traj=ovt)
+        for t in range(T):
+            con = {"ncon": torch.zeros(3, dtype=torch.int32, device="cuda"),
+                   "overflow": torch.zeros(3, dtype=torch.int32, device="cuda")}
+            model.step(qt[t].clone(), vt[t].clone(), contacts=con)
+            assert torch.equal(con["ncon"], nct[t]) and torch.equal(con["overflow"], ovt[t]), (cm, t)
+        if cm < 100:
+            assert (ovt > 0).all() and (nct == cm).all()
+        else:
+            assert (ovt == 0).all() and (nct > 40).all()
+
+
 def test_in_place_update_and_determinism(torch_cuda):
     """q_out/v_out aliasing q/v gives the same bits as separate outputs; two
     runs from the same state are bitwise identical."""
@@ -321,7 +352,9 @@ def _rollout_vs_steps(torch, model, s, T, tau=None):
     trajectories and per-step contact counts."""
     q0, v0 = tdev(s["q0"]), tdev(s["v0"])
     ncon = torch.zeros((T, s["nworld"]), dtype=torch.int32, device="cuda")
-    qt, vt = model.rollout(T, q0, v0, tau_seq=tau, ncon_traj=ncon)
+    over = torch.full((T, s["nworld"]), -1, dtype=torch.int32, device="cuda")
+    qt, vt = model.rollout(T, q0, v0, tau_seq=tau, ncon_traj=ncon, overflow_traj=over)
+    assert int(over.abs().sum()) == 0, "contact capacity overflowed in the rollout"
     q, v = q0, v0
     worst = 0.0
     for t in range(T):
