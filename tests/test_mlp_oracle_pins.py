@@ -68,3 +68,57 @@ def test_first_adam_step_moves_by_lr_times_sign():
     s = slice(mlp.TRAIN_FROM, mlp.NPARAM)
     np.testing.assert_allclose(p1[s] - p[s], -1e-3 * g[s] / (np.abs(g[s]) + 1e-8), rtol=1e-12)
     np.testing.assert_array_equal(p1[:mlp.TRAIN_FROM], p[:mlp.TRAIN_FROM])
+
+
+def test_forward_of_a_hand_worked_network():
+    """A network with three active hidden units, worked out by hand from the
+    stated definition (normalise, two SiLU layers, linear output; weights
+    W[in][out]): pins the normalisation, SiLU after each hidden layer and not
+    after the output, the layout of every weight matrix and bias, and that the
+    eighth (padding) feature is ignored."""
+    import math
+    sig = lambda z: 1.0 / (1.0 + math.exp(-z))
+    silu = lambda z: z * sig(z)
+    mean = [-2e-3, 0.01, -0.02, 0.03, 0.2, 0.6, 0.002, 0.0]
+    std = [1e-3, 0.05, 0.1, 0.2, 0.1, 0.25, 1.0, 1.0]
+    p = np.zeros(mlp.NPARAM)
+    p[mlp.OFF_MEAN:mlp.OFF_STD] = mean
+    p[mlp.OFF_STD:mlp.OFF_W1] = std
+    W1 = np.zeros((mlp.NIN, mlp.NH))
+    W1[0, 3], W1[4, 3], W1[2, 9] = 0.7, -1.2, 0.5
+    b1 = np.zeros(mlp.NH)
+    b1[3], b1[9] = 0.1, -0.3
+    W2 = np.zeros((mlp.NH, mlp.NH))
+    W2[3, 5], W2[9, 5], W2[9, 60] = 1.5, -0.8, 2.0
+    b2 = np.zeros(mlp.NH)
+    b2[5], b2[60] = 0.05, -0.2
+    W3 = np.zeros((mlp.NH, mlp.NOUT))
+    W3[5, 0], W3[60, 0], W3[60, 3] = 0.9, -0.4, 1.1
+    b3 = 0.01 * np.arange(mlp.NOUT)
+    b3[0], b3[3] = 0.2, -0.1
+    p[mlp.OFF_W1:mlp.OFF_B1] = W1.ravel()
+    p[mlp.OFF_B1:mlp.OFF_W2] = b1
+    p[mlp.OFF_W2:mlp.OFF_B2] = W2.ravel()
+    p[mlp.OFF_B2:mlp.OFF_W3] = b2
+    p[mlp.OFF_W3:mlp.OFF_B3] = W3.ravel()
+    p[mlp.OFF_B3:] = b3
+    feats = np.array([[-3.5e-3, 0.04, 0.13, -0.05, 0.31, 0.45, 0.002, 7.0],
+                      [1.0e-3, -0.02, -0.27, 0.11, 0.05, 0.95, 0.002, -3.0]])
+    y, _ = mlp.forward(p, feats)
+    for r, f in enumerate(feats):
+        x0 = (f[0] - mean[0]) / std[0]
+        x2 = (f[2] - mean[2]) / std[2]
+        x4 = (f[4] - mean[4]) / std[4]
+        a13 = silu(0.7 * x0 - 1.2 * x4 + 0.1)
+        a19 = silu(0.5 * x2 - 0.3)
+        a25 = silu(1.5 * a13 - 0.8 * a19 + 0.05)
+        a260 = silu(2.0 * a19 - 0.2)
+        expect = 0.01 * np.arange(mlp.NOUT)
+        expect[0] = 0.9 * a25 - 0.4 * a260 + 0.2
+        expect[3] = 1.1 * a260 - 0.1
+        np.testing.assert_allclose(y[r], expect, rtol=1e-14, atol=1e-15)
+    # every hidden unit without weights sits at silu(0) = 0: a bias on an
+    # unused first-layer unit does not reach the output
+    p2 = p.copy()
+    p2[mlp.OFF_B1 + 20] = 3.0
+    np.testing.assert_array_equal(mlp.forward(p2, feats)[0], y)

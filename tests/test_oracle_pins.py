@@ -396,15 +396,64 @@ def test_torsional_stick_decay(condim):
     q, v = s["q0"].astype(float), s["v0"].astype(float)
     w0 = v[0, 5]
     for n in range(1, 50):
+        w_before = v[0, 5]
         q, v, out = o.step(q, v)
         assert out["impulse"][0, 0, 4] > 0 and out["impulse"][0, 0, 5] > 0
+        # facet order and sign: sigma = +1 first, lambda(+) - lambda(-) = 2 A a mu_tor (n . w)
+        np.testing.assert_allclose(out["impulse"][0, 0, 4] - out["impulse"][0, 0, 5],
+                                   2 * (rho_star(s) * m / 3) * a * mu_tor * w_before, rtol=1e-9)
         np.testing.assert_allclose(v[0, 5], fac ** n * w0, rtol=1e-11)
         np.testing.assert_allclose(v[0, 3:5], 0, atol=1e-14)
 
 
+@pytest.mark.parametrize("direction", [(1.0, 0.0), (0.6, -0.8)])
+def test_rolling_stick_decay(direction):
+    """Rolling facets alone (condim 6, mu_t = mu_tor = 0): a sphere resting on
+    the plane with angular velocity w in the tangent plane.  With mu_t = 0 the
+    tangential and torsional facets are plain normal rows, so no tangential
+    force acts and nothing but the rolling couple -mu_rol sum_f lambda_f d_f
+    turns the sphere (its torque about the COM from forces along n vanishes).
+    While all four rolling facets are active, lambda_(+d) - lambda_(-d) =
+    2 A a mu_rol (d . w) for d = t1, t2 (Eq. cf_wrench), so every tangential
+    direction decays by the same factor per step:
+    w_{n+1} = (1 - 2 A a mu_rol^2 / I) w_n, A = rho* m / 3, while the normal
+    spin, the linear velocity and the normal state are untouched by w."""
+    R, mu_rol = 0.05, 0.01
+    s = scenes.sphere_on_plane(radius=R, mu=(0.0, 0.0, mu_rol), condim=6)
+    R = s["geom_size"][0, 1, 0]
+    mu_rol = s["geom_friction"][0, 1, 2]
+    s["q0"][0, 2] = R - steady_depth(s, 10)
+    w0 = 8.0 * np.array(direction)
+    s["v0"][0, 3:5] = w0
+    s["v0"][0, 0:2] = (0.3, -0.2)  # free tangential slip (mu_t = 0)
+    o = Oracle(s)
+    a = s["k_user"] * s["h"] + s["d_user"]
+    m, I = s["body_mass"][0, 0], s["body_inertia"][0, 0, 0]
+    fac = 1 - 2 * (rho_star(s) * m / 3) * a * mu_rol ** 2 / I
+    assert 0.99 < fac < 1
+    q, v = s["q0"].astype(float), s["v0"].astype(float)
+    w_start = v[0, 3:5].copy()
+    vt = v[0, 0:2].copy()
+    A = rho_star(s) * m / 3
+    for n in range(1, 60):
+        w_before = v[0, 3:5].copy()
+        q, v, out = o.step(q, v)
+        assert out["ncon"][0] == 1 and (out["impulse"][0, 0, 6:10] > 0).all()
+        # facet order and sign (t1 = +x, t2 = +y here): lambda(+d) - lambda(-d) = 2 A a mu_rol (d . w)
+        lam = out["impulse"][0, 0]
+        np.testing.assert_allclose(out["frame"][0, 0, 3:9], [1, 0, 0, 0, 1, 0], atol=1e-15)
+        np.testing.assert_allclose([lam[6] - lam[8], lam[7] - lam[9]], 2 * A * a * mu_rol * w_before,
+                                   rtol=1e-9, atol=1e-18)
+        assert -out["dist"][0, 0] >= s["solimp"][2]  # |phi| >= w: rho = rho*
+        np.testing.assert_allclose(v[0, 3:5], fac ** n * w_start, rtol=1e-11, atol=1e-15)
+        assert abs(v[0, 5]) < 1e-15
+        np.testing.assert_allclose(v[0, 0:2], vt, rtol=1e-13, atol=1e-15)
+
+
 def test_rolling_friction_decays_monotonically():
-    """Rolling sphere (condim 6): speed decays monotonically and faster with larger mu_rol.
-    (Exact rolling decay is not pinned.)"""
+    """Rolling sphere (condim 6) with tangential friction: speed decays
+    monotonically and faster with larger mu_rol (the exact stick-regime decay
+    of the rolling facets alone is pinned by test_rolling_stick_decay)."""
     finals = []
     for mu_rol in (0.0, 0.002, 0.005):
         R = 0.05
