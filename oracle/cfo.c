@@ -53,6 +53,18 @@
  *    k_user : d_user / h of Eq. k_d_setting, so the scalar A of the impulse
  *    becomes A_f = 1 / ((k_user h + d_user) g_f), g_f = J~_f M^-1 J~_f^T; r(|phi|)
  *    does not enter.  With k_user h + d_user = 0 or g_f = 0 the impulse is 0.
+ *  - Learned gains (option; Sec. III.B allows a learned K, D, the network is
+ *    this build's design): per contact the network's output y_f scales the
+ *    heuristic gain, A_f = A exp(clip(y_f, -ln 256, ln 256)).  Fallback rule
+ *    (also this build's design): the contact alone along its normal with
+ *    inverse mass w = (tr_a + tr_b) / 3 (1/m_a + 1/m_b for free bodies); the
+ *    normal velocity after the heuristic's impulses is v_h = v_n + w sum_f
+ *    lambda_h,f, after the learned ones v_l likewise; the next-step
+ *    penetration max(-(phi + h v_x), 0) and the normal kinetic energy
+ *    v_x^2 / (2 w) of each; the learned impulses are kept iff the learned
+ *    penetration is at most the heuristic's plus the margin delta, the
+ *    learned energy at most the heuristic's plus (delta/h)^2 / (2 w), and v_l
+ *    is finite; a contact with tr_a + tr_b = 0 keeps the heuristic.
  *  - Integration: semi-implicit Euler; free-joint orientation is updated by the
  *    exact exponential of h*omega (world frame, left-multiplied) then
  *    normalised; a state quaternion denotes the rotation of its normalised value.
@@ -74,6 +86,8 @@ struct cfo_model {
   double *geom_size, *geom_pos, *geom_quat, *geom_friction;
   double *dof_kp, *dof_kd; /* [nv], NULL without actuators */
   int *dof_q;              /* [nv] q index of an actuated dof, -1 otherwise */
+  const double *learned_y; /* [nworld][ncon_max][16] network outputs, or NULL */
+  double learned_margin;   /* fallback margin (m) */
 };
 
 /* ------------------------------------------------------------------ */
@@ -731,8 +745,9 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
   double *tr = (double *)calloc(nb ? nb : 1, sizeof(double));
   double *rows = (double *)malloc(sizeof(double) * 16 * (nv ? nv : 1)); /* Jn, Jt1, Jt2, Jtor, Jr1, Jr2, facet, scratch */
   double *Jp = (double *)malloc(sizeof(double) * 6 * (nv ? nv : 1));
+  double *Jfs = (double *)malloc(sizeof(double) * 10 * (nv ? nv : 1)); /* the contact's facet rows */
   contact_t *con = (contact_t *)malloc(sizeof(contact_t) * (size_t)(d->ncon_max > 0 ? d->ncon_max : 1));
-  if (!M || !c || !vs || !p || !tr || !rows || !Jp || !con) { rc = CFO_ENOMEM; goto done; }
+  if (!M || !c || !vs || !p || !tr || !rows || !Jp || !Jfs || !con) { rc = CFO_ENOMEM; goto done; }
 
   /* --- M(q), c(q,v), Cholesky --- */
   mass_matrix(m, w, f, Jall, M);
@@ -808,7 +823,7 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
       }
     }
     double *Jn = rows, *Jt1 = rows + nv, *Jt2 = rows + 2 * nv, *Jtor = rows + 3 * nv;
-    double *Jr1 = rows + 4 * nv, *Jr2 = rows + 5 * nv, *Jf = rows + 6 * nv;
+    double *Jr1 = rows + 4 * nv, *Jr2 = rows + 5 * nv;
     for (int i = 0; i < nv; i++) {
       double lv[3] = {Jp[i], Jp[nv + i], Jp[2 * nv + i]}, av[3] = {Jp[3 * nv + i], Jp[4 * nv + i], Jp[5 * nv + i]};
       Jn[i] = dot3(C->n, lv); Jt1[i] = dot3(t1, lv); Jt2[i] = dot3(t2, lv);
@@ -822,8 +837,9 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
     /* M(phi) scalar: r/(1-r) / (tr_a + tr_b) */
     double A = trs > 0 ? cfo_impedance_ratio(m, C->phi) / trs : 0.0;
     static const double dir4[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
-    double lam[10], gain[10];
+    double lam[10], gain[10], args[10];
     for (int fi = 0; fi < nf; fi++) {
+      double *Jf = Jfs + (size_t)fi * nv;
       /* facet row J~ = J_n - mu_s d^T J_s */
       for (int i = 0; i < nv; i++) {
         double row = Jn[i];
@@ -858,8 +874,42 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
         lh = arg > 0 ? gain[fi] * arg : 0.0;
       }
       lam[fi] = lh;
-      for (int i = 0; i < nv; i++) p[i] += Jf[i] * lh;
+      args[fi] = arg;
     }
+    double vn = 0, u1 = 0, u2 = 0;
+    for (int i = 0; i < nv; i++) { vn += Jn[i] * vs[i]; u1 += Jt1[i] * vs[i]; u2 += Jt2[i] * vs[i]; }
+    int fell_back = 1;
+    double slack[2] = {0, 0};
+    if (m->learned_y && d->impedance == 0) {
+      /* learned gains and the fallback rule (readings above) */
+      const double *y = m->learned_y + (cbase + k) * 16;
+      const double L256 = log(256.0);
+      double ll[10], gl[10], Sh = 0, Sl = 0;
+      for (int fi = 0; fi < nf; fi++) {
+        double yf = y[fi] < -L256 ? -L256 : y[fi] > L256 ? L256 : y[fi];
+        gl[fi] = trs > 0 ? A * exp(yf) : 0.0;
+        ll[fi] = args[fi] > 0 ? gl[fi] * args[fi] : 0.0;
+        Sh += lam[fi];
+        Sl += ll[fi];
+      }
+      if (trs > 0) {
+        double wi = trs / 3.0, delta = m->learned_margin;
+        double v_h = vn + wi * Sh, v_l = vn + wi * Sl;
+        double pen_h = -(C->phi + h * v_h), pen_l = -(C->phi + h * v_l);
+        if (pen_h < 0) pen_h = 0;
+        if (pen_l < 0) pen_l = 0;
+        double e_h = 0.5 * v_h * v_h / wi, e_l = 0.5 * v_l * v_l / wi;
+        double e_m = 0.5 * (delta / h) * (delta / h) / wi;
+        slack[0] = pen_h + delta - pen_l;
+        slack[1] = e_h + e_m - e_l;
+        if (slack[0] >= 0 && slack[1] >= 0 && isfinite(v_l)) {
+          fell_back = 0;
+          for (int fi = 0; fi < nf; fi++) { lam[fi] = ll[fi]; gain[fi] = gl[fi]; }
+        }
+      }
+    }
+    for (int fi = 0; fi < nf; fi++)
+      for (int i = 0; i < nv; i++) p[i] += Jfs[(size_t)fi * nv + i] * lam[fi];
     if (out) {
       size_t ci = cbase + k;
       if (out->geom) { out->geom[2 * ci] = C->ga; out->geom[2 * ci + 1] = C->gb; }
@@ -873,6 +923,15 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
       }
       if (out->impulse) memcpy(out->impulse + (size_t)nf * ci, lam, sizeof(double) * nf);
       if (out->facet_gain) memcpy(out->facet_gain + (size_t)nf * ci, gain, sizeof(double) * nf);
+      if (out->features) {
+        double *fe = out->features + 8 * ci;
+        fe[0] = C->phi; fe[1] = vn; fe[2] = u1; fe[3] = u2;
+        fe[4] = trs > 0 ? 1.0 / trs : 0.0; fe[5] = mu[0]; fe[6] = h; fe[7] = 0.0;
+      }
+      if (m->learned_y && d->impedance == 0) {
+        if (out->fallback) out->fallback[ci] = fell_back;
+        if (out->fallback_slack) { out->fallback_slack[2 * ci] = slack[0]; out->fallback_slack[2 * ci + 1] = slack[1]; }
+      }
     }
   }
 
@@ -915,8 +974,16 @@ static int step_world(const cfo_model *m, int w, const double *q, const double *
   }
   rc = CFO_OK;
 done:
-  free(f); free(Jall); free(M); free(c); free(vs); free(p); free(tr); free(rows); free(Jp); free(con);
+  free(f); free(Jall); free(M); free(c); free(vs); free(p); free(tr); free(rows); free(Jp); free(Jfs); free(con);
   return rc;
+}
+
+int cfo_set_learned(cfo_model *m, const double *y, double margin) {
+  if (!m || !(margin >= 0)) return CFO_EINVAL;
+  if (y && m->d.impedance != 0) return CFO_EINVAL;
+  m->learned_y = y;
+  m->learned_margin = margin;
+  return CFO_OK;
 }
 
 int cfo_step(const cfo_model *m, int w0, int w1, const double *q, const double *v, const double *tau,

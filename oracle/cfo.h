@@ -77,6 +77,12 @@ typedef struct {
   double *gen_impulse;              /* [nworld][nv] p = sum J~^T lambda h         */
   double *trace;                    /* [nworld][nbody] tr(J_b M^-1 J_b^T)          */
   double *facet_gain;               /* [..][nfacet] A_f with lambda_f h = A_f max(arg_f, 0) */
+  double *features;                 /* [..][8] learned-gain features: phi, v_n, u_1, u_2,
+                                       m_eff = 1/(tr_a + tr_b), mu_t, h, 0 (at v_s)   */
+  int *fallback;                    /* [..] with learned gains set: 1 where the contact
+                                       kept the heuristic, 0 where the learned gains  */
+  double *fallback_slack;           /* [..][2] with learned gains set: penetration and
+                                       energy slack of the fallback rule (>= 0: kept) */
 } cfo_out;
 
 int  cfo_create(const cfo_desc *d, cfo_model **out, char *err, int errlen);
@@ -87,6 +93,15 @@ void cfo_dims(const cfo_model *m, int *nq, int *nv, int *nfacet);
  * q_out, v_out are full-size arrays; only the rows of the range are touched. */
 int cfo_step(const cfo_model *m, int w0, int w1, const double *q, const double *v,
              const double *tau, double *q_out, double *v_out, const cfo_out *out);
+
+/* Learned impedance gains (Sec. III.B lets K and D be learned; the network is
+ * the build's, oracle/mlp.py).  y: [nworld][ncon_max][16] network outputs of
+ * every contact in canonical order (the caller evaluates the network on the
+ * features a plain step of the same state exports), or NULL to switch the
+ * option off; read by cfo_step, owned by the caller.  Each facet gain of the
+ * heuristic becomes A exp(clip(y_f, -ln 256, ln 256)) unless the fallback rule
+ * (cfo.c) keeps the heuristic for the contact.  Heuristic impedance only. */
+int cfo_set_learned(cfo_model *m, const double *y, double margin);
 
 /* Building blocks, exposed for the closed-form tests (world w, state q/v of that world). */
 int cfo_body_frames(const cfo_model *m, int w, const double *q, double *com /*[nb][3]*/,

@@ -44,7 +44,8 @@ class _Out(C.Structure):
         ("ncon", _ip), ("overflow", _ip), ("geom", _ip), ("sub", _ip),
         ("dist", _dp), ("pos", _dp), ("frame", _dp), ("impulse", _dp),
         ("guard_phi", _dp), ("guard_frame", _dp), ("v_smooth", _dp), ("gen_impulse", _dp),
-        ("trace", _dp), ("facet_gain", _dp),
+        ("trace", _dp), ("facet_gain", _dp), ("features", _dp), ("fallback", _ip),
+        ("fallback_slack", _dp),
     ]
 
 
@@ -86,6 +87,8 @@ def lib():
             L.cfo_impedance_ratio.restype = C.c_double
             L.cfo_gamma.argtypes = [C.c_void_p, C.c_double]
             L.cfo_gamma.restype = C.c_double
+            L.cfo_set_learned.argtypes = [C.c_void_p, _dp, C.c_double]
+            L.cfo_set_learned.restype = C.c_int
             _lib = L
     return _lib
 
@@ -159,12 +162,37 @@ class Oracle:
             self._h = None
 
     # ---------------------------------------------------------------- step
-    def step(self, q, v, tau=None, worlds=None, outputs=True):
+    def step(self, q, v, tau=None, worlds=None, outputs=True, learned=None):
         """One step of every world (or of the range/list `worlds`).
 
         Returns (q_out, v_out, out) with float64 arrays; out holds the contact
         list, facet impulses, guards and intermediates when outputs=True.
+        learned = (params, margin) or (params, margin, operands): the learned
+        impedance gains of the network `params` (oracle/mlp.py layout) with the
+        fallback margin (m): a plain step of the same state exports each
+        contact's features, the network maps them to its outputs (in float64,
+        or with operands="bf16" at a bf16 matrix unit's operand precision), and
+        the step is taken again with them; out["learned_y"] holds the outputs.
         """
+        if learned is None:
+            return self._step(q, v, tau, worlds, outputs)
+        from oracle import mlp
+        params, margin = learned[0], learned[1]
+        operands = learned[2] if len(learned) > 2 else None
+        _, _, o1 = self._step(q, v, tau, worlds, True)
+        y, _ = mlp.forward(params, o1["features"].reshape(-1, mlp.NIN), operands=operands)
+        y = np.ascontiguousarray(y.reshape(self.nworld, self.ncon_max, mlp.NOUT))
+        L = lib()
+        if L.cfo_set_learned(self._h, _d(y), float(margin)) != 0:
+            raise OracleError("cfo_set_learned failed (heuristic impedance only, margin >= 0)")
+        try:
+            qo, vo, out = self._step(q, v, tau, worlds, True)
+        finally:
+            L.cfo_set_learned(self._h, None, 0.0)
+        out["learned_y"] = y
+        return qo, vo, out
+
+    def _step(self, q, v, tau, worlds, outputs):
         nw, nq, nv = self.nworld, self.nq, self.nv
         q = np.ascontiguousarray(q, np.float64).reshape(nw, nq)
         v = np.ascontiguousarray(v, np.float64).reshape(nw, nv)
@@ -180,12 +208,13 @@ class Oracle:
                 impulse=np.zeros((nw, cm, nf)), guard_phi=np.full(nw, np.inf),
                 guard_frame=np.full(nw, np.inf), v_smooth=np.zeros((nw, nv)),
                 gen_impulse=np.zeros((nw, nv)), trace=np.zeros((nw, self.nbody)),
-                facet_gain=np.zeros((nw, cm, nf)))
+                facet_gain=np.zeros((nw, cm, nf)), features=np.zeros((nw, cm, 8)),
+                fallback=np.full((nw, cm), -1, np.int32), fallback_slack=np.zeros((nw, cm, 2)))
             o = _Out()
-            for k in ("ncon", "overflow", "geom", "sub"):
+            for k in ("ncon", "overflow", "geom", "sub", "fallback"):
                 setattr(o, k, _i(out[k]))
             for k in ("dist", "pos", "frame", "impulse", "guard_phi", "guard_frame", "v_smooth",
-                      "gen_impulse", "trace", "facet_gain"):
+                      "gen_impulse", "trace", "facet_gain", "features", "fallback_slack"):
                 setattr(o, k, _d(out[k]))
         if worlds is None:
             ranges = [(0, nw)]

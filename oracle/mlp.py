@@ -81,18 +81,71 @@ def init_params(feats, seed=0):
     return p
 
 
-def forward(p, feats):
-    """Outputs y [n][16] and the intermediates."""
+def bf16(a):
+    """Round to bfloat16 (round to nearest, ties to even) through float32, the
+    way a float32 operand is narrowed for a bf16 matrix product; returned as
+    float64 values."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _bf16_neighbours(r):
+    """The bf16 values next to |r| above and below (|r| itself a bf16 value;
+    for 0 both are the smallest positive bf16 value)."""
+    bits = np.abs(r).astype(np.float32).view(np.uint32).astype(np.int64)
+    up = (bits + 0x10000).astype(np.uint32).view(np.float32).astype(np.float64)
+    dn = np.where(bits > 0, bits - 0x10000, bits + 0x10000).astype(np.uint32).view(np.float32)
+    return up, dn.astype(np.float64)
+
+
+def bf16_tie_distance(a):
+    """Distance of each value to the nearest point where its bf16 rounding
+    changes (the midpoints to the neighbouring bf16 values)."""
+    a = np.abs(np.asarray(a, np.float64))
+    r = bf16(a)
+    up, dn = _bf16_neighbours(r)
+    return np.minimum(np.abs(a - 0.5 * (r + up)), np.abs(a - 0.5 * (r + dn)))
+
+
+def bf16_spacing(a):
+    """Larger of the gaps from bf16(a) to its two neighbouring bf16 values."""
+    r = np.abs(bf16(a))
+    up, dn = _bf16_neighbours(r)
+    return np.maximum(up - r, np.abs(r - dn))
+
+
+def forward(p, feats, operands=None):
+    """Outputs y [n][16] and the intermediates.
+
+    operands="bf16" evaluates the same network at the precision of a bf16
+    matrix unit: the normalised inputs, the weights and the two hidden
+    activations are rounded to bf16 before each product, products and sums
+    stay in float64, biases are not rounded.  The intermediates then also hold
+    the values before each rounding (x_pre, a1_pre, a2_pre)."""
     P = unpack(p)
     f = np.zeros((len(feats), NIN))
     f[:, :NFEAT] = np.asarray(feats, np.float64)[:, :NFEAT]
     x = (f - P["mean"]) / P["std"]
-    z1 = x @ P["W1"] + P["b1"]
+    if operands is None:
+        z1 = x @ P["W1"] + P["b1"]
+        a1 = silu(z1)
+        z2 = a1 @ P["W2"] + P["b2"]
+        a2 = silu(z2)
+        y = a2 @ P["W3"] + P["b3"]
+        return y, dict(x=x, z1=z1, a1=a1, z2=z2, a2=a2)
+    if operands != "bf16":
+        raise ValueError("operands must be None or 'bf16'")
+    xb = bf16(x)
+    xb[:, NFEAT:] = 0.0
+    z1 = xb @ bf16(P["W1"]) + P["b1"]
     a1 = silu(z1)
-    z2 = a1 @ P["W2"] + P["b2"]
+    a1b = bf16(a1)
+    z2 = a1b @ bf16(P["W2"]) + P["b2"]
     a2 = silu(z2)
-    y = a2 @ P["W3"] + P["b3"]
-    return y, dict(x=x, z1=z1, a1=a1, z2=z2, a2=a2)
+    a2b = bf16(a2)
+    y = a2b @ bf16(P["W3"]) + P["b3"]
+    return y, dict(x=xb, z1=z1, a1=a1b, z2=z2, a2=a2b, x_pre=x, a1_pre=a1, a2_pre=a2)
 
 
 def loss_and_grad(p, feats, targets, nout):

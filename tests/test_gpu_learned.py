@@ -10,6 +10,14 @@ and the training data the step exports.
     keeps the heuristic everywhere: the facet impulses equal the plain step's
     bit for bit;
   * exported features and targets equal what the oracle's own step implies;
+  * element-wise parity with the oracle's learned-gain step (the network's
+    outputs scale each facet, then the fallback rule): a network of output
+    biases alone, different on every facet, with the fallback off (exact y on
+    both sides: standard tolerances); the same with a margin at which some
+    contacts fall back and some do not (per-contact decisions bit-equal outside
+    a guard band); a network trained by the oracle's own FP64 Adam (decisions
+    bit-equal outside a guard band derived from the bf16 error bound of the
+    network's output, impulses and velocities within that bound);
   * a network trained on the GPU on exported data lowers the kinetic jitter
     of a held-out dense pile without raising its mean penetration.
 """
@@ -43,6 +51,18 @@ def _const_net(c):
     p[mlp.OFF_STD:mlp.OFF_W1] = 1.0
     p[mlp.OFF_B3:] = c
     return cfsim.ImpedanceNet(p)
+
+
+def _bias_params(b3):
+    p = np.zeros(mlp.NPARAM)
+    p[mlp.OFF_STD:mlp.OFF_W1] = 1.0
+    p[mlp.OFF_B3:mlp.OFF_B3 + len(b3)] = b3
+    return p
+
+
+def _net(params):
+    from paper_2603_12185_amd import cfsim
+    return cfsim.ImpedanceNet(np.asarray(params, np.float32))
 
 
 def _oracle_state(s, n):
@@ -182,3 +202,265 @@ def test_trained_network_quiets_the_pile(torch_cuda):
           f"max {xp * 1e3:.3f} / {xl * 1e3:.3f} mm; mean |v|^2 {kp:.3e} / {kl:.3e}")
     assert ml <= mp * 1.01
     assert kl < kp
+
+
+def _learned_scenes():
+    return [("mixed3", scenes.mixed_shapes(nworld=4, seed=41, condim=3), 120),
+            ("mixed6", scenes.mixed_shapes(nworld=4, seed=42, condim=6), 120),
+            ("pile", scenes.dense_pile(nworld=4, nsphere=64, seed=5), 300)]
+
+
+B3 = np.array([0.75, -0.5, 1.25, -1.0, 0.5, -0.25, 1.5, -1.5, 0.25, 0.125, 0, 0, 0, 0, 0, 0])
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_distinct_bias_network_matches_oracle(torch_cuda, which):
+    """Output biases alone, a different one on every facet, fallback off (a
+    margin of 1 km): each facet's gain is exp(b3_f) times the heuristic's on
+    both sides (y is exact in float32), so the step matches the oracle's
+    learned step at the standard tolerances, and no contact falls back."""
+    from paper_2603_12185_amd import cfsim
+    name, s, n = _learned_scenes()[which]
+    q, v = _oracle_state(s, n)
+    model = cfsim.Model(s)
+    params = _bias_params(B3)
+    model.set_learned_impedance(_net(params), margin=1e3)
+    con = model.alloc_contacts()
+    con["fallback"] = con["ncon"].new_full((s["nworld"], s["ncon_max"]), -1)
+    q1, v1 = model.step(tdev(q), tdev(v), contacts=con)
+    c = to_np(con)
+    stats = compare_step(s, Oracle(s), q, v, None, q1.cpu().numpy(), v1.cpu().numpy(), c,
+                         learned=(params, 1e3))
+    print(name, stats)
+    assert stats["contacts"] > 10 and stats["checked"] >= s["nworld"] - 1
+    for w in range(s["nworld"]):
+        assert (c["fallback"][w, :c["ncon"][w]] == 0).all()
+
+
+def _slack_robust(out, w, n, band0, band1):
+    """Contacts whose fallback decision no perturbation within (band0, band1)
+    of the two slacks can flip."""
+    s0, s1 = out["fallback_slack"][w, :n, 0], out["fallback_slack"][w, :n, 1]
+    keep = (s0 >= 0) & (s1 >= 0)
+    return np.where(keep, (s0 > band0) & (s1 > band1), (s0 < -band0) | (s1 < -band1))
+
+
+@pytest.mark.parametrize("which", [0, 2])
+def test_fallback_decisions_match_oracle(torch_cuda, which):
+    """Output biases alone with a margin at which some contacts keep the
+    learned gains and others fall back: per-contact decisions equal the
+    oracle's, and the step matches at the standard tolerances, in every world
+    whose contacts all sit outside a guard band of the rule's two slacks
+    (1e-6 of the penetration terms, 1e-4 of the energy terms: float32 against
+    float64 arithmetic of the same rule)."""
+    from paper_2603_12185_amd import cfsim
+    name, s, n = _learned_scenes()[which]
+    q, v = _oracle_state(s, n)
+    o = Oracle(s)
+    params = _bias_params(B3)
+    # the margin whose fallback fraction is nearest one half, on the oracle
+    best = None
+    for margin in (1e-7, 1e-6, 1e-5, 3e-5, 1e-4, 3e-4, 1e-3):
+        _, _, out = o.step(q, v, learned=(params, margin))
+        dec = np.concatenate([out["fallback"][w, :out["ncon"][w]] for w in range(s["nworld"])])
+        frac = float(dec.mean())
+        if best is None or abs(frac - 0.5) < abs(best[1] - 0.5):
+            best = (margin, frac, out)
+    margin, frac, out = best
+    print(name, "margin", margin, "fallback fraction (oracle)", frac)
+    assert 0.1 < frac < 0.9
+    model = cfsim.Model(s)
+    model.set_learned_impedance(_net(params), margin=margin)
+    con = model.alloc_contacts()
+    con["fallback"] = con["ncon"].new_full((s["nworld"], s["ncon_max"]), -1)
+    q1, v1 = model.step(tdev(q), tdev(v), contacts=con)
+    c = to_np(con)
+    worlds, compared, guarded = [], 0, 0
+    for w in range(s["nworld"]):
+        nc = int(out["ncon"][w])
+        assert int(c["ncon"][w]) == nc
+        h = s["h"]
+        vscale = max(np.abs(out["v_smooth"][w]).max(initial=0.0), 9.81 * h)
+        band0 = 1e-6 * (margin + h * vscale) + 1e-9
+        e_scale = np.abs(out["fallback_slack"][w, :nc, 1]).max(initial=0.0)
+        band1 = 1e-4 * max(e_scale, 1e-12)
+        ok = _slack_robust(out, w, nc, band0, band1)
+        np.testing.assert_array_equal(c["fallback"][w, :nc][ok], out["fallback"][w, :nc][ok],
+                                      err_msg=f"world {w}: fallback decisions")
+        compared += int(ok.sum())
+        guarded += int((~ok).sum())
+        if ok.all():
+            worlds.append(w)
+    print(name, "decisions compared", compared, "guarded", guarded, "worlds checked", worlds)
+    assert compared > 10 and guarded <= max(2, compared // 20)
+    stats = compare_step(s, o, q, v, None, q1.cpu().numpy(), v1.cpu().numpy(), c, worlds=worlds,
+                         learned=(params, margin))
+    print(name, stats)
+    assert stats["checked"] >= 1
+
+
+def _oracle_training_data(s, q, v, steps):
+    """Features and clipped log targets (exact diagonal gain over the
+    heuristic's) of every contact of `steps` oracle steps from (q, v)."""
+    o = Oracle(s)
+    sd = dict(s)
+    sd["impedance"] = 1
+    od = Oracle(sd)
+    F, T = [], []
+    q, v = q.astype(np.float64), v.astype(np.float64)
+    nf = scenes.nfacet(s["condim"])
+    for _ in range(steps):
+        q1, v1, out = o.step(q, v)
+        _, _, outd = od.step(q, v)
+        for w in range(s["nworld"]):
+            n = int(out["ncon"][w])
+            F.append(out["features"][w, :n])
+            t = np.zeros((n, mlp.NOUT))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t[:, :nf] = np.clip(np.log(outd["facet_gain"][w, :n] / out["facet_gain"][w, :n]),
+                                    -mlp.CLIP, mlp.CLIP)
+            T.append(np.nan_to_num(t))
+        q, v = q1, v1
+    return np.concatenate(F), np.concatenate(T)
+
+
+def _network_error_bound(params, feats, dfeat):
+    """Bound on |y_gpu - y| per contact and output, y the oracle's network at
+    bf16 operand precision on the oracle's features, y_gpu the kernel's on
+    features within dfeat of them.  Forward error propagation: a difference d
+    before a bf16 rounding leaves at most d + (one bf16 spacing where d reaches
+    the value's tie point, else 0) after it; a layer adds |W|^T of its inputs'
+    differences and the float32 accumulation error n 2^-24 of its absolute
+    terms (n products plus the bias); SiLU passes 1.1 (its largest slope) of
+    its input's difference plus 4 2^-24 of its value (hardware exp and
+    reciprocal); the normalisation adds 3 2^-24 of x."""
+    u = 2.0 ** -24
+    P = mlp.unpack(params)
+    y, it = mlp.forward(params, feats, operands="bf16")
+    W1, W2, W3 = (np.abs(mlp.bf16(P[k])) for k in ("W1", "W2", "W3"))
+
+    def rounded(pre, d):
+        return d + mlp.bf16_spacing(pre) * (mlp.bf16_tie_distance(pre) <= d)
+
+    dx = np.zeros_like(it["x_pre"])
+    dx[:, :mlp.NFEAT] = dfeat[:, :mlp.NFEAT] / P["std"][:mlp.NFEAT] + 3 * u * np.abs(it["x_pre"][:, :mlp.NFEAT])
+    dxb = rounded(it["x_pre"], dx)
+    dxb[:, mlp.NFEAT:] = 0.0
+    dz1 = dxb @ W1 + (mlp.NIN + 1) * u * (np.abs(it["x"]) @ W1 + np.abs(P["b1"]))
+    da1 = rounded(it["a1_pre"], 1.1 * dz1 + 4 * u * np.abs(it["a1_pre"]))
+    dz2 = da1 @ W2 + (mlp.NH + 1) * u * (np.abs(it["a1"]) @ W2 + np.abs(P["b2"]))
+    da2 = rounded(it["a2_pre"], 1.1 * dz2 + 4 * u * np.abs(it["a2_pre"]))
+    return da2 @ W3 + (mlp.NH + 1) * u * (np.abs(it["a2"]) @ W3 + np.abs(P["b3"]))
+
+
+def test_trained_network_matches_oracle(torch_cuda):
+    """A network trained by the oracle's own FP64 Adam on the oracle's
+    training data (features and diagonal-gain targets of a settled pile),
+    evaluated by the oracle at the kernel's operand precision (bf16 operands,
+    wide accumulation): the GPU's features lie within stated bounds of the
+    oracle's; those bounds, carried through the network (a bf16 rounding may
+    flip only where the carried difference reaches its tie point), bound the
+    outputs' difference; per-contact decisions equal the oracle's wherever the
+    fallback rule's slacks exceed what that bound can move; facet impulses and
+    velocities match within the standard tolerances widened by the bound, in
+    the worlds with no guarded contact."""
+    from paper_2603_12185_amd import cfsim
+    s = scenes.dense_pile(nworld=4, nsphere=64, seed=5)
+    q, v = _oracle_state(s, 300)
+    F, T = _oracle_training_data(s, q, v, 3)
+    params = mlp.init_params(F, seed=2)
+    m_, v_ = np.zeros(mlp.NPARAM), np.zeros(mlp.NPARAM)
+    losses = []
+    for it in range(1, 151):
+        loss, g = mlp.loss_and_grad(params, F, T, 4)
+        params, m_, v_ = mlp.adam(params, m_, v_, g, it, 3e-3)
+        losses.append(loss)
+    print("oracle training: rows", len(F), "loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.2 * losses[0]
+    params = np.asarray(params, np.float32).astype(np.float64)  # the float32 values both sides use
+    o = Oracle(s)
+    nw, cm, nf = s["nworld"], s["ncon_max"], scenes.nfacet(s["condim"])
+    best = None
+    for margin in (1e-5, 1e-4, 3e-4, 1e-3, 3e-3, 1e-2):
+        _, _, out = o.step(q, v, learned=(params, margin, "bf16"))
+        frac = float(np.concatenate([out["fallback"][w, :out["ncon"][w]] for w in range(nw)]).mean())
+        if best is None or abs(frac - 0.5) < abs(best[1] - 0.5):
+            best = (margin, frac, out)
+    margin, frac, out = best
+    print("trained network: margin", margin, "fallback fraction (oracle)", frac)
+    assert 0.05 < frac < 0.95
+    model = cfsim.Model(s)
+    model.set_learned_impedance(_net(params), margin=margin)
+    con = model.alloc_contacts(training=True)
+    con["fallback"] = con["ncon"].new_full((nw, cm), -1)
+    q1, v1 = model.step(tdev(q), tdev(v), contacts=con)
+    c = to_np(con)
+    # feature differences the network sees, checked on the GPU's own export
+    # (float32 arithmetic of the same quantities): gap 3e-8 m (a few ulp of a
+    # sphere distance), velocities 2e-7 of the world's speed scale (largest
+    # linear smooth speed + 0.05 m times the largest angular speed + g h),
+    # effective mass 1e-6 relative, friction and step exact
+    dfeat = np.zeros((nw, cm, mlp.NIN))
+    for w in range(nw):
+        vsw = out["v_smooth"][w].reshape(-1, 6)
+        vsc = np.abs(vsw[:, :3]).max() + 0.05 * np.abs(vsw[:, 3:]).max() + 9.81 * s["h"]
+        dfeat[w, :, 0] = 3e-8
+        dfeat[w, :, 1:4] = 2e-7 * vsc
+        dfeat[w, :, 4] = 1e-6 * np.abs(out["features"][w, :, 4])
+        n = int(out["ncon"][w])
+        assert (np.abs(c["features"][w, :n, :7] - out["features"][w, :n, :7]) <= dfeat[w, :n, :7]).all(), \
+            f"world {w}: features beyond the bound the network's error bound assumes"
+    yerr = _network_error_bound(params, out["features"].reshape(-1, mlp.NIN),
+                                dfeat.reshape(-1, mlp.NIN)).reshape(nw, cm, mlp.NOUT)
+    h = s["h"]
+    imp_extra = np.zeros((nw, cm, nf))
+    vtol = np.zeros(nw)
+    worlds, compared, guarded, kept = [], 0, 0, 0
+    m_b = s["body_mass"]
+    for w in range(nw):
+        n = int(out["ncon"][w])
+        keep = out["fallback"][w, :n] == 0
+        kept += int(keep.sum())
+        lam = out["impulse"][w, :n]
+        # a gain error of expm1(y error) + 1e-6 (hardware exp) on the learned impulses
+        gerr = np.expm1(yerr[w, :n, :nf]) + 1e-6
+        # learned impulses: kept ones as exported, else the heuristic's times exp(clip(y))
+        lam_l = np.where(keep[:, None], lam,
+                         lam * np.exp(np.clip(out["learned_y"][w, :n, :nf], -mlp.CLIP, mlp.CLIP)))
+        dlam = lam_l * gerr
+        dS = dlam.sum(1)
+        imp_extra[w, :n] = np.where(keep[:, None], dlam, 0.0)
+        wi = 1.0 / (3.0 * np.maximum(out["features"][w, :n, 4], 1e-300))
+        vn = out["features"][w, :n, 1]
+        vl = vn + wi * lam_l.sum(1)
+        band0 = h * wi * dS + 1e-6 * (margin + h * np.abs(vn)) + 1e-9
+        band1 = (np.abs(vl) + wi * dS) * dS + 1e-4 * np.abs(out["fallback_slack"][w, :n, 1])
+        s0, s1 = out["fallback_slack"][w, :n, 0], out["fallback_slack"][w, :n, 1]
+        dec = (s0 >= 0) & (s1 >= 0)
+        ok = np.where(dec, (s0 > band0) & (s1 > band1), (s0 < -band0) | (s1 < -band1))
+        np.testing.assert_array_equal(c["fallback"][w, :n][ok], out["fallback"][w, :n][ok],
+                                      err_msg=f"world {w}: fallback decisions")
+        compared += int(ok.sum())
+        guarded += int((~ok).sum())
+        # a facet row moves a sphere by at most (1 + mu) |dlam| / m linearly and by
+        # (1 + mu) |dlam| r^2 / I = 2.5 (1 + mu) |dlam| / m as a speed at its radius
+        per_body = np.zeros(s["nbody"])
+        for k in range(n):
+            if not keep[k]:
+                continue
+            for g_ in out["geom"][w, k]:
+                b = s["geom_body"][g_]
+                if b >= 0:
+                    per_body[b] += 2.0 * 2.5 * dS[k] / m_b[w, b]
+        vtol[w] = per_body.max(initial=0.0)
+        if ok.all():
+            worlds.append(w)
+    print("trained network: kept learned", kept, "decisions compared", compared, "guarded", guarded,
+          "output error bound max", float(yerr[:, :, :nf].max()), "median",
+          float(np.median(np.concatenate([yerr[w, :out["ncon"][w], :nf].ravel() for w in range(nw)]))),
+          "worlds checked", worlds)
+    assert compared > 200 and guarded <= compared // 10
+    if worlds:
+        stats = compare_step(s, o, q, v, None, q1.cpu().numpy(), v1.cpu().numpy(), c, worlds=worlds,
+                             learned=(params, margin, "bf16"), vtol_extra=vtol, imp_tol_extra=imp_extra)
+        print("trained network", stats)

@@ -122,3 +122,45 @@ def test_forward_of_a_hand_worked_network():
     p2 = p.copy()
     p2[mlp.OFF_B1 + 20] = 3.0
     np.testing.assert_array_equal(mlp.forward(p2, feats)[0], y)
+
+
+def test_bf16_rounding_and_ties():
+    """bf16 keeps 8 significant bits, rounding to nearest with ties to even:
+    1 + 2^-8 lies halfway between 1 and 1 + 2^-7 and goes to 1; 1 + 3 2^-8
+    halfway between 1 + 2^-7 and 1 + 2^-6 goes to 1 + 2^-6; pi -> 3.140625;
+    signs are symmetric; tie distance and spacing follow the grid, 2^-7 above
+    1 and 2^-8 below it."""
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, np.pi, -np.pi, 0.0])
+    np.testing.assert_array_equal(mlp.bf16(vals),
+                                  [1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, 3.140625, -3.140625, 0.0])
+    np.testing.assert_allclose(mlp.bf16_tie_distance([1 + 2 ** -9, 1.0, 1 - 2 ** -10]),
+                               [2 ** -9, 2 ** -9, 2 ** -10], rtol=1e-12)
+    np.testing.assert_array_equal(mlp.bf16_spacing([1.5, 0.75]), [2 ** -7, 2 ** -8])
+
+
+def test_bf16_operand_forward():
+    """At bf16 operand precision the network rounds x, the weights and both
+    hidden activations before each product (biases as given, float64 sums):
+    a one-unit chain worked out with those roundings."""
+    import math
+    p = np.zeros(mlp.NPARAM)
+    p[mlp.OFF_STD:mlp.OFF_W1] = 1.0
+    p[mlp.OFF_STD] = 3.0
+    p[mlp.OFF_W1 + 0 * mlp.NH + 2] = 0.3            # W1[0][2]
+    p[mlp.OFF_B1 + 2] = 0.01
+    p[mlp.OFF_W2 + 2 * mlp.NH + 7] = -1.7           # W2[2][7]
+    p[mlp.OFF_W3 + 7 * mlp.NOUT + 1] = 0.9          # W3[7][1]
+    p[mlp.OFF_B3 + 1] = 0.1
+    f = np.array([[0.7, 0, 0, 0, 0, 0, 0, 0]])
+    y, it = mlp.forward(p, f, operands="bf16")
+    b = lambda x: float(mlp.bf16(np.array([x]))[0])
+    silu = lambda z: z / (1 + math.exp(-z))
+    x0 = b(0.7 / 3.0)
+    a1 = b(silu(b(0.3) * x0 + 0.01))
+    a2 = b(silu(b(-1.7) * a1))
+    np.testing.assert_allclose(y[0, 1], b(0.9) * a2 + 0.1, rtol=1e-15)
+    assert y[0, 0] == 0.0
+    np.testing.assert_allclose(it["x_pre"][0, 0], 0.7 / 3.0, rtol=1e-15)
+    # float64 operands: the same chain without roundings
+    y64, _ = mlp.forward(p, f)
+    np.testing.assert_allclose(y64[0, 1], 0.9 * silu(-1.7 * silu(0.3 * 0.7 / 3 + 0.01)) + 0.1, rtol=1e-14)
