@@ -294,6 +294,20 @@ int64_t cf_mlp_work_floats(int32_t n);
  * Deterministic: per-wave partial sums in `work`, added in a fixed order. */
 cf_status cf_mlp_gradient(void *stream, const float *params, const float *feats, const float *targets,
                           int32_t n, int32_t nout, float *work, int64_t work_floats, float *grad, float *loss);
+/* cf_mlp_gradient for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving or training loops that forbid hipMalloc): the
+ * same kernels and the same per-wave partition, so the same grad and loss bit
+ * for bit, with the partial sums in a fixed static device array instead of a
+ * caller workspace.  Allocates nothing, ever: the array holds the partials of
+ * the largest grid the gradient launches (2048 waves x (nparam + 1) floats,
+ * 47.5 MB), every GPU the library runs on keeps its own copy until the process
+ * ends, and any n >= 1 fits (an n whose partials would not fit is rejected
+ * with CF_E_INVALID_ARG).  The first call on a device looks up that device's
+ * copy (CF_E_DEVICE if the lookup fails).  Nothing in the array needs to start
+ * at zero; calls that overlap on one GPU share it and race, so serialise
+ * them (one stream, or events).  Arguments as for cf_mlp_gradient. */
+cf_status cf_mlp_gradient_noalloc(void *stream, const float *params, const float *feats, const float *targets,
+                                  int32_t n, int32_t nout, float *grad, float *loss);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) of the
  * trained parameters (W1 onwards) with moment buffers m, v [nparam]. */
 cf_status cf_mlp_adam(void *stream, float *params, float *m, float *v, const float *grad, int32_t step, float lr);

@@ -77,6 +77,7 @@ SIGNATURES = {
     "cf_mlp_forward": ([C.c_void_p, _fp, _fp, C.c_int32, _fp], C.c_int32),
     "cf_mlp_work_floats": ([C.c_int32], C.c_int64),
     "cf_mlp_gradient": ([C.c_void_p, _fp, _fp, _fp, C.c_int32, C.c_int32, _fp, C.c_int64, _fp, _fp], C.c_int32),
+    "cf_mlp_gradient_noalloc": ([C.c_void_p, _fp, _fp, _fp, C.c_int32, C.c_int32, _fp, _fp], C.c_int32),
     "cf_mlp_adam": ([C.c_void_p, _fp, _fp, _fp, _fp, C.c_int32, C.c_float], C.c_int32),
     "cf_last_error": ([], C.c_char_p),
 }
@@ -389,6 +390,20 @@ class ImpedanceNet:
         s = torch.cuda.current_stream() if stream is None else stream
         _check(load().cf_mlp_gradient(C.c_void_p(s.cuda_stream), _ptr(self.params), _ptr(feats), _ptr(targets), n,
                                       int(nout), _ptr(self._work), self._work.numel(), _ptr(grad), _ptr(loss)))
+        return grad, loss
+
+    def gradient_noalloc(self, feats, targets, nout, grad, loss, stream=None):
+        """gradient() through the entry point that allocates nothing: the
+        caller passes the outputs grad [nparam] and loss [1]."""
+        import torch
+        self._check(feats, 8, "feats")
+        self._check(targets, 16, "targets")
+        for t, k, name in ((grad, self.nparam, "grad"), (loss, 1, "loss")):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != k:
+                raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of {k} values")
+        s = torch.cuda.current_stream() if stream is None else stream
+        _check(load().cf_mlp_gradient_noalloc(C.c_void_p(s.cuda_stream), _ptr(self.params), _ptr(feats),
+                                              _ptr(targets), feats.shape[0], int(nout), _ptr(grad), _ptr(loss)))
         return grad, loss
 
     def train_step(self, feats, targets, nout, lr, stream=None):

@@ -4,6 +4,7 @@
 // per-wave partial sums, Adam.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/cfsim.h"
@@ -254,6 +255,19 @@ extern "C" cf_status cf_mlp_forward(void *stream, const float *params, const flo
   return e == hipSuccess ? CF_OK : cf::api_error(CF_E_DEVICE, std::string("mlp forward: ") + hipGetErrorString(e));
 }
 
+// The gradient's two launches: per-wave partials into `work` (nw rows of
+// NPARAM + 1 floats, every entry written), then their sum in wave order.
+static cf_status launch_gradient(hipStream_t s, const float *params, const float *feats, const float *targets, int n,
+                                 int nout, int nw, float *work, float *grad, float *loss) {
+  hipLaunchKernelGGL(grad_kernel, dim3(nw / NWAVE), dim3(BS), 0, s, params, feats, targets, n, nout, work);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(reduce_kernel, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, s, work, nw, grad, loss);
+    e = hipGetLastError();
+  }
+  return e == hipSuccess ? CF_OK : cf::api_error(CF_E_DEVICE, std::string("mlp gradient: ") + hipGetErrorString(e));
+}
+
 extern "C" cf_status cf_mlp_gradient(void *stream, const float *params, const float *feats, const float *targets,
                                      int32_t n, int32_t nout, float *work, int64_t work_floats, float *grad,
                                      float *loss) {
@@ -264,14 +278,59 @@ extern "C" cf_status cf_mlp_gradient(void *stream, const float *params, const fl
   const int nw = grad_waves(n);
   if (work_floats < (int64_t)nw * (NPARAM + 1))
     return cf::api_error(CF_E_INVALID_ARG, "work buffer smaller than cf_mlp_work_floats(n)");
-  hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(grad_kernel, dim3(nw / NWAVE), dim3(BS), 0, s, params, feats, targets, n, nout, work);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(reduce_kernel, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, s, work, nw, grad, loss);
-    e = hipGetLastError();
+  return launch_gradient((hipStream_t)stream, params, feats, targets, n, nout, nw, work, grad, loss);
+}
+
+// ---- cf_mlp_gradient without a caller workspace
+// The per-wave partial gradients live in `scratch`: room for the largest grid
+// the gradient launches (MAX_GRAD_WAVES waves of NPARAM + 1 floats, 47.5 MB),
+// so every n fits.  Each GPU the library runs on holds its own copy until the
+// process ends.  The kernel writes every entry of each row it uses before the
+// sum reads it, so nothing is cleared between calls; calls that overlap on one
+// GPU share the array and race.
+constexpr size_t kScratchFloats = (size_t)MAX_GRAD_WAVES * (NPARAM + 1);
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch[kMaxDevices] = {};  // device address of each GPU's `scratch`, taken once per device
+
+// Device address of the current GPU's `scratch` (the array's name is a host
+// stand-in: only this address may reach a kernel).
+cf_status scratch_address(float **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return cf::api_error(CF_E_DEVICE, "cf_mlp_gradient_noalloc: no current HIP device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return cf::api_error(CF_E_DEVICE, std::string("cf_mlp_gradient_noalloc: address of the static scratch: ") +
+                                            hipGetErrorString(e));
+    g_scratch[dev] = static_cast<float *>(p);
   }
-  return e == hipSuccess ? CF_OK : cf::api_error(CF_E_DEVICE, std::string("mlp gradient: ") + hipGetErrorString(e));
+  *out = g_scratch[dev];
+  return CF_OK;
+}
+}  // namespace
+
+extern "C" cf_status cf_mlp_gradient_noalloc(void *stream, const float *params, const float *feats,
+                                             const float *targets, int32_t n, int32_t nout, float *grad,
+                                             float *loss) {
+  if (!params || !feats || !targets || !grad || n < 1 || nout < 1 || nout > NOUT)
+    return cf::api_error(CF_E_INVALID_ARG, "cf_mlp_gradient_noalloc: bad argument");
+  if (!al16(params) || !al16(feats) || !al16(targets) || !al16(grad))
+    return cf::api_error(CF_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  const int nw = grad_waves(n);
+  if ((size_t)nw * (NPARAM + 1) > kScratchFloats)
+    return cf::api_error(CF_E_INVALID_ARG, "cf_mlp_gradient_noalloc: partial sums exceed the fixed scratch (" +
+                                               std::to_string(kScratchFloats) + " floats)");
+  float *work = nullptr;
+  const cf_status st = scratch_address(&work);
+  if (st != CF_OK) return st;
+  return launch_gradient((hipStream_t)stream, params, feats, targets, n, nout, nw, work, grad, loss);
 }
 
 extern "C" cf_status cf_mlp_adam(void *stream, float *params, float *m, float *v, const float *grad, int32_t step,
