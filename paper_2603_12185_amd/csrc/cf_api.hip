@@ -39,6 +39,7 @@ struct cf_model {
   int nslot = 0;
   int nslot_pre = 0, sph0 = 0, nsph = 0;  // sphere block of the narrow phase (see below)
   int npl = 0;                            // static planes tested as rows against the block
+  int sph_mfma = 0;                       // block masks from an MFMA Gram matrix (see collide_args)
   cf::Params p{};
   // device constants
   uint32_t *d_slots = nullptr;
@@ -58,6 +59,7 @@ struct cf_model {
   float4 *d_cnp = nullptr, *d_cpos = nullptr;
   int *d_ncon = nullptr, *d_over = nullptr;
   size_t lds_collide = 0, lds_resolve = 0;
+  size_t lds_resolve_free = 0;  // resolution with each free body's state in its lane
   const float *mlp = nullptr;  // learned-gain network parameters (caller-owned device memory)
   float4 *d_mlp_img = nullptr; // their LDS image, rewritten by every step that uses them
   bool box_pairs = false;      // box-sphere or box-capsule slots present
@@ -335,14 +337,27 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
         if (rows) m->npl = m->sph0;
       }
     }
+    // The block's hit masks come from an MFMA Gram matrix when it holds at most
+    // 64 spheres on pairwise different bodies (so every pair is a slot) and the
+    // margin is not negative (then r_i + r_j + margin > 0 for every pair).
+    if (m->nsph > 0 && m->nsph <= 64 && m->p.margin >= 0.f) {
+      std::vector<int> bodies;
+      for (int g = m->sph0; g < ng; ++g) bodies.push_back(d->geom_body[g]);
+      std::sort(bodies.begin(), bodies.end());
+      m->sph_mfma = std::adjacent_find(bodies.begin(), bodies.end()) == bodies.end() ? 1 : 0;
+    }
   }
   // Default launch shape by world size (cf_model_autotune measures instead):
-  // one sphere-block row per collision thread, and a resolution workgroup of
-  // 256 threads once a world has more than 64 bodies (fewer contact chunks).
+  // one sphere-block row per collision thread; for free bodies one body per
+  // resolution thread (the smallest workgroup that holds every body), else a
+  // resolution workgroup of 256 threads once a world has more than 64 bodies
+  // (fewer contact chunks).
   m->block_collide = m->nsph > 128 ? 256 : m->nsph > 64 ? 128 : 64;
-  m->block_resolve = nb > 64 ? 256 : 128;
+  if (m->nsub == 0 && nb <= 256) m->block_resolve = nb > 128 ? 256 : nb > 64 ? 128 : 64;
+  else m->block_resolve = nb > 64 ? 256 : 128;
   m->lds_collide = cf::collide_lds_bytes(m->nq, nb, ng, m->norient, m->nsub, m->nsph);
   m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, nb, ng, m->nsub, m->art_floats);
+  m->lds_resolve_free = cf::resolve_free_lds_bytes(nb, ng);
   if (m->lds_collide > kLdsLimit || m->lds_resolve > kLdsLimit) {
     delete m;
     return set_err(CF_E_UNSUPPORTED, "world too large for one workgroup's LDS (reduce bodies or geoms)");
@@ -445,7 +460,7 @@ static cf::CollideArgs collide_args(const cf_model *m) {
   ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
   ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
   ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
-  ca.nslot_pre = m->nslot_pre; ca.sph0 = m->sph0; ca.nsph = m->nsph; ca.npl = m->npl;
+  ca.nslot_pre = m->nslot_pre; ca.sph0 = m->sph0; ca.nsph = m->nsph; ca.npl = m->npl; ca.sph_mfma = m->sph_mfma;
   return ca;
 }
 
@@ -463,10 +478,14 @@ static bool rollout_fused(const cf_model *m) {
   return m->lds_rollout <= kLdsLimit && !m->rollout_steps && !m->mlp;
 }
 
-// The resolution launch of a step: with learned gains the network's LDS image
-// is first written from the current parameters (one small kernel), then the
-// resolution copies it to LDS and runs at most 128 threads per world.
+// The resolution launch of a step: worlds of free bodies that fit the
+// workgroup one body per lane take the register-resident kernel; with learned
+// gains the network's LDS image is first written from the current parameters
+// (one small kernel), then the resolution copies it to LDS and runs at most
+// 128 threads per world.
 static hipError_t launch_resolve_model(const cf_model *m, cf::ResolveArgs ra, hipStream_t s) {
+  if (!m->mlp && !m->d_act && m->nsub == 0 && m->nb <= m->block_resolve)
+    return cf::launch_resolve_free(ra, m->nw, m->block_resolve, m->lds_resolve_free, s);
   if (!m->mlp) return cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
   const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
   ra.mlp = m->mlp;

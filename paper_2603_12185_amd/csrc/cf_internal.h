@@ -80,6 +80,7 @@ struct CollideArgs {
   int nslot_pre;                // slots tested one by one (all of them when nsph = 0)
   int sph0, nsph;               // sphere block: geoms [sph0, sph0 + nsph), pairs tested row-wise
   int npl;                      // > 0: geoms [0, npl) are static planes whose slots are their rows against the block
+  int sph_mfma;                 // 1: block of <= 64 spheres on pairwise different bodies, margin >= 0 (MFMA masks)
   int gpos_ws, gquat_ws;        // world stride in elements (0 = shared by all worlds)
   float margin;
 };
@@ -147,5 +148,9 @@ size_t resolve_lds_bytes(int nq, int nv, int nb, int ng, int nsub, int art_float
 size_t resolve_learned_lds_bytes(int block);  // extra LDS of the resolution with learned gains
 hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s);
+// Resolution of worlds of free bodies (no subtrees, actuators or learned
+// gains) with at most `block` bodies, each body's state in its lane.
+size_t resolve_free_lds_bytes(int nb, int ng);
+hipError_t launch_resolve_free(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 
 }  // namespace cf

@@ -655,6 +655,15 @@ __device__ inline GeomIn geom_in(const CollideArgs &a, int w, int g) {
 // pair reached by wrapping round) into row j at bit i (integer OR: the order of
 // the atomics does not matter).  A pair is a hit when |c_j - c_i|^2 <
 // (r_i + r_j + margin)^2 in float32, the same value from either end.
+// Contact test of a sphere pair from its LDS records (centre, radius):
+// |c_j - c_i|^2 < (r_i + r_j + margin)^2 in float32 with a fixed operation
+// order, so every path that decides a pair gets the same answer from either end.
+__device__ inline bool sphere_pair_hit(float4 Gi, float4 Gj, float margin) {
+  const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
+  const float R = (Gi.w + Gj.w) + margin;
+  return (R > 0.f) & (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < R * R);
+}
+
 template <int BS, int NWD>
 __device__ inline void sphere_masks(const float4 *Gs, const int *gbd, int g0, int S, float margin,
                                     unsigned long long *rm) {
@@ -672,9 +681,7 @@ __device__ inline void sphere_masks(const float4 *Gs, const int *gbd, int g0, in
     for (int d = 1; d <= dmax; ++d) {
       j = j + 1 == S ? 0 : j + 1;
       const float4 Gj = Gs[g0 + j];
-      const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
-      const float R = Gi.w + Gj.w + margin;
-      const bool hit = (bi != gbd[g0 + j]) & (R > 0.f) & (dx * dx + dy * dy + dz * dz < R * R);
+      const bool hit = (bi != gbd[g0 + j]) & sphere_pair_hit(Gi, Gj, margin);
       const unsigned long long bit = (unsigned long long)hit << (j & 63);
       if constexpr (NWD == 1) {
         h[0] |= bit;
@@ -693,6 +700,107 @@ __device__ inline void sphere_masks(const float4 *Gs, const int *gbd, int g0, in
         atomicOr(rm + (64 * w + __ffsll(b) - 1) * NWD + (i >> 6), 1ull << (i & 63));
     }
   }
+}
+
+// Hit masks of a sphere block of S <= 64 spheres on pairwise different
+// bodies (at most one static) with margin >= 0, from one Gram matrix on MFMA,
+// one wave.  With centres c taken relative to the block's mean and
+// rho = r + margin / 2, the test quantity g_ij = |c_i - c_j|^2 - (rho_i +
+// rho_j)^2 is the product a_i . b_j of the 6-vectors a = (x, y, z, rho, s, 1)
+// and b = (-2x, -2y, -2z, -2rho, 1, s), s = |c|^2 - rho^2; the upper triangle
+// of the 64 x 64 matrix is three 32 x 32 tiles of three v_mfma_f32_32x32x2f32
+// each.  Every term of a product is at most M = max(|c|^2 + rho^2) in
+// magnitude, so float32 products and sums put g within about 40 M 2^-24 of
+// the exact value, and the float32 test of sphere_pair_hit within about
+// 70 M 2^-24: outside the band |g| <= eps = M 2^-16 the sign of g is that
+// test's answer, and the few pairs inside it are decided by sphere_pair_hit
+// itself.  The masks are therefore the ones sphere_masks builds.  Ballots of
+// each accumulator register give two half rows of hits (lanes 0-31: row i0,
+// lanes 32-63: row i0 + 4 of the tile); v_writelane places them in the row
+// lane's mask words.  `ab`: 12 x 64 floats of LDS scratch.
+// v_writelane_b32: lane `lane` of v takes the wave-uniform value val (no
+// compiler builtin exposes the instruction).  The lane select must fold to an
+// inline constant (the call sites sit in fully unrolled loops): a second
+// scalar register would exceed the one-scalar operand limit of the encoding.
+// The leading s_nop is the one wait state a vector compare that wrote VCC
+// needs before VCC is read as a scalar operand (the compiler does not look
+// inside inline assembly for that hazard).
+__device__ inline int lane_write(int v, int val, int lane) {
+  asm volatile("s_nop 0\n\tv_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "i"(lane));
+  return v;
+}
+
+__device__ __attribute__((always_inline)) inline void sphere_masks_mfma(const float4 *Gs, int g0, int S,
+                                                                        float margin, unsigned long long *rm,
+                                                                        float *ab) {
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+  const int l = threadIdx.x;  // the workgroup is one wave
+  const bool real = l < S;
+  const float4 G = real ? Gs[g0 + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+  float cx = real ? G.x : 0.f, cy = real ? G.y : 0.f, cz = real ? G.z : 0.f;
+  for (int off = 32; off > 0; off >>= 1) {
+    cx += __shfl_xor(cx, off);
+    cy += __shfl_xor(cy, off);
+    cz += __shfl_xor(cz, off);
+  }
+  const float invS = 1.0f / (float)S;
+  const float x = G.x - cx * invS, y = G.y - cy * invS, z = G.z - cz * invS;
+  const float rho = G.w + 0.5f * margin;
+  const float c2 = fmaf(z, z, fmaf(y, y, x * x)), r2 = rho * rho;
+  float M = real ? c2 + r2 : 0.f;
+  for (int off = 32; off > 0; off >>= 1) M = fmaxf(M, __shfl_xor(M, off));
+  const float eps = M * (1.0f / 65536.0f);
+  // padding rows and columns sit at g >= 4 M + 1 > eps from everything
+  const float sa = real ? c2 - r2 : 4.0f * M + 1.0f;
+  const float av[6] = {real ? x : 0.f, real ? y : 0.f, real ? z : 0.f, real ? rho : 0.f, sa, 1.f};
+  const float bv[6] = {-2.f * av[0], -2.f * av[1], -2.f * av[2], -2.f * av[3], 1.f, sa};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    ab[k * 64 + l] = av[k];
+    ab[(6 + k) * 64 + l] = bv[k];
+  }
+  __syncthreads();
+  int hit0 = 0, hit1 = 0;  // lane l: its row's hits among columns 0-31 and 32-63
+  const int ntile = S > 32 ? 3 : 1;
+  const int col = l & 31, kh = l >> 5;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t >= ntile) break;
+    const int I = t == 2 ? 1 : 0, J = t == 0 ? 0 : 1;
+    f32x16 g = {};
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+      const int k = 2 * st + kh;
+      g = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[k * 64 + 32 * I + col], ab[(6 + k) * 64 + 32 * J + col], g, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int ia = 8 * (r >> 2) + (r & 3);  // tile row of lanes 0-31; lanes 32-63 hold ia + 4
+      unsigned long long h = __builtin_amdgcn_ballot_w64(g[r] < -eps);
+      unsigned long long m = __builtin_amdgcn_ballot_w64(fabsf(g[r]) <= eps);
+      if (I == J) {  // diagonal tile: only columns above the row (ia + 1 <= 28)
+        const uint32_t lo_m = 0xFFFFFFFFu << (ia + 1), hi_m = ia + 5 < 32 ? 0xFFFFFFFFu << (ia + 5) : 0u;
+        const unsigned long long up = ((unsigned long long)hi_m << 32) | lo_m;
+        h &= up;
+        m &= up;
+      }
+      const int rw = 32 * I + ia;
+      // pairs in the band (rare): the float32 test itself, wave-uniform
+      for (; m; m &= m - 1ull) {
+        const int b = __ffsll(m) - 1;
+        if (sphere_pair_hit(Gs[g0 + rw + 4 * (b >> 5)], Gs[g0 + 32 * J + (b & 31)], margin)) h |= 1ull << b;
+      }
+      if (J == 0) {
+        hit0 = lane_write(hit0, (int)(uint32_t)h, rw);
+        hit0 = lane_write(hit0, (int)(uint32_t)(h >> 32), rw + 4);
+      } else {
+        hit1 = lane_write(hit1, (int)(uint32_t)h, rw);
+        hit1 = lane_write(hit1, (int)(uint32_t)(h >> 32), rw + 4);
+      }
+    }
+  }
+  if (real) rm[l] = (unsigned long long)(uint32_t)hit0 | ((unsigned long long)(uint32_t)hit1 << 32);
+  __syncthreads();
 }
 
 // Narrow phase of world w from its q row `sq` (LDS).  Writes the first `cap`
@@ -913,7 +1021,9 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
         a.nsub > 0 ? reinterpret_cast<char *>(brot + 12 * a.nb) : reinterpret_cast<char *>(borg));
     for (int x = tid; x < S * nwd; x += BS) rm[x] = 0ull;
     __syncthreads();
-    if (S <= 64) {
+    if (BS == 64 && a.sph_mfma) {
+      sphere_masks_mfma(Gs, g0, S, a.margin, rm, reinterpret_cast<float *>(cand));
+    } else if (S <= 64) {
       sphere_masks<BS, 1>(Gs, gbd, g0, S, a.margin, rm);
     } else if (S <= 128) {
       sphere_masks<BS, 2>(Gs, gbd, g0, S, a.margin, rm);
@@ -929,9 +1039,7 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
           const int j = i + d < S ? i + d : i + d - S;
           const float4 Gj = Gs[g0 + j];
           const int bj = gbd[g0 + j];
-          const float dx = Gj.x - Gi.x, dy = Gj.y - Gi.y, dz = Gj.z - Gi.z;
-          const float R = Gi.w + Gj.w + a.margin;
-          if (bi != bj && R > 0.f && dx * dx + dy * dy + dz * dz < R * R) {
+          if (bi != bj && sphere_pair_hit(Gi, Gj, a.margin)) {
             const int lo = min(i, j), hi = max(i, j);
             atomicOr(rm + lo * nwd + (hi >> 6), 1ull << (hi & 63));
           }
@@ -1231,6 +1339,182 @@ __device__ inline bool learned_ok(const float *lh, const float *ll, float vn, fl
   return pl <= ph + margin && el <= eh + em && isfinite(vl);
 }
 
+// Smooth prediction of one free body (Eq. smooth_vel with the block-diagonal
+// M = diag(m I3, R diag(I) R^T) and c = (-m g, w x I_w w)) from its q (7), v (6)
+// and applied force (6) entries and its (m, Ixx, Iyy, Izz): (COM | 1/m),
+// (v_s | trace 3/m), (w_s | 0) and the inverse world inertia (xx yy zz xy | xz yz).
+__device__ inline void free_body_predict(const float *qb, const float *vb, const float *tb, float4 mi,
+                                         const Params &P, float4 &C, float4 &Vs, float4 &Ws, float4 &I0,
+                                         float4 &I1) {
+  float R[9];
+  quat_to_rot<float>(qb[3], qb[4], qb[5], qb[6], R);
+  // hardware reciprocals (1 ulp) for the per-body inverses
+  const float invm = __builtin_amdgcn_rcpf(mi.x);
+  const float d[3] = {mi.y, mi.z, mi.w},
+              e[3] = {__builtin_amdgcn_rcpf(mi.y), __builtin_amdgcn_rcpf(mi.z), __builtin_amdgcn_rcpf(mi.w)};
+  // world inertia R diag(I) R^T and its inverse R diag(1/I) R^T (xx, yy, zz, xy, xz, yz)
+  float Iw[6], Ii[6];
+  const int ri[6] = {0, 1, 2, 0, 0, 1}, rj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float *u = R + 3 * ri[k], *v = R + 3 * rj[k];
+    Iw[k] = u[0] * d[0] * v[0] + u[1] * d[1] * v[1] + u[2] * d[2] * v[2];
+    Ii[k] = u[0] * e[0] * v[0] + u[1] * e[1] * v[1] + u[2] * e[2] * v[2];
+  }
+  const V3 om = v3(vb[3], vb[4], vb[5]);
+  const V3 Io = v3(Iw[0] * om.x + Iw[3] * om.y + Iw[4] * om.z,
+                   Iw[3] * om.x + Iw[1] * om.y + Iw[5] * om.z,
+                   Iw[4] * om.x + Iw[5] * om.y + Iw[2] * om.z);
+  const V3 gyro = cross(om, Io);  // velocity-product part of c
+  const V3 ta = v3(tb[3] - gyro.x, tb[4] - gyro.y, tb[5] - gyro.z);
+  const V3 dw = v3(Ii[0] * ta.x + Ii[3] * ta.y + Ii[4] * ta.z,
+                   Ii[3] * ta.x + Ii[1] * ta.y + Ii[5] * ta.z,
+                   Ii[4] * ta.x + Ii[5] * ta.y + Ii[2] * ta.z);
+  // c_lin = -m g, so M^-1 (tau - c) = tau/m + g for the linear block
+  const V3 vs = v3(vb[0] + P.h * (tb[0] * invm + P.gx), vb[1] + P.h * (tb[1] * invm + P.gy),
+                   vb[2] + P.h * (tb[2] * invm + P.gz));
+  const V3 ws = om + P.h * dw;
+  C = make_float4(qb[0], qb[1], qb[2], invm);
+  Vs = make_float4(vs.x, vs.y, vs.z, 3.0f * invm);
+  Ws = make_float4(ws.x, ws.y, ws.z, 0.f);
+  I0 = make_float4(Ii[0], Ii[1], Ii[2], Ii[3]);
+  I1 = make_float4(Ii[4], Ii[5], 0.f, 0.f);
+}
+
+// Velocity correction (Eq. vel_correction) and semi-implicit Euler step of one
+// free body: v+ = v_s + (F/m, I_w^-1 T), x+ = x + h v+, quat+ = normalize(
+// exp(h w+) (x) quat) with the world-frame angular velocity.  qb: the body's q
+// entries (quaternion read from [3..6]); writes q+ (7) and v+ (6).
+__device__ inline void free_body_correct(float4 C, float4 Vs, float4 Ws, float4 I0, float4 I1, float4 F, float4 T,
+                                         const float *qb, const Params &P, float *qo, float *vo) {
+  const V3 vp = v3(Vs.x + C.w * F.x, Vs.y + C.w * F.y, Vs.z + C.w * F.z);
+  const V3 wp = v3(Ws.x + I0.x * T.x + I0.w * T.y + I1.x * T.z,
+                   Ws.y + I0.w * T.x + I0.y * T.y + I1.y * T.z,
+                   Ws.z + I1.x * T.x + I1.y * T.y + I0.z * T.z);
+  const float qw0 = qb[3], qx0 = qb[4], qy0 = qb[5], qz0 = qb[6];
+  vo[0] = vp.x; vo[1] = vp.y; vo[2] = vp.z; vo[3] = wp.x; vo[4] = wp.y; vo[5] = wp.z;
+  qo[0] = C.x + P.h * vp.x;
+  qo[1] = C.y + P.h * vp.y;
+  qo[2] = C.z + P.h * vp.z;
+  const V3 th = P.h * wp;
+  float ew, ex, ey, ez;
+  quat_of_rotvec(th, ew, ex, ey, ez);
+  const float nw_ = ew * qw0 - ex * qx0 - ey * qy0 - ez * qz0;
+  const float nx_ = ew * qx0 + ex * qw0 + ey * qz0 - ez * qy0;
+  const float ny_ = ew * qy0 - ex * qz0 + ey * qw0 + ez * qx0;
+  const float nz_ = ew * qz0 + ex * qy0 - ey * qx0 + ez * qw0;
+  const float inv = rsqrtf(nw_ * nw_ + nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+  qo[3] = nw_ * inv; qo[4] = nx_ * inv; qo[5] = ny_ * inv; qo[6] = nz_ * inv;
+}
+
+// Heuristic impedance of a contact (Eqs. k_d_setting, r_scaling): x = |phi|/w
+// clamped to [0, 1], gamma(x) from the solimp power law, r between r_min and
+// r_max, A = r / ((1 - r) (tr_a + tr_b)); 0 without a body trace.
+__device__ inline float heuristic_gain(float phi, float trs, const Params &P) {
+  const float x = fminf(fabsf(phi) * P.inv_width, 1.0f);
+  const bool lo = x < P.mid;
+  const float u = lo ? x * P.inv_mid : (1.0f - x) * P.inv_1mmid;
+  const float up = P.power2 ? u * u : powf(u, P.power);
+  const float gam = lo ? P.mid * up : 1.0f - (1.0f - P.mid) * up;
+  const float r = P.r_min + (P.r_max - P.r_min) * gam;
+  return trs > 0.f ? r * __builtin_amdgcn_rcpf((1.0f - r) * trs) : 0.f;
+}
+
+// Facet impulses lambda_f h = G_f max(-(k h + d) s_f - k phi, 0) (Eq. cf_wrench)
+// with s_f = v_n - mu_s d_f . (subspace velocity), facets in the fixed order:
+// tangential d = +t1, +t2, -t1, -t2, then torsional +, -, then rolling.
+template <int CONDIM>
+__device__ inline void facet_impulses(const float *G, const ContactKin &K, float aa, float c0, float *L) {
+  const float vn = dot(K.n, K.vrel);
+  if constexpr (CONDIM == 1) {
+    L[0] = G[0] * fmaxf(-aa * vn + c0, 0.f);
+  } else {
+    const float u1 = dot(K.t1, K.vrel), u2 = dot(K.t2, K.vrel), mut = K.mut;
+    L[0] = G[0] * fmaxf(-aa * (vn - mut * u1) + c0, 0.f);
+    L[1] = G[1] * fmaxf(-aa * (vn - mut * u2) + c0, 0.f);
+    L[2] = G[2] * fmaxf(-aa * (vn + mut * u1) + c0, 0.f);
+    L[3] = G[3] * fmaxf(-aa * (vn + mut * u2) + c0, 0.f);
+    if constexpr (CONDIM >= 4) {
+      const float wt = dot(K.n, K.wrel);
+      L[4] = G[4] * fmaxf(-aa * (vn - K.mutor * wt) + c0, 0.f);
+      L[5] = G[5] * fmaxf(-aa * (vn + K.mutor * wt) + c0, 0.f);
+    }
+    if constexpr (CONDIM == 6) {
+      const float o1 = dot(K.t1, K.wrel), o2 = dot(K.t2, K.wrel);
+      L[6] = G[6] * fmaxf(-aa * (vn - K.murol * o1) + c0, 0.f);
+      L[7] = G[7] * fmaxf(-aa * (vn - K.murol * o2) + c0, 0.f);
+      L[8] = G[8] * fmaxf(-aa * (vn + K.murol * o1) + c0, 0.f);
+      L[9] = G[9] * fmaxf(-aa * (vn + K.murol * o2) + c0, 0.f);
+    }
+  }
+}
+
+// Contact wrench of the facet impulses (J~^T lambda h in the contact frame):
+// force f = sum_f lambda_f (n - mu_t d_f) over the tangential facets plus the
+// normal part of the others, and the torsional / rolling torque tc.
+template <int CONDIM>
+__device__ inline void contact_wrench(const float *lam, const ContactKin &K, V3 &f, V3 &tc) {
+  tc = v3(0.f, 0.f, 0.f);
+  if constexpr (CONDIM == 1) {
+    f = lam[0] * K.n;
+  } else {
+    float N = lam[0] + lam[1] + lam[2] + lam[3];
+    const float e1 = -K.mut * (lam[0] - lam[2]), e2 = -K.mut * (lam[1] - lam[3]);
+    if constexpr (CONDIM >= 4) {
+      N += lam[4] + lam[5];
+      tc = (-K.mutor * (lam[4] - lam[5])) * K.n;
+    }
+    if constexpr (CONDIM == 6) {
+      N += lam[6] + lam[7] + lam[8] + lam[9];
+      tc = tc + (-K.murol * (lam[6] - lam[8])) * K.t1 + (-K.murol * (lam[7] - lam[9])) * K.t2;
+    }
+    f = N * K.n + e1 * K.t1 + e2 * K.t2;
+  }
+}
+
+// Optional per-contact exports of a step (row ci of the caller's arrays).
+template <int NF>
+__device__ inline void export_contact(const ResolveArgs &a, size_t ci, const ContactKin &K, const float *lam) {
+  if (a.x_geom) { a.x_geom[2 * ci] = K.ga; a.x_geom[2 * ci + 1] = K.gb; }
+  if (a.x_sub) a.x_sub[ci] = slot_sub(K.sl);
+  if (a.x_dist) a.x_dist[ci] = K.phi;
+  if (a.x_pos) { a.x_pos[3 * ci] = K.p.x; a.x_pos[3 * ci + 1] = K.p.y; a.x_pos[3 * ci + 2] = K.p.z; }
+  if (a.x_frame) {
+    float *fr = a.x_frame + 9 * ci;
+    fr[0] = K.n.x; fr[1] = K.n.y; fr[2] = K.n.z;
+    fr[3] = K.t1.x; fr[4] = K.t1.y; fr[5] = K.t1.z;
+    fr[6] = K.t2.x; fr[7] = K.t2.y; fr[8] = K.t2.z;
+  }
+  if (a.x_imp) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) a.x_imp[(size_t)NF * ci + i] = lam[i];
+  }
+}
+
+// Training data of the learned gains (free-body models), when requested: the
+// contact's network features and, per facet, the log of the exact diagonal
+// gain over the heuristic's A, clipped.
+template <int NF>
+__device__ inline void export_training(const ResolveArgs &a, size_t ci, const ContactKin &K, float A, float aa,
+                                       float h, const float4 *bC, const float4 *bI0, const float4 *bI1) {
+  if (a.x_feat) {
+    float fe[mlp::NIN];
+    contact_features(K, h, fe);
+#pragma unroll
+    for (int i = 0; i < mlp::NIN; ++i) a.x_feat[(size_t)mlp::NIN * ci + i] = fe[i];
+  }
+  if (a.x_target) {
+    float Ad[NF];
+    diag_impedance<NF>(K.n, K.t1, K.t2, K.ba, K.bb, K.ra, K.rb, bC, bI0, bI1, K.mut, K.mutor, K.murol, aa, Ad);
+#pragma unroll
+    for (int i = 0; i < mlp::NOUT; ++i) {
+      float t = 0.f;
+      if (i < NF && A > 0.f && Ad[i] > 0.f) t = fminf(fmaxf(__logf(Ad[i] / A), -mlp::CLIP), mlp::CLIP);
+      a.x_target[(size_t)mlp::NOUT * ci + i] = t;
+    }
+  }
+}
+
 // Fixed-point wrench sums of the resolution: exponent slot of a body with no
 // entry yet, exponent of a zero entry (below any float's), and the exponent
 // that flags a non-finite entry.
@@ -1349,40 +1633,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       dadr = bc.dadr;
     }
     const float4 mi = b == tid ? mi0 : a.bmi[(size_t)w * nb + b];
-    const float *qb = sq + qadr, *vb = sv + dadr, *tb = st + dadr;
-    float R[9];
-    quat_to_rot<float>(qb[3], qb[4], qb[5], qb[6], R);
-    // hardware reciprocals (1 ulp) for the per-body inverses
-    const float invm = __builtin_amdgcn_rcpf(mi.x);
-    const float d[3] = {mi.y, mi.z, mi.w},
-                e[3] = {__builtin_amdgcn_rcpf(mi.y), __builtin_amdgcn_rcpf(mi.z), __builtin_amdgcn_rcpf(mi.w)};
-    // world inertia R diag(I) R^T and its inverse R diag(1/I) R^T (xx, yy, zz, xy, xz, yz)
-    float Iw[6], Ii[6];
-    const int ri[6] = {0, 1, 2, 0, 0, 1}, rj[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float *u = R + 3 * ri[k], *v = R + 3 * rj[k];
-      Iw[k] = u[0] * d[0] * v[0] + u[1] * d[1] * v[1] + u[2] * d[2] * v[2];
-      Ii[k] = u[0] * e[0] * v[0] + u[1] * e[1] * v[1] + u[2] * e[2] * v[2];
-    }
-    const V3 om = v3(vb[3], vb[4], vb[5]);
-    const V3 Io = v3(Iw[0] * om.x + Iw[3] * om.y + Iw[4] * om.z,
-                     Iw[3] * om.x + Iw[1] * om.y + Iw[5] * om.z,
-                     Iw[4] * om.x + Iw[5] * om.y + Iw[2] * om.z);
-    const V3 gyro = cross(om, Io);  // velocity-product part of c
-    const V3 ta = v3(tb[3] - gyro.x, tb[4] - gyro.y, tb[5] - gyro.z);
-    const V3 dw = v3(Ii[0] * ta.x + Ii[3] * ta.y + Ii[4] * ta.z,
-                     Ii[3] * ta.x + Ii[1] * ta.y + Ii[5] * ta.z,
-                     Ii[4] * ta.x + Ii[5] * ta.y + Ii[2] * ta.z);
-    // c_lin = -m g, so M^-1 (tau - c) = tau/m + g for the linear block
-    const V3 vs = v3(vb[0] + P.h * (tb[0] * invm + P.gx), vb[1] + P.h * (tb[1] * invm + P.gy),
-                     vb[2] + P.h * (tb[2] * invm + P.gz));
-    const V3 ws = om + P.h * dw;
-    bC[b] = make_float4(qb[0], qb[1], qb[2], invm);
-    bV[b] = make_float4(vs.x, vs.y, vs.z, 3.0f * invm);
-    bW[b] = make_float4(ws.x, ws.y, ws.z, 0.f);
-    bI0[b] = make_float4(Ii[0], Ii[1], Ii[2], Ii[3]);
-    bI1[b] = make_float4(Ii[4], Ii[5], 0.f, 0.f);
+    free_body_predict(sq + qadr, sv + dadr, st + dadr, mi, P, bC[b], bV[b], bW[b], bI0[b], bI1[b]);
   }
   for (int b = tid; b < nb; b += BS) {
     accF[b] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1428,80 +1679,33 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     }
     if (k < nc) {
       const ContactKin K = contact_kin(base == 0 ? c0n : inn[k], base == 0 ? c0p : inp[k], gB, gM, bC, bV, bW);
-      const uint32_t sl = K.sl;
-      const int ga = K.ga, gb = K.gb, ba = K.ba, bb = K.bb;
-      const V3 n = K.n, p = K.p, t1 = K.t1, t2 = K.t2, vrel = K.vrel, wrel = K.wrel, ra = K.ra, rb = K.rb;
+      const int ba = K.ba, bb = K.bb;
+      const V3 n = K.n, t1 = K.t1, t2 = K.t2, ra = K.ra, rb = K.rb;
       const float phi = K.phi, trs = K.trs, mut = K.mut, mutor = K.mutor, murol = K.murol;
-      // impedance (Eqs. k_d_setting, r_scaling), x clamped to [0, 1]
-      const float x = fminf(fabsf(phi) * P.inv_width, 1.0f);
-      const bool lo = x < P.mid;
-      const float u = lo ? x * P.inv_mid : (1.0f - x) * P.inv_1mmid;
-      const float up = P.power2 ? u * u : powf(u, P.power);
-      const float gam = lo ? P.mid * up : 1.0f - (1.0f - P.mid) * up;
-      const float r = P.r_min + (P.r_max - P.r_min) * gam;
-      const float A = trs > 0.f ? r * __builtin_amdgcn_rcpf((1.0f - r) * trs) : 0.f;
+      const float A = heuristic_gain(phi, trs, P);
       float Af[NF];
 #pragma unroll
       for (int i = 0; i < NF; ++i) Af[i] = A;
       if (P.imp_diag) diag_impedance<NF>(n, t1, t2, ba, bb, ra, rb, bC, bI0, bI1, mut, mutor, murol, aa, Af);
       const float c0 = -P.k_user * phi;
-      const float vn = dot(n, vrel);
       float lam[NF];
-      // facet impulses lambda_f h = gain_f * max(arg_f, 0) (Eq. cf_wrench)
-      auto facets = [&](const float *G, float *L) {
-        if constexpr (CONDIM == 1) {
-          L[0] = G[0] * fmaxf(-aa * vn + c0, 0.f);
-        } else {
-          const float u1 = dot(t1, vrel), u2 = dot(t2, vrel);
-          L[0] = G[0] * fmaxf(-aa * (vn - mut * u1) + c0, 0.f);
-          L[1] = G[1] * fmaxf(-aa * (vn - mut * u2) + c0, 0.f);
-          L[2] = G[2] * fmaxf(-aa * (vn + mut * u1) + c0, 0.f);
-          L[3] = G[3] * fmaxf(-aa * (vn + mut * u2) + c0, 0.f);
-          if constexpr (CONDIM >= 4) {
-            const float wt = dot(n, wrel);
-            L[4] = G[4] * fmaxf(-aa * (vn - mutor * wt) + c0, 0.f);
-            L[5] = G[5] * fmaxf(-aa * (vn + mutor * wt) + c0, 0.f);
-          }
-          if constexpr (CONDIM == 6) {
-            const float o1 = dot(t1, wrel), o2 = dot(t2, wrel);
-            L[6] = G[6] * fmaxf(-aa * (vn - murol * o1) + c0, 0.f);
-            L[7] = G[7] * fmaxf(-aa * (vn - murol * o2) + c0, 0.f);
-            L[8] = G[8] * fmaxf(-aa * (vn + murol * o1) + c0, 0.f);
-            L[9] = G[9] * fmaxf(-aa * (vn + murol * o2) + c0, 0.f);
-          }
-        }
-      };
-      facets(Af, lam);
+      facet_impulses<CONDIM>(Af, K, aa, c0, lam);
       if constexpr (LEARN) {
         // learned gains, kept unless they predict more penetration or more
         // kinetic energy along the normal than the heuristic's, beyond the margin
         float Gl[NF], ll[NF];
 #pragma unroll
         for (int i = 0; i < NF; ++i) Gl[i] = A * __expf(fminf(fmaxf(lout[tid * mlp::NOUT + i], -mlp::CLIP), mlp::CLIP));
-        facets(Gl, ll);
-        const bool keep = learned_ok<NF>(lam, ll, vn, phi, trs, P.h, P.mlp_margin);
+        facet_impulses<CONDIM>(Gl, K, aa, c0, ll);
+        const bool keep = learned_ok<NF>(lam, ll, dot(n, K.vrel), phi, trs, P.h, P.mlp_margin);
         if (keep) {
 #pragma unroll
           for (int i = 0; i < NF; ++i) lam[i] = ll[i];
         }
         if (a.x_fallback) a.x_fallback[xbase + k] = keep ? 0 : 1;
       }
-      V3 f, tc = v3(0.f, 0.f, 0.f);
-      if constexpr (CONDIM == 1) {
-        f = lam[0] * n;
-      } else {
-        float N = lam[0] + lam[1] + lam[2] + lam[3];
-        const float e1 = -mut * (lam[0] - lam[2]), e2 = -mut * (lam[1] - lam[3]);
-        if constexpr (CONDIM >= 4) {
-          N += lam[4] + lam[5];
-          tc = (-mutor * (lam[4] - lam[5])) * n;
-        }
-        if constexpr (CONDIM == 6) {
-          N += lam[6] + lam[7] + lam[8] + lam[9];
-          tc = tc + (-murol * (lam[6] - lam[8])) * t1 + (-murol * (lam[7] - lam[9])) * t2;
-        }
-        f = N * n + e1 * t1 + e2 * t2;
-      }
+      V3 f, tc;
+      contact_wrench<CONDIM>(lam, K, f, tc);
       if (bb >= 0) {
         const V3 T = cross(rb, f) + tc;
         kB = bb;
@@ -1514,38 +1718,9 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
         WA = make_float4(-f.x, -f.y, -f.z, -T.x);
         WA2 = make_float2(-T.y, -T.z);
       }
-      // optional exports
       const size_t ci = xbase + k;
-      if (a.x_geom) { a.x_geom[2 * ci] = ga; a.x_geom[2 * ci + 1] = gb; }
-      if (a.x_sub) a.x_sub[ci] = slot_sub(sl);
-      if (a.x_dist) a.x_dist[ci] = phi;
-      if (a.x_pos) { a.x_pos[3 * ci] = p.x; a.x_pos[3 * ci + 1] = p.y; a.x_pos[3 * ci + 2] = p.z; }
-      if (a.x_frame) {
-        float *fr = a.x_frame + 9 * ci;
-        fr[0] = n.x; fr[1] = n.y; fr[2] = n.z;
-        fr[3] = t1.x; fr[4] = t1.y; fr[5] = t1.z;
-        fr[6] = t2.x; fr[7] = t2.y; fr[8] = t2.z;
-      }
-      if (a.x_imp) {
-#pragma unroll
-        for (int i = 0; i < NF; ++i) a.x_imp[(size_t)NF * ci + i] = lam[i];
-      }
-      if (!ART && a.x_feat) {  // training data of the learned gains
-        float fe[mlp::NIN];
-        contact_features(K, P.h, fe);
-#pragma unroll
-        for (int i = 0; i < mlp::NIN; ++i) a.x_feat[(size_t)mlp::NIN * ci + i] = fe[i];
-      }
-      if (!ART && a.x_target) {  // log of the exact diagonal gain over the heuristic's, clipped
-        float Ad[NF];
-        diag_impedance<NF>(n, t1, t2, ba, bb, ra, rb, bC, bI0, bI1, mut, mutor, murol, aa, Ad);
-#pragma unroll
-        for (int i = 0; i < mlp::NOUT; ++i) {
-          float t = 0.f;
-          if (i < NF && A > 0.f && Ad[i] > 0.f) t = fminf(fmaxf(__logf(Ad[i] / A), -mlp::CLIP), mlp::CLIP);
-          a.x_target[(size_t)mlp::NOUT * ci + i] = t;
-        }
-      }
+      export_contact<NF>(a, ci, K, lam);
+      if (!ART) export_training<NF>(a, ci, K, A, aa, P.h, bC, bI0, bI1);
     }
     // Per-body sums of the chunk's wrench entries in fixed point: integer
     // additions commute, so the order of the LDS atomics does not change the
@@ -1593,28 +1768,8 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       qadr = bc.qadr;
       dadr = bc.dadr;
     }
-    const float4 C = bC[b], Vs = bV[b], Ws = bW[b], I0 = bI0[b], I1 = bI1[b];
-    const float4 F = accF[b], T = accT[b];
-    const V3 vp = v3(Vs.x + C.w * F.x, Vs.y + C.w * F.y, Vs.z + C.w * F.z);
-    const V3 wp = v3(Ws.x + I0.x * T.x + I0.w * T.y + I1.x * T.z,
-                     Ws.y + I0.w * T.x + I0.y * T.y + I1.y * T.z,
-                     Ws.z + I1.x * T.x + I1.y * T.y + I0.z * T.z);
-    float *qb = sq + qadr, *vb = sv + dadr;
-    vb[0] = vp.x; vb[1] = vp.y; vb[2] = vp.z; vb[3] = wp.x; vb[4] = wp.y; vb[5] = wp.z;
-    qb[0] = C.x + P.h * vp.x;
-    qb[1] = C.y + P.h * vp.y;
-    qb[2] = C.z + P.h * vp.z;
-    // quat <- normalize(exp(h w) (x) quat), world-frame angular velocity
-    const V3 th = P.h * wp;
-    float ew, ex, ey, ez;
-    quat_of_rotvec(th, ew, ex, ey, ez);
-    const float qw0 = qb[3], qx0 = qb[4], qy0 = qb[5], qz0 = qb[6];
-    const float nw_ = ew * qw0 - ex * qx0 - ey * qy0 - ez * qz0;
-    const float nx_ = ew * qx0 + ex * qw0 + ey * qz0 - ez * qy0;
-    const float ny_ = ew * qy0 - ex * qz0 + ey * qw0 + ez * qx0;
-    const float nz_ = ew * qz0 + ex * qy0 - ey * qx0 + ez * qw0;
-    const float inv = rsqrtf(nw_ * nw_ + nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
-    qb[3] = nw_ * inv; qb[4] = nx_ * inv; qb[5] = ny_ * inv; qb[6] = nz_ * inv;
+    float *qb = sq + qadr;
+    free_body_correct(bC[b], bV[b], bW[b], bI0[b], bI1[b], accF[b], accT[b], qb, P, qb, sv + dadr);
   }
   __syncthreads();
 }
@@ -1688,6 +1843,178 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   float *qo = a.q_out + (size_t)w * nq, *vo = a.v_out + (size_t)w * nv;
   for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
   for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
+}
+
+// ====================================================================
+// resolution of worlds of free bodies, one body per lane
+// ====================================================================
+// When every body is a free body without children, a world has at most BS
+// bodies and no actuators or learned gains are set, lane b owns body b: it
+// reads the body's q, v and tau entries itself (no rows staged in LDS), keeps
+// its accumulated contact wrench in registers through the contact chunks and
+// writes q+ and v+.  LDS holds only what other lanes read: per body (COM |
+// 1/m), (v_s | 3/m), (w_s | -) and the inverse world inertia, the fixed-point
+// chunk sums, and per geom its body and friction (8.7 KB for 64 spheres and
+// 69 geoms, against 15.5 KB with staged rows), so sixteen one-wave worlds fit
+// a CU together.  The next chunk's contact records are loaded while the
+// current chunk is resolved.  Arithmetic as in resolve_world.
+size_t resolve_free_lds_bytes(int nb, int ng) {
+  return sizeof(float4) * 5 * (size_t)nb + sizeof(int) * 8 * (size_t)pad4(nb) + sizeof(int) * (size_t)pad4(ng) +
+         sizeof(float4) * (size_t)ng;
+}
+
+template <int CONDIM, int BS>
+__global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
+  constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
+  extern __shared__ float4 lds[];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int nb = a.nb, ng = a.ng, nbp = pad4(nb);
+  float4 *bC = lds, *bV = bC + nb, *bW = bV + nb, *bI0 = bW + nb, *bI1 = bI0 + nb;
+  int *fx = reinterpret_cast<int *>(bI1 + nb);
+  int *fxE = fx + 6 * nbp;
+  unsigned long long *fxQ = reinterpret_cast<unsigned long long *>(fx);  // [3][nbp] packed sums
+  int *gB = fx + 8 * nbp;
+  float4 *gM = reinterpret_cast<float4 *>(gB + pad4(ng));
+  const Params P = a.p;
+  const size_t cbase = (size_t)w * a.ncon_max;
+
+  // every independent global load first: the count, the first chunk of
+  // contact records, the lane's body, the per-geom inputs
+  const int nc = a.ncon[w];
+  float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
+  if (tid < a.ncon_max) {  // records beyond the count are never used
+    cn = a.cnp[cbase + tid];
+    cp = a.cpos[cbase + tid];
+  }
+  const bool own = tid < nb;
+  float qb[7], vb[6], tb[6];
+  float4 mi = make_float4(1.f, 1.f, 1.f, 1.f);
+#pragma unroll
+  for (int i = 0; i < 7; ++i) qb[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) vb[i] = tb[i] = 0.f;
+  if (own) {
+    const float *qs = a.q + (size_t)w * a.nq + 7 * tid, *vs = a.v + (size_t)w * a.nv + 6 * tid;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qb[i] = qs[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vb[i] = vs[i];
+    if (a.tau) {
+      const float *ts = a.tau + (size_t)w * a.nv + 6 * tid;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) tb[i] = ts[i];
+    }
+    mi = a.bmi[(size_t)w * nb + tid];
+  }
+  for (int g = tid; g < ng; g += BS) {
+    gB[g] = a.gbody[g];
+    const float mu_t = a.gdat[(size_t)w * ng + g].w;
+    float2 fr = make_float2(0.f, 0.f);
+    if (CONDIM >= 4) fr = a.gfr2[(size_t)w * ng + g];
+    gM[g] = make_float4(mu_t, fr.x, fr.y, 0.f);
+  }
+  for (int i = tid; i < 8 * nbp; i += BS) fx[i] = i >= 6 * nbp ? FX_EMPTY : 0;
+  if (own) free_body_predict(qb, vb, tb, mi, P, bC[tid], bV[tid], bW[tid], bI0[tid], bI1[tid]);
+  float4 F = make_float4(0.f, 0.f, 0.f, 0.f), T = F;  // the lane's body: accumulated force and torque
+  __syncthreads();
+
+  const float aa = P.k_user * P.h + P.d_user;
+  for (int base = 0; base < nc; base += BS) {
+    const int k = base + tid, kn = k + BS;
+    float4 nn = make_float4(0.f, 0.f, 0.f, 0.f), np = nn;
+    if (kn < nc) {  // next chunk, in flight during this one
+      nn = a.cnp[cbase + kn];
+      np = a.cpos[cbase + kn];
+    }
+    int kA = nb, kB = nb;  // key nb = no body (static geom or idle lane)
+    float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
+    float2 WA2 = make_float2(0.f, 0.f), WB2 = WA2;
+    if (k < nc) {
+      const ContactKin K = contact_kin(cn, cp, gB, gM, bC, bV, bW);
+      const float A = heuristic_gain(K.phi, K.trs, P);
+      float Af[NF];
+#pragma unroll
+      for (int i = 0; i < NF; ++i) Af[i] = A;
+      if (P.imp_diag)
+        diag_impedance<NF>(K.n, K.t1, K.t2, K.ba, K.bb, K.ra, K.rb, bC, bI0, bI1, K.mut, K.mutor, K.murol, aa, Af);
+      float lam[NF];
+      facet_impulses<CONDIM>(Af, K, aa, -P.k_user * K.phi, lam);
+      V3 f, tc;
+      contact_wrench<CONDIM>(lam, K, f, tc);
+      if (K.bb >= 0) {
+        const V3 Tb = cross(K.rb, f) + tc;
+        kB = K.bb;
+        WB = make_float4(f.x, f.y, f.z, Tb.x);
+        WB2 = make_float2(Tb.y, Tb.z);
+      }
+      if (K.ba >= 0) {
+        const V3 Ta = cross(K.ra, f) + tc;
+        kA = K.ba;
+        WA = make_float4(-f.x, -f.y, -f.z, -Ta.x);
+        WA2 = make_float2(-Ta.y, -Ta.z);
+      }
+      export_contact<NF>(a, cbase + k, K, lam);
+      export_training<NF>(a, cbase + k, K, A, aa, P.h, bC, bI0, bI1);
+    }
+    // per-body fixed-point sums of the chunk (as in resolve_world)
+    if (kA < nb) fx_exponents(fxE + kA, nbp, WA, WA2);
+    if (kB < nb) fx_exponents(fxE + kB, nbp, WB, WB2);
+    __syncthreads();
+    if (kA < nb) fx_add<BS>(fxQ, fxE, kA, nbp, WA, WA2);
+    if (kB < nb) fx_add<BS>(fxQ, fxE, kB, nbp, WB, WB2);
+    __syncthreads();
+    if (own) {
+      const int ef = fxE[tid], et = fxE[nbp + tid];
+      if (ef != FX_EMPTY) {  // an entry raises both exponents
+        const unsigned long long q0 = fxQ[tid], q1 = fxQ[nbp + tid], q2 = fxQ[2 * nbp + tid];
+        F.x += fx_value<BS>(fx_lo(q0), ef);
+        F.y += fx_value<BS>(fx_hi(q0), ef);
+        F.z += fx_value<BS>(fx_lo(q1), ef);
+        T.x += fx_value<BS>(fx_hi(q1), et);
+        T.y += fx_value<BS>(fx_lo(q2), et);
+        T.z += fx_value<BS>(fx_hi(q2), et);
+        fxQ[tid] = 0ull; fxQ[nbp + tid] = 0ull; fxQ[2 * nbp + tid] = 0ull;
+        fxE[tid] = FX_EMPTY;
+        fxE[nbp + tid] = FX_EMPTY;
+      }
+    }
+    __syncthreads();
+    cn = nn;
+    cp = np;
+  }
+
+  // velocity correction and integration of the lane's body, stored directly
+  if (own) {
+    float qo[7], vo[6];
+    free_body_correct(bC[tid], bV[tid], bW[tid], bI0[tid], bI1[tid], F, T, qb, P, qo, vo);
+    float *qd = a.q_out + (size_t)w * a.nq + 7 * tid, *vd = a.v_out + (size_t)w * a.nv + 6 * tid;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qd[i] = qo[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vd[i] = vo[i];
+  }
+}
+
+template <int CONDIM>
+static hipError_t launch_resolve_free_c(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  switch (block) {
+    case 64: hipLaunchKernelGGL((resolve_free_kernel<CONDIM, 64>), dim3(nworld), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((resolve_free_kernel<CONDIM, 128>), dim3(nworld), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((resolve_free_kernel<CONDIM, 256>), dim3(nworld), dim3(256), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_free(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
+  if (a.nsub > 0 || a.mlp || a.act || a.nb > block) return hipErrorInvalidValue;
+  switch (a.condim) {
+    case 1: return launch_resolve_free_c<1>(a, nworld, block, lds, s);
+    case 3: return launch_resolve_free_c<3>(a, nworld, block, lds, s);
+    case 4: return launch_resolve_free_c<4>(a, nworld, block, lds, s);
+    case 6: return launch_resolve_free_c<6>(a, nworld, block, lds, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ====================================================================
