@@ -38,17 +38,18 @@ PAPER_CONTEXT = ("context only, not a target: the paper reports 2-3x the through
                  "32-core CPU, precision not stated, no absolute env-steps/s printed")
 
 
-def alg_bytes(nq, nv, nb, ng, contacts):
+def alg_bytes(nq, nv, nb, ng, contacts, condim=3):
     """Algorithmic HBM bytes per world-step of each kernel (contacts = C_w).
 
     collide: read q and per-world geom data (size, friction: 16 B/geom), write
              the contact records (32 B each) and the count.
-    resolve: read q, v, per-body mass/inertia (16 B/body), per-world geom data,
+    resolve: read q, v, per-body mass/inertia (16 B/body), per-world geom
+             friction (mu_t: 4 B/geom, plus mu_tor and mu_rol for condim >= 4),
              the contact records and count; write q and v.
     Shared tables (candidate slots, static geom poses) are read from L2 by every
     world and are not counted."""
     collide = 4 * nq + 16 * ng + 32 * contacts + 8
-    resolve = 8 * nq + 8 * nv + 16 * nb + 16 * ng + 32 * contacts + 4
+    resolve = 8 * nq + 8 * nv + 16 * nb + (4 + (8 if condim >= 4 else 0)) * ng + 32 * contacts + 4
     return collide, resolve
 
 
@@ -305,7 +306,7 @@ def main():
     ms_step = wall * 1e3 / K
     env_steps = nw * K / wall
     imp = contacts_per_step * K / wall
-    b_col, b_res = alg_bytes(nq, nv, nb, ng, c_w)
+    b_col, b_res = alg_bytes(nq, nv, nb, ng, c_w, args.condim)
     t_col, t_res = us_col * 1e-6, us_res * 1e-6
     if t_col >= t_res:
         dom, t_dom, b_dom = "collide_kernel", t_col, b_col

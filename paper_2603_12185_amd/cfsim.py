@@ -87,6 +87,10 @@ def load(path: str = LIB_PATH):
     """Load libcfsim.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch loaded
+        # (a second runtime loaded ahead of torch's leaves one of them without
+        # the device)
+        import torch  # noqa: F401
         if not os.path.exists(path):
             raise ImportError(f"{path} is missing: build it with paper_2603_12185_amd.build.build()")
         L = C.CDLL(path)
@@ -143,6 +147,11 @@ class Model:
     """A cf_model on the current HIP device."""
 
     def __init__(self, scene):
+        import torch
+        # torch's HIP context first: the library's own first HIP call would
+        # otherwise leave torch unable to initialise the device
+        if not torch.cuda.is_available():
+            raise RuntimeError("cfsim.Model needs a HIP device")
         L = load()
         d, keep = make_desc(scene)
         h = C.c_void_p()

@@ -53,6 +53,7 @@ struct cf_model {
   size_t lds_backward = 0;
   bool rollout_steps = false;  // autotuner found T cf_step calls faster than the persistent kernel
   float4 *d_bmi = nullptr, *d_gdat = nullptr, *d_gpos = nullptr, *d_gquat = nullptr;
+  float *d_gmu = nullptr;  // [nworld][ngeom] tangential friction alone
   float2 *d_gfr2 = nullptr;
   int gpos_ws = 0, gquat_ws = 0;
   // workspace
@@ -90,7 +91,7 @@ void free_model(cf_model *m) {
   (void)hipFree(m->d_slots); (void)hipFree(m->d_gbody); (void)hipFree(m->d_gorient); (void)hipFree(m->d_act);
   (void)hipFree(m->d_mlp_img);
   (void)hipFree(m->d_body); (void)hipFree(m->d_sub); (void)hipFree(m->d_bmi); (void)hipFree(m->d_gdat);
-  (void)hipFree(m->d_gpos); (void)hipFree(m->d_gquat); (void)hipFree(m->d_gfr2);
+  (void)hipFree(m->d_gpos); (void)hipFree(m->d_gquat); (void)hipFree(m->d_gfr2); (void)hipFree(m->d_gmu);
   (void)hipFree(m->d_cnp); (void)hipFree(m->d_cpos); (void)hipFree(m->d_ncon); (void)hipFree(m->d_over);
   for (auto &s : m->events)
     for (auto e : s.e) (void)hipEventDestroy(e);
@@ -376,9 +377,11 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
     const double *I = d->body_inertia + 3 * i;
     bmi[i] = make_float4((float)d->body_mass[i], (float)I[0], (float)I[1], (float)I[2]);
   }
+  std::vector<float> gmu(wg);
   for (size_t i = 0; i < wg; ++i) {
     const double *s = d->geom_size + 3 * i, *f = d->geom_friction + 3 * i;
     gdat[i] = make_float4((float)s[0], (float)s[1], (float)s[2], (float)f[0]);
+    gmu[i] = (float)f[0];
   }
   auto uniform = [&](const double *a, int width) {
     for (int w = 1; w < nw; ++w)
@@ -415,6 +418,7 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   chk(upload(&m->d_sub, subs));
   chk(upload(&m->d_bmi, bmi));
   chk(upload(&m->d_gdat, gdat));
+  chk(upload(&m->d_gmu, gmu));
   chk(upload(&m->d_gpos, gpos));
   chk(upload(&m->d_gquat, gquat));
   if (m->condim >= 4) chk(upload(&m->d_gfr2, gfr2));
@@ -466,7 +470,7 @@ static cf::CollideArgs collide_args(const cf_model *m) {
 
 static cf::ResolveArgs resolve_args(const cf_model *m) {
   cf::ResolveArgs ra{};
-  ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
+  ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gmu = m->d_gmu; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
   ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats;
   ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
   ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;

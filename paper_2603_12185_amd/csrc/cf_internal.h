@@ -91,6 +91,7 @@ struct ResolveArgs {
   float *q_out, *v_out;
   const float4 *bmi;            // [nw][nb] (m, Ixx, Iyy, Izz) principal inertia
   const float4 *gdat;           // [nw][ng] (size0, size1, size2, mu_t)
+  const float *gmu;             // [nw][ng] mu_t alone (what the resolution reads)
   const float2 *gfr2;           // [nw][ng] (mu_tor, mu_rol) or null when condim < 4
   const int *gbody;             // [ng]
   const BodyC *body;            // [nb]

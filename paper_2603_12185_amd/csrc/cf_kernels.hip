@@ -3,25 +3,30 @@
 // Two kernels per step, one workgroup per world (64, 128 or 256 threads):
 //
 //  collide_kernel  analytic narrow phase over the model's candidate slots
-//                  (plane-sphere, plane-capsule, plane-box corner, sphere-sphere)
-//                  in canonical order.  Pass 1 tests every slot in float32 on
-//                  16-byte LDS records and keeps, in order, the slots within a
-//                  small band of contact; pass 2 evaluates only those candidates
-//                  (decision, gap, normal, point) from float64 geometry, except
-//                  sphere pairs centred on their bodies (float32).  Both
-//                  passes compact in order with wave ballots plus per-wave
-//                  counts, so contacts land in the flat structure-of-arrays
-//                  buffer [world][ncon_max] without atomics.
+//                  (plane-sphere, plane-capsule, plane-box corner, sphere-sphere,
+//                  box-sphere, box-capsule) in canonical order.  Pass 1 tests
+//                  every slot in float32 on 16-byte LDS records and keeps, in
+//                  order, the slots within a small band of contact; pass 2
+//                  evaluates only those candidates (decision, gap, normal,
+//                  point) from float64 geometry, except sphere pairs centred on
+//                  their bodies (float32).  Static planes against a trailing
+//                  block of spheres are tested as rows, and the block's pairs
+//                  through hit masks (an MFMA Gram matrix for up to 64 spheres
+//                  in one wave).  Compaction is in order with wave ballots plus
+//                  per-wave counts, so contacts land in the flat
+//                  structure-of-arrays buffer [world][ncon_max] without atomics.
 //
 //  resolve_kernel  smooth prediction v_s = v + h M^-1 (tau - c) (Eq. smooth_vel);
 //                  one lane per contact: tangent basis, relative velocity at v_s,
 //                  impedance A = r/(1-r)/(tr_a + tr_b) (Eqs. k_d_setting, r_scaling),
 //                  facet impulses lambda*h = A max(-(k h + d) J~ v_s - k phi, 0)
-//                  (Eq. cf_wrench) and the contact wrench J~^T lambda h; a
-//                  deterministic per-body segmented reduction of the wrenches
-//                  (wave64 ballot key matching, fixed summation order, no
-//                  atomics); velocity correction v+ = v_s + M^-1 p
-//                  (Eq. vel_correction) and semi-implicit Euler integration.
+//                  (Eq. cf_wrench) and the contact wrench J~^T lambda h; per-body
+//                  sums of the wrenches in fixed point with LDS integer atomics
+//                  (order-free, so bitwise reproducible; no global atomics);
+//                  velocity correction v+ = v_s + M^-1 p (Eq. vel_correction)
+//                  and semi-implicit Euler integration.  Worlds of free bodies
+//                  take resolve_free_kernel: the same steps with each body's
+//                  state held in its own lane.
 //
 // Free bodies: M is block diagonal (m I3, R diag(I) R^T) and the COM trace of
 // a body is 3/m, so the factorisation of M reduces to the per-body inverse
@@ -38,6 +43,44 @@ static __host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }
 __device__ inline unsigned long long lanes_below(int lane) {
   return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
+
+// Wave64 inclusive prefix sum and maximum over lanes by DPP row shifts and
+// row broadcasts (no LDS round trips); the last lane holds the total.
+__device__ inline int wave_incl_sum(int x) {
+  int v = x;
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+  return v;
+}
+__device__ inline float wave_incl_sum(float x) {
+  float v = x;
+  const int z = 0;
+  v += __int_as_float(__builtin_amdgcn_update_dpp(z, __float_as_int(v), 0x111, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(z, __float_as_int(v), 0x112, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(z, __float_as_int(v), 0x114, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(z, __float_as_int(v), 0x118, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(z, __float_as_int(v), 0x142, 0xA, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(z, __float_as_int(v), 0x143, 0xC, 0xF, false));
+  return v;
+}
+__device__ inline float wave_incl_max(float x) {
+  float v = x;
+  // lanes without a source keep their own value
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x111, 0xF, 0xF, false)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x112, 0xF, 0xF, false)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x114, 0xF, 0xF, false)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x118, 0xF, 0xF, false)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x142, 0xA, 0xF, false)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x143, 0xC, 0xF, false)));
+  return v;
+}
+// Value of lane 63 (the total of an inclusive scan), wave-uniform.
+__device__ inline int wave_last(int v) { return __builtin_amdgcn_readlane(v, 63); }
+__device__ inline float wave_last(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
 
 // Exclusive prefix of `flag` over the workgroup in thread order; *total gets
 // the workgroup count.  wcnt: shared [2][BS/64]; callers alternate `parity`
@@ -72,14 +115,9 @@ template <int BS>
 __device__ inline int block_scan_int(int x, int *total, int *wsum) {
   constexpr int NW = BS / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int inc = x;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(inc, off);
-    if (lane >= off) inc += y;
-  }
+  const int inc = wave_incl_sum(x);
   if (NW == 1) {
-    *total = __shfl(inc, 63);
+    *total = wave_last(inc);
     return inc - x;
   }
   if (lane == 63) wsum[wave] = inc;
@@ -99,7 +137,7 @@ __device__ inline int block_scan_int(int x, int *total, int *wsum) {
 // Maximum over the workgroup (every thread gets it); wmax: shared [BS/64].
 template <int BS>
 __device__ inline float block_max(float x, float *wmax) {
-  for (int off = 32; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off));
+  x = wave_last(wave_incl_max(x));
   if (BS == 64) return x;
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = x;
   __syncthreads();
@@ -664,6 +702,22 @@ __device__ inline bool sphere_pair_hit(float4 Gi, float4 Gj, float margin) {
   return (R > 0.f) & (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < R * R);
 }
 
+// Contact record of a sphere pair (a's centre and radius in A, b's in B):
+// n = (c_b - c_a)/|c_b - c_a| (+z for coincident centres), phi = |c_b - c_a| -
+// r_a - r_b, point c_a + (r_a + phi/2) n, the slot word in the last lane.  The
+// distance and the normal come from one hardware reciprocal square root.
+__device__ inline void sphere_pair_record(float4 A, float4 B, uint32_t sl, float4 &cn, float4 &cp) {
+  const V3 d = v3(B.x - A.x, B.y - A.y, B.z - A.z);
+  const float d2 = dot(d, d);
+  const bool apart = d2 >= 1e-24f;
+  const float inv = apart ? __builtin_amdgcn_rsqf(d2) : 0.f;
+  const V3 n = apart ? inv * d : v3(0.f, 0.f, 1.f);
+  const float phi = d2 * inv - A.w - B.w;
+  const float k = A.w + 0.5f * phi;
+  cn = make_float4(n.x, n.y, n.z, phi);
+  cp = make_float4(A.x + k * n.x, A.y + k * n.y, A.z + k * n.z, __uint_as_float(sl));
+}
+
 template <int BS, int NWD>
 __device__ inline void sphere_masks(const float4 *Gs, const int *gbd, int g0, int S, float margin,
                                     unsigned long long *rm) {
@@ -737,18 +791,14 @@ __device__ __attribute__((always_inline)) inline void sphere_masks_mfma(const fl
   const int l = threadIdx.x;  // the workgroup is one wave
   const bool real = l < S;
   const float4 G = real ? Gs[g0 + l] : make_float4(0.f, 0.f, 0.f, 0.f);
-  float cx = real ? G.x : 0.f, cy = real ? G.y : 0.f, cz = real ? G.z : 0.f;
-  for (int off = 32; off > 0; off >>= 1) {
-    cx += __shfl_xor(cx, off);
-    cy += __shfl_xor(cy, off);
-    cz += __shfl_xor(cz, off);
-  }
   const float invS = 1.0f / (float)S;
-  const float x = G.x - cx * invS, y = G.y - cy * invS, z = G.z - cz * invS;
+  const float cx = wave_last(wave_incl_sum(real ? G.x : 0.f)) * invS,
+              cy = wave_last(wave_incl_sum(real ? G.y : 0.f)) * invS,
+              cz = wave_last(wave_incl_sum(real ? G.z : 0.f)) * invS;
+  const float x = G.x - cx, y = G.y - cy, z = G.z - cz;
   const float rho = G.w + 0.5f * margin;
   const float c2 = fmaf(z, z, fmaf(y, y, x * x)), r2 = rho * rho;
-  float M = real ? c2 + r2 : 0.f;
-  for (int off = 32; off > 0; off >>= 1) M = fmaxf(M, __shfl_xor(M, off));
+  const float M = wave_last(wave_incl_max(real ? c2 + r2 : 0.f));
   const float eps = M * (1.0f / 65536.0f);
   // padding rows and columns sit at g >= 4 M + 1 > eps from everything
   const float sa = real ? c2 - r2 : 4.0f * M + 1.0f;
@@ -891,7 +941,7 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
 
   // Pass-1 band: float32 gaps are accurate to a few ulp of the coordinates and
   // sizes involved; one band per world, from the largest of them.
-  float band;
+  float band, pband;
   {
     float ext = 0.f;
     for (int g = tid; g < a.ng; g += BS) {
@@ -902,6 +952,9 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
       ext = fmaxf(ext, fmaxf(fmaxf(Of[o].s[0], Of[o].s[1]), Of[o].s[2]));
     ext = block_max<BS>(ext, wmax);
     band = 1e-4f + 8e-6f * ext;
+    // plane rows: a float32 gap within pband of the margin is decided in
+    // float64 (float32 rounding of a gap is a few 1e-8 of the extent)
+    pband = 1e-6f + 1e-6f * ext;
   }
   int running = 0, ncand = 0, par = 0;
   // Pass 2 over the candidate list: float64 decision, ordered store.
@@ -917,15 +970,8 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
         if (slot_type(sl) == kSphereSphere && go[ga] < 0 && go[gb] < 0) {
           // two spheres centred on their bodies: the centres are exact float32
           // state values and the gap needs no rotation, float32 suffices
-          const float4 A = Gs[ga], B = Gs[gb];
-          const V3 d = v3(B.x - A.x, B.y - A.y, B.z - A.z);
-          const float dist = sqrtf(dot(d, d));
-          const V3 n = dist >= 1e-12f ? (1.0f / dist) * d : v3(0.f, 0.f, 1.f);
-          const float phi = dist - A.w - B.w;
-          const float k = A.w + 0.5f * phi;
-          hit = phi < a.margin;
-          cn = make_float4(n.x, n.y, n.z, phi);
-          cp = make_float4(A.x + k * n.x, A.y + k * n.y, A.z + k * n.z, __uint_as_float(sl));
+          sphere_pair_record(Gs[ga], Gs[gb], sl, cn, cp);
+          hit = cn.w < a.margin;
         } else {
           double nd[3], pd[3];
           const double phi = slot_eval(sl, Gs, go, Od, nd, pd);
@@ -949,27 +995,39 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
 
   // Plane rows: when the slots before the sphere block are exactly every
   // (static plane p, sphere i) pair, plane-major, each lane takes a sphere and
-  // decides every plane's pair directly in float64 (the decision and the
-  // record of the per-slot path, without its slot words, type dispatch and
-  // candidate list); hits are stored in slot order by a workgroup scan.
+  // decides every plane's pair directly (without slot words, type dispatch
+  // and candidate list): in float32, or, when the float32 gap lies within
+  // pband of the margin, by the per-slot path's float64 decision and record;
+  // hits are stored in slot order by a workgroup scan.
   if (a.npl > 0) {
     const int g0 = a.sph0, S = a.nsph;
     for (int pl = 0; pl < a.npl; ++pl) {
-      const Pose<double> &Pd = Od[go[pl]];
-      const double nx = Pd.r[2], ny = Pd.r[5], nz = Pd.r[8];  // plane normal: local z
+      const Pose<float> &Pf = Of[go[pl]];
+      const float px = Pf.p[0], py = Pf.p[1], pz = Pf.p[2];
+      const float nx = Pf.r[2], ny = Pf.r[5], nz = Pf.r[8];  // plane normal: local z
       for (int r0 = 0; r0 < S; r0 += BS) {
         const int i = r0 + tid;
         bool hit = false;
         float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
         if (i < S) {
           const float4 G = Gs[g0 + i];
-          const double cx = G.x, cy = G.y, cz = G.z, rad = G.w;
-          const double phi = nx * (cx - Pd.p[0]) + ny * (cy - Pd.p[1]) + nz * (cz - Pd.p[2]) - rad;
-          const double k = rad + 0.5 * phi;
-          hit = phi < (double)a.margin;
-          cn = make_float4((float)nx, (float)ny, (float)nz, (float)phi);
-          cp = make_float4((float)(cx - k * nx), (float)(cy - k * ny), (float)(cz - k * nz),
-                           __uint_as_float(slot_pack(pl, g0 + i, 0, kPlaneSphere)));
+          const uint32_t sl = slot_pack(pl, g0 + i, 0, kPlaneSphere);
+          const float phi = fmaf(nx, G.x - px, fmaf(ny, G.y - py, nz * (G.z - pz))) - G.w;
+          if (fabsf(phi - a.margin) > pband) {
+            const float k = G.w + 0.5f * phi;
+            hit = phi < a.margin;
+            cn = make_float4(nx, ny, nz, phi);
+            cp = make_float4(G.x - k * nx, G.y - k * ny, G.z - k * nz, __uint_as_float(sl));
+          } else {  // near the margin: the float64 decision and record
+            const Pose<double> &Pd = Od[go[pl]];
+            const double dx = Pd.r[2], dy = Pd.r[5], dz = Pd.r[8];
+            const double cx = G.x, cy = G.y, cz = G.z, rad = G.w;
+            const double phd = dx * (cx - Pd.p[0]) + dy * (cy - Pd.p[1]) + dz * (cz - Pd.p[2]) - rad;
+            const double k = rad + 0.5 * phd;
+            hit = phd < (double)a.margin;
+            cn = make_float4((float)dx, (float)dy, (float)dz, (float)phd);
+            cp = make_float4((float)(cx - k * dx), (float)(cy - k * dy), (float)(cz - k * dz), __uint_as_float(sl));
+          }
         }
         int tot;
         const int idx = running + block_scan<BS>(hit, &tot, wcnt, par);
@@ -1080,14 +1138,10 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
           const int pos = running + lo + idx;
           if (idx < nwin && pos < cap) {
             const uint32_t sl = cand[idx];
-            const float4 A = Gs[slot_ga(sl)], B = Gs[slot_gb(sl)];
-            const V3 d = v3(B.x - A.x, B.y - A.y, B.z - A.z);
-            const float dist = sqrtf(dot(d, d));
-            const V3 n = dist >= 1e-12f ? (1.0f / dist) * d : v3(0.f, 0.f, 1.f);
-            const float phi = dist - A.w - B.w;
-            const float kk = A.w + 0.5f * phi;
-            outn[pos] = make_float4(n.x, n.y, n.z, phi);
-            outp[pos] = make_float4(A.x + kk * n.x, A.y + kk * n.y, A.z + kk * n.z, __uint_as_float(sl));
+            float4 cn, cp;
+            sphere_pair_record(Gs[slot_ga(sl)], Gs[slot_gb(sl)], sl, cn, cp);
+            outn[pos] = cn;
+            outp[pos] = cp;
           }
         }
         __syncthreads();
@@ -1346,10 +1400,22 @@ __device__ inline bool learned_ok(const float *lh, const float *ll, float vn, fl
 __device__ inline void free_body_predict(const float *qb, const float *vb, const float *tb, float4 mi,
                                          const Params &P, float4 &C, float4 &Vs, float4 &Ws, float4 &I0,
                                          float4 &I1) {
-  float R[9];
-  quat_to_rot<float>(qb[3], qb[4], qb[5], qb[6], R);
   // hardware reciprocals (1 ulp) for the per-body inverses
   const float invm = __builtin_amdgcn_rcpf(mi.x);
+  if (mi.y == mi.z && mi.y == mi.w) {
+    // isotropic inertia (spheres, cubes): I_w = I 1 in every orientation, so
+    // the gyroscopic bias w x I_w w vanishes and I_w^-1 = (1/I) 1
+    const float ei = __builtin_amdgcn_rcpf(mi.y);
+    C = make_float4(qb[0], qb[1], qb[2], invm);
+    Vs = make_float4(vb[0] + P.h * (tb[0] * invm + P.gx), vb[1] + P.h * (tb[1] * invm + P.gy),
+                     vb[2] + P.h * (tb[2] * invm + P.gz), 3.0f * invm);
+    Ws = make_float4(vb[3] + P.h * (ei * tb[3]), vb[4] + P.h * (ei * tb[4]), vb[5] + P.h * (ei * tb[5]), 0.f);
+    I0 = make_float4(ei, ei, ei, 0.f);
+    I1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  float R[9];
+  quat_to_rot<float>(qb[3], qb[4], qb[5], qb[6], R);
   const float d[3] = {mi.y, mi.z, mi.w},
               e[3] = {__builtin_amdgcn_rcpf(mi.y), __builtin_amdgcn_rcpf(mi.z), __builtin_amdgcn_rcpf(mi.w)};
   // world inertia R diag(I) R^T and its inverse R diag(1/I) R^T (xx, yy, zz, xy, xz, yz)
@@ -1520,12 +1586,15 @@ __device__ inline void export_training(const ResolveArgs &a, size_t ci, const Co
 // that flags a non-finite entry.
 constexpr int FX_EMPTY = -1024, FX_ZERO = -1000, FX_BAD = 1 << 20;
 
-// e with |x|, |y|, |z| < 2^e: the binary exponent of the largest, FX_ZERO
-// when all are zero (zero fits any scale) and FX_BAD when one is not finite.
+// e with |x|, |y|, |z| < 2^e: from the bit pattern of the largest magnitude
+// (magnitudes of floats order as their bit patterns), e = biased exponent -
+// 126 (the frexp exponent of a normal float; -126 bounds every subnormal);
+// FX_ZERO when all are zero (zero fits any scale) and FX_BAD when one is
+// infinite or NaN.
 __device__ inline int fx_exp(float x, float y, float z) {
-  const float m = fmaxf(fmaxf(fabsf(x), fabsf(y)), fabsf(z));
-  if (!(fabsf(x) + fabsf(y) + fabsf(z) <= 3.40282347e38f)) return FX_BAD;  // NaN or infinity
-  return m == 0.f ? FX_ZERO : __builtin_amdgcn_frexp_expf(m);
+  const uint32_t m = max(max(__float_as_uint(x) & 0x7fffffffu, __float_as_uint(y) & 0x7fffffffu),
+                         __float_as_uint(z) & 0x7fffffffu);
+  return m == 0u ? FX_ZERO : m >= 0x7f800000u ? FX_BAD : (int)(m >> 23) - 126;
 }
 
 // Headroom bits of a chunk's sums: a body gets at most one entry per lane (a
@@ -1552,7 +1621,8 @@ template <int BS>
 __device__ inline void fx_add(unsigned long long *q, const int *e, int k, int stride, float4 a, float2 b) {
   constexpr int L = fx_headroom<BS>();
   const int sf = 31 - e[k] - L, st = 31 - e[stride + k] - L;
-  auto u = [&](float x, int sh) { return (unsigned long long)(long long)__float2int_rz(ldexpf(x, sh)); };
+  // the conversion truncates toward zero
+  auto u = [&](float x, int sh) { return (unsigned long long)(long long)(int)ldexpf(x, sh); };
   atomicAdd(q + k, u(a.x, sf) + (u(a.y, sf) << 32));
   atomicAdd(q + stride + k, u(a.z, sf) + (u(a.w, st) << 32));
   atomicAdd(q + 2 * stride + k, u(b.x, st) + (u(b.y, st) << 32));
@@ -1577,7 +1647,7 @@ template <int CONDIM, int BS>
 __device__ inline void resolve_geoms(const ResolveArgs &a, int w, int *gB, float4 *gM, int g0) {
   for (int g = g0 + (int)threadIdx.x; g < a.ng; g += BS) {
     gB[g] = a.gbody[g];
-    const float mu_t = a.gdat[(size_t)w * a.ng + g].w;
+    const float mu_t = a.gmu[(size_t)w * a.ng + g];
     float2 fr = make_float2(0.f, 0.f);
     if (CONDIM >= 4) fr = a.gfr2[(size_t)w * a.ng + g];
     gM[g] = make_float4(mu_t, fr.x, fr.y, 0.f);
@@ -1707,13 +1777,13 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       V3 f, tc;
       contact_wrench<CONDIM>(lam, K, f, tc);
       if (bb >= 0) {
-        const V3 T = cross(rb, f) + tc;
+        const V3 T = CONDIM >= 4 ? cross(rb, f) + tc : cross(rb, f);
         kB = bb;
         WB = make_float4(f.x, f.y, f.z, T.x);
         WB2 = make_float2(T.y, T.z);
       }
       if (ba >= 0) {
-        const V3 T = cross(ra, f) + tc;
+        const V3 T = CONDIM >= 4 ? cross(ra, f) + tc : cross(ra, f);
         kA = ba;
         WA = make_float4(-f.x, -f.y, -f.z, -T.x);
         WA2 = make_float2(-T.y, -T.z);
@@ -1803,7 +1873,7 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   float2 fr0 = make_float2(0.f, 0.f);
   if (tid < ng) {
     gb0 = a.gbody[tid];
-    mu0 = a.gdat[(size_t)w * ng + tid].w;
+    mu0 = a.gmu[(size_t)w * ng + tid];
     if (CONDIM >= 4) fr0 = a.gfr2[(size_t)w * ng + tid];
   }
   const float *qw = a.q + (size_t)w * nq, *vw = a.v + (size_t)w * nv;
@@ -1908,7 +1978,7 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
   }
   for (int g = tid; g < ng; g += BS) {
     gB[g] = a.gbody[g];
-    const float mu_t = a.gdat[(size_t)w * ng + g].w;
+    const float mu_t = a.gmu[(size_t)w * ng + g];
     float2 fr = make_float2(0.f, 0.f);
     if (CONDIM >= 4) fr = a.gfr2[(size_t)w * ng + g];
     gM[g] = make_float4(mu_t, fr.x, fr.y, 0.f);
@@ -1929,6 +1999,7 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
     int kA = nb, kB = nb;  // key nb = no body (static geom or idle lane)
     float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
     float2 WA2 = make_float2(0.f, 0.f), WB2 = WA2;
+    int eF = FX_ZERO;  // force exponent of the contact (the same on both sides)
     if (k < nc) {
       const ContactKin K = contact_kin(cn, cp, gB, gM, bC, bV, bW);
       const float A = heuristic_gain(K.phi, K.trs, P);
@@ -1941,14 +2012,15 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
       facet_impulses<CONDIM>(Af, K, aa, -P.k_user * K.phi, lam);
       V3 f, tc;
       contact_wrench<CONDIM>(lam, K, f, tc);
+      eF = fx_exp(f.x, f.y, f.z);
       if (K.bb >= 0) {
-        const V3 Tb = cross(K.rb, f) + tc;
+        const V3 Tb = CONDIM >= 4 ? cross(K.rb, f) + tc : cross(K.rb, f);
         kB = K.bb;
         WB = make_float4(f.x, f.y, f.z, Tb.x);
         WB2 = make_float2(Tb.y, Tb.z);
       }
       if (K.ba >= 0) {
-        const V3 Ta = cross(K.ra, f) + tc;
+        const V3 Ta = CONDIM >= 4 ? cross(K.ra, f) + tc : cross(K.ra, f);
         kA = K.ba;
         WA = make_float4(-f.x, -f.y, -f.z, -Ta.x);
         WA2 = make_float2(-Ta.y, -Ta.z);
@@ -1957,8 +2029,14 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
       export_training<NF>(a, cbase + k, K, A, aa, P.h, bC, bI0, bI1);
     }
     // per-body fixed-point sums of the chunk (as in resolve_world)
-    if (kA < nb) fx_exponents(fxE + kA, nbp, WA, WA2);
-    if (kB < nb) fx_exponents(fxE + kB, nbp, WB, WB2);
+    if (kA < nb) {
+      atomicMax(fxE + kA, eF);
+      atomicMax(fxE + nbp + kA, fx_exp(WA.w, WA2.x, WA2.y));
+    }
+    if (kB < nb) {
+      atomicMax(fxE + kB, eF);
+      atomicMax(fxE + nbp + kB, fx_exp(WB.w, WB2.x, WB2.y));
+    }
     __syncthreads();
     if (kA < nb) fx_add<BS>(fxQ, fxE, kA, nbp, WA, WA2);
     if (kB < nb) fx_add<BS>(fxQ, fxE, kB, nbp, WB, WB2);
