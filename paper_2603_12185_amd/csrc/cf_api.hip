@@ -475,11 +475,19 @@ static cf::ResolveArgs resolve_args(const cf_model *m) {
   ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
   ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
   ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p; ra.act = m->d_act;
+  ra.nworld = m->nw;
   return ra;
 }
 
 static bool rollout_fused(const cf_model *m) {
   return m->lds_rollout <= kLdsLimit && !m->rollout_steps && !m->mlp;
+}
+
+// Learned gains on the register-resident resolution (several worlds per
+// workgroup sharing the network's K = 32 image): free bodies, at most 128.
+static bool learned_k32(const cf_model *m) {
+  return m->nsub == 0 && !m->d_act && m->nb <= 128 &&
+         cf::resolve_learned_k32_lds_bytes(m->nb, m->ng) <= kLdsLimit;
 }
 
 // The resolution launch of a step: worlds of free bodies that fit the
@@ -491,6 +499,13 @@ static hipError_t launch_resolve_model(const cf_model *m, cf::ResolveArgs ra, hi
   if (!m->mlp && !m->d_act && m->nsub == 0 && m->nb <= m->block_resolve)
     return cf::launch_resolve_free(ra, m->nw, m->block_resolve, m->lds_resolve_free, s);
   if (!m->mlp) return cf::launch_resolve(ra, m->nw, m->block_resolve, m->lds_resolve, s);
+  if (learned_k32(m)) {
+    ra.mlp = m->mlp;
+    ra.mlp_img = m->d_mlp_img;
+    const hipError_t e = cf::launch_mlp_pack_k32(m->mlp, m->d_mlp_img, s);
+    if (e != hipSuccess) return e;
+    return cf::launch_resolve_learned(ra, m->nw, cf::resolve_learned_k32_lds_bytes(m->nb, m->ng), s);
+  }
   const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
   ra.mlp = m->mlp;
   ra.mlp_img = m->d_mlp_img;
@@ -635,9 +650,11 @@ cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float
   if (m->nsub > 0) return set_err(CF_E_UNSUPPORTED, "learned impedance covers models of free bodies only");
   if (m->p.imp_diag) return set_err(CF_E_UNSUPPORTED, "learned impedance scales the heuristic, not the diagonal form");
   const int block = m->block_resolve > 128 ? 128 : m->block_resolve;
-  if (cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, 0, 0) + cf::resolve_learned_lds_bytes(block) > kLdsLimit)
+  if (!learned_k32(m) &&
+      cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, 0, 0) + cf::resolve_learned_lds_bytes(block) > kLdsLimit)
     return set_err(CF_E_UNSUPPORTED, "world too large for the learned resolution's LDS");
-  if (!m->d_mlp_img && hipMalloc((void **)&m->d_mlp_img, cf::mlp_image_bytes()) != hipSuccess) {
+  const size_t img = std::max(cf::mlp_image_bytes(), cf::mlp_image_k32_bytes());
+  if (!m->d_mlp_img && hipMalloc((void **)&m->d_mlp_img, img) != hipSuccess) {
     m->d_mlp_img = nullptr;
     return set_err(CF_E_NOMEM, "learned-gain network image");
   }

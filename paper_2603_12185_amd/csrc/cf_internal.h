@@ -107,6 +107,7 @@ struct ResolveArgs {
   const float4 *mlp_img;        // their LDS image (launch_mlp_pack), with mlp
   const float4 *act;            // [nv] position actuators (kp, kd, q index bits, -), or null
   int nq, nv, nb, ng, ncon_max, condim, nfacet, nbits, nsub, art_floats;
+  int nworld;
   Params p;
 };
 
@@ -151,7 +152,13 @@ hipError_t launch_collide(const CollideArgs &a, int nworld, int block, size_t ld
 hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 // Resolution of worlds of free bodies (no subtrees, actuators or learned
 // gains) with at most `block` bodies, each body's state in its lane.
-size_t resolve_free_lds_bytes(int nb, int ng);
+__host__ __device__ size_t resolve_free_lds_bytes(int nb, int ng);
 hipError_t launch_resolve_free(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s);
+// The same with learned gains (network image of launch_mlp_pack_k32 in
+// mlp_img), four worlds of at most 128 free bodies per workgroup.
+size_t resolve_learned_k32_lds_bytes(int nb, int ng);
+hipError_t launch_resolve_learned(const ResolveArgs &a, int nworld, size_t lds, hipStream_t s);
+size_t mlp_image_k32_bytes();
+hipError_t launch_mlp_pack_k32(const float *params, void *img, hipStream_t s);
 
 }  // namespace cf

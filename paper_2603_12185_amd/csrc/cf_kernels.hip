@@ -757,37 +757,29 @@ __device__ inline void sphere_masks(const float4 *Gs, const int *gbd, int g0, in
 }
 
 // Hit masks of a sphere block of S <= 64 spheres on pairwise different
-// bodies (at most one static) with margin >= 0, from one Gram matrix on MFMA,
-// one wave.  With centres c taken relative to the block's mean and
+// bodies (at most one static) with margin >= 0, from a Gram matrix on bf16
+// MFMA, one wave.  With centres c taken relative to the block's mean and
 // rho = r + margin / 2, the test quantity g_ij = |c_i - c_j|^2 - (rho_i +
 // rho_j)^2 is the product a_i . b_j of the 6-vectors a = (x, y, z, rho, s, 1)
-// and b = (-2x, -2y, -2z, -2rho, 1, s), s = |c|^2 - rho^2; the upper triangle
-// of the 64 x 64 matrix is three 32 x 32 tiles of three v_mfma_f32_32x32x2f32
-// each.  Every term of a product is at most M = max(|c|^2 + rho^2) in
-// magnitude, so float32 products and sums put g within about 40 M 2^-24 of
-// the exact value, and the float32 test of sphere_pair_hit within about
-// 70 M 2^-24: outside the band |g| <= eps = M 2^-16 the sign of g is that
-// test's answer, and the few pairs inside it are decided by sphere_pair_hit
-// itself.  The masks are therefore the ones sphere_masks builds.  Ballots of
-// each accumulator register give two half rows of hits (lanes 0-31: row i0,
-// lanes 32-63: row i0 + 4 of the tile); v_writelane places them in the row
-// lane's mask words.  `ab`: 12 x 64 floats of LDS scratch.
-// v_writelane_b32: lane `lane` of v takes the wave-uniform value val (no
-// compiler builtin exposes the instruction).  The lane select must fold to an
-// inline constant (the call sites sit in fully unrolled loops): a second
-// scalar register would exceed the one-scalar operand limit of the encoding.
-// The leading s_nop is the one wait state a vector compare that wrote VCC
-// needs before VCC is read as a scalar operand (the compiler does not look
-// inside inline assembly for that hazard).
-__device__ inline int lane_write(int v, int val, int lane) {
-  asm volatile("s_nop 0\n\tv_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "i"(lane));
-  return v;
-}
-
+// and b = (-2x, -2y, -2z, -2rho, 1, s), s = |c|^2 - rho^2.  Each float32
+// component is split into bf16 parts, a = ah + al (+ a rest below 2^-18 |a|),
+// and a . b is taken as ah . bh + ah . bl + al . bh: 18 exact bf16 products
+// summed in float32, one v_mfma_f32_16x16x32_bf16 per 16 x 16 tile (K groups
+// of eight: 0 ah.bh, 1 ah.bl, 2 al.bh, 3 zero), ten tiles for the upper
+// triangle of 64 spheres.  Every product is at most M = max(|c|^2 + rho^2)
+// in magnitude (their sum at most 4 M), so the dropped parts and the float32
+// sums put g within 6e-5 M of the float32 test of sphere_pair_hit: outside
+// the band |g| <= eps = M 2^-13 the sign of g is that test's answer, and the
+// pairs inside it are decided by sphere_pair_hit itself.  The masks are
+// therefore the ones sphere_masks builds.  The tiles are formed transposed,
+// so lane l holds row i = 16 I + l % 16 at columns 16 J + 4 (l / 16) + r and
+// sets its own bits; the four lanes of a row OR their parts at the end.
+// `ab`: 4 x 64 x 16 bytes of LDS scratch.
 __device__ __attribute__((always_inline)) inline void sphere_masks_mfma(const float4 *Gs, int g0, int S,
                                                                         float margin, unsigned long long *rm,
-                                                                        float *ab) {
-  typedef float f32x16 __attribute__((ext_vector_type(16)));
+                                                                        void *ab) {
+  typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
   const int l = threadIdx.x;  // the workgroup is one wave
   const bool real = l < S;
   const float4 G = real ? Gs[g0 + l] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -799,57 +791,78 @@ __device__ __attribute__((always_inline)) inline void sphere_masks_mfma(const fl
   const float rho = G.w + 0.5f * margin;
   const float c2 = fmaf(z, z, fmaf(y, y, x * x)), r2 = rho * rho;
   const float M = wave_last(wave_incl_max(real ? c2 + r2 : 0.f));
-  const float eps = M * (1.0f / 65536.0f);
+  const float eps = M * (1.0f / 8192.0f);
   // padding rows and columns sit at g >= 4 M + 1 > eps from everything
   const float sa = real ? c2 - r2 : 4.0f * M + 1.0f;
   const float av[6] = {real ? x : 0.f, real ? y : 0.f, real ? z : 0.f, real ? rho : 0.f, sa, 1.f};
   const float bv[6] = {-2.f * av[0], -2.f * av[1], -2.f * av[2], -2.f * av[3], 1.f, sa};
+  bf16x8 ah, al, bh, bl;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    ab[k * 64 + l] = av[k];
-    ab[(6 + k) * 64 + l] = bv[k];
+  for (int k = 0; k < 8; ++k) {
+    const float a = k < 6 ? av[k] : 0.f, b = k < 6 ? bv[k] : 0.f;
+    ah[k] = (__bf16)a;
+    al[k] = (__bf16)(a - (float)ah[k]);
+    bh[k] = (__bf16)b;
+    bl[k] = (__bf16)(b - (float)bh[k]);
   }
+  bf16x8 *tab = reinterpret_cast<bf16x8 *>(ab);  // [AH | AL | BH | BL][64]
+  tab[l] = ah;
+  tab[64 + l] = al;
+  tab[128 + l] = bh;
+  tab[192 + l] = bl;
   __syncthreads();
-  int hit0 = 0, hit1 = 0;  // lane l: its row's hits among columns 0-31 and 32-63
-  const int ntile = S > 32 ? 3 : 1;
-  const int col = l & 31, kh = l >> 5;
+  const int c = l & 15, kg = l >> 4;
+  // K group of this lane: the row operand (a) is ah, ah, al, 0 and the column
+  // operand (b) bh, bl, bh, 0 for groups 0..3
+  const bf16x8 zero8 = {};
+  const bf16x8 *arow = tab + (kg == 2 ? 64 : 0), *bcol = tab + (kg == 1 ? 192 : 128);
+  const int nt = (S + 15) >> 4;
+  // the lane's bits of row 16 I + c (columns 16 J + 4 kg + r), per row block I
+  uint32_t part[4][4] = {};
+  uint32_t bit[4];
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    if (t >= ntile) break;
-    const int I = t == 2 ? 1 : 0, J = t == 0 ? 0 : 1;
-    f32x16 g = {};
+  for (int r = 0; r < 4; ++r) bit[r] = 1u << (4 * kg + r);
 #pragma unroll
-    for (int st = 0; st < 3; ++st) {
-      const int k = 2 * st + kh;
-      g = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[k * 64 + 32 * I + col], ab[(6 + k) * 64 + 32 * J + col], g, 0, 0, 0);
-    }
+  for (int I = 0; I < 4; ++I) {
+    if (I >= nt) break;
+    const bf16x8 bop = kg < 3 ? arow[16 * I + c] : zero8;  // rows i of this block (the product's N side)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int ia = 8 * (r >> 2) + (r & 3);  // tile row of lanes 0-31; lanes 32-63 hold ia + 4
-      unsigned long long h = __builtin_amdgcn_ballot_w64(g[r] < -eps);
-      unsigned long long m = __builtin_amdgcn_ballot_w64(fabsf(g[r]) <= eps);
-      if (I == J) {  // diagonal tile: only columns above the row (ia + 1 <= 28)
-        const uint32_t lo_m = 0xFFFFFFFFu << (ia + 1), hi_m = ia + 5 < 32 ? 0xFFFFFFFFu << (ia + 5) : 0u;
-        const unsigned long long up = ((unsigned long long)hi_m << 32) | lo_m;
-        h &= up;
-        m &= up;
+    for (int J = 0; J < 4; ++J) {
+      if (J < I || J >= nt) continue;
+      const bf16x8 aop = kg < 3 ? bcol[16 * J + c] : zero8;  // columns j (the product's M side)
+      f32x4 g = {0.f, 0.f, 0.f, 0.f};
+      g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, g, 0, 0, 0);
+      // lane l: g[r] = g_ij, i = 16 I + c, j = 16 J + 4 kg + r; a diagonal
+      // tile keeps the columns above the row
+      bool amb = false;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool above = I < J || 4 * kg + r > c;
+        part[I][J] |= (above && g[r] < -eps) ? bit[r] : 0u;
+        amb |= above && fabsf(g[r]) <= eps;
       }
-      const int rw = 32 * I + ia;
-      // pairs in the band (rare): the float32 test itself, wave-uniform
-      for (; m; m &= m - 1ull) {
-        const int b = __ffsll(m) - 1;
-        if (sphere_pair_hit(Gs[g0 + rw + 4 * (b >> 5)], Gs[g0 + 32 * J + (b & 31)], margin)) h |= 1ull << b;
-      }
-      if (J == 0) {
-        hit0 = lane_write(hit0, (int)(uint32_t)h, rw);
-        hit0 = lane_write(hit0, (int)(uint32_t)(h >> 32), rw + 4);
-      } else {
-        hit1 = lane_write(hit1, (int)(uint32_t)h, rw);
-        hit1 = lane_write(hit1, (int)(uint32_t)(h >> 32), rw + 4);
+      if (__builtin_amdgcn_ballot_w64(amb)) {  // pairs in the band (rare): the float32 test itself
+        if (amb) {
+          const float4 Gi = Gs[g0 + 16 * I + c];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const bool above = I < J || 4 * kg + r > c;
+            if (above && fabsf(g[r]) <= eps && sphere_pair_hit(Gi, Gs[g0 + 16 * J + 4 * kg + r], margin))
+              part[I][J] |= bit[r];
+          }
+        }
       }
     }
   }
-  if (real) rm[l] = (unsigned long long)(uint32_t)hit0 | ((unsigned long long)(uint32_t)hit1 << 32);
+  // the four lanes of a row (equal l % 16) OR their parts into its mask
+  // (zero on entry; integer OR is order-free)
+#pragma unroll
+  for (int I = 0; I < 4; ++I) {
+    if (I >= nt) break;
+    const unsigned long long m = (unsigned long long)(part[I][0] | (part[I][1] << 16)) |
+                                 ((unsigned long long)(part[I][2] | (part[I][3] << 16)) << 32);
+    if (m && 16 * I + c < S) atomicOr(rm + 16 * I + c, m);
+  }
   __syncthreads();
 }
 
@@ -1080,7 +1093,7 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     for (int x = tid; x < S * nwd; x += BS) rm[x] = 0ull;
     __syncthreads();
     if (BS == 64 && a.sph_mfma) {
-      sphere_masks_mfma(Gs, g0, S, a.margin, rm, reinterpret_cast<float *>(cand));
+      sphere_masks_mfma(Gs, g0, S, a.margin, rm, cand);
     } else if (S <= 64) {
       sphere_masks<BS, 1>(Gs, gbd, g0, S, a.margin, rm);
     } else if (S <= 128) {
@@ -1928,7 +1941,7 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
 // 69 geoms, against 15.5 KB with staged rows), so sixteen one-wave worlds fit
 // a CU together.  The next chunk's contact records are loaded while the
 // current chunk is resolved.  Arithmetic as in resolve_world.
-size_t resolve_free_lds_bytes(int nb, int ng) {
+__host__ __device__ size_t resolve_free_lds_bytes(int nb, int ng) {
   return sizeof(float4) * 5 * (size_t)nb + sizeof(int) * 8 * (size_t)pad4(nb) + sizeof(int) * (size_t)pad4(ng) +
          sizeof(float4) * (size_t)ng;
 }
@@ -2071,6 +2084,267 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) vd[i] = vo[i];
   }
+}
+
+// ---- learned gains on worlds of free bodies (at most 128; lane b owns
+// bodies b and b + 64): four one-wave worlds per workgroup share one LDS copy
+// of the network (WeightsK32, written for the
+// step by launch_mlp_pack_k32); each wave resolves its world as
+// resolve_free_kernel does, with wave-local ordering in place of workgroup
+// barriers (worlds differ in their number of contact chunks).  Per chunk each
+// 16-contact tile of the wave runs the network on K = 32 bf16 MFMA (features
+// moved to the tile's K-group-0 lanes and outputs back by lane permutes); the
+// contact lane then keeps the learned facet impulses unless the fallback rule
+// rejects them (learned_ok).
+// Worlds (waves) per workgroup: four of up to 64 bodies, two of up to 128.
+__host__ __device__ constexpr int learn_worlds(int nbl) { return nbl == 1 ? 4 : 2; }
+
+size_t resolve_learned_k32_lds_bytes(int nb, int ng) {
+  return (sizeof(mlp::WeightsK32) + 15) / 16 * 16 + learn_worlds(nb > 64 ? 2 : 1) * resolve_free_lds_bytes(nb, ng);
+}
+
+// Orders the wave's LDS accesses before and after (the wave's lanes exchange
+// data through LDS without a workgroup barrier).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int CONDIM, int NBL>
+__global__ __launch_bounds__(64 * learn_worlds(NBL)) void resolve_learned_kernel(ResolveArgs a) {
+  constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
+  constexpr int kLearnWorlds = learn_worlds(NBL);
+  extern __shared__ float4 lds[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int w = blockIdx.x * kLearnWorlds + wv;
+  mlp::WeightsK32 *W = reinterpret_cast<mlp::WeightsK32 *>(lds);
+  {  // the network's image for this step, copied by the whole workgroup
+    static_assert(sizeof(mlp::WeightsK32) % sizeof(float4) == 0, "image copied in float4");
+    float4 *dst = reinterpret_cast<float4 *>(W);
+    for (int i = threadIdx.x; i < (int)(sizeof(mlp::WeightsK32) / sizeof(float4)); i += 64 * kLearnWorlds)
+      dst[i] = a.mlp_img[i];
+  }
+  __syncthreads();
+  if (w >= a.nworld) return;
+  const int nb = a.nb, ng = a.ng, nbp = pad4(nb);
+  char *region = reinterpret_cast<char *>(lds) + (sizeof(mlp::WeightsK32) + 15) / 16 * 16 +
+                 (size_t)wv * resolve_free_lds_bytes(nb, ng);
+  float4 *bC = reinterpret_cast<float4 *>(region), *bV = bC + nb, *bW = bV + nb, *bI0 = bW + nb, *bI1 = bI0 + nb;
+  int *fx = reinterpret_cast<int *>(bI1 + nb);
+  int *fxE = fx + 6 * nbp;
+  unsigned long long *fxQ = reinterpret_cast<unsigned long long *>(fx);
+  int *gB = fx + 8 * nbp;
+  float4 *gM = reinterpret_cast<float4 *>(gB + pad4(ng));
+  const Params P = a.p;
+  const size_t cbase = (size_t)w * a.ncon_max;
+
+  const int nc = a.ncon[w];
+  float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
+  if (lane < a.ncon_max) {
+    cn = a.cnp[cbase + lane];
+    cp = a.cpos[cbase + lane];
+  }
+  // the lane's bodies: lane + 64 j, j < NBL
+  float qb[NBL][7];
+  float4 F[NBL], T[NBL];
+#pragma unroll
+  for (int j = 0; j < NBL; ++j) {
+    const int b = lane + 64 * j;
+    float vb[6], tb[6];
+    float4 mi = make_float4(1.f, 1.f, 1.f, 1.f);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qb[j][i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vb[i] = tb[i] = 0.f;
+    if (b < nb) {
+      const float *qs = a.q + (size_t)w * a.nq + 7 * b, *vs = a.v + (size_t)w * a.nv + 6 * b;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) qb[j][i] = qs[i];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) vb[i] = vs[i];
+      if (a.tau) {
+        const float *ts = a.tau + (size_t)w * a.nv + 6 * b;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) tb[i] = ts[i];
+      }
+      mi = a.bmi[(size_t)w * nb + b];
+      free_body_predict(qb[j], vb, tb, mi, P, bC[b], bV[b], bW[b], bI0[b], bI1[b]);
+    }
+    F[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    T[j] = F[j];
+  }
+  for (int g = lane; g < ng; g += 64) {
+    gB[g] = a.gbody[g];
+    const float mu_t = a.gmu[(size_t)w * ng + g];
+    float2 fr = make_float2(0.f, 0.f);
+    if (CONDIM >= 4) fr = a.gfr2[(size_t)w * ng + g];
+    gM[g] = make_float4(mu_t, fr.x, fr.y, 0.f);
+  }
+  for (int i = lane; i < 8 * nbp; i += 64) fx[i] = i >= 6 * nbp ? FX_EMPTY : 0;
+  wave_sync();
+
+  const float aa = P.k_user * P.h + P.d_user;
+  const int kg = lane >> 4, c16 = lane & 15;
+  for (int base = 0; base < nc; base += 64) {
+    const int k = base + lane, kn = k + 64;
+    float4 nn = make_float4(0.f, 0.f, 0.f, 0.f), np = nn;
+    if (kn < nc) {
+      nn = a.cnp[cbase + kn];
+      np = a.cpos[cbase + kn];
+    }
+    const bool live = k < nc;
+    // the lane's normalised features as bf16, four packed words (the contact's
+    // kinematics are formed again after the network rather than held through it)
+    int xw[4];
+    {
+      float fe[mlp::NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (live) contact_features(contact_kin(cn, cp, gB, gM, bC, bV, bW), P.h, fe);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int f0 = 2 * i, f1 = 2 * i + 1;
+        const float v0 = f0 < mlp::NFEAT ? (fe[f0] - W->mean[f0]) * W->istd[f0] : 0.f;
+        const float v1 = f1 < mlp::NFEAT ? (fe[f1] - W->mean[f1]) * W->istd[f1] : 0.f;
+        const __bf16 h0 = (__bf16)v0, h1 = (__bf16)v1;
+        xw[i] = (int)((uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16));
+      }
+    }
+    float yo[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) yo[i] = 0.f;
+    const int nlive = min(64, nc - base);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (16 * t >= nlive) break;
+      // K group 0 lanes take the features of the tile's contact c16
+      mlp::bf16x8 x = {};
+      const int src = (16 * t + c16) << 2;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int v = __builtin_amdgcn_ds_bpermute(src, xw[i]);
+        if (kg == 0) {
+          x[2 * i] = __builtin_bit_cast(__bf16, (uint16_t)(v & 0xFFFF));
+          x[2 * i + 1] = __builtin_bit_cast(__bf16, (uint16_t)((uint32_t)v >> 16));
+        }
+      }
+      const mlp::f32x4 y = mlp::forward_tile_k32(W, x);
+      // outputs back to the contact lanes of the tile: output o of contact c16
+      // sits in lane 16 (o / 4) + c16, register o % 4
+#pragma unroll
+      for (int q = 0; q < (NF + 3) / 4; ++q) {
+        const int from = (16 * q + c16) << 2;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (4 * q + r >= NF) break;
+          const float v = __int_as_float(__builtin_amdgcn_ds_bpermute(from, __float_as_int(y[r])));
+          if ((lane >> 4) == t) yo[4 * q + r] = v;
+        }
+      }
+    }
+    int kA = nb, kB = nb;
+    float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
+    float2 WA2 = make_float2(0.f, 0.f), WB2 = WA2;
+    int eF = FX_ZERO;
+    if (live) {
+      const ContactKin K = contact_kin(cn, cp, gB, gM, bC, bV, bW);
+      const float A = heuristic_gain(K.phi, K.trs, P);
+      float Af[NF];
+#pragma unroll
+      for (int i = 0; i < NF; ++i) Af[i] = A;
+      const float c0 = -P.k_user * K.phi;
+      float lam[NF], Gl[NF], ll[NF];
+      facet_impulses<CONDIM>(Af, K, aa, c0, lam);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) Gl[i] = A * __expf(fminf(fmaxf(yo[i], -mlp::CLIP), mlp::CLIP));
+      facet_impulses<CONDIM>(Gl, K, aa, c0, ll);
+      const bool keep = learned_ok<NF>(lam, ll, dot(K.n, K.vrel), K.phi, K.trs, P.h, P.mlp_margin);
+      if (keep) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) lam[i] = ll[i];
+      }
+      if (a.x_fallback) a.x_fallback[cbase + k] = keep ? 0 : 1;
+      V3 f, tc;
+      contact_wrench<CONDIM>(lam, K, f, tc);
+      eF = fx_exp(f.x, f.y, f.z);
+      if (K.bb >= 0) {
+        const V3 Tb = CONDIM >= 4 ? cross(K.rb, f) + tc : cross(K.rb, f);
+        kB = K.bb;
+        WB = make_float4(f.x, f.y, f.z, Tb.x);
+        WB2 = make_float2(Tb.y, Tb.z);
+      }
+      if (K.ba >= 0) {
+        const V3 Ta = CONDIM >= 4 ? cross(K.ra, f) + tc : cross(K.ra, f);
+        kA = K.ba;
+        WA = make_float4(-f.x, -f.y, -f.z, -Ta.x);
+        WA2 = make_float2(-Ta.y, -Ta.z);
+      }
+      export_contact<NF>(a, cbase + k, K, lam);
+      export_training<NF>(a, cbase + k, K, A, aa, P.h, bC, bI0, bI1);
+    }
+    if (kA < nb) {
+      atomicMax(fxE + kA, eF);
+      atomicMax(fxE + nbp + kA, fx_exp(WA.w, WA2.x, WA2.y));
+    }
+    if (kB < nb) {
+      atomicMax(fxE + kB, eF);
+      atomicMax(fxE + nbp + kB, fx_exp(WB.w, WB2.x, WB2.y));
+    }
+    wave_sync();
+    if (kA < nb) fx_add<64>(fxQ, fxE, kA, nbp, WA, WA2);
+    if (kB < nb) fx_add<64>(fxQ, fxE, kB, nbp, WB, WB2);
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < NBL; ++j) {
+      const int b = lane + 64 * j;
+      const int ef = b < nb ? fxE[b] : FX_EMPTY, et = b < nb ? fxE[nbp + b] : FX_EMPTY;
+      if (ef != FX_EMPTY) {
+        const unsigned long long q0 = fxQ[b], q1 = fxQ[nbp + b], q2 = fxQ[2 * nbp + b];
+        F[j].x += fx_value<64>(fx_lo(q0), ef);
+        F[j].y += fx_value<64>(fx_hi(q0), ef);
+        F[j].z += fx_value<64>(fx_lo(q1), ef);
+        T[j].x += fx_value<64>(fx_hi(q1), et);
+        T[j].y += fx_value<64>(fx_lo(q2), et);
+        T[j].z += fx_value<64>(fx_hi(q2), et);
+        fxQ[b] = 0ull; fxQ[nbp + b] = 0ull; fxQ[2 * nbp + b] = 0ull;
+        fxE[b] = FX_EMPTY;
+        fxE[nbp + b] = FX_EMPTY;
+      }
+    }
+    wave_sync();
+    cn = nn;
+    cp = np;
+  }
+
+#pragma unroll
+  for (int j = 0; j < NBL; ++j) {
+    const int b = lane + 64 * j;
+    if (b >= nb) continue;
+    float qo[7], vo[6];
+    free_body_correct(bC[b], bV[b], bW[b], bI0[b], bI1[b], F[j], T[j], qb[j], P, qo, vo);
+    float *qd = a.q_out + (size_t)w * a.nq + 7 * b, *vd = a.v_out + (size_t)w * a.nv + 6 * b;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qd[i] = qo[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vd[i] = vo[i];
+  }
+}
+
+template <int NBL>
+static hipError_t launch_resolve_learned_n(const ResolveArgs &a, int nworld, size_t lds, hipStream_t s) {
+  constexpr int kLearnWorlds = learn_worlds(NBL);
+  const dim3 grid((nworld + kLearnWorlds - 1) / kLearnWorlds), block(64 * kLearnWorlds);
+  switch (a.condim) {
+    case 1: hipLaunchKernelGGL((resolve_learned_kernel<1, NBL>), grid, block, lds, s, a); break;
+    case 3: hipLaunchKernelGGL((resolve_learned_kernel<3, NBL>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((resolve_learned_kernel<4, NBL>), grid, block, lds, s, a); break;
+    case 6: hipLaunchKernelGGL((resolve_learned_kernel<6, NBL>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_learned(const ResolveArgs &a, int nworld, size_t lds, hipStream_t s) {
+  if (a.nsub > 0 || !a.mlp_img || a.act || a.nb > 128 || a.nworld != nworld) return hipErrorInvalidValue;
+  return a.nb > 64 ? launch_resolve_learned_n<2>(a, nworld, lds, s) : launch_resolve_learned_n<1>(a, nworld, lds, s);
 }
 
 template <int CONDIM>

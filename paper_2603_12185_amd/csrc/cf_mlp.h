@@ -144,5 +144,108 @@ __device__ inline void forward_tile(const Weights *W, F f4, Tile &T) {
   T.y = y;
 }
 
+// ---- inference inside the resolution: v_mfma_f32_16x16x32_bf16 (K = 32)
+//
+// Per 16-contact tile the products are again formed transposed (outputs x
+// contacts).  The 16 x 16 accumulator of an output block gives lane l the units
+// 16 m + 4 (l / 16) + r of contact l % 16, and a K = 32 operand takes eight
+// K values per lane (K = 8 (l / 16) + t).  Ordering the K index of input block
+// b as pi_b(8 g + t) = 32 b + 4 g + t (t < 4), 32 b + 16 + 4 g + t - 4 (t >= 4)
+// makes lane l's own activations of blocks m = 2 b and 2 b + 1 exactly its
+// operand, so they never leave registers; the weights are stored in that
+// order.  Layer 1 has 8 inputs (7 features and a zero), held by the lanes of
+// K group 0.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct WeightsK32 {
+  bf16x8 w1[4][16];     // [output block][row]: W1^T rows, inputs 0..7 (K group 0 only)
+  bf16x8 w2[4][2][64];  // [output block][input block][lane]: W2^T in pi order
+  bf16x8 w3[2][64];     // [input block][lane]: W3^T in pi order
+  float4 b1[16], b2[16], b3[4];  // biases by (output block, K group): units 16 m + 4 g + 0..3
+  float mean[NIN], istd[NIN];
+};
+
+// Pack the float32 parameters into WeightsK32 (all threads of the block; ends
+// with a barrier).
+template <int BS>
+__device__ inline void pack_weights_k32(const float *p, WeightsK32 *W) {
+  auto in_of = [](int b, int k) {  // input unit of K index k of input block b
+    const int g = k >> 3, t = k & 7;
+    return 32 * b + (t < 4 ? 4 * g + t : 16 + 4 * g + t - 4);
+  };
+  for (int i = threadIdx.x; i < 4 * 16; i += BS) {
+    const int m = i >> 4, row = i & 15;
+    bf16x8 v;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = (__bf16)(t < NFEAT ? p[OFF_W1 + t * NH + 16 * m + row] : 0.f);
+    W->w1[m][row] = v;
+  }
+  for (int i = threadIdx.x; i < 4 * 2 * 64; i += BS) {
+    const int m = i >> 7, b = (i >> 6) & 1, lane = i & 63;
+    const int out = 16 * m + (lane & 15), g = lane >> 4;
+    bf16x8 v;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = (__bf16)p[OFF_W2 + in_of(b, 8 * g + t) * NH + out];
+    W->w2[m][b][lane] = v;
+  }
+  for (int i = threadIdx.x; i < 2 * 64; i += BS) {
+    const int b = i >> 6, lane = i & 63;
+    const int out = lane & 15, g = lane >> 4;
+    bf16x8 v;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = (__bf16)p[OFF_W3 + in_of(b, 8 * g + t) * NOUT + out];
+    W->w3[b][lane] = v;
+  }
+  for (int i = threadIdx.x; i < 16; i += BS) {
+    const int m = i >> 2, g = i & 3, u = 16 * m + 4 * g;
+    W->b1[i] = make_float4(p[OFF_B1 + u], p[OFF_B1 + u + 1], p[OFF_B1 + u + 2], p[OFF_B1 + u + 3]);
+    W->b2[i] = make_float4(p[OFF_B2 + u], p[OFF_B2 + u + 1], p[OFF_B2 + u + 2], p[OFF_B2 + u + 3]);
+  }
+  for (int i = threadIdx.x; i < 4; i += BS)
+    W->b3[i] = make_float4(p[OFF_B3 + 4 * i], p[OFF_B3 + 4 * i + 1], p[OFF_B3 + 4 * i + 2], p[OFF_B3 + 4 * i + 3]);
+  for (int i = threadIdx.x; i < NIN; i += BS) {
+    W->mean[i] = p[OFF_MEAN + i];
+    W->istd[i] = 1.0f / p[OFF_STD + i];
+  }
+  __syncthreads();
+}
+
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Outputs of one 16-contact tile: lane l gets outputs 4 (l / 16) + r of contact
+// l % 16 of the tile.  `x` is the lane's input operand: the bf16 normalised
+// features of contact l % 16 in the lanes of K group 0, zero elsewhere.
+__device__ inline f32x4 forward_tile_k32(const WeightsK32 *W, bf16x8 x) {
+  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero8 = {};
+  bf16x8 a[2];  // layer-1 activations as the operands of input blocks 0, 1
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    f32x4 z = mfma32(g == 0 ? W->w1[m][c] : zero8, x, zero);
+    const float4 b = W->b1[4 * m + g];
+    z[0] += b.x; z[1] += b.y; z[2] += b.z; z[3] += b.w;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[m >> 1][4 * (m & 1) + r] = (__bf16)silu(z[r]);
+  }
+  bf16x8 a2[2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    f32x4 z = mfma32(W->w2[m][0][l], a[0], zero);
+    z = mfma32(W->w2[m][1][l], a[1], z);
+    const float4 b = W->b2[4 * m + g];
+    z[0] += b.x; z[1] += b.y; z[2] += b.z; z[3] += b.w;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a2[m >> 1][4 * (m & 1) + r] = (__bf16)silu(z[r]);
+  }
+  f32x4 y = mfma32(W->w3[0][l], a2[0], zero);
+  y = mfma32(W->w3[1][l], a2[1], y);
+  const float4 b = W->b3[g];
+  y[0] += b.x; y[1] += b.y; y[2] += b.z; y[3] += b.w;
+  return y;
+}
+
 }  // namespace mlp
 }  // namespace cf

@@ -222,9 +222,20 @@ static int grad_waves(int n) {
 // so each workgroup of the resolution copies it instead of converting.
 __global__ __launch_bounds__(256) void pack_kernel(const float *p, Weights *img) { stage_weights<256>(p, img); }
 
+// The resolution's K = 32 image (WeightsK32), written once per step.
+__global__ __launch_bounds__(256) void pack_k32_kernel(const float *p, WeightsK32 *img) {
+  pack_weights_k32<256>(p, img);
+}
+
 }  // namespace mlp
 
 size_t mlp_image_bytes() { return sizeof(mlp::Weights); }
+size_t mlp_image_k32_bytes() { return sizeof(mlp::WeightsK32); }
+
+hipError_t launch_mlp_pack_k32(const float *params, void *img, hipStream_t s) {
+  hipLaunchKernelGGL(mlp::pack_k32_kernel, dim3(1), dim3(256), 0, s, params, reinterpret_cast<mlp::WeightsK32 *>(img));
+  return hipGetLastError();
+}
 
 hipError_t launch_mlp_pack(const float *params, void *img, hipStream_t s) {
   hipLaunchKernelGGL(mlp::pack_kernel, dim3(1), dim3(256), 0, s, params, reinterpret_cast<mlp::Weights *>(img));
