@@ -195,6 +195,9 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       art_floats += st.nd * st.nd + 9 * st.nd;
       st.bofs = artb_floats;
       artb_floats += cf::art_backward_floats(st.nd, st.nb);
+      st.small = st.nb <= cf::kSmallSub ? 1 : 0;
+      for (int k = b; k < e; ++k)
+        if (d->body_jnt[k] == CF_JNT_FREE) st.small = 0;
       subs.push_back(st);
     }
     for (int k = b; k < e; ++k) {

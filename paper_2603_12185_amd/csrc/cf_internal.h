@@ -46,8 +46,10 @@ struct BodyC {
 struct SubTree {
   int b0, nb, d0, nd, lofs;  // bodies [b0, b0+nb), dofs [d0, d0+nd), forward work block offset
   int bofs;                  // reverse-pass work block offset (cf_step_backward)
-  int pad[2];
+  int small;                 // 1: at most kSmallSub hinge/slide bodies (one dof each), registers path
+  int pad;
 };
+constexpr int kSmallSub = 4;
 constexpr int kMaxSubDof = 32;
 
 // Per-model solver constants (passed by value).

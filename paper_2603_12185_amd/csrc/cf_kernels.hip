@@ -335,7 +335,8 @@ __device__ inline void bwd_solve(const float *L, int n, float *x) {
 // bias c = sum_b J_b^T [m (Jdot_b v - g); I_b (Jdot_b v)_ang + w_b x I_b w_b],
 // Cholesky, v_s = v + h M^-1 (tau - c), body velocities at v_s and COM traces.
 // Work block: M/L [nd*nd] | c [nd] | v_s [nd] | cols [6 nd] | idx [nd].
-__device__ void art_predict(const SubTree S, const BodyC *B, const float4 *bmi, const float *sq, const float *sv,
+__device__ __attribute__((noinline)) void art_predict(const SubTree S, const BodyC *B, const float4 *bmi,
+                                                      const float *sq, const float *sv,
                             const float *st, float4 *bC, float4 *bV, float4 *bW, float4 *bO, float4 *bAx,
                             float4 *bR, float *blk, const Params &P) {
   const int nd = S.nd, d0 = S.d0;
@@ -423,6 +424,328 @@ __device__ void art_predict(const SubTree S, const BodyC *B, const float4 *bmi, 
   }
 }
 
+// ---- small subtrees in registers
+// A subtree of at most kSmallSub bodies, each with one hinge or slide dof
+// (body k of the subtree owns dof k), computed by one lane entirely in
+// registers: the same equations as art_predict / art_correct with the chain
+// structure held as ancestor bit masks (anc[k] bit j: body j is body k or one
+// of its ancestors), every loop unrolled over kSmallSub, and the bodies'
+// constants loaded once up front.  The work block holds what the other
+// passes read: the Cholesky factor L (nd x nd), M^-1 p after the correction
+// (at nd^2) and v_s (at nd^2 + nd).
+struct SmallChain {
+  int n, anc[kSmallSub], jnt[kSmallSub], qadr[kSmallSub], dadr[kSmallSub];
+};
+
+__device__ inline SmallChain small_chain(const SubTree S, const BodyC *B) {
+  SmallChain C;
+  C.n = S.nb;
+#pragma unroll
+  for (int k = 0; k < kSmallSub; ++k) {
+    C.anc[k] = 0;
+    C.jnt[k] = kHinge;
+    C.qadr[k] = C.dadr[k] = 0;
+    if (k < C.n) {
+      const BodyC c = B[S.b0 + k];
+      const int p = c.parent - S.b0;  // -1 for the root
+      int pa = 0;
+#pragma unroll
+      for (int j = 0; j < k; ++j) pa = p == j ? C.anc[j] : pa;
+      C.anc[k] = pa | (1 << k);
+      C.jnt[k] = c.jnt;
+      C.qadr[k] = c.qadr;
+      C.dadr[k] = c.dadr;
+    }
+  }
+  return C;
+}
+
+// Jacobian column of dof j at body k's COM: (a_j x (c_k - o_j), a_j) for a
+// hinge, (a_j, 0) for a slide.
+__device__ inline void small_col(int jt, V3 a, V3 o, V3 c, V3 &lin, V3 &ang) {
+  if (jt == kHinge) {
+    lin = cross(a, c - o);
+    ang = a;
+  } else {
+    lin = a;
+    ang = v3(0.f, 0.f, 0.f);
+  }
+}
+
+__device__ void art_predict_small(const SubTree S, const BodyC *B, const float4 *bmi, const float *sq,
+                                  const float *sv, const float *st, float4 *bC, float4 *bV, float4 *bW,
+                                  float4 *bO, float4 *bAx, float4 *bR, float *blk, const Params &P) {
+  constexpr int N = kSmallSub;
+  const SmallChain C = small_chain(S, B);
+  const int n = C.n;
+  // forward kinematics (parents precede children; a parent's rotation is read
+  // back from the LDS rows this lane wrote)
+  V3 o[N], a[N], c[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    o[k] = a[k] = c[k] = v3(0.f, 0.f, 0.f);
+    if (k >= n) continue;
+    const BodyC bc = B[S.b0 + k];
+    const int p = bc.parent - S.b0;
+    V3 po = v3(0.f, 0.f, 0.f);
+    float pR[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+#pragma unroll
+    for (int j = 0; j < k; ++j)
+      if (p == j) po = o[j];
+    if (p >= 0) {
+      const float4 r0 = bR[3 * (S.b0 + p)], r1 = bR[3 * (S.b0 + p) + 1], r2 = bR[3 * (S.b0 + p) + 2];
+      pR[0] = r0.x; pR[1] = r0.y; pR[2] = r0.z;
+      pR[3] = r1.x; pR[4] = r1.y; pR[5] = r1.z;
+      pR[6] = r2.x; pR[7] = r2.y; pR[8] = r2.z;
+    }
+    float bq[9], R0[9];
+    quat_to_rot<float>(bc.quat.x, bc.quat.y, bc.quat.z, bc.quat.w, bq);
+    mul33<float>(pR, bq, R0);
+    const float lp[3] = {bc.pos.x, bc.pos.y, bc.pos.z}, la[3] = {bc.axis.x, bc.axis.y, bc.axis.z};
+    o[k] = v3(po.x + pR[0] * lp[0] + pR[1] * lp[1] + pR[2] * lp[2],
+              po.y + pR[3] * lp[0] + pR[4] * lp[1] + pR[5] * lp[2],
+              po.z + pR[6] * lp[0] + pR[7] * lp[1] + pR[8] * lp[2]);
+    a[k] = v3(R0[0] * la[0] + R0[1] * la[1] + R0[2] * la[2], R0[3] * la[0] + R0[4] * la[1] + R0[5] * la[2],
+              R0[6] * la[0] + R0[7] * la[1] + R0[8] * la[2]);
+    const float th = sq[bc.qadr];
+    float Rk[9];
+    if (bc.jnt == kHinge) {
+      float Rj[9];
+      axis_angle_rot<float>(la[0], la[1], la[2], th, Rj);
+      mul33<float>(R0, Rj, Rk);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Rk[i] = R0[i];
+      o[k] = o[k] + th * a[k];
+    }
+    const float ip[3] = {bc.ipos.x, bc.ipos.y, bc.ipos.z};
+    c[k] = v3(o[k].x + Rk[0] * ip[0] + Rk[1] * ip[1] + Rk[2] * ip[2],
+              o[k].y + Rk[3] * ip[0] + Rk[4] * ip[1] + Rk[5] * ip[2],
+              o[k].z + Rk[6] * ip[0] + Rk[7] * ip[1] + Rk[8] * ip[2]);
+    const int b = S.b0 + k;
+    bO[b] = make_float4(o[k].x, o[k].y, o[k].z, 0.f);
+    bAx[b] = make_float4(a[k].x, a[k].y, a[k].z, 0.f);
+    bR[3 * b] = make_float4(Rk[0], Rk[1], Rk[2], 0.f);
+    bR[3 * b + 1] = make_float4(Rk[3], Rk[4], Rk[5], 0.f);
+    bR[3 * b + 2] = make_float4(Rk[6], Rk[7], Rk[8], 0.f);
+  }
+  float v[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = j < n ? sv[C.dadr[j]] : 0.f;
+  // body velocities at v: COM and origin linear velocity, angular velocity
+  V3 vc[N], vo[N], om[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    vc[k] = om[k] = v3(0.f, 0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (!((C.anc[k] >> j) & 1)) continue;
+      V3 lin, ang;
+      small_col(C.jnt[j], a[j], o[j], c[k], lin, ang);
+      vc[k] = vc[k] + v[j] * lin;
+      om[k] = om[k] + v[j] * ang;
+    }
+    vo[k] = vc[k] + cross(om[k], o[k] - c[k]);
+  }
+  // bias c (velocity products and gravity) and the mass matrix (lower triangle)
+  const V3 g = v3(P.gx, P.gy, P.gz);
+  float cv[N], M[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    cv[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < N; ++j) M[i][j] = 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (k >= n) continue;
+    V3 jl = v3(0.f, 0.f, 0.f), ja = jl;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (!((C.anc[k] >> j) & 1)) continue;
+      const V3 wa = cross(om[j], a[j]);
+      if (C.jnt[j] == kHinge) {
+        jl = jl + v[j] * (cross(wa, c[k] - o[j]) + cross(a[j], vc[k] - vo[j]));
+        ja = ja + v[j] * wa;
+      } else {
+        jl = jl + v[j] * wa;
+      }
+    }
+    const float4 mi = bmi[S.b0 + k];
+    float Ib[6];
+    world_inertia(bR + 3 * (S.b0 + k), mi, Ib);
+    const V3 Flin = mi.x * (jl - g);
+    const V3 Fang = sym_mul(Ib, ja) + cross(om[k], sym_mul(Ib, om[k]));
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (!((C.anc[k] >> i) & 1)) continue;
+      V3 li, ai;
+      small_col(C.jnt[i], a[i], o[i], c[k], li, ai);
+      cv[i] += dot(li, Flin) + dot(ai, Fang);
+      const V3 Ia = sym_mul(Ib, ai);
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        if (!((C.anc[k] >> j) & 1)) continue;
+        V3 lj, aj;
+        small_col(C.jnt[j], a[j], o[j], c[k], lj, aj);
+        M[i][j] += mi.x * dot(li, lj) + dot(Ia, aj);
+      }
+    }
+  }
+  // Cholesky factor (in place, lower), then v_s = v + h M^-1 (tau - c)
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (j >= n) continue;
+    float sj = M[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) sj -= M[j][k] * M[j][k];
+    const float l = sqrtf(fmaxf(sj, 1e-30f));
+    M[j][j] = l;
+    const float il = 1.0f / l;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      if (i >= n) continue;
+      float t = M[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= M[i][k] * M[j][k];
+      M[i][j] = t * il;
+    }
+  }
+  auto solve_fwd = [&](float *x) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (i >= n) continue;
+      float t = x[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) t -= M[i][k] * x[k];
+      x[i] = t / M[i][i];
+    }
+  };
+  float vs[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) vs[i] = i < n ? st[C.dadr[i]] - cv[i] : 0.f;
+  solve_fwd(vs);
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    if (i >= n) continue;
+    float t = vs[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k)
+      if (k < n) t -= M[k][i] * vs[k];
+    vs[i] = t / M[i][i];
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) vs[i] = v[i] + P.h * vs[i];
+  // body velocities at v_s and COM traces ||L^-1 J_lin^T||_F^2
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (k >= n) continue;
+    V3 vk = v3(0.f, 0.f, 0.f), wk = vk;
+    float e[3][N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      e[0][j] = e[1][j] = e[2][j] = 0.f;
+      if (!((C.anc[k] >> j) & 1)) continue;
+      V3 lin, ang;
+      small_col(C.jnt[j], a[j], o[j], c[k], lin, ang);
+      vk = vk + vs[j] * lin;
+      wk = wk + vs[j] * ang;
+      e[0][j] = lin.x; e[1][j] = lin.y; e[2][j] = lin.z;
+    }
+    float tr = 0.f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      solve_fwd(e[r]);
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (j < n) tr += e[r][j] * e[r][j];
+    }
+    const int b = S.b0 + k;
+    bC[b] = make_float4(c[k].x, c[k].y, c[k].z, 0.f);
+    bV[b] = make_float4(vk.x, vk.y, vk.z, tr);
+    bW[b] = make_float4(wk.x, wk.y, wk.z, 0.f);
+  }
+  // work block: L row-major (nd x nd), v_s at nd^2 + nd
+  float *Lb = blk, *vsb = blk + n * n + n;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (i >= n) continue;
+    vsb[i] = vs[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j < n) Lb[i * n + j] = j <= i ? M[i][j] : 0.f;
+  }
+}
+
+// Velocity correction and integration of a small subtree (art_correct):
+// p = sum_k J_k^T (F_k, T_k), v+ = v_s + M^-1 p, theta+ = theta + h v+; the
+// work block keeps M^-1 p after L (as art_correct leaves it).
+__device__ void art_correct_small(const SubTree S, const BodyC *B, const float4 *bC, const float4 *bO,
+                                  const float4 *bAx, const float4 *accF, const float4 *accT, float *sq, float *sv,
+                                  float *blk, const Params &P) {
+  constexpr int N = kSmallSub;
+  const SmallChain C = small_chain(S, B);
+  const int n = C.n;
+  V3 o[N], a[N], c[N], F[N], T[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    o[k] = a[k] = c[k] = F[k] = T[k] = v3(0.f, 0.f, 0.f);
+    if (k >= n) continue;
+    const int b = S.b0 + k;
+    o[k] = v3(bO[b].x, bO[b].y, bO[b].z);
+    a[k] = v3(bAx[b].x, bAx[b].y, bAx[b].z);
+    c[k] = v3(bC[b].x, bC[b].y, bC[b].z);
+    F[k] = v3(accF[b].x, accF[b].y, accF[b].z);
+    T[k] = v3(accT[b].x, accT[b].y, accT[b].z);
+  }
+  float L[N][N], p[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    p[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < N; ++j) L[i][j] = (i < n && j < n) ? blk[i * n + j] : 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (!((C.anc[k] >> j) & 1)) continue;
+      V3 lin, ang;
+      small_col(C.jnt[j], a[j], o[j], c[k], lin, ang);
+      p[j] += dot(lin, F[k]) + dot(ang, T[k]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (i >= n) continue;
+    float t = p[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) t -= L[i][k] * p[k];
+    p[i] = t / L[i][i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    if (i >= n) continue;
+    float t = p[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k)
+      if (k < n) t -= L[k][i] * p[k];
+    p[i] = t / L[i][i];
+  }
+  // z = M^-1 p goes to the work block (the adjoint reads it back), then
+  // v+ = v_s + z and theta+ = theta + h v+
+  float *zb = blk + n * n;
+  const float *vsb = blk + n * n + n;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (i >= n) continue;
+    zb[i] = p[i];
+    const float vp = vsb[i] + p[i];
+    sv[C.dadr[i]] = vp;
+    sq[C.qadr[i]] += P.h * vp;
+  }
+}
+
 // Unit quaternion exp(th/2) = (cos x, sin(x) th/|th|), x = |th|/2, of a rotation
 // vector: below x = 1/4 from the Taylor series of cos x and of sin(x)/x (the
 // first omitted terms are below 1e-13 relative, so the float32 result is that
@@ -443,7 +766,8 @@ __device__ inline void quat_of_rotvec(V3 th, float &ew, float &ex, float &ey, fl
 
 // Velocity correction and integration of one articulated subtree:
 // p = sum_b J_b^T (F_b, T_b), v+ = v_s + M^-1 p, q+ = q (+) h v+.
-__device__ void art_correct(const SubTree S, const BodyC *B, const float4 *bC, const float4 *bO,
+__device__ __attribute__((noinline)) void art_correct(const SubTree S, const BodyC *B, const float4 *bC,
+                                                      const float4 *bO,
                             const float4 *bAx, const float4 *accF, const float4 *accT, float *sq, float *sv,
                             float *blk, const Params &P) {
   const int nd = S.nd, d0 = S.d0;
@@ -1727,7 +2051,10 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   if (ART)
   for (int si = tid; si < a.nsub; si += BS) {
     const SubTree S = a.sub[si];
-    art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
+    if (S.small)
+      art_predict_small(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
+    else
+      art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
   }
   __syncthreads();
 
@@ -1841,7 +2168,10 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   if (ART)
   for (int si = tid; si < a.nsub; si += BS) {
     const SubTree S = a.sub[si];
-    art_correct(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
+    if (S.small)
+      art_correct_small(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
+    else
+      art_correct(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
   }
   for (int b = tid; b < nb; b += BS) {
     int qadr = 7 * b, dadr = 6 * b;
