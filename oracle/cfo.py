@@ -15,7 +15,8 @@ import threading
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(HERE, "libcfo.so")
+# CFO_LIB names another build of the same source (the sanitizer test's)
+LIB = os.environ.get("CFO_LIB") or os.path.join(HERE, "libcfo.so")
 SRC = os.path.join(HERE, "cfo.c")
 HDR = os.path.join(HERE, "cfo.h")
 
@@ -49,16 +50,22 @@ class _Out(C.Structure):
     ]
 
 
-def build(force: bool = False) -> str:
-    """Compile libcfo.so with gcc (portable -O2, no fast-math)."""
-    if (not force and os.path.exists(LIB)
-            and os.path.getmtime(LIB) >= max(os.path.getmtime(SRC), os.path.getmtime(HDR))):
-        return LIB
-    tmp = LIB + ".tmp"
-    subprocess.check_call(["gcc", "-std=c99", "-O2", "-fno-fast-math", "-Wall", "-fPIC",
+def build(force: bool = False, path: str | None = None, sanitize: bool = False) -> str:
+    """Compile libcfo.so with gcc (portable -O2, no fast-math).
+
+    sanitize: AddressSanitizer + UndefinedBehaviorSanitizer build (-O1, every
+    finding fatal), for the test that runs the oracle's pins on it."""
+    out = path or LIB
+    if (not force and os.path.exists(out)
+            and os.path.getmtime(out) >= max(os.path.getmtime(SRC), os.path.getmtime(HDR))):
+        return out
+    tmp = out + ".tmp"
+    opt = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=all"] if sanitize else ["-O2"])
+    subprocess.check_call(["gcc", "-std=c99", *opt, "-fno-fast-math", "-Wall", "-fPIC",
                            "-shared", "-o", tmp, SRC, "-lm"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None
