@@ -424,18 +424,30 @@ __device__ __attribute__((noinline)) void art_predict(const SubTree S, const Bod
   }
 }
 
-// ---- small subtrees in registers
+// ---- small subtrees: one quad of lanes per subtree, one lane per body
 // A subtree of at most kSmallSub bodies, each with one hinge or slide dof
-// (body k of the subtree owns dof k), computed by one lane entirely in
-// registers: the same equations as art_predict / art_correct with the chain
-// structure held as ancestor bit masks (anc[k] bit j: body j is body k or one
-// of its ancestors), every loop unrolled over kSmallSub, and the bodies'
-// constants loaded once up front.  The work block holds what the other
-// passes read: the Cholesky factor L (nd x nd), M^-1 p after the correction
-// (at nd^2) and v_s (at nd^2 + nd).
+// (body k of the subtree owns dof k), is computed by the four lanes of a quad:
+// lane k forms body k's frame (walking its own ancestor chain in registers),
+// its Jacobian columns, velocities, velocity-product and gravity forces and
+// its terms of M and of the bias; quad sums (DPP) give every lane the whole
+// M and bias, each lane factors the 4 x 4 matrix itself and lane k finishes
+// body k (velocities at v_s, COM trace).  The chain structure is held as
+// ancestor bit masks (anc[k] bit j: body j is body k or one of its
+// ancestors).  Same equations as art_predict / art_correct; the work block
+// holds what the other passes read: the Cholesky factor L (nd x nd), M^-1 p
+// after the correction (at nd^2) and v_s (at nd^2 + nd).
 struct SmallChain {
   int n, anc[kSmallSub], jnt[kSmallSub], qadr[kSmallSub], dadr[kSmallSub];
 };
+
+// x[k] for a lane-dependent k, as selects (no indexed register access).
+template <class T>
+__device__ inline T pick(const T (&x)[kSmallSub], int k) {
+  T r = x[0];
+#pragma unroll
+  for (int j = 1; j < kSmallSub; ++j) r = j == k ? x[j] : r;
+  return r;
+}
 
 __device__ inline SmallChain small_chain(const SubTree S, const BodyC *B) {
   SmallChain C;
@@ -460,165 +472,178 @@ __device__ inline SmallChain small_chain(const SubTree S, const BodyC *B) {
   return C;
 }
 
-// Jacobian column of dof j at body k's COM: (a_j x (c_k - o_j), a_j) for a
-// hinge, (a_j, 0) for a slide.
-__device__ inline void small_col(int jt, V3 a, V3 o, V3 c, V3 &lin, V3 &ang) {
-  if (jt == kHinge) {
-    lin = cross(a, c - o);
-    ang = a;
-  } else {
-    lin = a;
-    ang = v3(0.f, 0.f, 0.f);
-  }
+// Sum over the four lanes of a quad (every lane gets the same value).
+__device__ inline float quad_sum(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+  return x;
 }
 
-__device__ void art_predict_small(const SubTree S, const BodyC *B, const float4 *bmi, const float *sq,
+// Lane k of the quad: body k's frame and its ancestors' origins and world
+// axes (o[j], a[j] for j on the chain), walking the chain root first.
+struct SmallFrames {
+  V3 o[kSmallSub], a[kSmallSub], c;  // c: body k's COM
+  float R[9];                        // body k's rotation
+};
+
+__device__ inline SmallFrames small_frames(const SubTree S, const BodyC *B, const SmallChain &C, int k,
+                                           const float *sq) {
+  SmallFrames Fr;
+  V3 po = v3(0.f, 0.f, 0.f);
+  Fr.c = po;
+  float pR[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  const int anc = k < C.n ? pick(C.anc, k) : 0;
+#pragma unroll
+  for (int j = 0; j < kSmallSub; ++j) {
+    Fr.o[j] = Fr.a[j] = v3(0.f, 0.f, 0.f);
+    if (!((anc >> j) & 1)) continue;
+    const BodyC bc = B[S.b0 + j];
+    float bq[9], R0[9];
+    quat_to_rot<float>(bc.quat.x, bc.quat.y, bc.quat.z, bc.quat.w, bq);
+    mul33<float>(pR, bq, R0);
+    const float lp[3] = {bc.pos.x, bc.pos.y, bc.pos.z}, la[3] = {bc.axis.x, bc.axis.y, bc.axis.z};
+    V3 o = v3(po.x + pR[0] * lp[0] + pR[1] * lp[1] + pR[2] * lp[2], po.y + pR[3] * lp[0] + pR[4] * lp[1] + pR[5] * lp[2],
+              po.z + pR[6] * lp[0] + pR[7] * lp[1] + pR[8] * lp[2]);
+    const V3 a = v3(R0[0] * la[0] + R0[1] * la[1] + R0[2] * la[2], R0[3] * la[0] + R0[4] * la[1] + R0[5] * la[2],
+                    R0[6] * la[0] + R0[7] * la[1] + R0[8] * la[2]);
+    const float th = sq[bc.qadr];
+    if (bc.jnt == kHinge) {
+      float sn, cs;
+      sincosf(th, &sn, &cs);
+      const float ax = la[0], ay = la[1], az = la[2], cc = 1.f - cs;
+      const float Rj[9] = {cs + ax * ax * cc, ax * ay * cc - az * sn, ax * az * cc + ay * sn,
+                           ay * ax * cc + az * sn, cs + ay * ay * cc, ay * az * cc - ax * sn,
+                           az * ax * cc - ay * sn, az * ay * cc + ax * sn, cs + az * az * cc};
+      mul33<float>(R0, Rj, pR);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) pR[i] = R0[i];
+      o = o + th * a;
+    }
+    po = o;
+    Fr.o[j] = o;
+    Fr.a[j] = a;
+    if (j == k) {
+      const float ip[3] = {bc.ipos.x, bc.ipos.y, bc.ipos.z};
+      Fr.c = v3(o.x + pR[0] * ip[0] + pR[1] * ip[1] + pR[2] * ip[2], o.y + pR[3] * ip[0] + pR[4] * ip[1] + pR[5] * ip[2],
+                o.z + pR[6] * ip[0] + pR[7] * ip[1] + pR[8] * ip[2]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fr.R[i] = pR[i];
+  return Fr;
+}
+
+__device__ void art_predict_small(const SubTree S, int k, const BodyC *B, const float4 *bmi, const float *sq,
                                   const float *sv, const float *st, float4 *bC, float4 *bV, float4 *bW,
                                   float4 *bO, float4 *bAx, float4 *bR, float *blk, const Params &P) {
   constexpr int N = kSmallSub;
   const SmallChain C = small_chain(S, B);
   const int n = C.n;
-  // forward kinematics (parents precede children; a parent's rotation is read
-  // back from the LDS rows this lane wrote)
-  V3 o[N], a[N], c[N];
+  const bool own = k < n;
+  const int b = S.b0 + k;
+  const int anck = own ? pick(C.anc, k) : 0;
+  const SmallFrames Fr = small_frames(S, B, C, k, sq);
+  const V3 ok = pick(Fr.o, k), ak = pick(Fr.a, k);
+  if (own) {
+    bO[b] = make_float4(ok.x, ok.y, ok.z, 0.f);
+    bAx[b] = make_float4(ak.x, ak.y, ak.z, 0.f);
+    bR[3 * b] = make_float4(Fr.R[0], Fr.R[1], Fr.R[2], 0.f);
+    bR[3 * b + 1] = make_float4(Fr.R[3], Fr.R[4], Fr.R[5], 0.f);
+    bR[3 * b + 2] = make_float4(Fr.R[6], Fr.R[7], Fr.R[8], 0.f);
+  }
+  // body k's Jacobian columns: lin[j] = a_j x (c_k - o_j) (hinge) or a_j
+  // (slide) where dof j moves body k, ang[j] = a_j (hinge); else 0
+  float mk[N], v[N];
+  V3 lin[N], ang[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    o[k] = a[k] = c[k] = v3(0.f, 0.f, 0.f);
-    if (k >= n) continue;
-    const BodyC bc = B[S.b0 + k];
-    const int p = bc.parent - S.b0;
-    V3 po = v3(0.f, 0.f, 0.f);
-    float pR[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  for (int j = 0; j < N; ++j) {
+    mk[j] = ((anck >> j) & 1) ? 1.f : 0.f;
+    const float hj = C.jnt[j] == kHinge ? 1.f : 0.f;
+    lin[j] = mk[j] * (hj * cross(Fr.a[j], Fr.c - Fr.o[j]) + (1.f - hj) * Fr.a[j]);
+    ang[j] = (mk[j] * hj) * Fr.a[j];
+    v[j] = j < n ? sv[C.dadr[j]] : 0.f;
+  }
+  // velocities at v of body k (the quad shares them through LDS)
+  V3 vc = v3(0.f, 0.f, 0.f), om = vc;
 #pragma unroll
-    for (int j = 0; j < k; ++j)
-      if (p == j) po = o[j];
-    if (p >= 0) {
-      const float4 r0 = bR[3 * (S.b0 + p)], r1 = bR[3 * (S.b0 + p) + 1], r2 = bR[3 * (S.b0 + p) + 2];
-      pR[0] = r0.x; pR[1] = r0.y; pR[2] = r0.z;
-      pR[3] = r1.x; pR[4] = r1.y; pR[5] = r1.z;
-      pR[6] = r2.x; pR[7] = r2.y; pR[8] = r2.z;
-    }
-    float bq[9], R0[9];
-    quat_to_rot<float>(bc.quat.x, bc.quat.y, bc.quat.z, bc.quat.w, bq);
-    mul33<float>(pR, bq, R0);
-    const float lp[3] = {bc.pos.x, bc.pos.y, bc.pos.z}, la[3] = {bc.axis.x, bc.axis.y, bc.axis.z};
-    o[k] = v3(po.x + pR[0] * lp[0] + pR[1] * lp[1] + pR[2] * lp[2],
-              po.y + pR[3] * lp[0] + pR[4] * lp[1] + pR[5] * lp[2],
-              po.z + pR[6] * lp[0] + pR[7] * lp[1] + pR[8] * lp[2]);
-    a[k] = v3(R0[0] * la[0] + R0[1] * la[1] + R0[2] * la[2], R0[3] * la[0] + R0[4] * la[1] + R0[5] * la[2],
-              R0[6] * la[0] + R0[7] * la[1] + R0[8] * la[2]);
-    const float th = sq[bc.qadr];
-    float Rk[9];
-    if (bc.jnt == kHinge) {
-      float Rj[9];
-      axis_angle_rot<float>(la[0], la[1], la[2], th, Rj);
-      mul33<float>(R0, Rj, Rk);
+  for (int j = 0; j < N; ++j) {
+    vc = vc + v[j] * lin[j];
+    om = om + v[j] * ang[j];
+  }
+  const V3 vo = vc + cross(om, ok - Fr.c);
+  if (own) {
+    bV[b] = make_float4(vo.x, vo.y, vo.z, 0.f);
+    bW[b] = make_float4(om.x, om.y, om.z, 0.f);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // velocity-product accelerations Jdot_k v over the chain
+  V3 jl = v3(0.f, 0.f, 0.f), ja = jl;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (mk[j] == 0.f) continue;
+    const float4 Wj = bW[S.b0 + j], Vj = bV[S.b0 + j];
+    const V3 wa = cross(v3(Wj.x, Wj.y, Wj.z), Fr.a[j]);
+    if (C.jnt[j] == kHinge) {
+      jl = jl + v[j] * (cross(wa, Fr.c - Fr.o[j]) + cross(Fr.a[j], vc - v3(Vj.x, Vj.y, Vj.z)));
+      ja = ja + v[j] * wa;
     } else {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) Rk[i] = R0[i];
-      o[k] = o[k] + th * a[k];
+      jl = jl + v[j] * wa;
     }
-    const float ip[3] = {bc.ipos.x, bc.ipos.y, bc.ipos.z};
-    c[k] = v3(o[k].x + Rk[0] * ip[0] + Rk[1] * ip[1] + Rk[2] * ip[2],
-              o[k].y + Rk[3] * ip[0] + Rk[4] * ip[1] + Rk[5] * ip[2],
-              o[k].z + Rk[6] * ip[0] + Rk[7] * ip[1] + Rk[8] * ip[2]);
-    const int b = S.b0 + k;
-    bO[b] = make_float4(o[k].x, o[k].y, o[k].z, 0.f);
-    bAx[b] = make_float4(a[k].x, a[k].y, a[k].z, 0.f);
-    bR[3 * b] = make_float4(Rk[0], Rk[1], Rk[2], 0.f);
-    bR[3 * b + 1] = make_float4(Rk[3], Rk[4], Rk[5], 0.f);
-    bR[3 * b + 2] = make_float4(Rk[6], Rk[7], Rk[8], 0.f);
   }
-  float v[N];
+  const float4 mi = own ? bmi[b] : make_float4(0.f, 1.f, 1.f, 1.f);
+  float Ib[6];
+  {
+    const float d[3] = {mi.y, mi.z, mi.w};
+    const int ri[6] = {0, 1, 2, 0, 0, 1}, rj[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-  for (int j = 0; j < N; ++j) v[j] = j < n ? sv[C.dadr[j]] : 0.f;
-  // body velocities at v: COM and origin linear velocity, angular velocity
-  V3 vc[N], vo[N], om[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    vc[k] = om[k] = v3(0.f, 0.f, 0.f);
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      if (!((C.anc[k] >> j) & 1)) continue;
-      V3 lin, ang;
-      small_col(C.jnt[j], a[j], o[j], c[k], lin, ang);
-      vc[k] = vc[k] + v[j] * lin;
-      om[k] = om[k] + v[j] * ang;
+    for (int q = 0; q < 6; ++q) {
+      const float *u = Fr.R + 3 * ri[q], *w = Fr.R + 3 * rj[q];
+      Ib[q] = u[0] * d[0] * w[0] + u[1] * d[1] * w[1] + u[2] * d[2] * w[2];
     }
-    vo[k] = vc[k] + cross(om[k], o[k] - c[k]);
   }
-  // bias c (velocity products and gravity) and the mass matrix (lower triangle)
   const V3 g = v3(P.gx, P.gy, P.gz);
+  const V3 Flin = mi.x * (jl - g);
+  const V3 Fang = sym_mul(Ib, ja) + cross(om, sym_mul(Ib, om));
+  // body k's terms of the bias and of M (lower triangle), summed over the quad
   float cv[N], M[N][N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    cv[i] = 0.f;
+    cv[i] = quad_sum(dot(lin[i], Flin) + dot(ang[i], Fang));
+    const V3 Ia = sym_mul(Ib, ang[i]);
 #pragma unroll
-    for (int j = 0; j < N; ++j) M[i][j] = 0.f;
+    for (int j = 0; j < N; ++j) M[i][j] = j <= i ? quad_sum(mi.x * dot(lin[i], lin[j]) + dot(Ia, ang[j])) : 0.f;
   }
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    if (k >= n) continue;
-    V3 jl = v3(0.f, 0.f, 0.f), ja = jl;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      if (!((C.anc[k] >> j) & 1)) continue;
-      const V3 wa = cross(om[j], a[j]);
-      if (C.jnt[j] == kHinge) {
-        jl = jl + v[j] * (cross(wa, c[k] - o[j]) + cross(a[j], vc[k] - vo[j]));
-        ja = ja + v[j] * wa;
-      } else {
-        jl = jl + v[j] * wa;
-      }
-    }
-    const float4 mi = bmi[S.b0 + k];
-    float Ib[6];
-    world_inertia(bR + 3 * (S.b0 + k), mi, Ib);
-    const V3 Flin = mi.x * (jl - g);
-    const V3 Fang = sym_mul(Ib, ja) + cross(om[k], sym_mul(Ib, om[k]));
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      if (!((C.anc[k] >> i) & 1)) continue;
-      V3 li, ai;
-      small_col(C.jnt[i], a[i], o[i], c[k], li, ai);
-      cv[i] += dot(li, Flin) + dot(ai, Fang);
-      const V3 Ia = sym_mul(Ib, ai);
-#pragma unroll
-      for (int j = 0; j <= i; ++j) {
-        if (!((C.anc[k] >> j) & 1)) continue;
-        V3 lj, aj;
-        small_col(C.jnt[j], a[j], o[j], c[k], lj, aj);
-        M[i][j] += mi.x * dot(li, lj) + dot(Ia, aj);
-      }
-    }
-  }
-  // Cholesky factor (in place, lower), then v_s = v + h M^-1 (tau - c)
+  // Cholesky factor (lower, reciprocal diagonal kept) and v_s = v + h M^-1 (tau - c),
+  // the same in every lane of the quad
+  float dinv[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
+    dinv[j] = 0.f;
     if (j >= n) continue;
     float sj = M[j][j];
 #pragma unroll
-    for (int k = 0; k < j; ++k) sj -= M[j][k] * M[j][k];
+    for (int q = 0; q < j; ++q) sj -= M[j][q] * M[j][q];
     const float l = sqrtf(fmaxf(sj, 1e-30f));
     M[j][j] = l;
-    const float il = 1.0f / l;
+    dinv[j] = 1.0f / l;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       if (i >= n) continue;
       float t = M[i][j];
 #pragma unroll
-      for (int k = 0; k < j; ++k) t -= M[i][k] * M[j][k];
-      M[i][j] = t * il;
+      for (int q = 0; q < j; ++q) t -= M[i][q] * M[j][q];
+      M[i][j] = t * dinv[j];
     }
   }
   auto solve_fwd = [&](float *x) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      if (i >= n) continue;
       float t = x[i];
 #pragma unroll
-      for (int k = 0; k < i; ++k) t -= M[i][k] * x[k];
-      x[i] = t / M[i][i];
+      for (int q = 0; q < i; ++q) t -= M[i][q] * x[q];
+      x[i] = t * dinv[i];
     }
   };
   float vs[N];
@@ -627,122 +652,106 @@ __device__ void art_predict_small(const SubTree S, const BodyC *B, const float4 
   solve_fwd(vs);
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
-    if (i >= n) continue;
     float t = vs[i];
 #pragma unroll
-    for (int k = i + 1; k < N; ++k)
-      if (k < n) t -= M[k][i] * vs[k];
-    vs[i] = t / M[i][i];
+    for (int q = i + 1; q < N; ++q) t -= M[q][i] * vs[q];
+    vs[i] = t * dinv[i];
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) vs[i] = v[i] + P.h * vs[i];
-  // body velocities at v_s and COM traces ||L^-1 J_lin^T||_F^2
+  // body k at v_s: velocities and COM trace ||L^-1 J_lin^T||_F^2
+  V3 vk = v3(0.f, 0.f, 0.f), wk = vk;
+  float e0[N], e1[N], e2[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    if (k >= n) continue;
-    V3 vk = v3(0.f, 0.f, 0.f), wk = vk;
-    float e[3][N];
+  for (int j = 0; j < N; ++j) {
+    vk = vk + vs[j] * lin[j];
+    wk = wk + vs[j] * ang[j];
+    e0[j] = lin[j].x; e1[j] = lin[j].y; e2[j] = lin[j].z;
+  }
+  solve_fwd(e0);
+  solve_fwd(e1);
+  solve_fwd(e2);
+  float tr = 0.f;
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      e[0][j] = e[1][j] = e[2][j] = 0.f;
-      if (!((C.anc[k] >> j) & 1)) continue;
-      V3 lin, ang;
-      small_col(C.jnt[j], a[j], o[j], c[k], lin, ang);
-      vk = vk + vs[j] * lin;
-      wk = wk + vs[j] * ang;
-      e[0][j] = lin.x; e[1][j] = lin.y; e[2][j] = lin.z;
-    }
-    float tr = 0.f;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      solve_fwd(e[r]);
-#pragma unroll
-      for (int j = 0; j < N; ++j)
-        if (j < n) tr += e[r][j] * e[r][j];
-    }
-    const int b = S.b0 + k;
-    bC[b] = make_float4(c[k].x, c[k].y, c[k].z, 0.f);
+  for (int j = 0; j < N; ++j) tr += e0[j] * e0[j] + e1[j] * e1[j] + e2[j] * e2[j];
+  // the Jdot reads of the quad precede these writes (one wave, program order)
+  if (own) {
+    bC[b] = make_float4(Fr.c.x, Fr.c.y, Fr.c.z, 0.f);
     bV[b] = make_float4(vk.x, vk.y, vk.z, tr);
     bW[b] = make_float4(wk.x, wk.y, wk.z, 0.f);
   }
-  // work block: L row-major (nd x nd), v_s at nd^2 + nd
-  float *Lb = blk, *vsb = blk + n * n + n;
+  if (k == 0) {  // work block: L row-major (nd x nd), v_s at nd^2 + nd
+    float *Lb = blk, *vsb = blk + n * n + n;
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    if (i >= n) continue;
-    vsb[i] = vs[i];
+    for (int i = 0; i < N; ++i) {
+      if (i >= n) continue;
+      vsb[i] = vs[i];
 #pragma unroll
-    for (int j = 0; j < N; ++j)
-      if (j < n) Lb[i * n + j] = j <= i ? M[i][j] : 0.f;
+      for (int j = 0; j < N; ++j)
+        if (j < n) Lb[i * n + j] = j <= i ? M[i][j] : 0.f;
+    }
   }
 }
 
-// Velocity correction and integration of a small subtree (art_correct):
-// p = sum_k J_k^T (F_k, T_k), v+ = v_s + M^-1 p, theta+ = theta + h v+; the
-// work block keeps M^-1 p after L (as art_correct leaves it).
-__device__ void art_correct_small(const SubTree S, const BodyC *B, const float4 *bC, const float4 *bO,
+// Velocity correction and integration of a small subtree (art_correct), lane
+// k of the quad: body k's terms of p = sum_k J_k^T (F_k, T_k), quad sums,
+// v+ = v_s + M^-1 p in every lane, then lane k updates dof k; the work block
+// keeps M^-1 p after L (as art_correct leaves it).
+__device__ void art_correct_small(const SubTree S, int k, const BodyC *B, const float4 *bC, const float4 *bO,
                                   const float4 *bAx, const float4 *accF, const float4 *accT, float *sq, float *sv,
                                   float *blk, const Params &P) {
   constexpr int N = kSmallSub;
   const SmallChain C = small_chain(S, B);
   const int n = C.n;
-  V3 o[N], a[N], c[N], F[N], T[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    o[k] = a[k] = c[k] = F[k] = T[k] = v3(0.f, 0.f, 0.f);
-    if (k >= n) continue;
-    const int b = S.b0 + k;
-    o[k] = v3(bO[b].x, bO[b].y, bO[b].z);
-    a[k] = v3(bAx[b].x, bAx[b].y, bAx[b].z);
-    c[k] = v3(bC[b].x, bC[b].y, bC[b].z);
-    F[k] = v3(accF[b].x, accF[b].y, accF[b].z);
-    T[k] = v3(accT[b].x, accT[b].y, accT[b].z);
+  const bool own = k < n;
+  const int b = S.b0 + k;
+  const int anck = own ? pick(C.anc, k) : 0;
+  V3 cb = v3(0.f, 0.f, 0.f), F = cb, T = cb;
+  if (own) {
+    cb = v3(bC[b].x, bC[b].y, bC[b].z);
+    F = v3(accF[b].x, accF[b].y, accF[b].z);
+    T = v3(accT[b].x, accT[b].y, accT[b].z);
   }
-  float L[N][N], p[N];
+  float p[N], L[N][N], dinv[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    p[i] = 0.f;
-#pragma unroll
-    for (int j = 0; j < N; ++j) L[i][j] = (i < n && j < n) ? blk[i * n + j] : 0.f;
-  }
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      if (!((C.anc[k] >> j) & 1)) continue;
-      V3 lin, ang;
-      small_col(C.jnt[j], a[j], o[j], c[k], lin, ang);
-      p[j] += dot(lin, F[k]) + dot(ang, T[k]);
+  for (int j = 0; j < N; ++j) {
+    const float mk = ((anck >> j) & 1) ? 1.f : 0.f;
+    float t = 0.f;
+    if (j < n) {
+      const V3 oj = v3(bO[S.b0 + j].x, bO[S.b0 + j].y, bO[S.b0 + j].z);
+      const V3 aj = v3(bAx[S.b0 + j].x, bAx[S.b0 + j].y, bAx[S.b0 + j].z);
+      const bool hinge = C.jnt[j] == kHinge;
+      const V3 lin = hinge ? cross(aj, cb - oj) : aj;
+      t = mk * (dot(lin, F) + (hinge ? dot(aj, T) : 0.f));
     }
+    p[j] = quad_sum(t);
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    if (i >= n) continue;
+#pragma unroll
+    for (int j = 0; j < N; ++j) L[i][j] = (i < n && j <= i) ? blk[i * n + j] : 0.f;
+    dinv[i] = i < n ? 1.0f / L[i][i] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
     float t = p[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) t -= L[i][k] * p[k];
-    p[i] = t / L[i][i];
+    for (int q = 0; q < i; ++q) t -= L[i][q] * p[q];
+    p[i] = t * dinv[i];
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
-    if (i >= n) continue;
     float t = p[i];
 #pragma unroll
-    for (int k = i + 1; k < N; ++k)
-      if (k < n) t -= L[k][i] * p[k];
-    p[i] = t / L[i][i];
+    for (int q = i + 1; q < N; ++q) t -= L[q][i] * p[q];
+    p[i] = t * dinv[i];
   }
-  // z = M^-1 p goes to the work block (the adjoint reads it back), then
-  // v+ = v_s + z and theta+ = theta + h v+
-  float *zb = blk + n * n;
-  const float *vsb = blk + n * n + n;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    if (i >= n) continue;
-    zb[i] = p[i];
-    const float vp = vsb[i] + p[i];
-    sv[C.dadr[i]] = vp;
-    sq[C.qadr[i]] += P.h * vp;
+  if (own) {
+    const float pk = pick(p, k);
+    blk[n * n + k] = pk;  // z = M^-1 p, read by the adjoint
+    const float vp = blk[n * n + n + k] + pk;
+    sv[pick(C.dadr, k)] = vp;
+    sq[pick(C.qadr, k)] += P.h * vp;
   }
 }
 
@@ -2048,12 +2057,15 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   }
   for (int i = tid; i < 8 * nbp; i += BS) fx[i] = i >= 6 * nbp ? FX_EMPTY : 0;
   // ---- articulated subtrees: one lane each (same equations, dense per-subtree M)
+  // (lanes 4 si .. 4 si + 3 take subtree si: a quad for a small one, its first
+  // lane for any other)
   if (ART)
-  for (int si = tid; si < a.nsub; si += BS) {
-    const SubTree S = a.sub[si];
+  for (int t = tid; t < 4 * a.nsub; t += BS) {
+    const SubTree S = a.sub[t >> 2];
     if (S.small)
-      art_predict_small(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
-    else
+      art_predict_small(S, t & 3, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR,
+                        art + S.lofs, P);
+    else if ((t & 3) == 0)
       art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
   }
   __syncthreads();
@@ -2166,11 +2178,11 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
 
   // ---- velocity correction (Eq. vel_correction) and semi-implicit Euler
   if (ART)
-  for (int si = tid; si < a.nsub; si += BS) {
-    const SubTree S = a.sub[si];
+  for (int t = tid; t < 4 * a.nsub; t += BS) {
+    const SubTree S = a.sub[t >> 2];
     if (S.small)
-      art_correct_small(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
-    else
+      art_correct_small(S, t & 3, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
+    else if ((t & 3) == 0)
       art_correct(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
   }
   for (int b = tid; b < nb; b += BS) {
