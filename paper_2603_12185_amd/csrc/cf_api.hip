@@ -54,6 +54,8 @@ struct cf_model {
   bool rollout_steps = false;  // autotuner found T cf_step calls faster than the persistent kernel
   float4 *d_bmi = nullptr, *d_gdat = nullptr, *d_gpos = nullptr, *d_gquat = nullptr;
   float *d_gmu = nullptr;  // [nworld][ngeom] tangential friction alone
+  cf::JointK<double> *d_jk64 = nullptr;  // [nb] joint constants (float64: narrow phase)
+  cf::JointK<float> *d_jk32 = nullptr;   // [nb] the same in float32 (resolution)
   float2 *d_gfr2 = nullptr;
   int gpos_ws = 0, gquat_ws = 0;
   // workspace
@@ -86,12 +88,42 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
   return e;
 }
 
+// Joint constants of a hinge (or slide) body from its frame quaternion bq
+// (w, x, y, z, normalised here), offset lp in the parent and unit axis a.
+cf::JointK<double> joint_constants(const double *bq, const double *lp, const double *a, bool hinge) {
+  const double n = std::sqrt(bq[0] * bq[0] + bq[1] * bq[1] + bq[2] * bq[2] + bq[3] * bq[3]);
+  const double w = bq[0] / n, x = bq[1] / n, y = bq[2] / n, z = bq[3] / n;
+  const double B[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                       2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                       2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)};
+  const double ax[9] = {0, -a[2], a[1], a[2], 0, -a[0], -a[1], a[0], 0};  // [a]x
+  cf::JointK<double> K{};
+  for (int i = 0; i < 3; ++i) {
+    K.lp[i] = lp[i];
+    K.Ba[i] = B[3 * i] * a[0] + B[3 * i + 1] * a[1] + B[3 * i + 2] * a[2];
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      if (hinge) {
+        K.Mk[3 * i + j] = K.Ba[i] * a[j];
+        K.Mc[3 * i + j] = B[3 * i + j] - K.Ba[i] * a[j];
+        K.Ms[3 * i + j] = B[3 * i] * ax[j] + B[3 * i + 1] * ax[3 + j] + B[3 * i + 2] * ax[6 + j];
+      } else {
+        K.Mk[3 * i + j] = B[3 * i + j];
+      }
+    }
+  if (!hinge)
+    for (int i = 0; i < 3; ++i) K.s[i] = K.Ba[i];
+  return K;
+}
+
 void free_model(cf_model *m) {
   if (!m) return;
   (void)hipFree(m->d_slots); (void)hipFree(m->d_gbody); (void)hipFree(m->d_gorient); (void)hipFree(m->d_act);
   (void)hipFree(m->d_mlp_img);
   (void)hipFree(m->d_body); (void)hipFree(m->d_sub); (void)hipFree(m->d_bmi); (void)hipFree(m->d_gdat);
   (void)hipFree(m->d_gpos); (void)hipFree(m->d_gquat); (void)hipFree(m->d_gfr2); (void)hipFree(m->d_gmu);
+  (void)hipFree(m->d_jk64); (void)hipFree(m->d_jk32);
   (void)hipFree(m->d_cnp); (void)hipFree(m->d_cpos); (void)hipFree(m->d_ncon); (void)hipFree(m->d_over);
   for (auto &s : m->events)
     for (auto e : s.e) (void)hipEventDestroy(e);
@@ -178,6 +210,8 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
     nv += d->body_jnt[b] == CF_JNT_FREE ? 6 : 1;
   }
   std::vector<cf::BodyC> bodyc(nb);
+  std::vector<cf::JointK<double>> jk64(nb);
+  std::vector<cf::JointK<float>> jk32(nb);
   std::vector<cf::SubTree> subs;
   int art_floats = 0, artb_floats = 0;
   for (int b = 0; b < nb;) {
@@ -215,6 +249,13 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       if (c.jnt != CF_JNT_FREE && !(an > 0)) return set_err(CF_E_INVALID_ARG, "zero joint axis");
       const double *q = d->body_quat + 4 * k;
       if (!(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] > 0)) return set_err(CF_E_INVALID_ARG, "zero body_quat");
+      if (c.jnt != CF_JNT_FREE) {
+        const double a[3] = {ax[0] / an, ax[1] / an, ax[2] / an};
+        jk64[k] = joint_constants(bq, bp, a, c.jnt == CF_JNT_HINGE);
+        const double *src = reinterpret_cast<const double *>(&jk64[k]);
+        float *dst = reinterpret_cast<float *>(&jk32[k]);
+        for (size_t i = 0; i < sizeof(jk64[k]) / sizeof(double); ++i) dst[i] = (float)src[i];
+      }
     }
     b = e;
   }
@@ -419,6 +460,8 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   chk(upload(&m->d_gorient, gorient));
   chk(upload(&m->d_body, bodyc));
   chk(upload(&m->d_sub, subs));
+  chk(upload(&m->d_jk64, jk64));
+  chk(upload(&m->d_jk32, jk32));
   chk(upload(&m->d_bmi, bmi));
   chk(upload(&m->d_gdat, gdat));
   chk(upload(&m->d_gmu, gmu));
@@ -463,7 +506,7 @@ static cf::CollideArgs collide_args(const cf_model *m) {
   cf::CollideArgs ca{};
   ca.gpos = m->d_gpos; ca.gquat = m->d_gquat; ca.gdat = m->d_gdat; ca.gbody = m->d_gbody;
   ca.gorient = m->d_gorient; ca.norient = m->norient;
-  ca.body = m->d_body; ca.sub = m->d_sub; ca.nsub = m->nsub;
+  ca.body = m->d_body; ca.sub = m->d_sub; ca.nsub = m->nsub; ca.jk = m->d_jk64;
   ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
   ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
   ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
@@ -474,7 +517,7 @@ static cf::CollideArgs collide_args(const cf_model *m) {
 static cf::ResolveArgs resolve_args(const cf_model *m) {
   cf::ResolveArgs ra{};
   ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gmu = m->d_gmu; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
-  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats;
+  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats; ra.jk = m->d_jk32;
   ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
   ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
   ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p; ra.act = m->d_act;

@@ -50,6 +50,18 @@ struct SubTree {
   int pad;
 };
 constexpr int kSmallSub = 4;
+
+// Joint constants of a hinge or slide body (model constants, computed on the
+// host in float64): with B the body frame's rotation in its parent at q = 0
+// and a its unit joint axis, the rotation in the parent at joint position th
+// is Mk + cos(th) Mc + sin(th) Ms (hinge: B Rot(a, th) = B a a^T +
+// cos(th) B (1 - a a^T) + sin(th) B [a]x; slide: Mk = B, Mc = Ms = 0), the
+// origin in the parent frame is lp + th s (s = B a for a slide, 0 for a hinge)
+// and the joint axis in the parent frame is Ba = B a.
+template <class T>
+struct JointK {
+  T Mk[9], Mc[9], Ms[9], lp[3], s[3], Ba[3];
+};
 constexpr int kMaxSubDof = 32;
 
 // Per-model solver constants (passed by value).
@@ -83,6 +95,7 @@ struct CollideArgs {
   int sph0, nsph;               // sphere block: geoms [sph0, sph0 + nsph), pairs tested row-wise
   int npl;                      // > 0: geoms [0, npl) are static planes whose slots are their rows against the block
   int sph_mfma;                 // 1: block of <= 64 spheres on pairwise different bodies, margin >= 0 (MFMA masks)
+  const JointK<double> *jk;     // [nb] joint constants (articulated models)
   int gpos_ws, gquat_ws;        // world stride in elements (0 = shared by all worlds)
   float margin;
 };
@@ -108,6 +121,7 @@ struct ResolveArgs {
   const float *mlp;             // learned-gain network parameters, or null
   const float4 *mlp_img;        // their LDS image (launch_mlp_pack), with mlp
   const float4 *act;            // [nv] position actuators (kp, kd, q index bits, -), or null
+  const JointK<float> *jk;      // [nb] joint constants (articulated models)
   int nq, nv, nb, ng, ncon_max, condim, nfacet, nbits, nsub, art_floats;
   int nworld;
   Params p;

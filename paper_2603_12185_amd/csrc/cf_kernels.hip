@@ -479,73 +479,125 @@ __device__ inline float quad_sum(float x) {
   return x;
 }
 
-// Lane k of the quad: body k's frame and its ancestors' origins and world
-// axes (o[j], a[j] for j on the chain), walking the chain root first.
-struct SmallFrames {
-  V3 o[kSmallSub], a[kSmallSub], c;  // c: body k's COM
-  float R[9];                        // body k's rotation
+// Broadcast of lane J of each quad to the quad's four lanes.
+template <int J>
+__device__ inline int quad_bcast_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, J * 0x55, 0xF, 0xF, false);
+}
+template <int J>
+__device__ inline float quad_bcast(float x) {
+  return __int_as_float(quad_bcast_i<J>(__float_as_int(x)));
+}
+template <int J>
+__device__ inline double quad_bcast(double x) {
+  return __hiloint2double(quad_bcast_i<J>(__double2hiint(x)), quad_bcast_i<J>(__double2loint(x)));
+}
+__device__ inline void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ inline void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
+
+// Lane k of the quad: frames along the chain of body k of a small subtree
+// from the joint constants (JointK).  Each lane takes the sine and cosine of
+// its own body's joint angle once and the quad shares them; walking the
+// ancestors root first, R_j = R_p (Mk + cos Mc + sin Ms), o_j = o_p +
+// R_p (lp + th s), world axis a_j = R_p Ba (p: the previous ancestor, the
+// world frame for the root).  o[j], a[j]: zero where j is not an ancestor of
+// k (nor k); R, ok: body k's rotation and origin (identity and zero for a
+// lane beyond the subtree).
+template <class T>
+struct QuadChain {
+  T o[kSmallSub][3], a[kSmallSub][3], R[9], ok[3];
 };
 
-__device__ inline SmallFrames small_frames(const SubTree S, const BodyC *B, const SmallChain &C, int k,
-                                           const float *sq) {
-  SmallFrames Fr;
-  V3 po = v3(0.f, 0.f, 0.f);
-  Fr.c = po;
-  float pR[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
-  const int anc = k < C.n ? pick(C.anc, k) : 0;
+template <class T>
+__device__ inline void quad_chain(const SubTree S, const SmallChain &C, int k, const JointK<T> *JK,
+                                  const float *sq, QuadChain<T> &Q) {
+  constexpr int N = kSmallSub;
+  const bool own = k < C.n;
+  const T th = own ? (T)sq[pick(C.qadr, k)] : T(0);
+  T sn, cs;
+  sin_cos(th, &sn, &cs);
+  const T tj[N] = {quad_bcast<0>(th), quad_bcast<1>(th), quad_bcast<2>(th), quad_bcast<3>(th)};
+  const T sj[N] = {quad_bcast<0>(sn), quad_bcast<1>(sn), quad_bcast<2>(sn), quad_bcast<3>(sn)};
+  const T cj[N] = {quad_bcast<0>(cs), quad_bcast<1>(cs), quad_bcast<2>(cs), quad_bcast<3>(cs)};
+  const int anc = own ? pick(C.anc, k) : 0;
+  T pR[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)}, po[3] = {T(0), T(0), T(0)};
 #pragma unroll
-  for (int j = 0; j < kSmallSub; ++j) {
-    Fr.o[j] = Fr.a[j] = v3(0.f, 0.f, 0.f);
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Q.o[j][i] = Q.a[j][i] = T(0);
     if (!((anc >> j) & 1)) continue;
-    const BodyC bc = B[S.b0 + j];
-    float bq[9], R0[9];
-    quat_to_rot<float>(bc.quat.x, bc.quat.y, bc.quat.z, bc.quat.w, bq);
-    mul33<float>(pR, bq, R0);
-    const float lp[3] = {bc.pos.x, bc.pos.y, bc.pos.z}, la[3] = {bc.axis.x, bc.axis.y, bc.axis.z};
-    V3 o = v3(po.x + pR[0] * lp[0] + pR[1] * lp[1] + pR[2] * lp[2], po.y + pR[3] * lp[0] + pR[4] * lp[1] + pR[5] * lp[2],
-              po.z + pR[6] * lp[0] + pR[7] * lp[1] + pR[8] * lp[2]);
-    const V3 a = v3(R0[0] * la[0] + R0[1] * la[1] + R0[2] * la[2], R0[3] * la[0] + R0[4] * la[1] + R0[5] * la[2],
-                    R0[6] * la[0] + R0[7] * la[1] + R0[8] * la[2]);
-    const float th = sq[bc.qadr];
-    if (bc.jnt == kHinge) {
-      float sn, cs;
-      sincosf(th, &sn, &cs);
-      const float ax = la[0], ay = la[1], az = la[2], cc = 1.f - cs;
-      const float Rj[9] = {cs + ax * ax * cc, ax * ay * cc - az * sn, ax * az * cc + ay * sn,
-                           ay * ax * cc + az * sn, cs + ay * ay * cc, ay * az * cc - ax * sn,
-                           az * ax * cc - ay * sn, az * ay * cc + ax * sn, cs + az * az * cc};
-      mul33<float>(R0, Rj, pR);
-    } else {
+    const JointK<T> &K = JK[S.b0 + j];
+    T l[3], Rl[9], R[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) pR[i] = R0[i];
-      o = o + th * a;
+    for (int i = 0; i < 3; ++i) l[i] = K.lp[i] + tj[j] * K.s[i];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Rl[i] = K.Mk[i] + cj[j] * K.Mc[i] + sj[j] * K.Ms[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Q.o[j][i] = po[i] + pR[3 * i] * l[0] + pR[3 * i + 1] * l[1] + pR[3 * i + 2] * l[2];
+      Q.a[j][i] = pR[3 * i] * K.Ba[0] + pR[3 * i + 1] * K.Ba[1] + pR[3 * i + 2] * K.Ba[2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) R[3 * i + c] = pR[3 * i] * Rl[c] + pR[3 * i + 1] * Rl[3 + c] + pR[3 * i + 2] * Rl[6 + c];
     }
-    po = o;
-    Fr.o[j] = o;
-    Fr.a[j] = a;
-    if (j == k) {
-      const float ip[3] = {bc.ipos.x, bc.ipos.y, bc.ipos.z};
-      Fr.c = v3(o.x + pR[0] * ip[0] + pR[1] * ip[1] + pR[2] * ip[2], o.y + pR[3] * ip[0] + pR[4] * ip[1] + pR[5] * ip[2],
-                o.z + pR[6] * ip[0] + pR[7] * ip[1] + pR[8] * ip[2]);
-    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) pR[i] = R[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) po[i] = Q.o[j][i];
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) Fr.R[i] = pR[i];
-  return Fr;
+  for (int i = 0; i < 9; ++i) Q.R[i] = pR[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Q.ok[i] = po[i];
 }
 
-__device__ void art_predict_small(const SubTree S, int k, const BodyC *B, const float4 *bmi, const float *sq,
-                                  const float *sv, const float *st, float4 *bC, float4 *bV, float4 *bW,
-                                  float4 *bO, float4 *bAx, float4 *bR, float *blk, const Params &P) {
+// Float64 forward kinematics of a small subtree for the narrow phase (the
+// frames fk_range writes), lane k of the quad writing body k's.
+__device__ __attribute__((always_inline)) inline void fk_small(const SubTree S, int k, const BodyC *B, const JointK<double> *JK, const float *sq,
+                                double *org, double *rot) {
+  const SmallChain C = small_chain(S, B);
+  QuadChain<double> Q;
+  quad_chain<double>(S, C, k, JK, sq, Q);
+  if (k < C.n) {
+    const int b = S.b0 + k;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      org[4 * b + i] = Q.ok[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) rot[12 * b + 4 * i + j] = Q.R[3 * i + j];
+    }
+  }
+}
+
+__device__ void art_predict_small(const SubTree S, int k, const BodyC *B, const JointK<float> *JK,
+                                  const float4 *bmi, const float *sq, const float *sv, const float *st, float4 *bC,
+                                  float4 *bV, float4 *bW, float4 *bO, float4 *bAx, float4 *bR, float *blk,
+                                  const Params &P) {
   constexpr int N = kSmallSub;
   const SmallChain C = small_chain(S, B);
   const int n = C.n;
   const bool own = k < n;
   const int b = S.b0 + k;
   const int anck = own ? pick(C.anc, k) : 0;
-  const SmallFrames Fr = small_frames(S, B, C, k, sq);
-  const V3 ok = pick(Fr.o, k), ak = pick(Fr.a, k);
+  QuadChain<float> Q;
+  quad_chain<float>(S, C, k, JK, sq, Q);
+  struct {
+    V3 o[N], a[N], c;
+    float R[9];
+  } Fr;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    Fr.o[j] = v3(Q.o[j][0], Q.o[j][1], Q.o[j][2]);
+    Fr.a[j] = v3(Q.a[j][0], Q.a[j][1], Q.a[j][2]);
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fr.R[i] = Q.R[i];
+  const V3 ok = v3(Q.ok[0], Q.ok[1], Q.ok[2]), ak = pick(Fr.a, k);
+  Fr.c = ok;
   if (own) {
+    const float4 ip = B[b].ipos;
+    Fr.c = v3(ok.x + Fr.R[0] * ip.x + Fr.R[1] * ip.y + Fr.R[2] * ip.z,
+              ok.y + Fr.R[3] * ip.x + Fr.R[4] * ip.y + Fr.R[5] * ip.z,
+              ok.z + Fr.R[6] * ip.x + Fr.R[7] * ip.y + Fr.R[8] * ip.z);
     bO[b] = make_float4(ok.x, ok.y, ok.z, 0.f);
     bAx[b] = make_float4(ak.x, ak.y, ak.z, 0.f);
     bR[3 * b] = make_float4(Fr.R[0], Fr.R[1], Fr.R[2], 0.f);
@@ -1228,9 +1280,14 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
   uint32_t nxt4 = tid + 3 * BS < npre ? a.slots[tid + 3 * BS] : 0u;
 
   if (ART) {  // forward kinematics of articulated subtrees, float64
-    for (int si = tid; si < a.nsub; si += BS) {
-      const SubTree S = a.sub[si];
-      fk_range<double>(S.b0, S.nb, a.body, sq, borg, brot, nullptr, nullptr);
+    // (lanes 4 si .. 4 si + 3 take subtree si: a quad for a small one, its
+    // first lane for any other)
+    for (int t = tid; t < 4 * a.nsub; t += BS) {
+      const SubTree S = a.sub[t >> 2];
+      if (S.small)
+        fk_small(S, t & 3, a.body, a.jk, sq, borg, brot);
+      else if ((t & 3) == 0)
+        fk_range<double>(S.b0, S.nb, a.body, sq, borg, brot, nullptr, nullptr);
     }
     __syncthreads();
   }
@@ -2063,7 +2120,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   for (int t = tid; t < 4 * a.nsub; t += BS) {
     const SubTree S = a.sub[t >> 2];
     if (S.small)
-      art_predict_small(S, t & 3, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR,
+      art_predict_small(S, t & 3, a.body, a.jk, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR,
                         art + S.lofs, P);
     else if ((t & 3) == 0)
       art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
