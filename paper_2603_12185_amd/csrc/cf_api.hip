@@ -232,6 +232,16 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       st.small = st.nb <= cf::kSmallSub ? 1 : 0;
       for (int k = b; k < e; ++k)
         if (d->body_jnt[k] == CF_JNT_FREE) st.small = 0;
+      if (st.small) {
+        int anc[cf::kSmallSub] = {};
+        for (int k = 0; k < st.nb; ++k) {
+          const int p = d->body_parent[b + k] - b;  // parents precede children; -1 - b for the root
+          anc[k] = (p >= 0 ? anc[p] : 0) | (1 << k);
+          st.chain |= anc[k] << (4 * k);
+          if (d->body_jnt[b + k] == CF_JNT_HINGE) st.chain |= 1 << (16 + k);
+        }
+        st.q0 = qadr[b];
+      }
       subs.push_back(st);
     }
     for (int k = b; k < e; ++k) {

@@ -47,7 +47,10 @@ struct SubTree {
   int b0, nb, d0, nd, lofs;  // bodies [b0, b0+nb), dofs [d0, d0+nd), forward work block offset
   int bofs;                  // reverse-pass work block offset (cf_step_backward)
   int small;                 // 1: at most kSmallSub hinge/slide bodies (one dof each), registers path
-  int pad;
+  // small subtrees: body b0 + k has q index q0 + k and dof d0 + k; chain bits
+  // 4k..4k+3 mark body k and its ancestors (bit j: body b0 + j), bit 16 + k a
+  // hinge (else a slide)
+  int chain, q0;
 };
 constexpr int kSmallSub = 4;
 

@@ -449,25 +449,16 @@ __device__ inline T pick(const T (&x)[kSmallSub], int k) {
   return r;
 }
 
-__device__ inline SmallChain small_chain(const SubTree S, const BodyC *B) {
+__device__ inline SmallChain small_chain(const SubTree S) {
   SmallChain C;
   C.n = S.nb;
 #pragma unroll
   for (int k = 0; k < kSmallSub; ++k) {
-    C.anc[k] = 0;
-    C.jnt[k] = kHinge;
-    C.qadr[k] = C.dadr[k] = 0;
-    if (k < C.n) {
-      const BodyC c = B[S.b0 + k];
-      const int p = c.parent - S.b0;  // -1 for the root
-      int pa = 0;
-#pragma unroll
-      for (int j = 0; j < k; ++j) pa = p == j ? C.anc[j] : pa;
-      C.anc[k] = pa | (1 << k);
-      C.jnt[k] = c.jnt;
-      C.qadr[k] = c.qadr;
-      C.dadr[k] = c.dadr;
-    }
+    const bool in = k < C.n;
+    C.anc[k] = in ? (S.chain >> (4 * k)) & 15 : 0;
+    C.jnt[k] = ((S.chain >> (16 + k)) & 1) ? kHinge : kSlide;
+    C.qadr[k] = in ? S.q0 + k : 0;
+    C.dadr[k] = in ? S.d0 + k : 0;
   }
   return C;
 }
@@ -554,7 +545,7 @@ __device__ inline void quad_chain(const SubTree S, const SmallChain &C, int k, c
 // frames fk_range writes), lane k of the quad writing body k's.
 __device__ __attribute__((always_inline)) inline void fk_small(const SubTree S, int k, const BodyC *B, const JointK<double> *JK, const float *sq,
                                 double *org, double *rot) {
-  const SmallChain C = small_chain(S, B);
+  const SmallChain C = small_chain(S);
   QuadChain<double> Q;
   quad_chain<double>(S, C, k, JK, sq, Q);
   if (k < C.n) {
@@ -573,11 +564,14 @@ __device__ void art_predict_small(const SubTree S, int k, const BodyC *B, const 
                                   float4 *bV, float4 *bW, float4 *bO, float4 *bAx, float4 *bR, float *blk,
                                   const Params &P) {
   constexpr int N = kSmallSub;
-  const SmallChain C = small_chain(S, B);
+  const SmallChain C = small_chain(S);
   const int n = C.n;
   const bool own = k < n;
   const int b = S.b0 + k;
   const int anck = own ? pick(C.anc, k) : 0;
+  // body k's inertia and COM offset, loaded ahead of the chain walk
+  const float4 mi = own ? bmi[b] : make_float4(0.f, 1.f, 1.f, 1.f);
+  const float4 ip = own ? B[b].ipos : make_float4(0.f, 0.f, 0.f, 0.f);
   QuadChain<float> Q;
   quad_chain<float>(S, C, k, JK, sq, Q);
   struct {
@@ -594,7 +588,6 @@ __device__ void art_predict_small(const SubTree S, int k, const BodyC *B, const 
   const V3 ok = v3(Q.ok[0], Q.ok[1], Q.ok[2]), ak = pick(Fr.a, k);
   Fr.c = ok;
   if (own) {
-    const float4 ip = B[b].ipos;
     Fr.c = v3(ok.x + Fr.R[0] * ip.x + Fr.R[1] * ip.y + Fr.R[2] * ip.z,
               ok.y + Fr.R[3] * ip.x + Fr.R[4] * ip.y + Fr.R[5] * ip.z,
               ok.z + Fr.R[6] * ip.x + Fr.R[7] * ip.y + Fr.R[8] * ip.z);
@@ -644,7 +637,6 @@ __device__ void art_predict_small(const SubTree S, int k, const BodyC *B, const 
       jl = jl + v[j] * wa;
     }
   }
-  const float4 mi = own ? bmi[b] : make_float4(0.f, 1.f, 1.f, 1.f);
   float Ib[6];
   {
     const float d[3] = {mi.y, mi.z, mi.w};
@@ -753,7 +745,7 @@ __device__ void art_correct_small(const SubTree S, int k, const BodyC *B, const 
                                   const float4 *bAx, const float4 *accF, const float4 *accT, float *sq, float *sv,
                                   float *blk, const Params &P) {
   constexpr int N = kSmallSub;
-  const SmallChain C = small_chain(S, B);
+  const SmallChain C = small_chain(S);
   const int n = C.n;
   const bool own = k < n;
   const int b = S.b0 + k;
@@ -1278,12 +1270,24 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
   uint32_t nxt2 = tid + BS < npre ? a.slots[tid + BS] : 0u;
   uint32_t nxt3 = tid + 2 * BS < npre ? a.slots[tid + 2 * BS] : 0u;
   uint32_t nxt4 = tid + 3 * BS < npre ? a.slots[tid + 3 * BS] : 0u;
+  // articulated models: the lane's subtree record and the body record of
+  // geom tid, also in flight before the kinematics
+  SubTree sub0{};
+  int gfast0 = 1, gqadr0 = 0;
+  if (ART) {
+    if (tid < 4 * a.nsub) sub0 = a.sub[tid >> 2];
+    if (pre && tid < a.ng && pre->b >= 0) {
+      const BodyC &bc = a.body[pre->b];
+      gfast0 = bc.fast;
+      gqadr0 = bc.qadr;
+    }
+  }
 
   if (ART) {  // forward kinematics of articulated subtrees, float64
     // (lanes 4 si .. 4 si + 3 take subtree si: a quad for a small one, its
     // first lane for any other)
     for (int t = tid; t < 4 * a.nsub; t += BS) {
-      const SubTree S = a.sub[t >> 2];
+      const SubTree S = t == tid ? sub0 : a.sub[t >> 2];
       if (S.small)
         fk_small(S, t & 3, a.body, a.jk, sq, borg, brot);
       else if ((t & 3) == 0)
@@ -1299,16 +1303,27 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     const float4 gp = gi.gp, gd = gi.gd, gq = gi.gq;
     go[g] = o;
     gbd[g] = b;
+    const bool own = pre && g == tid;  // body record prefetched
     if (o < 0) {  // sphere at the origin of a free body (or static)
-      const float *qb = b >= 0 ? sq + (ART ? a.body[b].qadr : 7 * b) : nullptr;
+      const float *qb = b >= 0 ? sq + (ART ? (own ? gqadr0 : a.body[b].qadr) : 7 * b) : nullptr;
       Gs[g] = b >= 0 ? make_float4(qb[0], qb[1], qb[2], gd.x) : make_float4(gp.x, gp.y, gp.z, gd.x);
       continue;
     }
     double bp[3] = {0.0, 0.0, 0.0}, br[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0}, gr[9];
     if (b >= 0) {
-      const BodyC bc = ART ? a.body[b] : BodyC{};
-      if (!ART || bc.fast) {
-        const float *qb = sq + (ART ? bc.qadr : 7 * b);
+      int fast = 1, qadr = 7 * b;
+      if (ART) {
+        if (own) {
+          fast = gfast0;
+          qadr = gqadr0;
+        } else {
+          const BodyC &bc = a.body[b];
+          fast = bc.fast;
+          qadr = bc.qadr;
+        }
+      }
+      if (fast) {
+        const float *qb = sq + qadr;
         bp[0] = qb[0]; bp[1] = qb[1]; bp[2] = qb[2];
         quat_to_rot<double>(qb[3], qb[4], qb[5], qb[6], br);
       } else {
@@ -2082,13 +2097,28 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   float4 *bO = RR.bO, *bAx = RR.bAx, *bR = RR.bR;  // articulated bodies only
   float *art = RR.art;
   const Params P = a.p;
+  // constants read below, loaded together up front: the lane's actuator,
+  // body record and subtree
+  float4 act0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+  if (a.act && tid < a.nv) act0 = a.act[tid];
+  int fast0 = 1, qadr0 = 7 * tid, dadr0 = 6 * tid;
+  SubTree sub0{};
+  if (ART) {
+    if (tid < nb) {
+      const BodyC &bc = a.body[tid];
+      fast0 = bc.fast;
+      qadr0 = bc.qadr;
+      dadr0 = bc.dadr;
+    }
+    if (tid < 4 * a.nsub) sub0 = a.sub[tid >> 2];
+  }
   if (!geoms_ready) resolve_geoms<CONDIM, BS>(a, w, gB, gM, 0);
   __syncthreads();
   if (a.act) {
     // position actuators: the input of an actuated dof is its target u, the
     // applied force kp (u - q) - kd v on the state at the start of the step
     for (int i = tid; i < a.nv; i += BS) {
-      const float4 c = a.act[i];
+      const float4 c = i == tid ? act0 : a.act[i];
       const int qi = __float_as_int(c.z);
       if (qi >= 0) st[i] = c.x * (st[i] - sq[qi]) - c.y * sv[i];
     }
@@ -2100,10 +2130,16 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   for (int b = tid; b < nb; b += BS) {
     int qadr = 7 * b, dadr = 6 * b;
     if (ART) {
-      const BodyC bc = a.body[b];
-      if (!bc.fast) continue;
-      qadr = bc.qadr;
-      dadr = bc.dadr;
+      if (b == tid) {
+        if (!fast0) continue;
+        qadr = qadr0;
+        dadr = dadr0;
+      } else {
+        const BodyC &bc = a.body[b];
+        if (!bc.fast) continue;
+        qadr = bc.qadr;
+        dadr = bc.dadr;
+      }
     }
     const float4 mi = b == tid ? mi0 : a.bmi[(size_t)w * nb + b];
     free_body_predict(sq + qadr, sv + dadr, st + dadr, mi, P, bC[b], bV[b], bW[b], bI0[b], bI1[b]);
@@ -2118,7 +2154,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   // lane for any other)
   if (ART)
   for (int t = tid; t < 4 * a.nsub; t += BS) {
-    const SubTree S = a.sub[t >> 2];
+    const SubTree S = t == tid ? sub0 : a.sub[t >> 2];
     if (S.small)
       art_predict_small(S, t & 3, a.body, a.jk, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR,
                         art + S.lofs, P);
@@ -2236,7 +2272,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   // ---- velocity correction (Eq. vel_correction) and semi-implicit Euler
   if (ART)
   for (int t = tid; t < 4 * a.nsub; t += BS) {
-    const SubTree S = a.sub[t >> 2];
+    const SubTree S = t == tid ? sub0 : a.sub[t >> 2];
     if (S.small)
       art_correct_small(S, t & 3, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
     else if ((t & 3) == 0)
@@ -2778,7 +2814,7 @@ size_t rollout_lds_bytes(int nq, int nv, int nb, int ng, int norient, int nsub, 
 }
 
 template <int CONDIM, int BS, bool ART>
-__global__ __launch_bounds__(BS) void rollout_kernel(RolloutArgs r) {
+__global__ __launch_bounds__(BS, 2) void rollout_kernel(RolloutArgs r) {
   extern __shared__ float4 lds[];
   const CollideArgs &ca = r.c;
   const ResolveArgs &ra = r.s;
