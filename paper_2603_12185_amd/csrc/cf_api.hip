@@ -54,8 +54,8 @@ struct cf_model {
   bool rollout_steps = false;  // autotuner found T cf_step calls faster than the persistent kernel
   float4 *d_bmi = nullptr, *d_gdat = nullptr, *d_gpos = nullptr, *d_gquat = nullptr;
   float *d_gmu = nullptr;  // [nworld][ngeom] tangential friction alone
-  cf::JointK<double> *d_jk64 = nullptr;  // [nb] joint constants (float64: narrow phase)
-  cf::JointK<float> *d_jk32 = nullptr;   // [nb] the same in float32 (resolution)
+  cf::JointK<double> *d_jk64 = nullptr;  // [nb] joint constants (narrow phase kinematics)
+  float4 *d_frames = nullptr;  // [nworld][nb][5] small-subtree frames, narrow phase -> resolution
   float2 *d_gfr2 = nullptr;
   int gpos_ws = 0, gquat_ws = 0;
   // workspace
@@ -123,7 +123,7 @@ void free_model(cf_model *m) {
   (void)hipFree(m->d_mlp_img);
   (void)hipFree(m->d_body); (void)hipFree(m->d_sub); (void)hipFree(m->d_bmi); (void)hipFree(m->d_gdat);
   (void)hipFree(m->d_gpos); (void)hipFree(m->d_gquat); (void)hipFree(m->d_gfr2); (void)hipFree(m->d_gmu);
-  (void)hipFree(m->d_jk64); (void)hipFree(m->d_jk32);
+  (void)hipFree(m->d_jk64); (void)hipFree(m->d_frames);
   (void)hipFree(m->d_cnp); (void)hipFree(m->d_cpos); (void)hipFree(m->d_ncon); (void)hipFree(m->d_over);
   for (auto &s : m->events)
     for (auto e : s.e) (void)hipEventDestroy(e);
@@ -211,7 +211,7 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   }
   std::vector<cf::BodyC> bodyc(nb);
   std::vector<cf::JointK<double>> jk64(nb);
-  std::vector<cf::JointK<float>> jk32(nb);
+  bool any_small = false;
   std::vector<cf::SubTree> subs;
   int art_floats = 0, artb_floats = 0;
   for (int b = 0; b < nb;) {
@@ -241,6 +241,7 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
           if (d->body_jnt[b + k] == CF_JNT_HINGE) st.chain |= 1 << (16 + k);
         }
         st.q0 = qadr[b];
+        any_small = true;
       }
       subs.push_back(st);
     }
@@ -262,9 +263,6 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
       if (c.jnt != CF_JNT_FREE) {
         const double a[3] = {ax[0] / an, ax[1] / an, ax[2] / an};
         jk64[k] = joint_constants(bq, bp, a, c.jnt == CF_JNT_HINGE);
-        const double *src = reinterpret_cast<const double *>(&jk64[k]);
-        float *dst = reinterpret_cast<float *>(&jk32[k]);
-        for (size_t i = 0; i < sizeof(jk64[k]) / sizeof(double); ++i) dst[i] = (float)src[i];
       }
     }
     b = e;
@@ -471,7 +469,10 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   chk(upload(&m->d_body, bodyc));
   chk(upload(&m->d_sub, subs));
   chk(upload(&m->d_jk64, jk64));
-  chk(upload(&m->d_jk32, jk32));
+  if (any_small) {
+    chk(hipMalloc((void **)&m->d_frames, sizeof(float4) * 5 * (size_t)nw * nb));
+    if (e == hipSuccess) chk(hipMemset(m->d_frames, 0, sizeof(float4) * 5 * (size_t)nw * nb));
+  }
   chk(upload(&m->d_bmi, bmi));
   chk(upload(&m->d_gdat, gdat));
   chk(upload(&m->d_gmu, gmu));
@@ -517,6 +518,7 @@ static cf::CollideArgs collide_args(const cf_model *m) {
   ca.gpos = m->d_gpos; ca.gquat = m->d_gquat; ca.gdat = m->d_gdat; ca.gbody = m->d_gbody;
   ca.gorient = m->d_gorient; ca.norient = m->norient;
   ca.body = m->d_body; ca.sub = m->d_sub; ca.nsub = m->nsub; ca.jk = m->d_jk64;
+  ca.frames = m->d_frames;
   ca.slots = m->d_slots; ca.cnp = m->d_cnp; ca.cpos = m->d_cpos; ca.ncon = m->d_ncon; ca.overflow = m->d_over;
   ca.nq = m->nq; ca.nb = m->nb; ca.ng = m->ng; ca.nslot = m->nslot; ca.ncon_max = m->ncon_max;
   ca.gpos_ws = m->gpos_ws; ca.gquat_ws = m->gquat_ws; ca.margin = m->p.margin;
@@ -527,7 +529,8 @@ static cf::CollideArgs collide_args(const cf_model *m) {
 static cf::ResolveArgs resolve_args(const cf_model *m) {
   cf::ResolveArgs ra{};
   ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gmu = m->d_gmu; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
-  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats; ra.jk = m->d_jk32;
+  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats;
+  ra.frames = m->d_frames;
   ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
   ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
   ra.condim = m->condim; ra.nfacet = m->nf; ra.nbits = m->nbits; ra.p = m->p; ra.act = m->d_act;

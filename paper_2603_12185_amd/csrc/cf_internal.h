@@ -99,6 +99,8 @@ struct CollideArgs {
   int npl;                      // > 0: geoms [0, npl) are static planes whose slots are their rows against the block
   int sph_mfma;                 // 1: block of <= 64 spheres on pairwise different bodies, margin >= 0 (MFMA masks)
   const JointK<double> *jk;     // [nb] joint constants (articulated models)
+  float4 *frames;               // [nw][nb][5] frames of small-subtree bodies (origin, joint axis,
+                                // rotation rows) for the resolution, or null
   int gpos_ws, gquat_ws;        // world stride in elements (0 = shared by all worlds)
   float margin;
 };
@@ -124,7 +126,8 @@ struct ResolveArgs {
   const float *mlp;             // learned-gain network parameters, or null
   const float4 *mlp_img;        // their LDS image (launch_mlp_pack), with mlp
   const float4 *act;            // [nv] position actuators (kp, kd, q index bits, -), or null
-  const JointK<float> *jk;      // [nb] joint constants (articulated models)
+  const float4 *frames;         // [nw][nb][5] frames of small-subtree bodies written by the
+                                // narrow phase on the same q (CollideArgs::frames), or null
   int nq, nv, nb, ng, ncon_max, condim, nfacet, nbits, nsub, art_floats;
   int nworld;
   Params p;

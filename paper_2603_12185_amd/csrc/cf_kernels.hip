@@ -476,14 +476,9 @@ __device__ inline int quad_bcast_i(int x) {
   return __builtin_amdgcn_update_dpp(0, x, J * 0x55, 0xF, 0xF, false);
 }
 template <int J>
-__device__ inline float quad_bcast(float x) {
-  return __int_as_float(quad_bcast_i<J>(__float_as_int(x)));
-}
-template <int J>
 __device__ inline double quad_bcast(double x) {
   return __hiloint2double(quad_bcast_i<J>(__double2hiint(x)), quad_bcast_i<J>(__double2loint(x)));
 }
-__device__ inline void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
 __device__ inline void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
 
 // Lane k of the quad: frames along the chain of body k of a small subtree
@@ -542,9 +537,12 @@ __device__ inline void quad_chain(const SubTree S, const SmallChain &C, int k, c
 }
 
 // Float64 forward kinematics of a small subtree for the narrow phase (the
-// frames fk_range writes), lane k of the quad writing body k's.
-__device__ __attribute__((always_inline)) inline void fk_small(const SubTree S, int k, const BodyC *B, const JointK<double> *JK, const float *sq,
-                                double *org, double *rot) {
+// frames fk_range writes), lane k of the quad writing body k's; `fr` (the
+// world's frame rows, or null) receives body k's origin, world joint axis
+// and rotation rows in float32 for the resolution of the same step.
+__device__ __attribute__((always_inline)) inline void fk_small(const SubTree S, int k, const JointK<double> *JK,
+                                                               const float *sq, double *org, double *rot,
+                                                               float4 *fr) {
   const SmallChain C = small_chain(S);
   QuadChain<double> Q;
   quad_chain<double>(S, C, k, JK, sq, Q);
@@ -556,47 +554,65 @@ __device__ __attribute__((always_inline)) inline void fk_small(const SubTree S, 
 #pragma unroll
       for (int j = 0; j < 3; ++j) rot[12 * b + 4 * i + j] = Q.R[3 * i + j];
     }
+    if (fr) {
+      double ak[3] = {Q.a[0][0], Q.a[0][1], Q.a[0][2]};
+#pragma unroll
+      for (int j = 1; j < kSmallSub; ++j)
+        if (j == k) {
+          ak[0] = Q.a[j][0]; ak[1] = Q.a[j][1]; ak[2] = Q.a[j][2];
+        }
+      fr += 5 * b;
+      fr[0] = make_float4((float)Q.ok[0], (float)Q.ok[1], (float)Q.ok[2], 0.f);
+      fr[1] = make_float4((float)ak[0], (float)ak[1], (float)ak[2], 0.f);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        fr[2 + i] = make_float4((float)Q.R[3 * i], (float)Q.R[3 * i + 1], (float)Q.R[3 * i + 2], 0.f);
+    }
   }
 }
 
-__device__ void art_predict_small(const SubTree S, int k, const BodyC *B, const JointK<float> *JK,
-                                  const float4 *bmi, const float *sq, const float *sv, const float *st, float4 *bC,
-                                  float4 *bV, float4 *bW, float4 *bO, float4 *bAx, float4 *bR, float *blk,
-                                  const Params &P) {
+// The frames of the subtree's bodies (bO, bAx, bR: origin, world joint axis,
+// rotation) are in LDS already (the narrow phase's float64 kinematics of the
+// same q, staged by resolve_world), and so are body k's inertia in bW[b] and
+// COM offset in bC[b], which this call replaces with its velocity and COM.
+__device__ void art_predict_small(const SubTree S, int k, const float *sv, const float *st, float4 *bC,
+                                  float4 *bV, float4 *bW, const float4 *bO, const float4 *bAx, const float4 *bR,
+                                  float *blk, const Params &P) {
   constexpr int N = kSmallSub;
   const SmallChain C = small_chain(S);
   const int n = C.n;
   const bool own = k < n;
   const int b = S.b0 + k;
   const int anck = own ? pick(C.anc, k) : 0;
-  // body k's inertia and COM offset, loaded ahead of the chain walk
-  const float4 mi = own ? bmi[b] : make_float4(0.f, 1.f, 1.f, 1.f);
-  const float4 ip = own ? B[b].ipos : make_float4(0.f, 0.f, 0.f, 0.f);
-  QuadChain<float> Q;
-  quad_chain<float>(S, C, k, JK, sq, Q);
+  const float4 mi = own ? bW[b] : make_float4(0.f, 1.f, 1.f, 1.f);
+  const float4 ip = own ? bC[b] : make_float4(0.f, 0.f, 0.f, 0.f);
   struct {
     V3 o[N], a[N], c;
     float R[9];
   } Fr;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    Fr.o[j] = v3(Q.o[j][0], Q.o[j][1], Q.o[j][2]);
-    Fr.a[j] = v3(Q.a[j][0], Q.a[j][1], Q.a[j][2]);
+    Fr.o[j] = Fr.a[j] = v3(0.f, 0.f, 0.f);
+    if ((anck >> j) & 1) {
+      const float4 o = bO[S.b0 + j], x = bAx[S.b0 + j];
+      Fr.o[j] = v3(o.x, o.y, o.z);
+      Fr.a[j] = v3(x.x, x.y, x.z);
+    }
   }
-#pragma unroll
-  for (int i = 0; i < 9; ++i) Fr.R[i] = Q.R[i];
-  const V3 ok = v3(Q.ok[0], Q.ok[1], Q.ok[2]), ak = pick(Fr.a, k);
-  Fr.c = ok;
+  V3 ok = v3(0.f, 0.f, 0.f);
+  const float4 r0 = own ? bR[3 * b] : make_float4(1.f, 0.f, 0.f, 0.f);
+  const float4 r1 = own ? bR[3 * b + 1] : make_float4(0.f, 1.f, 0.f, 0.f);
+  const float4 r2 = own ? bR[3 * b + 2] : make_float4(0.f, 0.f, 1.f, 0.f);
+  Fr.R[0] = r0.x; Fr.R[1] = r0.y; Fr.R[2] = r0.z;
+  Fr.R[3] = r1.x; Fr.R[4] = r1.y; Fr.R[5] = r1.z;
+  Fr.R[6] = r2.x; Fr.R[7] = r2.y; Fr.R[8] = r2.z;
   if (own) {
-    Fr.c = v3(ok.x + Fr.R[0] * ip.x + Fr.R[1] * ip.y + Fr.R[2] * ip.z,
-              ok.y + Fr.R[3] * ip.x + Fr.R[4] * ip.y + Fr.R[5] * ip.z,
-              ok.z + Fr.R[6] * ip.x + Fr.R[7] * ip.y + Fr.R[8] * ip.z);
-    bO[b] = make_float4(ok.x, ok.y, ok.z, 0.f);
-    bAx[b] = make_float4(ak.x, ak.y, ak.z, 0.f);
-    bR[3 * b] = make_float4(Fr.R[0], Fr.R[1], Fr.R[2], 0.f);
-    bR[3 * b + 1] = make_float4(Fr.R[3], Fr.R[4], Fr.R[5], 0.f);
-    bR[3 * b + 2] = make_float4(Fr.R[6], Fr.R[7], Fr.R[8], 0.f);
+    const float4 o = bO[b];
+    ok = v3(o.x, o.y, o.z);
   }
+  Fr.c = v3(ok.x + Fr.R[0] * ip.x + Fr.R[1] * ip.y + Fr.R[2] * ip.z,
+            ok.y + Fr.R[3] * ip.x + Fr.R[4] * ip.y + Fr.R[5] * ip.z,
+            ok.z + Fr.R[6] * ip.x + Fr.R[7] * ip.y + Fr.R[8] * ip.z);
   // body k's Jacobian columns: lin[j] = a_j x (c_k - o_j) (hinge) or a_j
   // (slide) where dof j moves body k, ang[j] = a_j (hinge); else 0
   float mk[N], v[N];
@@ -1289,7 +1305,7 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     for (int t = tid; t < 4 * a.nsub; t += BS) {
       const SubTree S = t == tid ? sub0 : a.sub[t >> 2];
       if (S.small)
-        fk_small(S, t & 3, a.body, a.jk, sq, borg, brot);
+        fk_small(S, t & 3, a.jk, sq, borg, brot, a.frames ? a.frames + (size_t)w * a.nb * 5 : nullptr);
       else if ((t & 3) == 0)
         fk_range<double>(S.b0, S.nb, a.body, sq, borg, brot, nullptr, nullptr);
     }
@@ -2072,6 +2088,48 @@ __device__ inline void resolve_geoms(const ResolveArgs &a, int w, int *gB, float
   }
 }
 
+// Per-lane records the resolution of world w reads after its first barrier:
+// lane tid's actuator, body record (free-body flag, q and dof offsets),
+// subtree (lanes 4 si .. 4 si + 3: subtree si) and, for a body of a small
+// subtree, its frame rows and COM offset.
+struct LanePre {
+  float4 act;
+  int fast, qadr, dadr;
+  SubTree sub;
+  float4 fr[5], ipos;
+};
+
+template <bool ART>
+__device__ inline LanePre lane_prefetch(const ResolveArgs &a, int w) {
+  const int tid = threadIdx.x;
+  LanePre L;
+  L.act = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+  if (a.act && tid < a.nv) L.act = a.act[tid];
+  L.fast = 1;
+  L.qadr = 7 * tid;
+  L.dadr = 6 * tid;
+  L.sub = SubTree{};
+#pragma unroll
+  for (int i = 0; i < 5; ++i) L.fr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  L.ipos = L.fr[0];
+  if (ART) {
+    if (tid < a.nb) {
+      const BodyC &bc = a.body[tid];
+      L.fast = bc.fast;
+      L.qadr = bc.qadr;
+      L.dadr = bc.dadr;
+      L.ipos = bc.ipos;
+      if (a.frames) {
+        const float4 *f = a.frames + ((size_t)w * a.nb + tid) * 5;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) L.fr[i] = f[i];
+      }
+    }
+    if (tid < 4 * a.nsub) L.sub = a.sub[tid >> 2];
+  }
+  return L;
+}
+
 // Resolution of world w: its q and v rows (LDS sq, sv) become q+ and v+ in
 // place; st holds the step input (applied forces; an actuated dof's target is
 // replaced by its actuator force); the nc contacts are read from inn/inp
@@ -2083,7 +2141,8 @@ template <int CONDIM, int BS, bool ART, bool LEARN = false>
 __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv, float *st,
                               const float4 *inn, const float4 *inp, int nc, float4 c0n, float4 c0p,
                               float4 mi0, float4 *reg, size_t xbase, bool geoms_ready = false,
-                              const mlp::Weights *lnet = nullptr, float *lfeat = nullptr, float *lout = nullptr) {
+                              const mlp::Weights *lnet = nullptr, float *lfeat = nullptr, float *lout = nullptr,
+                              const LanePre *pre = nullptr) {
   constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = a.nb, ng = a.ng;
@@ -2097,22 +2156,31 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   float4 *bO = RR.bO, *bAx = RR.bAx, *bR = RR.bR;  // articulated bodies only
   float *art = RR.art;
   const Params P = a.p;
-  // constants read below, loaded together up front: the lane's actuator,
-  // body record and subtree
-  float4 act0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-  if (a.act && tid < a.nv) act0 = a.act[tid];
-  int fast0 = 1, qadr0 = 7 * tid, dadr0 = 6 * tid;
-  SubTree sub0{};
-  if (ART) {
-    if (tid < nb) {
-      const BodyC &bc = a.body[tid];
-      fast0 = bc.fast;
-      qadr0 = bc.qadr;
-      dadr0 = bc.dadr;
-    }
-    if (tid < 4 * a.nsub) sub0 = a.sub[tid >> 2];
-  }
+  // what the lane reads below, loaded together up front unless the caller
+  // has (its actuator, body record, subtree and body frame)
+  const LanePre L = pre ? *pre : lane_prefetch<ART>(a, w);
+  const float4 act0 = L.act;
+  const int fast0 = L.fast, qadr0 = L.qadr, dadr0 = L.dadr;
+  const SubTree sub0 = L.sub;
   if (!geoms_ready) resolve_geoms<CONDIM, BS>(a, w, gB, gM, 0);
+  if (ART && a.frames) {
+    // small subtrees: frames from the narrow phase, inertia in bW and COM
+    // offset in bC until the prediction replaces them
+    const float4 *fw = a.frames + (size_t)w * nb * 5;
+    for (int b = tid; b < nb; b += BS) {
+      const bool mine = b == tid;
+      if (mine ? fast0 : a.body[b].fast) continue;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        const float4 f = mine ? L.fr[i] : fw[5 * b + i];
+        if (i == 0) bO[b] = f;
+        else if (i == 1) bAx[b] = f;
+        else bR[3 * b + i - 2] = f;
+      }
+      bC[b] = mine ? L.ipos : a.body[b].ipos;
+      bW[b] = mine ? mi0 : a.bmi[(size_t)w * nb + b];
+    }
+  }
   __syncthreads();
   if (a.act) {
     // position actuators: the input of an actuated dof is its target u, the
@@ -2156,8 +2224,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   for (int t = tid; t < 4 * a.nsub; t += BS) {
     const SubTree S = t == tid ? sub0 : a.sub[t >> 2];
     if (S.small)
-      art_predict_small(S, t & 3, a.body, a.jk, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR,
-                        art + S.lofs, P);
+      art_predict_small(S, t & 3, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
     else if ((t & 3) == 0)
       art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
   }
@@ -2316,6 +2383,7 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   }
   float4 mi0 = make_float4(1.f, 1.f, 1.f, 1.f);
   if (tid < nb) mi0 = a.bmi[(size_t)w * nb + tid];
+  const LanePre pre = lane_prefetch<ART>(a, w);
   int gb0 = -1;
   float mu0 = 0.f;
   float2 fr0 = make_float2(0.f, 0.f);
@@ -2357,7 +2425,7 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
     __syncthreads();
   }
   resolve_world<CONDIM, BS, ART, LEARN>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg,
-                                        cbase, true, lnet, lfeat, lout);
+                                        cbase, true, lnet, lfeat, lout, &pre);
   float *qo = a.q_out + (size_t)w * nq, *vo = a.v_out + (size_t)w * nv;
   for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
   for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
