@@ -438,7 +438,7 @@ def learned_form(model, state_q, state_v, L, env_steps, sp):
     qs, vs = state_q.clone(), state_v.clone()
     launch = model.get_launch()
     t0 = time.perf_counter()
-    feats, targets, _, _ = learned.collect(model, qs.clone(), vs.clone(), steps=1)
+    feats, targets, _, _ = learned.collect(model, qs.clone(), vs.clone(), steps=1, margin=LEARNED_MARGIN)
     net, losses = learned.train(feats, targets, model.nfacet, steps=300)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -505,7 +505,7 @@ def learned_big(args, sp):
     big_steps(SETTLE_STEPS_128)  # settle (even count: the state ends in buffer 0)
     torch.cuda.synchronize()
     sq0, sv0 = bq[0].clone(), bv[0].clone()
-    feats, targets, _, _ = learned.collect(bm, sq0.clone(), sv0.clone(), steps=1)
+    feats, targets, _, _ = learned.collect(bm, sq0.clone(), sv0.clone(), steps=1, margin=LEARNED_MARGIN)
     g = torch.Generator(device=dev)
     g.manual_seed(args.seed)
     pick = torch.randperm(feats.shape[0], generator=g, device=dev)[:1000000]

@@ -121,9 +121,16 @@ typedef struct {
   float *frame;       /* [nworld][ncon_max][9] rows n, t1, t2                    */
   float *impulse;     /* [nworld][ncon_max][nfacet] lambda*h per facet           */
   /* training data of the learned impedance network (models of free bodies
-   * only, else ignored): the contact's 7 features (8th 0) and, per facet, the
-   * log of the exact diagonal gain over the heuristic's, clipped to
-   * [-ln 256, ln 256] (outputs beyond nfacet 0) */
+   * only, else ignored): the contact's 7 features (8th 0) and, on each of the
+   * nfacet outputs (the rest 0), the log of the gain multiplier g, clipped to
+   * [-ln 256, ln 256], that the network should apply to the heuristic gains:
+   * for the contact alone along its normal (the fallback rule's model, see
+   * cf_model_set_learned_impedance), with the heuristic's facet impulses
+   * summing to S and w = 1/m_a + 1/m_b (tr/3), the normal velocity after the
+   * step v(g) = v_n + w g S is placed at min(-phi/h, (v(1) + v_max)/2),
+   * v_max = sqrt(v(1)^2 + (margin/h)^2) the largest the fallback rule accepts
+   * with the model's margin; g = 1 without normal impulse, e^-ln256 when the
+   * velocity would need a pulling impulse */
   float *features;    /* [nworld][ncon_max][8]                                   */
   float *target;      /* [nworld][ncon_max][16]                                  */
   /* with the learned impedance on (cf_model_set_learned_impedance): 1 where
@@ -226,7 +233,9 @@ cf_status cf_model_set_actuators(cf_model *m, const float *kp, const float *kd);
  * the contact alone along its normal, a next-step penetration larger than the
  * heuristic's by more than `margin` (m) or a normal kinetic energy larger by
  * more than that of moving `margin` in one step; then the contact keeps the
- * heuristic gain.  params NULL switches the network off.  Models of free
+ * heuristic gain.  params NULL switches the network off and keeps `margin`
+ * for the training targets that cf_contacts exports (finite, >= 0, else
+ * CF_E_INVALID_ARG).  Models of free
  * bodies with the heuristic impedance only (else CF_E_UNSUPPORTED); the
  * resolution then runs at most 128 threads per world, after a one-workgroup
  * kernel that writes the network's bf16 LDS image from params (a device buffer

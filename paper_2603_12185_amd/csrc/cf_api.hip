@@ -700,12 +700,13 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
 
 cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float margin) {
   if (!m) return set_err(CF_E_INVALID_ARG, "model is NULL");
+  if (!(margin >= 0.f) || !std::isfinite(margin)) return set_err(CF_E_INVALID_ARG, "margin must be finite and >= 0");
   if (!params) {
     m->mlp = nullptr;
+    m->p.mlp_margin = margin;  // still sets the exported training targets
     return CF_OK;
   }
   if (!aligned16(params)) return set_err(CF_E_INVALID_ARG, "params must be 16-byte aligned");
-  if (!(margin >= 0.f)) return set_err(CF_E_INVALID_ARG, "margin must be >= 0");
   if (m->nsub > 0) return set_err(CF_E_UNSUPPORTED, "learned impedance covers models of free bodies only");
   if (m->p.imp_diag) return set_err(CF_E_UNSUPPORTED, "learned impedance scales the heuristic, not the diagonal form");
   const int block = m->block_resolve > 128 ? 128 : m->block_resolve;

@@ -1991,27 +1991,44 @@ __device__ inline void export_contact(const ResolveArgs &a, size_t ci, const Con
   }
 }
 
-// Training data of the learned gains (free-body models), when requested: the
-// contact's network features and, per facet, the log of the exact diagonal
-// gain over the heuristic's A, clipped.
-template <int NF>
+// Training data of the learned gains: the contact's features and, on every
+// facet, the log of the gain multiplier g (clipped to [-ln 256, ln 256]) that
+// the learned gains should apply to the heuristic's.  g is taken for the
+// contact alone along its normal, the model of the fallback rule: with the
+// heuristic's facet impulses lh (normal impulse S = sum lh) the normal
+// velocity after the step is v(g) = v_n + w g S (w = trs / 3); g puts it at
+// v* = min(-phi / h, (v_h + v_max) / 2), the velocity that closes the gap in
+// this step, capped half-way between the heuristic's v_h = v(1) and the
+// largest v_max = sqrt(v_h^2 + (margin / h)^2) the rule's energy test
+// accepts (margin: the model's learned-gain margin).  No normal impulse: g = 1.
+template <int CONDIM>
 __device__ inline void export_training(const ResolveArgs &a, size_t ci, const ContactKin &K, float A, float aa,
-                                       float h, const float4 *bC, const float4 *bI0, const float4 *bI1) {
+                                       const Params &P) {
+  constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
   if (a.x_feat) {
     float fe[mlp::NIN];
-    contact_features(K, h, fe);
+    contact_features(K, P.h, fe);
 #pragma unroll
     for (int i = 0; i < mlp::NIN; ++i) a.x_feat[(size_t)mlp::NIN * ci + i] = fe[i];
   }
   if (a.x_target) {
-    float Ad[NF];
-    diag_impedance<NF>(K.n, K.t1, K.t2, K.ba, K.bb, K.ra, K.rb, bC, bI0, bI1, K.mut, K.mutor, K.murol, aa, Ad);
+    float Ah[NF], lh[NF], S = 0.f;
 #pragma unroll
-    for (int i = 0; i < mlp::NOUT; ++i) {
-      float t = 0.f;
-      if (i < NF && A > 0.f && Ad[i] > 0.f) t = fminf(fmaxf(__logf(Ad[i] / A), -mlp::CLIP), mlp::CLIP);
-      a.x_target[(size_t)mlp::NOUT * ci + i] = t;
+    for (int i = 0; i < NF; ++i) Ah[i] = A;
+    facet_impulses<CONDIM>(Ah, K, aa, -P.k_user * K.phi, lh);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) S += lh[i];
+    float t = 0.f;
+    const float wS = K.trs * (1.0f / 3.0f) * S;
+    if (wS > 0.f) {
+      const float vn = dot(K.n, K.vrel), vh = vn + wS, vm = P.mlp_margin / P.h;
+      const float vmax = sqrtf(vh * vh + vm * vm);
+      const float vs = fminf(-K.phi / P.h, 0.5f * (vh + vmax));
+      const float g = (vs - vn) / wS;
+      t = g > 0.f ? fminf(fmaxf(logf(g), -mlp::CLIP), mlp::CLIP) : -mlp::CLIP;
     }
+#pragma unroll
+    for (int i = 0; i < mlp::NOUT; ++i) a.x_target[(size_t)mlp::NOUT * ci + i] = i < NF ? t : 0.f;
   }
 }
 
@@ -2302,7 +2319,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       }
       const size_t ci = xbase + k;
       export_contact<NF>(a, ci, K, lam);
-      if (!ART) export_training<NF>(a, ci, K, A, aa, P.h, bC, bI0, bI1);
+      if (!ART) export_training<CONDIM>(a, ci, K, A, aa, P);
     }
     // Per-body sums of the chunk's wrench entries in fixed point: integer
     // additions commute, so the order of the LDS atomics does not change the
@@ -2542,7 +2559,7 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
         WA2 = make_float2(-Ta.y, -Ta.z);
       }
       export_contact<NF>(a, cbase + k, K, lam);
-      export_training<NF>(a, cbase + k, K, A, aa, P.h, bC, bI0, bI1);
+      export_training<CONDIM>(a, cbase + k, K, A, aa, P);
     }
     // per-body fixed-point sums of the chunk (as in resolve_world)
     if (kA < nb) {
@@ -2781,7 +2798,7 @@ __global__ __launch_bounds__(64 * learn_worlds(NBL)) void resolve_learned_kernel
         WA2 = make_float2(-Ta.y, -Ta.z);
       }
       export_contact<NF>(a, cbase + k, K, lam);
-      export_training<NF>(a, cbase + k, K, A, aa, P.h, bC, bI0, bI1);
+      export_training<CONDIM>(a, cbase + k, K, A, aa, P);
     }
     if (kA < nb) {
       atomicMax(fxE + kA, eF);

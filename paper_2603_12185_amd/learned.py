@@ -1,9 +1,11 @@
 """Learned per-contact impedance: training data, training and evaluation.
 
 The network and its gradient run in the library's kernels (cf_mlp_*); the
-step exports each contact's features and the training target (the log of the
-exact diagonal gain over the heuristic's, clipped) through cf_contacts.  This
-module only moves tensors between those calls.
+step exports each contact's features and the training target through
+cf_contacts: the log of the gain multiplier that, for the contact alone along
+its normal, closes its gap within the step as far as the fallback rule's
+energy margin allows (half-way to the largest accepted normal velocity).
+This module only moves tensors between those calls.
 """
 from __future__ import annotations
 
@@ -36,11 +38,13 @@ def init_params(feats, seed=0):
     return p.astype(np.float32)
 
 
-def collect(model, q, v, steps, every=1, tau=None):
+def collect(model, q, v, steps, margin, every=1, tau=None):
     """Run `steps` plain steps from (q, v) (device tensors, updated in place)
-    and gather the training rows of every contact of every `every`-th step.
-    Returns (features [n][8], targets [n][16], q, v)."""
+    and gather the training rows of every contact of every `every`-th step,
+    the targets for the fallback margin `margin` (m; the learned gains are
+    switched off).  Returns (features [n][8], targets [n][16], q, v)."""
     import torch
+    model.set_learned_impedance(None, margin=margin)
     feats, tgts = [], []
     for t in range(steps):
         con = model.alloc_contacts(training=True) if t % every == 0 else None

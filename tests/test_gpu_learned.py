@@ -9,7 +9,9 @@ and the training data the step exports.
     an impulse would leave with far more normal kinetic energy, so the fallback
     keeps the heuristic everywhere: the facet impulses equal the plain step's
     bit for bit;
-  * exported features and targets equal what the oracle's own step implies;
+  * exported features equal what the oracle's own step implies, and targets
+    the training-target definition applied to the step's exported features
+    and impulses;
   * element-wise parity with the oracle's learned-gain step (the network's
     outputs scale each facet, then the fallback rule): a network of output
     biases alone, different on every facet, with the fallback off (exact y on
@@ -18,8 +20,9 @@ and the training data the step exports.
     a guard band); a network trained by the oracle's own FP64 Adam (decisions
     bit-equal outside a guard band derived from the bf16 error bound of the
     network's output, impulses and velocities within that bound);
-  * a network trained on the GPU on exported data lowers the kinetic jitter
-    of a held-out dense pile without raising its mean penetration.
+  * a network trained on the GPU on exported data lowers both the mean
+    penetration (by at least 10%) and the kinetic jitter of a held-out dense
+    pile, with under 5% of contacts falling back.
 """
 import os
 
@@ -131,22 +134,45 @@ def test_excessive_gains_fall_back_to_the_heuristic(torch_cuda):
     assert stats["contacts"] == 8
 
 
+def training_targets(feats, imps, h, margin):
+    """The exported training target of each contact (float64), from its
+    features (phi, v_n, .., 1/tr at columns 0, 1, 4) and heuristic facet
+    impulses: the log of the gain multiplier g that puts the normal velocity
+    after the step, for the contact alone, v(g) = v_n + (tr / 3) g S (S the
+    normal impulse, the facet impulses' sum), at min(-phi / h, (v(1) +
+    v_max) / 2) with v_max = sqrt(v(1)^2 + (margin / h)^2); 0 without normal
+    impulse, -CLIP where g <= 0; clipped to [-CLIP, CLIP].  Also returns
+    |v*| + |v_n| + |v(1)| + |v_max| and |v* - v_n| for rounding bounds."""
+    phi, vn, itr = feats[:, 0], feats[:, 1], feats[:, 4]
+    S = imps.sum(1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        wS = np.where(itr > 0, S / (3.0 * itr), 0.0)
+        vh = vn + wS
+        vmax = np.sqrt(vh * vh + (margin / h) ** 2)
+        vs = np.minimum(-phi / h, 0.5 * (vh + vmax))
+        g = (vs - vn) / wS
+        t = np.where(g > 0, np.clip(np.log(np.where(g > 0, g, 1.0)), -mlp.CLIP, mlp.CLIP), -mlp.CLIP)
+    t = np.where(wS > 0, t, 0.0)
+    return t, np.abs(vs) + np.abs(vn) + np.abs(vh) + vmax, np.abs(vs - vn)
+
+
 def test_exported_training_data_matches_oracle(torch_cuda):
     """Features (phi, v_n, u_1, u_2, m_eff, mu_t, h) from the oracle's smooth
-    velocity, frame and point; targets log(A_exact / A_heuristic) from the
-    oracle's facet gains in its diagonal and heuristic modes, clipped."""
+    velocity, frame and point; each contact's target is the training-target
+    definition applied to the step's own exported features and facet impulses
+    (those two are the oracle's within the standard tolerances), at float32
+    rounding, on the nfacet outputs, zero on the rest."""
     from paper_2603_12185_amd import cfsim
     s = scenes.mixed_shapes(nworld=3, seed=43, condim=3)
     q, v = _oracle_state(s, 60)
     model = cfsim.Model(s)
+    margin = 3e-4
+    model.set_learned_impedance(None, margin=margin)
     con = model.alloc_contacts(training=True)
     model.step(tdev(q), tdev(v), contacts=con)
     c = to_np(con)
     o = Oracle(s)
     _, _, out = o.step(q.astype(np.float64), v.astype(np.float64))
-    sd = dict(s)
-    sd["impedance"] = 1
-    _, _, outd = Oracle(sd).step(q.astype(np.float64), v.astype(np.float64))
     checked = 0
     for w in range(s["nworld"]):
         n = int(out["ncon"][w])
@@ -169,8 +195,12 @@ def test_exported_training_data_matches_oracle(torch_cuda):
             want = np.array([out["dist"][w, k], nrm @ vrel, t1 @ vrel, t2 @ vrel, 1.0 / trs, mu, s["h"], 0.0])
             assert np.all(np.abs(c["features"][w, k] - want) <= 1e-5 * np.abs(want) + 2e-6), \
                 (w, k, c["features"][w, k], want)
-            tgt = np.clip(np.log(outd["facet_gain"][w, k] / out["facet_gain"][w, k]), -mlp.CLIP, mlp.CLIP)
-            np.testing.assert_allclose(c["target"][w, k, :4], tgt, atol=2e-4)
+            np.testing.assert_allclose(c["impulse"][w, k], out["impulse"][w, k],
+                                       atol=1e-4 * np.abs(out["impulse"][w]).max() + 1e-9)
+            tgt, scale, diff = training_targets(c["features"][w, k:k + 1].astype(np.float64),
+                                                c["impulse"][w, k:k + 1].astype(np.float64), s["h"], margin)
+            tol = 1e-5 + 1e-6 * scale[0] / max(diff[0], 1e-30)
+            assert np.all(np.abs(c["target"][w, k, :4] - tgt[0]) <= tol), (w, k, c["target"][w, k, :4], tgt, tol)
             assert not c["target"][w, k, 4:].any()
             checked += 1
     assert checked > 5
@@ -184,24 +214,28 @@ def test_trained_network_quiets_the_pile(torch_cuda):
     q, v = tdev(s["q0"]), tdev(s["v0"])
     for _ in range(400):
         q, v = m.step(q, v)
-    F, T, q, v = learned.collect(m, q, v, steps=4)
+    margin = 1e-4
+    F, T, q, v = learned.collect(m, q, v, steps=4, margin=margin)
     net, losses = learned.train(F, T, 4, steps=300)
     print("training rows", F.shape[0], "losses", losses)
-    assert losses[-1] < 0.05 * losses[0]
+    assert losses[-1] < 0.1 * losses[0]
     se = scenes.dense_pile(nworld=256, nsphere=64, seed=1)
     me = cfsim.Model(se)
     qe, ve = tdev(se["q0"]), tdev(se["v0"])
     for _ in range(400):
         qe, ve = me.step(qe, ve)
     mp, xp, _, va, _ = learned.penetration_stats(me, qe.clone(), ve.clone(), 200)
-    me.set_learned_impedance(net, margin=1e-4)
-    ml, xl, _, vb, _ = learned.penetration_stats(me, qe.clone(), ve.clone(), 200)
+    me.set_learned_impedance(net, margin=margin)
+    ml, xl, _, vb, fb = learned.penetration_stats(me, qe.clone(), ve.clone(), 200)
     kp = float((va.reshape(256, 64, 6)[:, :, 0:3] ** 2).sum(-1).mean())
     kl = float((vb.reshape(256, 64, 6)[:, :, 0:3] ** 2).sum(-1).mean())
     print(f"mean penetration plain {mp * 1e3:.4f} mm learned {ml * 1e3:.4f} mm; "
-          f"max {xp * 1e3:.3f} / {xl * 1e3:.3f} mm; mean |v|^2 {kp:.3e} / {kl:.3e}")
-    assert ml <= mp * 1.01
+          f"max {xp * 1e3:.3f} / {xl * 1e3:.3f} mm; mean |v|^2 {kp:.3e} / {kl:.3e}; fallback {fb:.4f}")
+    # what the network adds over the heuristic alone, on worlds it was not
+    # trained on: lower mean penetration, a quieter pile, few fallbacks
+    assert ml <= 0.9 * mp
     assert kl < kp
+    assert fb < 0.05
 
 
 def _learned_scenes():
@@ -305,27 +339,22 @@ def test_fallback_decisions_match_oracle(torch_cuda, which):
     assert stats["checked"] >= 1
 
 
-def _oracle_training_data(s, q, v, steps):
-    """Features and clipped log targets (exact diagonal gain over the
-    heuristic's) of every contact of `steps` oracle steps from (q, v)."""
+def _oracle_training_data(s, q, v, steps, margin):
+    """Features and training targets (the exported definition, for the
+    fallback margin `margin`) of every contact of `steps` oracle steps from
+    (q, v), from the oracle's own features and facet impulses."""
     o = Oracle(s)
-    sd = dict(s)
-    sd["impedance"] = 1
-    od = Oracle(sd)
     F, T = [], []
     q, v = q.astype(np.float64), v.astype(np.float64)
     nf = scenes.nfacet(s["condim"])
     for _ in range(steps):
         q1, v1, out = o.step(q, v)
-        _, _, outd = od.step(q, v)
         for w in range(s["nworld"]):
             n = int(out["ncon"][w])
             F.append(out["features"][w, :n])
             t = np.zeros((n, mlp.NOUT))
-            with np.errstate(divide="ignore", invalid="ignore"):
-                t[:, :nf] = np.clip(np.log(outd["facet_gain"][w, :n] / out["facet_gain"][w, :n]),
-                                    -mlp.CLIP, mlp.CLIP)
-            T.append(np.nan_to_num(t))
+            t[:, :nf] = training_targets(out["features"][w, :n], out["impulse"][w, :n], s["h"], margin)[0][:, None]
+            T.append(t)
         q, v = q1, v1
     return np.concatenate(F), np.concatenate(T)
 
@@ -361,7 +390,7 @@ def _network_error_bound(params, feats, dfeat):
 
 def test_trained_network_matches_oracle(torch_cuda):
     """A network trained by the oracle's own FP64 Adam on the oracle's
-    training data (features and diagonal-gain targets of a settled pile),
+    training data (features and training targets of a settled pile),
     evaluated by the oracle at the kernel's operand precision (bf16 operands,
     wide accumulation): the GPU's features lie within stated bounds of the
     oracle's; those bounds, carried through the network (a bf16 rounding may
@@ -373,7 +402,7 @@ def test_trained_network_matches_oracle(torch_cuda):
     from paper_2603_12185_amd import cfsim
     s = scenes.dense_pile(nworld=4, nsphere=64, seed=5)
     q, v = _oracle_state(s, 300)
-    F, T = _oracle_training_data(s, q, v, 3)
+    F, T = _oracle_training_data(s, q, v, 3, 1e-4)
     params = mlp.init_params(F, seed=2)
     m_, v_ = np.zeros(mlp.NPARAM), np.zeros(mlp.NPARAM)
     losses = []
@@ -387,7 +416,7 @@ def test_trained_network_matches_oracle(torch_cuda):
     o = Oracle(s)
     nw, cm, nf = s["nworld"], s["ncon_max"], scenes.nfacet(s["condim"])
     best = None
-    for margin in (1e-5, 1e-4, 3e-4, 1e-3, 3e-3, 1e-2):
+    for margin in (1e-5, 2e-5, 4e-5, 7e-5, 1e-4, 3e-4, 1e-3):
         _, _, out = o.step(q, v, learned=(params, margin, "bf16"))
         frac = float(np.concatenate([out["fallback"][w, :out["ncon"][w]] for w in range(nw)]).mean())
         if best is None or abs(frac - 0.5) < abs(best[1] - 0.5):
