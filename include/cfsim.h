@@ -194,10 +194,13 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
  * be NULL).  T >= 0.  The same step as cf_step (Algorithm 1 with collision
  * and integration, repeated): batched rollouts are the workload of the
  * paper's throughput-versus-environments and MPC experiments (Sec. IV.E,
- * Sec. V).  When a world's state, contact list (ncon_max records) and
- * scratch fit one workgroup's LDS, all T steps run in one persistent kernel
- * launch (one workgroup per world, nothing but the trajectory crosses HBM;
- * see cf_model_get_launch), else as T cf_step calls.  Allocates nothing, so a
+ * Sec. V).  All T steps run in one persistent kernel launch (one workgroup
+ * per world; see cf_model_get_launch) for worlds of at most 64 free bodies
+ * without actuators or learned gains (each body stepped by its own lane, the
+ * contact records in the model's workspace) and for other models whose
+ * world state, contact list (ncon_max records) and scratch fit one
+ * workgroup's LDS (nothing but the trajectory crosses HBM); else, or when
+ * cf_model_autotune finds step launches faster, as T cf_step calls.  Allocates nothing, so a
  * stream capture (HIP graph) of the call replays it. */
 cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, const float *v0,
                      const float *tau_seq, float *q_traj, float *v_traj, int32_t *ncon_traj,

@@ -49,6 +49,8 @@ struct cf_model {
   int norient = 0, nsub = 0, art_floats = 0, artb_floats = 0;
   int block_collide = 64, block_resolve = 128, block_rollout = 256;
   size_t lds_rollout = 0;
+  size_t lds_rollout_free = 0;  // persistent rollout of free bodies (0: not applicable)
+  int ncu = 256;                // compute units of the model's device
   int block_backward = 0;  // 0: the adjoint's LDS does not fit any workgroup size
   size_t lds_backward = 0;
   bool rollout_steps = false;  // autotuner found T cf_step calls faster than the persistent kernel
@@ -416,11 +418,15 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
     return set_err(CF_E_UNSUPPORTED, "world too large for one workgroup's LDS (reduce bodies or geoms)");
   }
   m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, nb, ng, m->norient, m->nsub, m->nsph, m->art_floats, m->ncon_max);
+  if (m->nsub == 0 && cf::rollout_free_fits(m->nq, nb))
+    m->lds_rollout_free = cf::rollout_free_lds_bytes(nb, ng, m->norient, m->nsph);
   for (int bs : {256, 128, 64}) {
     const size_t l = cf::backward_lds_bytes(m->nq, m->nv, nb, ng, bs, m->nsub, m->art_floats, m->artb_floats);
     if (l <= kLdsLimit) { m->block_backward = bs; m->lds_backward = l; break; }
   }
   if (hipGetDevice(&m->dev) != hipSuccess) { delete m; return set_err(CF_E_DEVICE, "no HIP device"); }
+  if (hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->dev) != hipSuccess || m->ncu < 1)
+    m->ncu = 256;
 
   // ---- per-world constants (float32); shared arrays get world stride 0
   std::vector<float4> bmi((size_t)nw * nb), gdat(wg), gpos, gquat;
@@ -538,8 +544,15 @@ static cf::ResolveArgs resolve_args(const cf_model *m) {
   return ra;
 }
 
+// Worlds of free bodies (no actuators, no learned gains) take the persistent
+// free-body rollout kernel (one wave per world, contacts in the global
+// workspace); other models the general one when a world fits its LDS.
+static bool rollout_free(const cf_model *m) {
+  return m->lds_rollout_free > 0 && m->lds_rollout_free <= kLdsLimit && !m->d_act && !m->mlp;
+}
+
 static bool rollout_fused(const cf_model *m) {
-  return m->lds_rollout <= kLdsLimit && !m->rollout_steps && !m->mlp;
+  return !m->rollout_steps && !m->mlp && (rollout_free(m) || m->lds_rollout <= kLdsLimit);
 }
 
 // Learned gains on the register-resident resolution (several worlds per
@@ -682,7 +695,12 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
     r.s = resolve_args(m);
     r.q0 = q_traj; r.v0 = v_traj; r.tau_seq = tau_seq; r.q_traj = q_traj; r.v_traj = v_traj;
     r.ncon_traj = ncon_traj; r.over_traj = overflow_traj; r.T = T; r.nworld = m->nw; r.cap = m->ncon_max;
-    hipError_t e = cf::launch_rollout(r, m->block_rollout, m->lds_rollout, s);
+    // the free-body kernel sized for three resident waves per SIMD (twelve
+    // one-wave worlds per CU, no register spills) while the batch fits the
+    // device at that occupancy, else for four
+    hipError_t e = rollout_free(m)
+                       ? cf::launch_rollout_free(r, m->lds_rollout_free, m->nw <= 12 * m->ncu ? 3 : 4, s)
+                       : cf::launch_rollout(r, m->block_rollout, m->lds_rollout, s);
     if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("rollout launch: ") + hipGetErrorString(e));
     return CF_OK;
   }
@@ -828,7 +846,7 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
   m->rollout_steps = false;
   for (int io = 0; io < 3 && st == CF_OK; ++io) {
     const size_t lds = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->nsph, m->art_floats, m->ncon_max);
-    if (lds > kLdsLimit) continue;
+    if (rollout_free(m) ? io > 0 : lds > kLdsLimit) continue;  // the free-body kernel has one shape
     m->block_rollout = sizes[io];
     m->lds_rollout = lds;
     st = cf_rollout(m, stream, 1, q, v, nullptr, qt, vt, nullptr, nullptr);  // warm-up

@@ -179,6 +179,13 @@ hipError_t launch_resolve_free(const ResolveArgs &a, int nworld, int block, size
 // The same with learned gains (network image of launch_mlp_pack_k32 in
 // mlp_img), four worlds of at most 128 free bodies per workgroup.
 size_t resolve_learned_k32_lds_bytes(int nb, int ng);
+// Rollout of worlds of free bodies (at most 64, q row within the narrow
+// phase's candidate list), one persistent one-wave workgroup per world;
+// `waves`: 3 (registers for twelve resident worlds per CU, no spills) or 4
+// (sixteen).
+bool rollout_free_fits(int nq, int nb);
+size_t rollout_free_lds_bytes(int nb, int ng, int norient, int nsph);
+hipError_t launch_rollout_free(const RolloutArgs &a, size_t lds, int waves, hipStream_t s);
 hipError_t launch_resolve_learned(const ResolveArgs &a, int nworld, size_t lds, hipStream_t s);
 size_t mlp_image_k32_bytes();
 hipError_t launch_mlp_pack_k32(const float *params, void *img, hipStream_t s);

@@ -1267,9 +1267,9 @@ __device__ __attribute__((always_inline)) inline void sphere_masks_mfma(const fl
 // workgroup barrier.
 template <int BS, bool ART>
 __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float4 *reg, float4 *outn,
-                             float4 *outp, int cap, uint32_t nxt, const GeomIn *pre = nullptr) {
+                             float4 *outp, int cap, uint32_t nxt, const GeomIn *pre = nullptr, int tid_in = -1) {
   constexpr int NW = BS / 64;
-  const int tid = threadIdx.x;
+  const int tid = tid_in >= 0 ? tid_in : (int)threadIdx.x;
   Pose<double> *Od = reinterpret_cast<Pose<double> *>(reg);
   Pose<float> *Of = reinterpret_cast<Pose<float> *>(Od + a.norient);
   float4 *Gs = reinterpret_cast<float4 *>(Of + a.norient);
@@ -2466,11 +2466,19 @@ __host__ __device__ size_t resolve_free_lds_bytes(int nb, int ng) {
          sizeof(float4) * (size_t)ng;
 }
 
+// Resolution of world w of free bodies, lane b owning body b: from the lane's
+// q (7), v (6) and applied-force (6) entries and mass/inertia, the world's nc
+// contacts (the first chunk's records cn, cp of lane threadIdx.x already
+// loaded by the caller, the rest read from cnp/cpos), to the lane's q+ and v+
+// (qo, vo; lanes beyond nb return zeros).  `lds`: resolve_free_lds_bytes();
+// `xbase`: row of the world in the export arrays.  Ends with a workgroup barrier
+// after the last read of the body arrays.
 template <int CONDIM, int BS>
-__global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
+__device__ void resolve_free_world(const ResolveArgs &a, int w, const float *qb, const float *vb, const float *tb,
+                                   float4 mi, int nc, float4 cn, float4 cp, const float4 *cnp, const float4 *cpos,
+                                   size_t xbase, float4 *lds, float *qo, float *vo, int tid_in = -1) {
   constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
-  extern __shared__ float4 lds[];
-  const int w = blockIdx.x, tid = threadIdx.x;
+  const int tid = tid_in >= 0 ? tid_in : (int)threadIdx.x;
   const int nb = a.nb, ng = a.ng, nbp = pad4(nb);
   float4 *bC = lds, *bV = bC + nb, *bW = bV + nb, *bI0 = bW + nb, *bI1 = bI0 + nb;
   int *fx = reinterpret_cast<int *>(bI1 + nb);
@@ -2479,36 +2487,7 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
   int *gB = fx + 8 * nbp;
   float4 *gM = reinterpret_cast<float4 *>(gB + pad4(ng));
   const Params P = a.p;
-  const size_t cbase = (size_t)w * a.ncon_max;
-
-  // every independent global load first: the count, the first chunk of
-  // contact records, the lane's body, the per-geom inputs
-  const int nc = a.ncon[w];
-  float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
-  if (tid < a.ncon_max) {  // records beyond the count are never used
-    cn = a.cnp[cbase + tid];
-    cp = a.cpos[cbase + tid];
-  }
   const bool own = tid < nb;
-  float qb[7], vb[6], tb[6];
-  float4 mi = make_float4(1.f, 1.f, 1.f, 1.f);
-#pragma unroll
-  for (int i = 0; i < 7; ++i) qb[i] = 0.f;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) vb[i] = tb[i] = 0.f;
-  if (own) {
-    const float *qs = a.q + (size_t)w * a.nq + 7 * tid, *vs = a.v + (size_t)w * a.nv + 6 * tid;
-#pragma unroll
-    for (int i = 0; i < 7; ++i) qb[i] = qs[i];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) vb[i] = vs[i];
-    if (a.tau) {
-      const float *ts = a.tau + (size_t)w * a.nv + 6 * tid;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) tb[i] = ts[i];
-    }
-    mi = a.bmi[(size_t)w * nb + tid];
-  }
   for (int g = tid; g < ng; g += BS) {
     gB[g] = a.gbody[g];
     const float mu_t = a.gmu[(size_t)w * ng + g];
@@ -2526,8 +2505,8 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
     const int k = base + tid, kn = k + BS;
     float4 nn = make_float4(0.f, 0.f, 0.f, 0.f), np = nn;
     if (kn < nc) {  // next chunk, in flight during this one
-      nn = a.cnp[cbase + kn];
-      np = a.cpos[cbase + kn];
+      nn = cnp[kn];
+      np = cpos[kn];
     }
     int kA = nb, kB = nb;  // key nb = no body (static geom or idle lane)
     float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
@@ -2558,8 +2537,8 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
         WA = make_float4(-f.x, -f.y, -f.z, -Ta.x);
         WA2 = make_float2(-Ta.y, -Ta.z);
       }
-      export_contact<NF>(a, cbase + k, K, lam);
-      export_training<CONDIM>(a, cbase + k, K, A, aa, P);
+      export_contact<NF>(a, xbase + k, K, lam);
+      export_training<CONDIM>(a, xbase + k, K, A, aa, P);
     }
     // per-body fixed-point sums of the chunk (as in resolve_world)
     if (kA < nb) {
@@ -2594,10 +2573,53 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
     cp = np;
   }
 
-  // velocity correction and integration of the lane's body, stored directly
+  // velocity correction and integration of the lane's body
+#pragma unroll
+  for (int i = 0; i < 7; ++i) qo[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) vo[i] = 0.f;
+  if (own) free_body_correct(bC[tid], bV[tid], bW[tid], bI0[tid], bI1[tid], F, T, qb, P, qo, vo);
+  __syncthreads();
+}
+
+template <int CONDIM, int BS>
+__global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
+  extern __shared__ float4 lds[];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int nb = a.nb;
+  const size_t cbase = (size_t)w * a.ncon_max;
+  // every independent global load first: the count, the first chunk of
+  // contact records, the lane's body
+  const int nc = a.ncon[w];
+  float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
+  if (tid < a.ncon_max) {  // records beyond the count are never used
+    cn = a.cnp[cbase + tid];
+    cp = a.cpos[cbase + tid];
+  }
+  const bool own = tid < nb;
+  float qb[7], vb[6], tb[6];
+  float4 mi = make_float4(1.f, 1.f, 1.f, 1.f);
+#pragma unroll
+  for (int i = 0; i < 7; ++i) qb[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) vb[i] = tb[i] = 0.f;
   if (own) {
-    float qo[7], vo[6];
-    free_body_correct(bC[tid], bV[tid], bW[tid], bI0[tid], bI1[tid], F, T, qb, P, qo, vo);
+    const float *qs = a.q + (size_t)w * a.nq + 7 * tid, *vs = a.v + (size_t)w * a.nv + 6 * tid;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qb[i] = qs[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vb[i] = vs[i];
+    if (a.tau) {
+      const float *ts = a.tau + (size_t)w * a.nv + 6 * tid;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) tb[i] = ts[i];
+    }
+    mi = a.bmi[(size_t)w * nb + tid];
+  }
+  float qo[7], vo[6];
+  resolve_free_world<CONDIM, BS>(a, w, qb, vb, tb, mi, nc, cn, cp, a.cnp + cbase, a.cpos + cbase, cbase, lds, qo, vo);
+  // the lane's body, stored directly
+  if (own) {
     float *qd = a.q_out + (size_t)w * a.nq + 7 * tid, *vd = a.v_out + (size_t)w * a.nv + 6 * tid;
 #pragma unroll
     for (int i = 0; i < 7; ++i) qd[i] = qo[i];
@@ -2942,6 +2964,119 @@ __global__ __launch_bounds__(BS, 2) void rollout_kernel(RolloutArgs r) {
     for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
     for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
   }
+}
+
+// ---- rollout of worlds of free bodies: one persistent one-wave workgroup per
+// world, lane b stepping body b.  Each step runs the narrow phase
+// (collide_world, contacts to the model's global workspace, read back by the
+// same workgroup) and the free-body resolution (resolve_free_world), whose
+// per-body inputs the lane reads back from its own trajectory row (nothing
+// held across the narrow phase, which keeps the kernel within 128 registers).  The q row the narrow phase reads
+// lives in LDS inside the narrow phase's candidate list, which nothing uses
+// between the end of a resolution and the geoms' world poses of the next
+// step; the LDS footprint is then the larger of the two regions (8.6 KB for
+// 64 spheres), so as many worlds share a CU as with step launches, and the
+// worlds drift out of step with each other, overlapping one world's loads with
+// another's arithmetic.  Same device functions, arithmetic and summation
+// order as cf_step: the trajectories equal T steps bit for bit.
+__host__ __device__ inline size_t collide_cand_offset(int ng, int norient) {
+  return (sizeof(Pose<double>) + sizeof(Pose<float>)) * (size_t)norient + sizeof(float4) * (size_t)ng +
+         2 * sizeof(int) * (size_t)pad4(ng);
+}
+
+size_t rollout_free_lds_bytes(int nb, int ng, int norient, int nsph) {
+  const size_t c = collide_region_bytes(nb, ng, norient, 0, nsph), r = resolve_free_lds_bytes(nb, ng);
+  return c > r ? c : r;
+}
+
+bool rollout_free_fits(int nq, int nb) { return nb <= 64 && nq <= kCandCap; }
+
+// WAVES: resident waves per SIMD the registers are sized for (3: no spills,
+// twelve worlds per CU; 4: sixteen, a few spills).
+template <int CONDIM, int WAVES>
+__global__ __launch_bounds__(64, WAVES) void rollout_free_kernel(RolloutArgs r) {
+  constexpr int BS = 64;
+  extern __shared__ float4 lds[];
+  const CollideArgs &ca = r.c;
+  const ResolveArgs &ra = r.s;
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int nq = ra.nq, nv = ra.nv, nb = ra.nb, nw = r.nworld, cap = r.cap;
+  const bool own = tid < nb;
+  float *sq = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + collide_cand_offset(ca.ng, ca.norient));
+  for (int i = tid; i < nq; i += BS) sq[i] = r.q_traj[(size_t)w * nq + i];  // row 0 = the initial state
+  const uint32_t nxt = tid < ca.nslot_pre ? ca.slots[tid] : 0u;
+  for (int t = 0; t < r.T; ++t) {
+    // the world and lane index, opaque to the compiler in each step, so
+    // addresses are formed where they are used instead of being hoisted out
+    // of the step loop and held (and spilled) across it
+    int wt = w, tl = tid;
+    asm volatile("" : "+s"(wt), "+v"(tl));
+    const size_t cbase = (size_t)wt * cap;
+    __syncthreads();  // the q row is complete
+    const int found = collide_world<BS, false>(ca, wt, sq, lds, ca.cnp + cbase, ca.cpos + cbase, cap, nxt, nullptr, tl);
+    const int nc = found < cap ? found : cap;
+    if (tid == 0 && r.ncon_traj) r.ncon_traj[(size_t)t * nw + wt] = nc;
+    if (tid == 0 && r.over_traj) r.over_traj[(size_t)t * nw + wt] = found - nc;
+    // the lane's body from trajectory row t (its own writes of the previous
+    // step), and the contact records this workgroup wrote (visible after
+    // collide_world's barrier)
+    float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
+    if (tid < nc) {
+      cn = ca.cnp[cbase + tid];
+      cp = ca.cpos[cbase + tid];
+    }
+    float qb[7], vb[6], tb[6];
+    float4 mi = make_float4(1.f, 1.f, 1.f, 1.f);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qb[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vb[i] = tb[i] = 0.f;
+    if (own) {
+      const float *qs = r.q_traj + ((size_t)t * nw + wt) * nq + 7 * tid;
+      const float *vs = r.v_traj + ((size_t)t * nw + wt) * nv + 6 * tid;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) qb[i] = qs[i];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) vb[i] = vs[i];
+      if (r.tau_seq) {
+        const float *ts = r.tau_seq + ((size_t)t * nw + wt) * nv + 6 * tid;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) tb[i] = ts[i];
+      }
+      mi = ra.bmi[(size_t)wt * nb + tid];
+    }
+    float qo[7], vo[6];
+    resolve_free_world<CONDIM, BS>(ra, wt, qb, vb, tb, mi, nc, cn, cp, ca.cnp + cbase, ca.cpos + cbase, 0, lds, qo, vo, tl);
+    if (own) {
+      float *qd = r.q_traj + ((size_t)(t + 1) * nw + wt) * nq + 7 * tid;
+      float *vd = r.v_traj + ((size_t)(t + 1) * nw + wt) * nv + 6 * tid;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        qd[i] = qo[i];
+        sq[7 * tid + i] = qo[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) vd[i] = vo[i];
+    }
+  }
+}
+
+template <int WAVES>
+static hipError_t launch_rollout_free_w(const RolloutArgs &a, size_t lds, hipStream_t s) {
+  switch (a.s.condim) {
+    case 1: hipLaunchKernelGGL((rollout_free_kernel<1, WAVES>), dim3(a.nworld), dim3(64), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((rollout_free_kernel<3, WAVES>), dim3(a.nworld), dim3(64), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((rollout_free_kernel<4, WAVES>), dim3(a.nworld), dim3(64), lds, s, a); break;
+    case 6: hipLaunchKernelGGL((rollout_free_kernel<6, WAVES>), dim3(a.nworld), dim3(64), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rollout_free(const RolloutArgs &a, size_t lds, int waves, hipStream_t s) {
+  if (a.s.nsub > 0 || a.s.act || a.s.mlp || !rollout_free_fits(a.s.nq, a.s.nb) || a.cap != a.s.ncon_max)
+    return hipErrorInvalidValue;
+  return waves == 3 ? launch_rollout_free_w<3>(a, lds, s) : launch_rollout_free_w<4>(a, lds, s);
 }
 
 template <int CONDIM, bool ART>

@@ -294,17 +294,19 @@ def test_empty_and_overflow_edge_cases(torch_cuda):
 def test_rollout_reports_overflow(torch_cuda):
     """cf_rollout counts, per step and world, the contacts dropped beyond
     ncon_max exactly as cf_step does: sunk spheres with a small capacity, on
-    the persistent kernel and on step launches (a capacity too large for the
-    persistent kernel's LDS)."""
+    the free-body persistent kernel (contacts in the global workspace, any
+    capacity) and on step launches (80 bodies, more than the free-body kernel
+    takes, with a capacity too large for the general persistent kernel's
+    LDS)."""
     from paper_2603_12185_amd import cfsim
     torch = torch_cuda
     s2 = scenes.dense_pile(nworld=3, nsphere=32, seed=2)
     s2["q0"].reshape(3, 32, 7)[:, :, 2] = 0.01
+    s3 = scenes.dense_pile(nworld=3, nsphere=80, seed=2)
+    s3["q0"].reshape(3, 80, 7)[:, :, 2] = 0.01
     T = 4
-    for cm, fused in ((5, True), (40, True), (4000, False)):
-        sc = scenes.with_params(s2, ncon_max=cm)
-        if cm == 4000:
-            sc["q0"].reshape(3, 32, 7)[:, :, 2] = 0.01  # same sunk state, capacity never reached
+    for base, cm, fused in ((s2, 5, True), (s2, 40, True), (s2, 4000, True), (s3, 4000, False)):
+        sc = scenes.with_params(base, ncon_max=cm)
         model = cfsim.Model(sc)
         assert model.get_launch()[3] == fused
         q0, v0 = tdev(sc["q0"]), tdev(sc["v0"])
