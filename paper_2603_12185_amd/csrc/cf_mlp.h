@@ -219,32 +219,29 @@ __device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
 // features of contact l % 16 in the lanes of K group 0, zero elsewhere.
 __device__ inline f32x4 forward_tile_k32(const WeightsK32 *W, bf16x8 x) {
   const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   const bf16x8 zero8 = {};
+  // each layer's bias is the accumulators' initial value
+  auto bias = [](float4 b) {
+    const f32x4 v = {b.x, b.y, b.z, b.w};
+    return v;
+  };
   bf16x8 a[2];  // layer-1 activations as the operands of input blocks 0, 1
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    f32x4 z = mfma32(g == 0 ? W->w1[m][c] : zero8, x, zero);
-    const float4 b = W->b1[4 * m + g];
-    z[0] += b.x; z[1] += b.y; z[2] += b.z; z[3] += b.w;
+    const f32x4 z = mfma32(g == 0 ? W->w1[m][c] : zero8, x, bias(W->b1[4 * m + g]));
 #pragma unroll
     for (int r = 0; r < 4; ++r) a[m >> 1][4 * (m & 1) + r] = (__bf16)silu(z[r]);
   }
   bf16x8 a2[2];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    f32x4 z = mfma32(W->w2[m][0][l], a[0], zero);
+    f32x4 z = mfma32(W->w2[m][0][l], a[0], bias(W->b2[4 * m + g]));
     z = mfma32(W->w2[m][1][l], a[1], z);
-    const float4 b = W->b2[4 * m + g];
-    z[0] += b.x; z[1] += b.y; z[2] += b.z; z[3] += b.w;
 #pragma unroll
     for (int r = 0; r < 4; ++r) a2[m >> 1][4 * (m & 1) + r] = (__bf16)silu(z[r]);
   }
-  f32x4 y = mfma32(W->w3[0][l], a2[0], zero);
-  y = mfma32(W->w3[1][l], a2[1], y);
-  const float4 b = W->b3[g];
-  y[0] += b.x; y[1] += b.y; y[2] += b.z; y[3] += b.w;
-  return y;
+  f32x4 y = mfma32(W->w3[0][l], a2[0], bias(W->b3[g]));
+  return mfma32(W->w3[1][l], a2[1], y);
 }
 
 }  // namespace mlp
