@@ -402,6 +402,29 @@ def test_rollout_matches_steps_and_oracle(torch_cuda, scene_fn):
     print("rollout", scene_fn, stats, "contacts", int(ncon.sum()), "worst vs step", worst)
 
 
+def test_rollout_full_pile_matches_steps(torch_cuda):
+    """The benchmark's batch (4096 worlds x 64 spheres) through cf_rollout: more
+    worlds than twelve per CU, so the free-body persistent kernel takes its
+    four-waves-per-SIMD register sizing (the bench's launch); the trajectory
+    and per-step contact counts equal repeated cf_step from each rollout state,
+    from the lattice and from a settled state."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    s = scenes.dense_pile(nworld=4096, nsphere=64, seed=0)
+    model = cfsim.Model(s)
+    assert model.get_launch()[3], "expected the persistent rollout kernel"
+    _, vt, ncon, worst = _rollout_vs_steps(torch, model, s, 30)
+    assert worst < 1e-6, f"rollout vs step relative difference {worst:.2e}"
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    for _ in range(300):
+        q, v = model.step(q, v)
+    s2 = dict(s)
+    s2["q0"], s2["v0"] = q.cpu().numpy(), v.cpu().numpy()
+    _, vt2, ncon2, worst2 = _rollout_vs_steps(torch, model, s2, 30)
+    assert worst2 < 1e-6, f"settled: rollout vs step relative difference {worst2:.2e}"
+    assert float(ncon2.double().mean()) > 100, "the settled pile should hold its contacts"
+
+
 def test_rollout_graph_capture_replays(torch_cuda):
     """A stream capture of cf_rollout replays correctly: three replays with new
     initial states, eager work and synchronisations in between, each checked
