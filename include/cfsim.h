@@ -180,9 +180,11 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
  * same model on another stream).  Articulated subtrees (hinge and slide joints
  * below a fixed or a free root) and position actuators are covered (an
  * actuated dof's gtau entry is the adjoint of its target), and so is the
- * diagonal impedance (its per-facet gains differentiated through the lever
- * arms, the contact frame and the bodies' world inverse inertia, i.e. their
- * orientation); the learned impedance returns CF_E_UNSUPPORTED. */
+ * diagonal impedance on models of free bodies (its per-facet gains
+ * differentiated through the lever arms, the contact frame and the bodies'
+ * world inverse inertia, i.e. their orientation); the diagonal impedance on a
+ * model with articulated subtrees and the learned impedance return
+ * CF_E_UNSUPPORTED. */
 cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                            const float *gq_out, const float *gv_out, float *gq, float *gv, float *gtau);
 
@@ -212,9 +214,16 @@ cf_status cf_rollout(cf_model *m, void *stream, int32_t T, const float *q0, cons
  * paper gives before its heuristic, K h + D = (1/h) (J~_f M^-1 J~_f^T)^-1 per
  * facet f, split between K and D in the ratio k_user : d_user / h, so
  * lambda_f h = max(-(k_user h + d_user) s_f - k_user phi, 0) / ((k_user h + d_user) g_f)
- * with g_f = J~_f M^-1 J~_f^T (0 when k_user h + d_user = 0).  The diagonal form
- * is available for models of free bodies only (else CF_E_UNSUPPORTED);
- * cf_step_backward covers it. */
+ * with g_f = J~_f M^-1 J~_f^T (0 when k_user h + d_user = 0, or when the row
+ * moves no dof).  M is block diagonal over free bodies and articulated
+ * subtrees: a free body contributes its closed-form block, a subtree
+ * |L^-1 J~_f^T|^2 over its dofs from its Cholesky factor L (both bodies of
+ * a contact inside one subtree make one row on its dofs).  On a model with
+ * articulated subtrees the resolution keeps each body's L^-1 J_b^T in LDS
+ * (6 nd floats per body, nd its subtree's dofs): CF_E_UNSUPPORTED when that
+ * does not fit beside the world's other LDS data; cf_step_backward covers
+ * the diagonal form on models of free bodies only.  Host call; takes effect
+ * from the next launch. */
 cf_status cf_model_set_impedance(cf_model *m, int32_t mode);
 
 /* Position actuators on hinge and slide dofs (the actuated hand of the

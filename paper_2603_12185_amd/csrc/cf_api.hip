@@ -47,6 +47,7 @@ struct cf_model {
   cf::BodyC *d_body = nullptr;
   cf::SubTree *d_sub = nullptr;
   int norient = 0, nsub = 0, art_floats = 0, artb_floats = 0;
+  int ydiag_floats = 0;  // the bodies' L^-1 J^T columns (exact diagonal impedance), after the work blocks
   int block_collide = 64, block_resolve = 128, block_rollout = 256;
   size_t lds_rollout = 0;
   size_t lds_rollout_free = 0;  // persistent rollout of free bodies (0: not applicable)
@@ -78,6 +79,17 @@ struct cf_model {
   double ms_collide = 0, ms_resolve = 0;
   long long prof_steps = 0;
 };
+
+// Floats of the resolution's articulated LDS region: the subtrees' work
+// blocks and, with the exact diagonal impedance, their bodies' L^-1 J^T columns.
+static int art_region_floats(const cf_model *m) {
+  return m->art_floats + (m->p.imp_diag && m->nsub > 0 ? m->ydiag_floats : 0);
+}
+
+static size_t rollout_lds(const cf_model *m) {
+  return cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->nsph, art_region_floats(m),
+                               m->ncon_max);
+}
 
 namespace {
 
@@ -329,6 +341,10 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
   m->nq = nq; m->nv = nv;
   m->nsub = (int)subs.size(); m->art_floats = art_floats;
   m->artb_floats = artb_floats;
+  for (cf::SubTree &st : subs) {
+    st.yofs = art_floats + m->ydiag_floats;
+    m->ydiag_floats += 6 * st.nb * st.nd;
+  }
   m->nslot = (int)slots.size();
   m->box_pairs = box_pairs;
   m->dof_jnt.resize(nv);
@@ -417,7 +433,7 @@ cf_status cf_model_create(const cf_model_desc *d, cf_model **out) {
     delete m;
     return set_err(CF_E_UNSUPPORTED, "world too large for one workgroup's LDS (reduce bodies or geoms)");
   }
-  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, nb, ng, m->norient, m->nsub, m->nsph, m->art_floats, m->ncon_max);
+  m->lds_rollout = rollout_lds(m);
   if (m->nsub == 0 && cf::rollout_free_fits(m->nq, nb))
     m->lds_rollout_free = cf::rollout_free_lds_bytes(nb, ng, m->norient, m->nsph);
   for (int bs : {256, 128, 64}) {
@@ -535,7 +551,7 @@ static cf::CollideArgs collide_args(const cf_model *m) {
 static cf::ResolveArgs resolve_args(const cf_model *m) {
   cf::ResolveArgs ra{};
   ra.bmi = m->d_bmi; ra.gdat = m->d_gdat; ra.gmu = m->d_gmu; ra.gfr2 = m->d_gfr2; ra.gbody = m->d_gbody;
-  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = m->art_floats;
+  ra.body = m->d_body; ra.sub = m->d_sub; ra.nsub = m->nsub; ra.art_floats = art_region_floats(m);
   ra.frames = m->d_frames;
   ra.cnp = m->d_cnp; ra.cpos = m->d_cpos; ra.ncon = m->d_ncon;
   ra.nq = m->nq; ra.nv = m->nv; ra.nb = m->nb; ra.ng = m->ng; ra.ncon_max = m->ncon_max;
@@ -656,6 +672,8 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
       overlap(gtau, sv, gq_out, sq) || overlap(gtau, sv, gv_out, sv))
     return set_err(CF_E_INVALID_ARG, "gq/gv may alias gq_out/gv_out only exactly; no other overlap");
   if (m->mlp) return set_err(CF_E_UNSUPPORTED, "cf_step_backward does not cover the learned impedance");
+  if (m->p.imp_diag && m->nsub > 0)
+    return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers the diagonal impedance on models of free bodies only");
   if (!m->block_backward) return set_err(CF_E_UNSUPPORTED, "world too large for the adjoint's LDS");
   hipStream_t s = (hipStream_t)stream;
   cf::CollideArgs ca = collide_args(m);
@@ -747,9 +765,12 @@ cf_status cf_model_set_impedance(cf_model *m, int32_t mode) {
     return set_err(CF_E_UNSUPPORTED, "switch the learned impedance off first");
   if (mode != CF_IMPEDANCE_HEURISTIC && mode != CF_IMPEDANCE_DIAGONAL)
     return set_err(CF_E_INVALID_ARG, "impedance mode must be CF_IMPEDANCE_HEURISTIC or CF_IMPEDANCE_DIAGONAL");
-  if (mode == CF_IMPEDANCE_DIAGONAL && m->nsub > 0)
-    return set_err(CF_E_UNSUPPORTED, "the diagonal impedance covers models of free bodies only");
+  if (mode == CF_IMPEDANCE_DIAGONAL && m->nsub > 0 &&
+      cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->nsub, m->art_floats + m->ydiag_floats) > kLdsLimit)
+    return set_err(CF_E_UNSUPPORTED, "world too large for the diagonal impedance's LDS (L^-1 J^T per body)");
   m->p.imp_diag = mode == CF_IMPEDANCE_DIAGONAL ? 1 : 0;
+  m->lds_resolve = cf::resolve_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->nsub, art_region_floats(m));
+  m->lds_rollout = rollout_lds(m);
   return CF_OK;
 }
 
@@ -793,7 +814,7 @@ cf_status cf_model_set_launch(cf_model *m, int32_t collide_block, int32_t resolv
   m->block_resolve = resolve_block;
   m->block_rollout = rollout_block;
   m->rollout_steps = false;
-  m->lds_rollout = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->nsph, m->art_floats, m->ncon_max);
+  m->lds_rollout = rollout_lds(m);
   return CF_OK;
 }
 
@@ -845,7 +866,7 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
     }
   m->rollout_steps = false;
   for (int io = 0; io < 3 && st == CF_OK; ++io) {
-    const size_t lds = cf::rollout_lds_bytes(m->nq, m->nv, m->nb, m->ng, m->norient, m->nsub, m->nsph, m->art_floats, m->ncon_max);
+    const size_t lds = rollout_lds(m);
     if (rollout_free(m) ? io > 0 : lds > kLdsLimit) continue;  // the free-body kernel has one shape
     m->block_rollout = sizes[io];
     m->lds_rollout = lds;

@@ -51,6 +51,10 @@ struct SubTree {
   // 4k..4k+3 mark body k and its ancestors (bit j: body b0 + j), bit 16 + k a
   // hinge (else a slide)
   int chain, q0;
+  // exact diagonal impedance only: float offset (in the same LDS region as
+  // the work blocks, after all of them) of the bodies' L^-1 J_b^T blocks,
+  // 6 nd floats per body, column r of body b0 + k at yofs + (6 k + r) nd
+  int yofs;
 };
 constexpr int kSmallSub = 4;
 

@@ -152,11 +152,14 @@ __device__ inline float block_max(float x, float *wmax) {
 template <int BS, int K>
 struct RowStage {
   float r[K];
+  // every lane issues all K loads (indices clamped to the row, values past
+  // its end unused), so no wait sits between them and later loads
   __device__ inline void load(const float *src, int n) {
+    if (n <= 0) return;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = threadIdx.x + k * BS;
-      r[k] = i < n ? src[i] : 0.f;
+      r[k] = src[i < n ? i : n - 1];
     }
   }
   __device__ inline void store(float *dst, const float *src, int n) const {
@@ -335,10 +338,12 @@ __device__ inline void bwd_solve(const float *L, int n, float *x) {
 // bias c = sum_b J_b^T [m (Jdot_b v - g); I_b (Jdot_b v)_ang + w_b x I_b w_b],
 // Cholesky, v_s = v + h M^-1 (tau - c), body velocities at v_s and COM traces.
 // Work block: M/L [nd*nd] | c [nd] | v_s [nd] | cols [6 nd] | idx [nd].
+// yd (or null): each body's L^-1 J_b^T, the six columns (linear, angular)
+// of body b0 + k at yd + (6 k + r) nd, for the exact diagonal impedance.
 __device__ __attribute__((noinline)) void art_predict(const SubTree S, const BodyC *B, const float4 *bmi,
                                                       const float *sq, const float *sv,
                             const float *st, float4 *bC, float4 *bV, float4 *bW, float4 *bO, float4 *bAx,
-                            float4 *bR, float *blk, const Params &P) {
+                            float4 *bR, float *blk, const Params &P, float *yd) {
   const int nd = S.nd, d0 = S.d0;
   float *M = blk, *cv = M + nd * nd, *vs = cv + nd, *cols = vs + nd;
   int *idx = reinterpret_cast<int *>(cols + 6 * nd);
@@ -412,11 +417,14 @@ __device__ __attribute__((noinline)) void art_predict(const SubTree S, const Bod
       om = om + vx * v3(c[3], c[4], c[5]);
     }
     float tr = 0.f;
-    for (int r = 0; r < 3; ++r) {
-      for (int i = 0; i < nd; ++i) cv[i] = 0.f;
-      for (int x = 0; x < n; ++x) cv[idx[x]] = cols[6 * x + r];
-      fwd_solve(M, nd, cv);
-      for (int i = 0; i < nd; ++i) tr += cv[i] * cv[i];
+    float *yb = yd ? yd + 6 * nd * (b - S.b0) : nullptr;
+    for (int r = 0; r < (yb ? 6 : 3); ++r) {
+      float *y = yb ? yb + r * nd : cv;
+      for (int i = 0; i < nd; ++i) y[i] = 0.f;
+      for (int x = 0; x < n; ++x) y[idx[x]] = cols[6 * x + r];
+      fwd_solve(M, nd, y);
+      if (r < 3)
+        for (int i = 0; i < nd; ++i) tr += y[i] * y[i];
     }
     bV[b] = make_float4(vc.x, vc.y, vc.z, tr);
     bW[b] = make_float4(om.x, om.y, om.z, 0.f);
@@ -577,7 +585,7 @@ __device__ __attribute__((always_inline)) inline void fk_small(const SubTree S, 
 // COM offset in bC[b], which this call replaces with its velocity and COM.
 __device__ void art_predict_small(const SubTree S, int k, const float *sv, const float *st, float4 *bC,
                                   float4 *bV, float4 *bW, const float4 *bO, const float4 *bAx, const float4 *bR,
-                                  float *blk, const Params &P) {
+                                  float *blk, const Params &P, float *yd) {
   constexpr int N = kSmallSub;
   const SmallChain C = small_chain(S);
   const int n = C.n;
@@ -734,6 +742,23 @@ __device__ void art_predict_small(const SubTree S, int k, const float *sv, const
   float tr = 0.f;
 #pragma unroll
   for (int j = 0; j < N; ++j) tr += e0[j] * e0[j] + e1[j] * e1[j] + e2[j] * e2[j];
+  if (yd && own) {  // body k's L^-1 J_k^T (art_predict's layout) for the exact diagonal impedance
+    float e3[N], e4[N], e5[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      e3[j] = ang[j].x; e4[j] = ang[j].y; e5[j] = ang[j].z;
+    }
+    solve_fwd(e3);
+    solve_fwd(e4);
+    solve_fwd(e5);
+    float *yk = yd + 6 * n * k;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (j >= n) continue;
+      yk[j] = e0[j]; yk[n + j] = e1[j]; yk[2 * n + j] = e2[j];
+      yk[3 * n + j] = e3[j]; yk[4 * n + j] = e4[j]; yk[5 * n + j] = e5[j];
+    }
+  }
   // the Jdot reads of the quad precede these writes (one wave, program order)
   if (own) {
     bC[b] = make_float4(Fr.c.x, Fr.c.y, Fr.c.z, 0.f);
@@ -1263,8 +1288,8 @@ __device__ __attribute__((always_inline)) inline void sphere_masks_mfma(const fl
 // contacts of the canonical order to outn/outp (global or LDS) and returns the
 // number found.  `reg` is LDS scratch of collide_region_bytes(); `nxt` is the
 // caller's prefetch of slots[threadIdx.x]; `pre`, when given, the caller's
-// prefetch of geom threadIdx.x (valid when threadIdx.x < ng).  Ends with a
-// workgroup barrier.
+// prefetch of geoms threadIdx.x and threadIdx.x + BS (each valid where below
+// ng).  Ends with a workgroup barrier.
 template <int BS, bool ART>
 __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float4 *reg, float4 *outn,
                              float4 *outp, int cap, uint32_t nxt, const GeomIn *pre = nullptr, int tid_in = -1) {
@@ -1282,16 +1307,18 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
   __shared__ float wmax[NW];
 
   // slot words of the next three chunks, in flight during the set-up below
-  const int npre = a.npl > 0 ? 0 : a.nslot_pre;
-  uint32_t nxt2 = tid + BS < npre ? a.slots[tid + BS] : 0u;
-  uint32_t nxt3 = tid + 2 * BS < npre ? a.slots[tid + 2 * BS] : 0u;
-  uint32_t nxt4 = tid + 3 * BS < npre ? a.slots[tid + 3 * BS] : 0u;
+  // (loaded by every lane, index clamped into the table; a word past the
+  // slots before the sphere block is never used)
+  const int npre = a.npl > 0 ? 0 : a.nslot_pre, spl = npre > 0 ? npre - 1 : 0;
+  uint32_t nxt2 = a.slots[tid + BS < npre ? tid + BS : spl];
+  uint32_t nxt3 = a.slots[tid + 2 * BS < npre ? tid + 2 * BS : spl];
+  uint32_t nxt4 = a.slots[tid + 3 * BS < npre ? tid + 3 * BS : spl];
   // articulated models: the lane's subtree record and the body record of
   // geom tid, also in flight before the kinematics
   SubTree sub0{};
   int gfast0 = 1, gqadr0 = 0;
   if (ART) {
-    if (tid < 4 * a.nsub) sub0 = a.sub[tid >> 2];
+    sub0 = a.sub[tid < 4 * a.nsub ? tid >> 2 : a.nsub - 1];  // (a lane past the subtrees: unused)
     if (pre && tid < a.ng && pre->b >= 0) {
       const BodyC &bc = a.body[pre->b];
       gfast0 = bc.fast;
@@ -1313,17 +1340,16 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
   }
 
   // geom world poses; oriented geoms also get float64 and float32 pose records
-  for (int g = tid; g < a.ng; g += BS) {
-    const GeomIn gi = (pre && g == tid) ? *pre : geom_in(a, w, g);
+  // (geoms tid and tid + BS from the caller's prefetch when given)
+  auto geom_pose = [&](int g, const GeomIn &gi, bool own /* body record prefetched */) {
     const int b = gi.b, o = gi.o;
     const float4 gp = gi.gp, gd = gi.gd, gq = gi.gq;
     go[g] = o;
     gbd[g] = b;
-    const bool own = pre && g == tid;  // body record prefetched
     if (o < 0) {  // sphere at the origin of a free body (or static)
       const float *qb = b >= 0 ? sq + (ART ? (own ? gqadr0 : a.body[b].qadr) : 7 * b) : nullptr;
       Gs[g] = b >= 0 ? make_float4(qb[0], qb[1], qb[2], gd.x) : make_float4(gp.x, gp.y, gp.z, gd.x);
-      continue;
+      return;
     }
     double bp[3] = {0.0, 0.0, 0.0}, br[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0}, gr[9];
     if (b >= 0) {
@@ -1370,7 +1396,14 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     Od[o] = pd;
     Of[o] = pf;
     Gs[g] = make_float4(pf.p[0], pf.p[1], pf.p[2], gd.x);
+  };
+  int g0 = tid;
+  if (pre) {
+    if (tid < a.ng) geom_pose(tid, pre[0], true);
+    if (tid + BS < a.ng) geom_pose(tid + BS, pre[1], false);
+    g0 = tid + 2 * BS;
   }
+  for (int g = g0; g < a.ng; g += BS) geom_pose(g, geom_in(a, w, g), false);
   __syncthreads();
 
   // Pass-1 band: float32 gaps are accurate to a few ulp of the coordinates and
@@ -1484,7 +1517,7 @@ __device__ int collide_world(const CollideArgs &a, int w, const float *sq, float
     nxt = nxt2;
     nxt2 = nxt3;
     nxt3 = nxt4;
-    nxt4 = s + 4 * BS < npre ? a.slots[s + 4 * BS] : 0u;
+    nxt4 = a.slots[s + 4 * BS < npre ? s + 4 * BS : spl];
     const bool c = s < npre && slot_candidate(sl, Gs, go, Of, a.margin + band);
     int tot;
     const int idx = block_scan<BS>(c, &tot, wcnt, par);
@@ -1593,10 +1626,12 @@ __global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
   const int w = blockIdx.x, tid = threadIdx.x;
   float *sq = reinterpret_cast<float *>(lds);
   constexpr int K = 512 / BS;
-  // issue the independent global loads (slots, geoms, q row) before the first wait
-  const uint32_t nxt = tid < a.nslot_pre ? a.slots[tid] : 0u;  // prefetch of the first chunk
-  GeomIn pre{};
-  if (tid < a.ng) pre = geom_in(a, w, tid);
+  // issue the independent global loads (slots, geoms tid and tid + BS, q row)
+  // before the first wait, every lane all of them (indices clamped into the
+  // arrays, which hold at least one entry; values past their ends unused)
+  const uint32_t nxt = a.slots[tid < a.nslot_pre ? tid : (a.nslot_pre > 0 ? a.nslot_pre - 1 : 0)];
+  const int gl = a.ng > 0 ? a.ng - 1 : 0;
+  const GeomIn pre[2] = {geom_in(a, w, tid < a.ng ? tid : gl), geom_in(a, w, tid + BS < a.ng ? tid + BS : gl)};
   const float *qw = a.q + (size_t)w * a.nq;
   RowStage<BS, K> rq;
   rq.load(qw, a.nq);
@@ -1604,7 +1639,7 @@ __global__ __launch_bounds__(BS) void collide_kernel(CollideArgs a) {
   __syncthreads();
   const size_t cbase = (size_t)w * a.ncon_max;
   const int found = collide_world<BS, ART>(a, w, sq, lds + pad4(a.nq) / 4, a.cnp + cbase, a.cpos + cbase,
-                                           a.ncon_max, nxt, &pre);
+                                           a.ncon_max, nxt, pre);
   if (tid == 0) {
     const int kept = found < a.ncon_max ? found : a.ncon_max;
     a.ncon[w] = kept;
@@ -1687,17 +1722,49 @@ __device__ inline float inv_inertia_form(float4 I0, float4 I1, V3 x, V3 y) {
   return dot(x, Sy);
 }
 
-// Exact diagonal impedance of one contact between free bodies (Sec. III.B,
-// K h + D = (1/h) (J~_f M^-1 J~_f^T)^-1 per facet, split between K and D in the
-// ratio k_user : d_user / h): A_f = 1 / ((k h + d) g_f) with
-// g_f = sum over the contact's bodies of |u_f|^2 / m + a_f^T Iw^-1 a_f, where the
+// Projections on dof i of a subtree of the facet rows' share on one of its
+// bodies, y_f = (L^-1 J_b^T w_f)_i with w_f = (u_f, a_f) as in diag_impedance,
+// from the body's columns Y = L^-1 J_b^T (column r at Y + r nd; linear 0-2,
+// angular 3-5): u . yl + (r x u + e) . ya = u . (yl + ya x r) + e . ya, with
+// e the torsional or rolling term of the angular direction.
+template <int NF>
+__device__ inline void art_facet_rows(const float *Y, int nd, int i, V3 r, V3 n, V3 t1, V3 t2, float mut,
+                                      float mutor, float murol, float *y) {
+  const V3 yl = v3(Y[i], Y[nd + i], Y[2 * nd + i]), ya = v3(Y[3 * nd + i], Y[4 * nd + i], Y[5 * nd + i]);
+  const V3 ye = yl + cross(ya, r);
+  const float pn = dot(n, ye);
+  if constexpr (NF == 1) {
+    y[0] = pn;
+  } else {
+    const float p1 = dot(t1, ye), p2 = dot(t2, ye);
+    y[0] = pn - mut * p1; y[1] = pn - mut * p2; y[2] = pn + mut * p1; y[3] = pn + mut * p2;
+    if constexpr (NF >= 6) {
+      const float qn = dot(n, ya);
+      y[4] = pn - mutor * qn; y[5] = pn + mutor * qn;
+    }
+    if constexpr (NF == 10) {
+      const float q1 = dot(t1, ya), q2 = dot(t2, ya);
+      y[6] = pn - murol * q1; y[7] = pn - murol * q2; y[8] = pn + murol * q1; y[9] = pn + murol * q2;
+    }
+  }
+}
+
+// Exact diagonal impedance of one contact (Sec. III.B, K h + D =
+// (1/h) (J~_f M^-1 J~_f^T)^-1 per facet, split between K and D in the ratio
+// k_user : d_user / h): A_f = 1 / ((k h + d) g_f), g_f = J~_f M^-1 J~_f^T.  The
 // facet row acts on a body as linear direction u_f and angular direction a_f:
 // tangential d: u = n - mu_t d, a = r x u; torsional sigma: u = n,
-// a = r x n - mu_tor sigma n; rolling d: u = n, a = r x n - mu_rol d.
-template <int NF>
+// a = r x n - mu_tor sigma n; rolling d: u = n, a = r x n - mu_rol d.  M is
+// block diagonal over free bodies and subtrees, so g_f sums one term per
+// block the row touches: a free body's |u_f|^2 / m + a_f^T Iw^-1 a_f; a
+// subtree's |L^-1 J~_f^T|^2 over its dofs (ART: bodies of subtrees carry
+// bI1.w = 1 as an integer and bI0 = (offset of their L^-1 J^T columns in
+// `art`, nd, subtree root) as integers), with the row J_b^T w_b - J_a^T w_a
+// when both bodies are in one subtree.
+template <int NF, bool ART = false>
 __device__ inline void diag_impedance(V3 n, V3 t1, V3 t2, int ba, int bb, V3 ra, V3 rb, const float4 *bC,
                                       const float4 *bI0, const float4 *bI1, float mut, float mutor, float murol,
-                                      float aa, float *Af) {
+                                      float aa, float *Af, const float *art = nullptr) {
   float g[NF];
 #pragma unroll
   for (int i = 0; i < NF; ++i) g[i] = 0.f;
@@ -1708,6 +1775,30 @@ __device__ inline void diag_impedance(V3 n, V3 t1, V3 t2, int ba, int bb, V3 ra,
     const int b = side ? bb : ba;
     if (b < 0) continue;
     const V3 r = side ? rb : ra;
+    if constexpr (ART) {
+      if (__float_as_int(bI1[b].w) != 0) {
+        const float4 D = bI0[b];
+        const int root = __float_as_int(D.z);
+        auto in_sub = [&](int o) { return o >= 0 && __float_as_int(bI1[o].w) != 0 && __float_as_int(bI0[o].z) == root; };
+        if (side == 1 && in_sub(ba)) continue;  // one row with body a's share, below
+        const bool both = side == 0 && in_sub(bb);
+        const int nd = __float_as_int(D.y);
+        const float *Ya = art + __float_as_int(D.x), *Yb = both ? art + __float_as_int(bI0[bb].x) : Ya;
+        for (int i = 0; i < nd; ++i) {
+          float y[NF];
+          art_facet_rows<NF>(Ya, nd, i, r, n, t1, t2, mut, mutor, murol, y);
+          if (both) {
+            float yb[NF];
+            art_facet_rows<NF>(Yb, nd, i, rb, n, t1, t2, mut, mutor, murol, yb);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) y[f] = yb[f] - y[f];
+          }
+#pragma unroll
+          for (int f = 0; f < NF; ++f) g[f] += y[f] * y[f];
+        }
+        continue;
+      }
+    }
     const float4 I0 = bI0[b], I1 = bI1[b];
     const float im = bC[b].w;
     const V3 rn = cross(r, n);
@@ -2119,9 +2210,12 @@ struct LanePre {
 template <bool ART>
 __device__ inline LanePre lane_prefetch(const ResolveArgs &a, int w) {
   const int tid = threadIdx.x;
+  // every lane loads (indices clamped into the tables; a lane past the dofs,
+  // bodies or subtrees holds another entry's values, which it never uses), so
+  // no wait separates these loads
   LanePre L;
   L.act = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-  if (a.act && tid < a.nv) L.act = a.act[tid];
+  if (a.act) L.act = a.act[tid < a.nv ? tid : a.nv - 1];
   L.fast = 1;
   L.qadr = 7 * tid;
   L.dadr = 6 * tid;
@@ -2129,20 +2223,19 @@ __device__ inline LanePre lane_prefetch(const ResolveArgs &a, int w) {
 #pragma unroll
   for (int i = 0; i < 5; ++i) L.fr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   L.ipos = L.fr[0];
-  if (ART) {
-    if (tid < a.nb) {
-      const BodyC &bc = a.body[tid];
-      L.fast = bc.fast;
-      L.qadr = bc.qadr;
-      L.dadr = bc.dadr;
-      L.ipos = bc.ipos;
-      if (a.frames) {
-        const float4 *f = a.frames + ((size_t)w * a.nb + tid) * 5;
+  if (ART) {  // (at least one body and one subtree)
+    const int b = tid < a.nb ? tid : a.nb - 1;
+    const BodyC &bc = a.body[b];
+    L.fast = bc.fast;
+    L.qadr = bc.qadr;
+    L.dadr = bc.dadr;
+    L.ipos = bc.ipos;
+    if (a.frames) {
+      const float4 *f = a.frames + ((size_t)w * a.nb + b) * 5;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) L.fr[i] = f[i];
-      }
+      for (int i = 0; i < 5; ++i) L.fr[i] = f[i];
     }
-    if (tid < 4 * a.nsub) L.sub = a.sub[tid >> 2];
+    L.sub = a.sub[tid < 4 * a.nsub ? tid >> 2 : a.nsub - 1];
   }
   return L;
 }
@@ -2240,10 +2333,17 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   if (ART)
   for (int t = tid; t < 4 * a.nsub; t += BS) {
     const SubTree S = t == tid ? sub0 : a.sub[t >> 2];
+    float *yd = P.imp_diag ? art + S.yofs : nullptr;
     if (S.small)
-      art_predict_small(S, t & 3, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
+      art_predict_small(S, t & 3, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P, yd);
     else if ((t & 3) == 0)
-      art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P);
+      art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P, yd);
+    if (yd && (t & 3) == 0)  // the subtree's bodies: where their L^-1 J^T columns are
+      for (int k = 0; k < S.nb; ++k) {
+        bI0[S.b0 + k] = make_float4(__int_as_float(S.yofs + 6 * S.nd * k), __int_as_float(S.nd),
+                                    __int_as_float(S.b0), 0.f);
+        bI1[S.b0 + k] = make_float4(0.f, 0.f, 0.f, __int_as_float(1));
+      }
   }
   __syncthreads();
 
@@ -2285,7 +2385,8 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       float Af[NF];
 #pragma unroll
       for (int i = 0; i < NF; ++i) Af[i] = A;
-      if (P.imp_diag) diag_impedance<NF>(n, t1, t2, ba, bb, ra, rb, bC, bI0, bI1, mut, mutor, murol, aa, Af);
+      if (P.imp_diag)
+        diag_impedance<NF, ART>(n, t1, t2, ba, bb, ra, rb, bC, bI0, bI1, mut, mutor, murol, aa, Af, art);
       const float c0 = -P.k_user * phi;
       float lam[NF];
       facet_impulses<CONDIM>(Af, K, aa, c0, lam);
@@ -2391,24 +2492,19 @@ __global__ __launch_bounds__(BS) void resolve_kernel(ResolveArgs a) {
   float *st = sv + pad4(nv);
   float4 *reg = reinterpret_cast<float4 *>(st + pad4(nv));
   const size_t cbase = (size_t)w * a.ncon_max;
-  // issue every independent global load before the first wait
+  // issue every independent global load before the first wait, every lane
+  // all of them (indices clamped into the arrays, which hold at least one
+  // entry; a lane past the records, bodies or geoms never uses what it read)
   const int nc = a.ncon[w];
-  float4 c0n = make_float4(0.f, 0.f, 0.f, 0.f), c0p = c0n;
-  if (tid < a.ncon_max) {  // the first chunk's records (only used below ncon)
-    c0n = a.cnp[cbase + tid];
-    c0p = a.cpos[cbase + tid];
-  }
-  float4 mi0 = make_float4(1.f, 1.f, 1.f, 1.f);
-  if (tid < nb) mi0 = a.bmi[(size_t)w * nb + tid];
+  const int r0 = tid < a.ncon_max ? tid : (a.ncon_max > 0 ? a.ncon_max - 1 : 0);
+  const float4 c0n = a.cnp[cbase + r0], c0p = a.cpos[cbase + r0];  // the first chunk's records
+  const float4 mi0 = a.bmi[(size_t)w * nb + (tid < nb ? tid : (nb > 0 ? nb - 1 : 0))];
   const LanePre pre = lane_prefetch<ART>(a, w);
-  int gb0 = -1;
-  float mu0 = 0.f;
+  const int g0 = tid < ng ? tid : (ng > 0 ? ng - 1 : 0);
+  const int gb0 = a.gbody[g0];
+  const float mu0 = a.gmu[(size_t)w * ng + g0];
   float2 fr0 = make_float2(0.f, 0.f);
-  if (tid < ng) {
-    gb0 = a.gbody[tid];
-    mu0 = a.gmu[(size_t)w * ng + tid];
-    if (CONDIM >= 4) fr0 = a.gfr2[(size_t)w * ng + tid];
-  }
+  if (CONDIM >= 4) fr0 = a.gfr2[(size_t)w * ng + g0];
   const float *qw = a.q + (size_t)w * nq, *vw = a.v + (size_t)w * nv;
   const float *tw = a.tau ? a.tau + (size_t)w * nv : nullptr;
   RowStage<BS, K> rq, rv, rt;
@@ -2488,12 +2584,32 @@ __device__ void resolve_free_world(const ResolveArgs &a, int w, const float *qb,
   float4 *gM = reinterpret_cast<float4 *>(gB + pad4(ng));
   const Params P = a.p;
   const bool own = tid < nb;
-  for (int g = tid; g < ng; g += BS) {
-    gB[g] = a.gbody[g];
-    const float mu_t = a.gmu[(size_t)w * ng + g];
-    float2 fr = make_float2(0.f, 0.f);
-    if (CONDIM >= 4) fr = a.gfr2[(size_t)w * ng + g];
-    gM[g] = make_float4(mu_t, fr.x, fr.y, 0.f);
+  {
+    // geom table: two entries per lane loaded together, unconditionally
+    // (indices clamped into the arrays, which hold at least one entry), then
+    // stored where they exist; any further entries in a loop
+    const int gl = ng > 0 ? ng - 1 : 0, g0 = tid < ng ? tid : gl, g1 = tid + BS < ng ? tid + BS : gl;
+    const int b0 = a.gbody[g0], b1 = a.gbody[g1];
+    const float u0 = a.gmu[(size_t)w * ng + g0], u1 = a.gmu[(size_t)w * ng + g1];
+    float2 f0 = make_float2(0.f, 0.f), f1 = f0;
+    if (CONDIM >= 4) {
+      f0 = a.gfr2[(size_t)w * ng + g0];
+      f1 = a.gfr2[(size_t)w * ng + g1];
+    }
+    if (tid < ng) {
+      gB[tid] = b0;
+      gM[tid] = make_float4(u0, f0.x, f0.y, 0.f);
+    }
+    if (tid + BS < ng) {
+      gB[tid + BS] = b1;
+      gM[tid + BS] = make_float4(u1, f1.x, f1.y, 0.f);
+    }
+    for (int g = tid + 2 * BS; g < ng; g += BS) {
+      gB[g] = a.gbody[g];
+      float2 fr = make_float2(0.f, 0.f);
+      if (CONDIM >= 4) fr = a.gfr2[(size_t)w * ng + g];
+      gM[g] = make_float4(a.gmu[(size_t)w * ng + g], fr.x, fr.y, 0.f);
+    }
   }
   for (int i = tid; i < 8 * nbp; i += BS) fx[i] = i >= 6 * nbp ? FX_EMPTY : 0;
   if (own) free_body_predict(qb, vb, tb, mi, P, bC[tid], bV[tid], bW[tid], bI0[tid], bI1[tid]);
@@ -2502,12 +2618,12 @@ __device__ void resolve_free_world(const ResolveArgs &a, int w, const float *qb,
 
   const float aa = P.k_user * P.h + P.d_user;
   for (int base = 0; base < nc; base += BS) {
-    const int k = base + tid, kn = k + BS;
-    float4 nn = make_float4(0.f, 0.f, 0.f, 0.f), np = nn;
-    if (kn < nc) {  // next chunk, in flight during this one
-      nn = cnp[kn];
-      np = cpos[kn];
-    }
+    const int k = base + tid;
+    // next chunk, in flight during this one: loaded by every lane (a lane
+    // past the count rereads the last record and ignores it), so the wait for
+    // this chunk's records leaves these two loads outstanding
+    const int kn = k + BS < nc ? k + BS : nc - 1;
+    const float4 nn = cnp[kn], np = cpos[kn];
     int kA = nb, kB = nb;  // key nb = no body (static geom or idle lane)
     float4 WA = make_float4(0.f, 0.f, 0.f, 0.f), WB = WA;
     float2 WA2 = make_float2(0.f, 0.f), WB2 = WA2;
@@ -2587,34 +2703,33 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
   extern __shared__ float4 lds[];
   const int w = blockIdx.x, tid = threadIdx.x;
   const int nb = a.nb;
+  if (nb == 0) return;
   const size_t cbase = (size_t)w * a.ncon_max;
-  // every independent global load first: the count, the first chunk of
-  // contact records, the lane's body
-  const int nc = a.ncon[w];
-  float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
-  if (tid < a.ncon_max) {  // records beyond the count are never used
-    cn = a.cnp[cbase + tid];
-    cp = a.cpos[cbase + tid];
-  }
+  // every independent global load first and unconditionally (a lane without
+  // a body rereads the last one, a lane beyond the capacity the last record;
+  // both ignore what they read; the workspace holds at least one record per
+  // world), so that no wait separates them: the lane's body, the count, the
+  // first chunk of contact records
   const bool own = tid < nb;
+  const int b = own ? tid : nb - 1;
   float qb[7], vb[6], tb[6];
-  float4 mi = make_float4(1.f, 1.f, 1.f, 1.f);
-#pragma unroll
-  for (int i = 0; i < 7; ++i) qb[i] = 0.f;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) vb[i] = tb[i] = 0.f;
-  if (own) {
-    const float *qs = a.q + (size_t)w * a.nq + 7 * tid, *vs = a.v + (size_t)w * a.nv + 6 * tid;
+  {
+    const float *qs = a.q + (size_t)w * a.nq + 7 * b, *vs = a.v + (size_t)w * a.nv + 6 * b;
 #pragma unroll
     for (int i = 0; i < 7; ++i) qb[i] = qs[i];
 #pragma unroll
     for (int i = 0; i < 6; ++i) vb[i] = vs[i];
-    if (a.tau) {
-      const float *ts = a.tau + (size_t)w * a.nv + 6 * tid;
+  }
+  const float4 mi = a.bmi[(size_t)w * nb + b];
+  const int nc = a.ncon[w];
+  const int r0 = tid < a.ncon_max ? tid : (a.ncon_max > 0 ? a.ncon_max - 1 : 0);
+  const float4 cn = a.cnp[cbase + r0], cp = a.cpos[cbase + r0];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) tb[i] = ts[i];
-    }
-    mi = a.bmi[(size_t)w * nb + tid];
+  for (int i = 0; i < 6; ++i) tb[i] = 0.f;
+  if (a.tau) {
+    const float *ts = a.tau + (size_t)w * a.nv + 6 * b;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) tb[i] = ts[i];
   }
   float qo[7], vo[6];
   resolve_free_world<CONDIM, BS>(a, w, qb, vb, tb, mi, nc, cn, cp, a.cnp + cbase, a.cpos + cbase, cbase, lds, qo, vo);
@@ -2989,7 +3104,7 @@ size_t rollout_free_lds_bytes(int nb, int ng, int norient, int nsph) {
   return c > r ? c : r;
 }
 
-bool rollout_free_fits(int nq, int nb) { return nb <= 64 && nq <= kCandCap; }
+bool rollout_free_fits(int nq, int nb) { return nb >= 1 && nb <= 64 && nq <= kCandCap; }
 
 // WAVES: resident waves per SIMD the registers are sized for (3: no spills,
 // twelve worlds per CU; 4: sixteen, a few spills).
@@ -3019,31 +3134,27 @@ __global__ __launch_bounds__(64, WAVES) void rollout_free_kernel(RolloutArgs r) 
     if (tid == 0 && r.over_traj) r.over_traj[(size_t)t * nw + wt] = found - nc;
     // the lane's body from trajectory row t (its own writes of the previous
     // step), and the contact records this workgroup wrote (visible after
-    // collide_world's barrier)
-    float4 cn = make_float4(0.f, 0.f, 0.f, 0.f), cp = cn;
-    if (tid < nc) {
-      cn = ca.cnp[cbase + tid];
-      cp = ca.cpos[cbase + tid];
-    }
+    // collide_world's barrier); every lane loads (a lane without a body
+    // rereads the last one, a lane past the count the last record or record
+    // 0 of the world's capacity, and ignores it), so no wait separates them
+    const int r0 = tid < nc ? tid : (nc > 0 ? nc - 1 : 0), bl = own ? tl : nb - 1;
+    const float4 cn = ca.cnp[cbase + r0], cp = ca.cpos[cbase + r0];
     float qb[7], vb[6], tb[6];
-    float4 mi = make_float4(1.f, 1.f, 1.f, 1.f);
-#pragma unroll
-    for (int i = 0; i < 7; ++i) qb[i] = 0.f;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) vb[i] = tb[i] = 0.f;
-    if (own) {
-      const float *qs = r.q_traj + ((size_t)t * nw + wt) * nq + 7 * tid;
-      const float *vs = r.v_traj + ((size_t)t * nw + wt) * nv + 6 * tid;
+    {
+      const float *qs = r.q_traj + ((size_t)t * nw + wt) * nq + 7 * bl;
+      const float *vs = r.v_traj + ((size_t)t * nw + wt) * nv + 6 * bl;
 #pragma unroll
       for (int i = 0; i < 7; ++i) qb[i] = qs[i];
 #pragma unroll
       for (int i = 0; i < 6; ++i) vb[i] = vs[i];
-      if (r.tau_seq) {
-        const float *ts = r.tau_seq + ((size_t)t * nw + wt) * nv + 6 * tid;
+    }
+    const float4 mi = ra.bmi[(size_t)wt * nb + bl];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) tb[i] = ts[i];
-      }
-      mi = ra.bmi[(size_t)wt * nb + tid];
+    for (int i = 0; i < 6; ++i) tb[i] = 0.f;
+    if (r.tau_seq) {
+      const float *ts = r.tau_seq + ((size_t)t * nw + wt) * nv + 6 * bl;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) tb[i] = ts[i];
     }
     float qo[7], vo[6];
     resolve_free_world<CONDIM, BS>(ra, wt, qb, vb, tb, mi, nc, cn, cp, ca.cnp + cbase, ca.cpos + cbase, 0, lds, qo, vo, tl);

@@ -313,6 +313,59 @@ def pendulum(length=0.5, mass=1.0, radius=0.02, gravity=(0, 0, -9.81), h=0.002):
     return b.build(gravity=gravity, h=h, name="pendulum")
 
 
+def hinge_bob_on_plane(length=0.3, mass=0.8, radius=0.03, inertia=(2e-3, 3e-3, 1e-3), angle=0.4,
+                       depth=0.001, mu=(0.6, 0.004, 0.0004), condim=3, k_user=0.1, d_user=0.001,
+                       gravity=(0, 0, -9.81), h=0.002, ncon_max=8):
+    """A hinge about world y at (0, 0, z_h) holding a sphere bob at distance
+    `length` (COM and sphere centre at angle `angle` from straight down), z_h
+    chosen so that the sphere reaches `depth` into the ground plane."""
+    b = _Builder(1)
+    b.geom(PLANE, -1)
+    zh = length * math.cos(angle) + radius - depth
+    bi = b.body(JNT_HINGE, -1, pos=(0, 0, zh), axis=(0, 1, 0), ipos=(0, 0, -length), mass=mass,
+                inertia=inertia)
+    b.geom(SPHERE, bi, size=(radius, 0, 0), pos=(0, 0, -length), friction=mu)
+    s = b.build(condim=condim, k_user=k_user, d_user=d_user, h=h, gravity=gravity, ncon_max=ncon_max,
+                name="hinge_bob_on_plane")
+    # a positive rotation about +y takes -z toward -x
+    s["q0"][0, 0] = angle
+    return s
+
+
+def sibling_sliders(nworld=1, seed=0, radius=0.03, overlap=0.002, mu=(0.6, 0.004, 0.0004), condim=3,
+                    k_user=0.1, d_user=0.001, gravity=(0, 0, 0), carrier="slide", axis2=(0, 1, 0),
+                    ncon_max=8):
+    """A carrier body (a slide along x, or a free joint) with two children
+    that slide along y (the second along `axis2`), each carrying a sphere; the
+    spheres overlap along x by `overlap`, so their contact joins two bodies of
+    one subtree (siblings, not parent and child).  World 0 has masses 0.7
+    (carrier), 0.3 and 0.5 and the velocities below; further worlds draw
+    masses and velocities (seeded)."""
+    rng = np.random.default_rng([seed, 13])
+    m = np.tile([0.7, 0.3, 0.5], (nworld, 1))
+    m[1:] = rng.uniform(0.2, 1.0, (nworld - 1, 3))
+    b = _Builder(nworld)
+    jc = JNT_SLIDE if carrier == "slide" else JNT_FREE
+    c = b.body(jc, -1, pos=(0, 0, 0.2), axis=(1, 0, 0), mass=m[:, 0],
+               inertia=np.stack([m[:, 0] * 4e-3, m[:, 0] * 5e-3, m[:, 0] * 6e-3], 1))
+    for k, x, ax in ((1, 0.0, (0, 1, 0)), (2, 2 * radius - overlap, axis2)):
+        bk = b.body(JNT_SLIDE, c, pos=(x, 0, 0), axis=ax, mass=m[:, k],
+                    inertia=np.repeat((0.4 * m[:, k] * radius * radius)[:, None], 3, 1))
+        b.geom(SPHERE, bk, size=(radius, 0, 0), friction=mu)
+    s = b.build(condim=condim, k_user=k_user, d_user=d_user, gravity=gravity, ncon_max=ncon_max,
+                name="sibling_sliders")
+    da = dadr(s)
+    for w in range(nworld):
+        v = s["v0"][w]
+        if w == 0:
+            v[da[0]:da[1]] = (0.05, 0.0, 0.0, 0.3, -0.2, 0.7)[:da[1] - da[0]]
+            v[da[1]], v[da[2]] = 0.04, -0.03
+        else:
+            v[da[0]:da[1]] = rng.normal(0, 0.1, da[1] - da[0])
+            v[da[1]], v[da[2]] = rng.normal(0, 0.05, 2)
+    return s
+
+
 def double_pendulum(l1=0.6, lc1=0.3, lc2=0.25, m1=1.3, m2=0.7, i1=(0.02, 0.03, 0.01),
                     i2=(0.015, 0.01, 0.02), gravity=(0, 0, -9.81)):
     """Planar two-link arm in the x-z plane, hinges about y; angles measured from +x."""

@@ -611,13 +611,66 @@ def test_diagonal_impedance_parity(torch_cuda, condim):
         assert stats["contacts"] > 100
 
 
+def _diag_articulated_case(case):
+    """(scene, steps of the heuristic trajectory, every, tau schedule or None)."""
+    kind, condim = case[:-1], int(case[-1])
+    if kind == "mix":
+        return scenes.articulated_mix(nworld=4, seed=40 + condim, condim=condim), 240, 8, None
+    if kind == "hand":
+        from test_gpu_hand import _target_schedule
+        s = scenes.hand_cube(nworld=4, seed=40 + condim, condim=condim)
+        return s, 240, 8, _target_schedule(s, 240, 40, 0.35, seed=condim)
+    if kind in ("sib", "sls"):  # same-subtree contacts on a free carrier (general path) or a slide (small)
+        return scenes.sibling_sliders(nworld=4, seed=condim, carrier="free" if kind == "sib" else "slide",
+                                      axis2=(0.6, 0.8, 0.0), condim=condim), 40, 4, None
+    return scenes.hinge_bob_on_plane(condim=condim), 40, 4, None
+
+
+@pytest.mark.parametrize("case", ["mix1", "mix3", "mix4", "mix6", "hand3", "hand6", "sib3", "sib6", "sls3", "sls6",
+                                  "bob3"])
+def test_diagonal_impedance_articulated_parity(torch_cuda, case):
+    """The exact diagonal impedance on articulated subtrees (each body's
+    L^-1 J^T from the subtree's Cholesky factor, one row over the subtree's
+    dofs when both bodies of a contact are in it) against the oracle's dense
+    J~ M^-1 J~^T.  Resolving each facet as if alone over-corrects coupled
+    facets, and an articulated trajectory under the diagonal form leaves the
+    bounded regime within tens of steps, so every GPU step starts from a state
+    of the oracle's heuristic trajectory (contacts present) and is compared
+    with one oracle step of the diagonal form from the same state."""
+    from paper_2603_12185_amd import cfsim
+    s, T, every, taus = _diag_articulated_case(case)
+    sd = dict(s)
+    sd["impedance"] = 1
+    model = cfsim.Model(sd)
+    oh, od = Oracle(s), Oracle(sd)
+    q, v = s["q0"].astype(np.float64), s["v0"].astype(np.float64)
+    stats = None
+    print(f"case: diagonal impedance articulated {case}", flush=True)
+    for t in range(T):
+        tau = None if taus is None else taus[t]
+        if t % every == 0:
+            q32, v32 = q.astype(np.float32), v.astype(np.float32)
+            con = model.alloc_contacts()
+            q1, v1 = model.step(tdev(q32), tdev(v32), tau=None if tau is None else tdev(tau), contacts=con)
+            stats = compare_step(sd, od, q32, v32, tau, q1.cpu().numpy(), v1.cpu().numpy(), to_np(con),
+                                 stats=stats)
+        q, v, _ = oh.step(q, v, tau=None if tau is None else tau.astype(np.float64), outputs=False)
+    print("diagonal impedance articulated", case, stats)
+    assert stats["contacts"] >= (8 if case[:-1] in ("sib", "sls", "bob") else 40)
+
+
 def test_diagonal_impedance_rules(torch_cuda):
-    """The diagonal impedance is a free-body option: an articulated model refuses
-    it, an invalid mode is rejected; the adjoint takes a diagonal model."""
+    """An articulated model takes the diagonal impedance, an invalid mode is
+    rejected; the adjoint takes a diagonal model of free bodies and refuses an
+    articulated one."""
     from paper_2603_12185_amd import cfsim
     m = cfsim.Model(scenes.pendulum())
+    m.set_impedance(1)
+    q, v = tdev(scenes.pendulum()["q0"]), tdev(scenes.pendulum()["v0"])
     with pytest.raises(cfsim.CFError, match="UNSUPPORTED"):
-        m.set_impedance(1)
+        m.step_backward(q, v, None, q, v)
+    m.set_impedance(0)
+    m.step_backward(q, v, None, q, v)
     with pytest.raises(cfsim.CFError, match="INVALID"):
         m.set_impedance(7)
     s = scenes.mixed_shapes(nworld=1, seed=2)

@@ -799,6 +799,78 @@ def test_exact_impedance_stick_decay_point_mass():
             np.testing.assert_allclose(v1[0, 0:2], fac * v[0, 0:2], rtol=1e-11, atol=1e-16)
 
 
+def test_exact_impedance_hinge_bob_closed_form():
+    """One hinge (axis a through o) holding a sphere bob on the ground: the
+    generalized mass is I_o = I_yy + m L^2 (parallel axes) and a facet row
+    with linear direction u at the contact point p acts on the hinge rate as
+    u . (a x (p - o)), so J~ M^-1 J~^T = (u . (a x (p - o)))^2 / I_o for the
+    normal row (condim 1) and for the four rows n -/+ mu d (condim 3); the
+    gains and impulses follow Sec. III.B with s read from the smooth rate."""
+    for condim in (1, 3):
+        s = scenes.hinge_bob_on_plane(condim=condim)
+        s["impedance"] = 1
+        o = Oracle(s)
+        _, _, out = o.step(s["q0"].astype(np.float64), s["v0"].astype(np.float64))
+        assert out["ncon"][0] == 1
+        L, m = -float(s["body_ipos"][0, 2]), float(s["body_mass"][0, 0])  # the model's float32 values
+        i_o = float(s["body_inertia"][0, 0, 1]) + m * L * L
+        a = np.array([0.0, 1.0, 0.0])
+        org = s["body_pos"][0].astype(np.float64)
+        p = out["pos"][0, 0]
+        n, t1, t2 = out["frame"][0, 0, 0:3], out["frame"][0, 0, 3:6], out["frame"][0, 0, 6:9]
+        np.testing.assert_allclose(n, (0, 0, 1), atol=1e-12)
+        arm = np.cross(a, p - org)
+        assert abs(arm @ n) > 0.05  # the bob sits off the vertical: the normal row is not degenerate
+        mu = float(s["geom_friction"][0, 1, 0])
+        rows = [n] if condim == 1 else [n - mu * d for d in (t1, t2, -t1, -t2)]
+        aa = s["k_user"] * s["h"] + s["d_user"]
+        phi = float(out["dist"][0, 0])
+        th_s = float(out["v_smooth"][0, 0])
+        for f, u in enumerate(rows):
+            jrow = float(u @ arm)
+            gain = 1.0 / (aa * jrow * jrow / i_o)
+            np.testing.assert_allclose(out["facet_gain"][0, 0, f], gain, rtol=1e-10)
+            lam = gain * max(-aa * jrow * th_s - s["k_user"] * phi, 0.0)
+            np.testing.assert_allclose(out["impulse"][0, 0, f], lam, rtol=1e-10, atol=1e-18)
+
+
+def test_exact_impedance_siblings_of_one_subtree():
+    """Two sibling slide bodies (along y) on a carrier sliding along x, their
+    spheres touching along x: the carrier's motion moves both alike, so the
+    contact's rows see only the siblings' own rates and J~ M^-1 J~^T =
+    mu^2 (d . y)^2 (1/m_1 + 1/m_2) for the row n - mu d (with M = diag(m_0 +
+    m_1 + m_2, m_1, m_2)), not the sum of the two bodies' separate forms,
+    which would add 2 / (m_0 + m_1 + m_2) from the shared carrier dof.  A row
+    with d . y = 0 moves nothing and gets no gain."""
+    s = scenes.sibling_sliders(condim=3)
+    s["impedance"] = 1
+    o = Oracle(s)
+    _, _, out = o.step(s["q0"].astype(np.float64), s["v0"].astype(np.float64))
+    assert out["ncon"][0] == 1
+    m1, m2 = (float(x) for x in s["body_mass"][0, 1:3])
+    ga, gb = out["geom"][0, 0]
+    n, t1, t2 = out["frame"][0, 0, 0:3], out["frame"][0, 0, 3:6], out["frame"][0, 0, 6:9]
+    assert abs(abs(n[0]) - 1.0) < 1e-12
+    vs = out["v_smooth"][0]
+    rate = {0: vs[1], 1: vs[2]}  # each sphere's body: its y slide rate
+    vrel_y = rate[gb] - rate[ga]
+    mu = float(s["geom_friction"][0, 0, 0])
+    aa = s["k_user"] * s["h"] + s["d_user"]
+    phi = float(out["dist"][0, 0])
+    seen = 0
+    for f, d in enumerate((t1, t2, -t1, -t2)):
+        g = mu * mu * d[1] * d[1] * (1 / m1 + 1 / m2)
+        if g < 1e-20:
+            assert out["facet_gain"][0, 0, f] == 0 and out["impulse"][0, 0, f] == 0
+            continue
+        seen += 1
+        np.testing.assert_allclose(out["facet_gain"][0, 0, f], 1.0 / (aa * g), rtol=1e-10)
+        sf = -mu * d[1] * vrel_y
+        lam = max(-aa * sf - s["k_user"] * phi, 0.0) / (aa * g)
+        np.testing.assert_allclose(out["impulse"][0, 0, f], lam, rtol=1e-10, atol=1e-18)
+    assert seen == 2
+
+
 def test_exact_impedance_sphere_tangential_row():
     """Free solid sphere on a plane (I = 0.4 m R^2): a tangential facet row
     (n - mu d.t at the contact point, the middle of the overlap, lever arm
