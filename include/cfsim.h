@@ -271,7 +271,8 @@ cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t
 /* Autotuner: times every workgroup size of the two step kernels and of the
  * rollout kernel over `steps` steps from the state (q, v) (device, not
  * modified), on this model's worlds, and keeps the fastest of each; cf_rollout
- * then uses the persistent kernel only where it beat T cf_step calls.  It
+ * then uses the persistent kernel only where it beat T cf_step calls by more
+ * than 3 % (closer timings are within run-to-run noise).  It
  * allocates temporary device buffers and synchronises the stream.  Optional
  * outputs: the best microseconds per step of cf_step and of cf_rollout. */
 cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const float *v, int32_t steps,
