@@ -182,9 +182,16 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
  * actuated dof's gtau entry is the adjoint of its target), and so is the
  * diagonal impedance on models of free bodies (its per-facet gains
  * differentiated through the lever arms, the contact frame and the bodies'
- * world inverse inertia, i.e. their orientation); the diagonal impedance on a
- * model with articulated subtrees and the learned impedance return
- * CF_E_UNSUPPORTED. */
+ * world inverse inertia, i.e. their orientation), and so are learned gains
+ * (cf_model_set_learned_impedance): the gains are recomputed from the float32
+ * network and differentiated through its features (gap, normal and
+ * tangential relative velocity, effective mass) and the heuristic gain they
+ * scale, each contact's keep-or-fall-back decision and each clamped output
+ * held as the step took them.  (The step evaluates the network with bf16
+ * operands, whose outputs are piecewise constant in the features; the
+ * adjoint is that of the float32 network, the function the bf16 evaluation
+ * rounds.)  The diagonal impedance on a model with articulated subtrees
+ * returns CF_E_UNSUPPORTED. */
 cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                            const float *gq_out, const float *gv_out, float *gq, float *gv, float *gtau);
 
@@ -252,7 +259,7 @@ cf_status cf_model_set_actuators(cf_model *m, const float *kp, const float *kd);
  * resolution then runs at most 128 threads per world, after a one-workgroup
  * kernel that writes the network's bf16 LDS image from params (a device buffer
  * of the model, allocated by the first call with params); cf_rollout uses step
- * launches; cf_step_backward does not cover it. */
+ * launches; cf_step_backward differentiates the float32 network (see there). */
 cf_status cf_model_set_learned_impedance(cf_model *m, const float *params, float margin);
 
 /* Workgroup size (64, 128 or 256 threads, one world per workgroup) of the

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "cf_mlp.h"
+
 namespace cf {
 namespace adj {
 
@@ -277,6 +279,10 @@ struct ContactIn {
   // (xx, yy, zz, xy, xz, yz); unused with the heuristic
   bool diag;
   T ima, imb, Sa[6], Sb[6];
+  // learned gains (free bodies): the network's float32 parameters (cf_mlp.h
+  // layout) or null, and the fallback margin (m)
+  const float *net;
+  T margin;
 };
 
 template <class T>
@@ -389,8 +395,135 @@ CF_HD void diag_side_vjp(Vec<T> r, Vec<T> n, Vec<T> t1, Vec<T> t2, T mut, T muto
   }
 }
 
-// Facet impulses and the wrench on body b (f, tb) and on body a (-f, ta).
+// ------------------------------------------------------------------ learned gains
+// The learned gains of Sec. III.B (K and D scaled per facet by a network),
+// evaluated in T from the float32 parameters: features (phi, v_n, u_1, u_2,
+// 1/tr_s, mu_t, h) normalised, two SiLU layers of 64, one output y_f per
+// facet; gain G_f = A exp(clamp(y_f, -ln 256, ln 256)) with A the heuristic
+// gain; kept unless the fallback rule rejects the learned impulses (the same
+// rule as the forward step: the contact alone along its normal, inverse mass
+// tr_s / 3, must not predict more penetration or more normal kinetic energy
+// than the heuristic impulses beyond the margin).  The derivative is that of
+// this float network on the branch the step takes (kept or not, clamped or
+// not); the forward step's bf16 evaluation of it is piecewise constant in its
+// inputs and has no useful derivative of its own.
+template <class T> CF_HD T silu_t(T z) { return z / (T(1) + exp(-z)); }
+template <class T> CF_HD T dsilu_t(T z) {
+  const T s = T(1) / (T(1) + exp(-z));
+  return s * (T(1) + z * (T(1) - s));
+}
+
 template <int NF, class T>
+struct LearnedEval {
+  T fe[mlp::NIN], z1[mlp::NH], z2[mlp::NH], y[NF], G[NF];
+  bool keep;
+};
+
+template <int NF, class T>
+CF_HD void net_forward(const float *p, LearnedEval<NF, T> &L) {
+  using namespace mlp;
+  T x[NIN];
+  for (int k = 0; k < NIN; ++k) x[k] = (L.fe[k] - T(p[OFF_MEAN + k])) / T(p[OFF_STD + k]);
+  for (int j = 0; j < NH; ++j) {
+    T s = T(p[OFF_B1 + j]);
+    for (int k = 0; k < NIN; ++k) s += x[k] * T(p[OFF_W1 + k * NH + j]);
+    L.z1[j] = s;
+  }
+  T a1[NH];
+  for (int k = 0; k < NH; ++k) a1[k] = silu_t(L.z1[k]);
+  for (int j = 0; j < NH; ++j) {
+    T s = T(p[OFF_B2 + j]);
+    for (int k = 0; k < NH; ++k) s += a1[k] * T(p[OFF_W2 + k * NH + j]);
+    L.z2[j] = s;
+  }
+  for (int f = 0; f < NF; ++f) L.y[f] = T(p[OFF_B3 + f]);
+  for (int j = 0; j < NH; ++j) {
+    const T a = silu_t(L.z2[j]);
+    for (int f = 0; f < NF; ++f) L.y[f] += a * T(p[OFF_W3 + j * NOUT + f]);
+  }
+}
+
+// Adjoints of the features from the adjoints yb of the outputs.
+template <int NF, class T>
+CF_HD void net_vjp(const float *p, const LearnedEval<NF, T> &L, const T *yb, T *feb) {
+  using namespace mlp;
+  T z2b[NH], z1b[NH];
+  for (int j = 0; j < NH; ++j) {
+    T s = T(0);
+    for (int f = 0; f < NF; ++f) s += yb[f] * T(p[OFF_W3 + j * NOUT + f]);
+    z2b[j] = s * dsilu_t(L.z2[j]);
+  }
+  for (int k = 0; k < NH; ++k) {
+    T s = T(0);
+    for (int j = 0; j < NH; ++j) s += z2b[j] * T(p[OFF_W2 + k * NH + j]);
+    z1b[k] = s * dsilu_t(L.z1[k]);
+  }
+  for (int k = 0; k < NIN; ++k) {
+    T s = T(0);
+    for (int j = 0; j < NH; ++j) s += z1b[j] * T(p[OFF_W1 + k * NH + j]);
+    feb[k] = s / T(p[OFF_STD + k]);
+  }
+}
+
+template <int NF, class T>
+CF_HD bool learned_keep(const T *lh, const T *ll, T vn, T phi, T trs, T h, T margin) {
+  if (!(trs > T(0))) return false;
+  const T winv = trs / T(3);
+  T Sh = T(0), Sl = T(0);
+  for (int i = 0; i < NF; ++i) {
+    Sh += lh[i];
+    Sl += ll[i];
+  }
+  const T vh = vn + winv * Sh, vl = vn + winv * Sl;
+  const T ph = fmax(-(phi + h * vh), T(0)), pl = fmax(-(phi + h * vl), T(0));
+  const T eh = T(0.5) * vh * vh / winv, el = T(0.5) * vl * vl / winv;
+  const T em = T(0.5) * (margin / h) * (margin / h) / winv;
+  return pl <= ph + margin && el <= eh + em && isfinite(vl);
+}
+
+// Learned gains of one contact from its heuristic gain A0, its normal and
+// tangential relative velocities and its facet arguments z_f = -aa s_f + c0.
+template <int NF, class T>
+CF_HD void learned_eval(const ContactIn<T> &C, T A0, T vn, T u1, T u2, const T *z, LearnedEval<NF, T> &L) {
+  L.fe[0] = C.phi; L.fe[1] = vn; L.fe[2] = u1; L.fe[3] = u2;
+  L.fe[4] = C.trs > T(0) ? T(1) / C.trs : T(0);
+  L.fe[5] = C.mut; L.fe[6] = C.h;
+  for (int k = mlp::NFEAT; k < mlp::NIN; ++k) L.fe[k] = T(0);
+  net_forward<NF>(C.net, L);
+  T lh[NF], ll[NF];
+  const T clip = T(mlp::CLIP);
+  for (int f = 0; f < NF; ++f) {
+    L.G[f] = A0 * exp(fmin(fmax(L.y[f], -clip), clip));
+    lh[f] = A0 * fmax(z[f], T(0));
+    ll[f] = L.G[f] * fmax(z[f], T(0));
+  }
+  L.keep = learned_keep<NF>(lh, ll, vn, C.phi, C.trs, C.h, C.margin);
+}
+
+// Facet velocity terms s_f (the bracket of -aa s_f in Eq. cf_wrench) in facet order.
+template <int NF, class T>
+CF_HD void facet_s(const ContactIn<T> &C, Vec<T> n, Vec<T> t1, Vec<T> t2, Vec<T> vrel, Vec<T> wrel, T *s) {
+  const T vn = dot(n, vrel);
+  if constexpr (NF == 1) {
+    s[0] = vn;
+  } else {
+    const T u1 = dot(t1, vrel), u2 = dot(t2, vrel);
+    s[0] = vn - C.mut * u1; s[1] = vn - C.mut * u2; s[2] = vn + C.mut * u1; s[3] = vn + C.mut * u2;
+    if constexpr (NF >= 6) {
+      const T wt = dot(n, wrel);
+      s[4] = vn - C.mutor * wt; s[5] = vn + C.mutor * wt;
+    }
+    if constexpr (NF == 10) {
+      const T o1 = dot(t1, wrel), o2 = dot(t2, wrel);
+      s[6] = vn - C.murol * o1; s[7] = vn - C.murol * o2; s[8] = vn + C.murol * o1; s[9] = vn + C.murol * o2;
+    }
+  }
+}
+
+// Facet impulses and the wrench on body b (f, tb) and on body a (-f, ta).
+// NET: whether the learned gains can occur (C.net); a caller without them
+// leaves the network's code out.
+template <int NF, class T, bool NET = true>
 CF_HD void contact_forward(const ContactIn<T> &C, const Impedance<T> &P, T *lam, Vec<T> &f, Vec<T> &ta,
                            Vec<T> &tb) {
   Vec<T> u;
@@ -409,6 +542,15 @@ CF_HD void contact_forward(const ContactIn<T> &C, const Impedance<T> &P, T *lam,
   else for (int i = 0; i < NF; ++i) Af[i] = A0;
   const T aa = C.k * C.h + C.d, c0 = -C.k * C.phi;
   const T vn = dot(C.n, vrel);
+  if (NET && C.net && !C.diag) {
+    T s[NF], z[NF];
+    facet_s<NF>(C, C.n, t1, t2, vrel, wrel, s);
+    for (int i = 0; i < NF; ++i) z[i] = -aa * s[i] + c0;
+    LearnedEval<NF, T> L;
+    learned_eval<NF>(C, A0, vn, dot(t1, vrel), dot(t2, vrel), z, L);
+    if (L.keep)
+      for (int i = 0; i < NF; ++i) Af[i] = L.G[i];
+  }
   Vec<T> tc = vec(T(0), T(0), T(0));
   if constexpr (NF == 1) {
     lam[0] = Af[0] * fmax(-aa * vn + c0, T(0));
@@ -445,8 +587,8 @@ CF_HD void contact_forward(const ContactIn<T> &C, const Impedance<T> &P, T *lam,
 
 // Given the adjoints of the wrenches the contact adds to body a (Fa, Ta) and
 // body b (Fb, Tb): adjoints of n, phi, p and of both bodies' COM and smooth
-// velocities.
-template <int NF, class T>
+// velocities.  NET as for contact_forward.
+template <int NF, class T, bool NET = true>
 CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b, Vec<T> Ta_b, Vec<T> Fb_b,
                        Vec<T> Tb_b, ContactBar<T> &o) {
   const Vec<T> Z = vec(T(0), T(0), T(0));
@@ -469,6 +611,18 @@ CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b
   }
   const T aa = C.k * C.h + C.d, c0 = -C.k * C.phi;
   const T vn = dot(n, vrel);
+  const bool learned = NET && C.net && !C.diag;
+  LearnedEval<NF, T> L;
+  L.keep = false;
+  if (learned) {
+    T s0[NF], z0[NF];
+    facet_s<NF>(C, n, t1, t2, vrel, wrel, s0);
+    for (int i = 0; i < NF; ++i) z0[i] = -aa * s0[i] + c0;
+    learned_eval<NF>(C, Af[0], vn, dot(t1, vrel), dot(t2, vrel), z0, L);
+  }
+  const T A0 = Af[0];
+  if (L.keep)
+    for (int i = 0; i < NF; ++i) Af[i] = L.G[i];
   T s[NF], z[NF], lam[NF];
   // facet velocity term s_f (the bracket of -aa * s_f) in facet order
   if constexpr (NF == 1) {
@@ -543,6 +697,7 @@ CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b
     c0b += zb;
   }
   T phib = -C.k * c0b;
+  T fvn = T(0), fu1 = T(0), fu2 = T(0);  // adjoints of the learned gains' features v_n, u_1, u_2
   o.trs = T(0);
   o.psa = o.psb = Z;
   Vec<T> rab_d = Z, rbb_d = Z;
@@ -552,15 +707,31 @@ CF_HD void contact_vjp(const ContactIn<T> &C, const Impedance<T> &P, Vec<T> Fa_b
     for (int i = 0; i < NF; ++i) gb[i] = -Afb[i] * aa * Af[i] * Af[i];
     if (C.has_a) diag_side_vjp<NF>(ra, n, t1, t2, C.mut, C.mutor, C.murol, C.Sa, gb, rab_d, nb, t1b, t2b, o.psa);
     if (C.has_b) diag_side_vjp<NF>(rb, n, t1, t2, C.mut, C.mutor, C.murol, C.Sb, gb, rbb_d, nb, t1b, t2b, o.psb);
+  } else if (L.keep) {
+    // G_f = A exp(clamp(y_f)), A = rho(phi) / trs, y = net(phi, v_n, u_1, u_2, 1/trs, mu_t, h)
+    T A0b = T(0), yb[NF], feb[mlp::NIN];
+    const T clip = T(mlp::CLIP);
+    for (int i = 0; i < NF; ++i) {
+      A0b += Afb[i] * (L.G[i] / A0);
+      yb[i] = fabs(L.y[i]) < clip ? Afb[i] * L.G[i] : T(0);
+    }
+    net_vjp<NF>(C.net, L, yb, feb);
+    phib += A0b * drho / C.trs + feb[0];
+    o.trs = -A0b * A0 / C.trs - feb[4] / (C.trs * C.trs);
+    fvn = feb[1];
+    fu1 = feb[2];
+    fu2 = feb[3];
   } else if (C.trs > T(0)) {  // A = rho(phi) / trs
     phib += Ab * drho / C.trs;
     o.trs = -Ab * Af[0] / C.trs;
   }
-  // s_f in terms of vn, u1, u2, wt, o1, o2
-  T vnb = T(0);
+  // s_f in terms of vn, u1, u2, wt, o1, o2 (and the learned gains' features)
+  T vnb = fvn;
   for (int i = 0; i < NF; ++i) vnb += sb[i];
-  Vec<T> vrelb = vnb * n, wrelb = Z;
+  Vec<T> vrelb = vnb * n + fu1 * t1 + fu2 * t2, wrelb = Z;
   nb = nb + vnb * vrel;
+  t1b = t1b + fu1 * vrel;
+  t2b = t2b + fu2 * vrel;
   if constexpr (NF > 1) {
     const T u1b = -C.mut * (sb[0] - sb[2]), u2b = -C.mut * (sb[1] - sb[3]);
     t1b = t1b + u1b * vrel;

@@ -671,7 +671,6 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
       overlap(gtau, sv, q, sq) || overlap(gtau, sv, v, sv) || overlap(gtau, sv, tau, sv) ||
       overlap(gtau, sv, gq_out, sq) || overlap(gtau, sv, gv_out, sv))
     return set_err(CF_E_INVALID_ARG, "gq/gv may alias gq_out/gv_out only exactly; no other overlap");
-  if (m->mlp) return set_err(CF_E_UNSUPPORTED, "cf_step_backward does not cover the learned impedance");
   if (m->p.imp_diag && m->nsub > 0)
     return set_err(CF_E_UNSUPPORTED, "cf_step_backward covers the diagonal impedance on models of free bodies only");
   if (!m->block_backward) return set_err(CF_E_UNSUPPORTED, "world too large for the adjoint's LDS");
@@ -682,6 +681,7 @@ cf_status cf_step_backward(cf_model *m, void *stream, const float *q, const floa
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("collide launch: ") + hipGetErrorString(e));
   cf::BackwardArgs b{};
   b.s = resolve_args(m);
+  b.s.mlp = m->mlp;  // learned gains: the adjoint recomputes them from the float32 parameters
   b.s.q = q; b.s.v = v; b.s.tau = tau;
   b.gpos = m->d_gpos; b.gpos_ws = m->gpos_ws;
   b.gquat = m->d_gquat; b.gquat_ws = m->gquat_ws;

@@ -2246,8 +2246,11 @@ __device__ inline LanePre lane_prefetch(const ResolveArgs &a, int w) {
 // (global or LDS), the first chunk already loaded by the caller into c0n/c0p
 // (lane tid's record), and mi0 is body tid's mass/inertia.  `reg`: LDS scratch of
 // resolve_region_bytes().  `xbase`: row of the world in the export arrays.
+// NETREF (the adjoint's recomputation of a step with learned gains): the
+// gains come from the float32 network of cf_adjoint.h, the function the
+// adjoint differentiates, in place of the bf16 matrix evaluation.
 // Ends with a workgroup barrier.
-template <int CONDIM, int BS, bool ART, bool LEARN = false>
+template <int CONDIM, int BS, bool ART, bool LEARN = false, bool NETREF = false>
 __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv, float *st,
                               const float4 *inn, const float4 *inp, int nc, float4 c0n, float4 c0p,
                               float4 mi0, float4 *reg, size_t xbase, bool geoms_ready = false,
@@ -2390,6 +2393,25 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
       const float c0 = -P.k_user * phi;
       float lam[NF];
       facet_impulses<CONDIM>(Af, K, aa, c0, lam);
+      if constexpr (NETREF) {
+        if (a.mlp) {
+          // positive parts of the facet arguments (unit gains), then the
+          // network's gains and the fallback rule on them
+          float one[NF], pz[NF];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) one[i] = 1.f;
+          facet_impulses<CONDIM>(one, K, aa, c0, pz);
+          adj::ContactIn<float> C{};
+          C.phi = phi; C.trs = trs; C.mut = mut; C.h = P.h;
+          C.net = a.mlp; C.margin = P.mlp_margin;
+          adj::LearnedEval<NF, float> Le;
+          adj::learned_eval<NF>(C, A, dot(n, K.vrel), dot(t1, K.vrel), dot(t2, K.vrel), pz, Le);
+          if (Le.keep) {
+#pragma unroll
+            for (int i = 0; i < NF; ++i) lam[i] = Le.G[i] * pz[i];
+          }
+        }
+      }
       if constexpr (LEARN) {
         // learned gains, kept unless they predict more penetration or more
         // kinetic energy along the normal than the heuristic's, beyond the margin
@@ -3550,7 +3572,9 @@ __device__ void art_rev_predict(const SubTree S, const BodyC *B, const float4 *b
 // integration and correction (per body), the contacts' impulses, wrenches and
 // geometry (lane per contact, per-body segmented sums) and the smooth
 // prediction (per body).  Contacts come from the collision kernel's workspace.
-template <int CONDIM, int BS, bool ART>
+// NET: learned gains (models of free bodies), recomputed and differentiated
+// through the float32 network.
+template <int CONDIM, int BS, bool ART, bool NET>
 __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   using adj::Vec;
   using adj::vec;
@@ -3589,7 +3613,8 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   } else {
     for (int i = tid; i < nv; i += BS) st[i] = 0.f;
   }
-  resolve_world<CONDIM, BS, ART>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0, reg, cbase);
+  resolve_world<CONDIM, BS, ART, false, NET>(a, w, sq, sv, st, a.cnp + cbase, a.cpos + cbase, nc, c0n, c0p, mi0,
+                                             reg, cbase);
   const ResolveRegion RR = resolve_region(reg, nb, ng);
   const Params P = a.p;
   auto xyz = [](float4 f) { return vec(f.x, f.y, f.z); };
@@ -3676,6 +3701,8 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
       C.mut = fmaxf(ma.x, mb.x); C.mutor = fmaxf(ma.y, mb.y); C.murol = fmaxf(ma.z, mb.z);
       C.h = P.h; C.k = P.k_user; C.d = P.d_user;
       C.diag = P.imp_diag != 0;
+      C.net = NET ? a.mlp : nullptr;  // learned gains (free bodies): the float32 network
+      C.margin = P.mlp_margin;
       C.ima = C.imb = 0.f;
       if (C.diag) {  // free bodies only: 1/m and the world inverse inertia at the step's start
         auto inertia = [&](int bi, float *S) {
@@ -3688,7 +3715,7 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
       const Vec<float> Fab = ba >= 0 ? xyz(bFb[ba]) : Z, Tab = ba >= 0 ? xyz(bTb[ba]) : Z;
       const Vec<float> Fbb = bbd >= 0 ? xyz(bFb[bbd]) : Z, Tbb = bbd >= 0 ? xyz(bTb[bbd]) : Z;
       adj::ContactBar<float> o;
-      adj::contact_vjp<NF>(C, I, Fab, Tab, Fbb, Tbb, o);
+      adj::contact_vjp<NF, float, NET>(C, I, Fab, Tab, Fbb, Tbb, o);
       // geometry: contact (n, phi, p) from the two geoms' poses
       Vec<float> xab = o.xa, xbb = o.xb, psa = Z, psb = Z;
       const float4 gda = a.gdat[(size_t)w * ng + ga], gdb = a.gdat[(size_t)w * ng + gb];
@@ -3842,31 +3869,32 @@ __global__ __launch_bounds__(BS) void backward_kernel(BackwardArgs b) {
   }
 }
 
-template <int CONDIM, bool ART>
+template <int CONDIM, bool ART, bool NET>
 static hipError_t launch_backward_c(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
   switch (block) {
-    case 64: hipLaunchKernelGGL((backward_kernel<CONDIM, 64, ART>), dim3(nworld), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((backward_kernel<CONDIM, 128, ART>), dim3(nworld), dim3(128), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((backward_kernel<CONDIM, 256, ART>), dim3(nworld), dim3(256), lds, s, a); break;
+    case 64: hipLaunchKernelGGL((backward_kernel<CONDIM, 64, ART, NET>), dim3(nworld), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((backward_kernel<CONDIM, 128, ART, NET>), dim3(nworld), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((backward_kernel<CONDIM, 256, ART, NET>), dim3(nworld), dim3(256), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <bool ART>
+template <bool ART, bool NET>
 static hipError_t launch_backward_a(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
   switch (a.s.condim) {
-    case 1: return launch_backward_c<1, ART>(a, nworld, block, lds, s);
-    case 3: return launch_backward_c<3, ART>(a, nworld, block, lds, s);
-    case 4: return launch_backward_c<4, ART>(a, nworld, block, lds, s);
-    case 6: return launch_backward_c<6, ART>(a, nworld, block, lds, s);
+    case 1: return launch_backward_c<1, ART, NET>(a, nworld, block, lds, s);
+    case 3: return launch_backward_c<3, ART, NET>(a, nworld, block, lds, s);
+    case 4: return launch_backward_c<4, ART, NET>(a, nworld, block, lds, s);
+    case 6: return launch_backward_c<6, ART, NET>(a, nworld, block, lds, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_backward(const BackwardArgs &a, int nworld, int block, size_t lds, hipStream_t s) {
-  return a.s.nsub > 0 ? launch_backward_a<true>(a, nworld, block, lds, s)
-                      : launch_backward_a<false>(a, nworld, block, lds, s);
+  if (a.s.nsub > 0) return a.s.mlp ? hipErrorInvalidValue : launch_backward_a<true, false>(a, nworld, block, lds, s);
+  return a.s.mlp ? launch_backward_a<false, true>(a, nworld, block, lds, s)
+                 : launch_backward_a<false, false>(a, nworld, block, lds, s);
 }
 
 }  // namespace cf

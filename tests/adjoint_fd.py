@@ -16,17 +16,24 @@ from paper_2603_12185_amd import scenes
 
 
 def branch_key(out, w, width):
-    """Everything discrete the oracle's step decided for world w."""
+    """Everything discrete the oracle's step decided for world w (with learned
+    gains also each contact's fallback decision and which outputs are clamped)."""
     n = int(out["ncon"][w])
-    return (n, out["geom"][w, :n].tobytes(), out["sub"][w, :n].tobytes(),
-            (out["impulse"][w, :n] > 0).tobytes(),
-            (np.abs(out["dist"][w, :n]) >= width).tobytes(),
-            (np.abs(out["frame"][w, :n, 0]) <= 0.5).tobytes())
+    key = (n, out["geom"][w, :n].tobytes(), out["sub"][w, :n].tobytes(),
+           (out["impulse"][w, :n] > 0).tobytes(),
+           (np.abs(out["dist"][w, :n]) >= width).tobytes(),
+           (np.abs(out["frame"][w, :n, 0]) <= 0.5).tobytes())
+    if "learned_y" in out:
+        nf = out["impulse"].shape[-1]
+        key += (out["fallback"][w, :n].tobytes(),
+                (np.abs(out["learned_y"][w, :n, :nf]) >= np.log(256.0)).tobytes())
+    return key
 
 
-def step_grad_fd(scene, w, q, v, tau, gq_out, gv_out, eps=1e-6):
+def step_grad_fd(scene, w, q, v, tau, gq_out, gv_out, eps=1e-6, learned=None):
     """FD gradient of <gq_out[w], q+> + <gv_out[w], v+> of world w with respect to
-    (q[w], v[w], tau[w]) in float64.  Returns (g, ok): g = concatenated
+    (q[w], v[w], tau[w]) in float64 (the oracle's learned-gain step when
+    learned = (params, margin)).  Returns (g, ok): g = concatenated
     (dq, dv, dtau), ok = stencil stayed on the base point's branch."""
     nq, nv = q.shape[-1], v.shape[-1]
     n_in = nq + 2 * nv
@@ -38,7 +45,7 @@ def step_grad_fd(scene, w, q, v, tau, gq_out, gv_out, eps=1e-6):
     idx = np.arange(n_in)
     X[1 + 2 * idx, idx] += eps
     X[2 + 2 * idx, idx] -= eps
-    qo, vo, out = o.step(X[:, :nq], X[:, nq:nq + nv], X[:, nq + nv:])
+    qo, vo, out = o.step(X[:, :nq], X[:, nq:nq + nv], X[:, nq + nv:], learned=learned)
     L = qo @ np.asarray(gq_out[w], np.float64) + vo @ np.asarray(gv_out[w], np.float64)
     g = (L[1::2] - L[2::2]) / (2 * eps)
     width = float(scene["solimp"][2])

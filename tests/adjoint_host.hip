@@ -119,8 +119,35 @@ static void check_update(int trial, D wscale) {
 
 static Impedance<D> imp() { return {0.9, 0.95, 0.001, 0.5, 2.0}; }
 
+// Learned gains: whether the fallback rule keeps them and which outputs are
+// clamped (recomputed here from the same pieces contact_forward uses).
+template <int NF>
+static unsigned learned_pattern(const ContactIn<D> &C) {
+  if (!C.net) return 0;
+  V u;
+  D il;
+  bool hx;
+  tangent_basis(C.n, u, il, hx);
+  const V t1 = il * u, t2 = cross(C.n, t1);
+  const V ra = C.p - C.xa, rb = C.p - C.xb;
+  V vrel = vec(0.0, 0.0, 0.0), wrel = vrel;
+  if (C.has_b) { vrel = C.vb + cross(C.wb, rb); wrel = C.wb; }
+  if (C.has_a) { vrel = vrel - (C.va + cross(C.wa, ra)); wrel = wrel - C.wa; }
+  D drho;
+  const D A0 = impedance_rho(C.phi, imp(), drho) / C.trs;
+  D s[NF], z[NF];
+  facet_s<NF>(C, C.n, t1, t2, vrel, wrel, s);
+  for (int i = 0; i < NF; ++i) z[i] = -(C.k * C.h + C.d) * s[i] - C.k * C.phi;
+  LearnedEval<NF, D> L;
+  learned_eval<NF>(C, A0, dot(C.n, vrel), dot(t1, vrel), dot(t2, vrel), z, L);
+  unsigned m = L.keep ? 1u : 0u;
+  for (int f = 0; f < NF; ++f) m |= (std::fabs(L.y[f]) >= cf::mlp::CLIP ? 1u : 0u) << (1 + f);
+  return m;
+}
+
 // Which branch each non-smooth operation of the contact takes: facet
-// activity, the clamp of x, the sign of phi, the tangent helper.
+// activity, the clamp of x, the sign of phi, the tangent helper, and for
+// learned gains the fallback decision and the output clamps.
 template <int NF>
 static unsigned pattern(const ContactIn<D> &C) {
   D lam[NF];
@@ -131,6 +158,7 @@ static unsigned pattern(const ContactIn<D> &C) {
   m |= (std::fabs(C.phi) >= imp().width ? 1u : 0u) << 12;
   m |= (C.phi > 0.0 ? 1u : 0u) << 13;
   m |= (std::fabs(C.n.x) <= 0.5 ? 1u : 0u) << 14;
+  m |= learned_pattern<NF>(C) << 16;
   return m;
 }
 
@@ -142,8 +170,11 @@ static void inv_inertia(const D *q, const D *d, D *S) {
 }
 
 template <int NF>
-static void make_contact(ContactIn<D> &C, bool has_a, bool has_b, D phi_scale) {
+static void make_contact(ContactIn<D> &C, bool has_a, bool has_b, D phi_scale, const float *net = nullptr,
+                         D margin = 0) {
   C.diag = false;
+  C.net = net;
+  C.margin = margin;
   C.ima = C.imb = 0;
   for (int i = 0; i < 6; ++i) C.Sa[i] = C.Sb[i] = 0;
   for (;;) {
@@ -179,9 +210,10 @@ static void make_contact(ContactIn<D> &C, bool has_a, bool has_b, D phi_scale) {
 // quaternions that are inputs of the check too (their adjoints reach them
 // through the rotation increments psa, psb).
 template <int NF>
-static void check_contact(int trial, bool has_a, bool has_b, D phi_scale, bool diag = false) {
+static void check_contact(int trial, bool has_a, bool has_b, D phi_scale, bool diag = false,
+                          const float *net = nullptr, D margin = 0) {
   ContactIn<D> C;
-  make_contact<NF>(C, has_a, has_b, phi_scale);
+  make_contact<NF>(C, has_a, has_b, phi_scale, net, margin);
   D qa[4], qb[4], da[3], db[3];
   for (int i = 0; i < 4; ++i) { qa[i] = U(-1, 1); qb[i] = U(-1, 1); }
   for (int i = 0; i < 3; ++i) { da[i] = 1.0 / U(1e-4, 1e-3); db[i] = 1.0 / U(1e-4, 1e-3); }
@@ -228,9 +260,30 @@ static void check_contact(int trial, bool has_a, bool has_b, D phi_scale, bool d
   for (int i = 0; i < 4; ++i) an.push_back(gqa[i]);
   for (int i = 0; i < 4; ++i) an.push_back(gqb[i]);
   char name[80];
-  snprintf(name, sizeof name, "contact nf=%d a=%d b=%d phi~%g%s #%d", NF, has_a, has_b, phi_scale,
-           diag ? " diag" : "", trial);
+  snprintf(name, sizeof name, "contact nf=%d a=%d b=%d phi~%g%s%s #%d", NF, has_a, has_b, phi_scale,
+           diag ? " diag" : "", net ? (learned_pattern<NF>(C) & 1u ? " learned" : " learned-fallback") : "",
+           trial);
   report(name, an, fd_grad(x, L, 1e-7), 2e-6);
+}
+
+// A random learned-gain network (cf_mlp.h layout) with feature scales of a
+// contact: outputs of order one, so the gains vary by factors of e.
+static std::vector<float> random_net() {
+  using namespace cf::mlp;
+  std::vector<float> p(NPARAM, 0.f);
+  const float mean[NFEAT] = {-0.002f, -0.02f, 0.f, 0.f, 0.1f, 0.6f, 0.002f};
+  const float sd[NFEAT] = {0.005f, 0.05f, 0.05f, 0.05f, 0.1f, 0.2f, 1.f};
+  for (int k = 0; k < NIN; ++k) {
+    p[OFF_MEAN + k] = k < NFEAT ? mean[k] : 0.f;
+    p[OFF_STD + k] = k < NFEAT ? sd[k] : 1.f;
+  }
+  for (int i = 0; i < NIN * NH; ++i) p[OFF_W1 + i] = (float)U(-0.6, 0.6);
+  for (int i = 0; i < NH; ++i) p[OFF_B1 + i] = (float)U(-0.3, 0.3);
+  for (int i = 0; i < NH * NH; ++i) p[OFF_W2 + i] = (float)U(-0.25, 0.25);
+  for (int i = 0; i < NH; ++i) p[OFF_B2 + i] = (float)U(-0.3, 0.3);
+  for (int i = 0; i < NH * NOUT; ++i) p[OFF_W3 + i] = (float)U(-0.3, 0.3);
+  for (int i = 0; i < NOUT; ++i) p[OFF_B3 + i] = (float)U(-0.5, 0.5);
+  return p;
 }
 
 static void check_sphere_pair(int trial) {
@@ -530,6 +583,16 @@ int main() {
     check_contact<10>(t, true, true, 0.01, true);
     check_contact<4>(t, false, true, 0.01, true);
     check_contact<6>(t, true, false, 0.0005, true);
+  }
+  const std::vector<float> net = random_net();
+  for (int t = 0; t < 3; ++t) {  // learned gains: kept (large margin) and under the tight rule
+    check_contact<1>(t, true, true, 0.01, false, net.data(), 1.0);
+    check_contact<4>(t, true, true, 0.01, false, net.data(), 1.0);
+    check_contact<6>(t, true, true, 0.01, false, net.data(), 1.0);
+    check_contact<10>(t, true, true, 0.01, false, net.data(), 1.0);
+    check_contact<4>(t, false, true, 0.0005, false, net.data(), 1.0);
+    check_contact<4>(t, true, true, 0.01, false, net.data(), 0.0);
+    check_contact<6>(t, true, false, 0.01, false, net.data(), 1e-4);
   }
   for (int t = 0; t < 3; ++t) check_sphere_pair(t);
   for (int t = 0; t < 3; ++t) check_plane_point(t);

@@ -149,6 +149,75 @@ def test_step_backward_matches_oracle_fd(torch_cuda, case):
     assert worst <= REL
 
 
+LEARNED = {
+    "mixed_c3": lambda: (scenes.mixed_shapes(nworld=3, seed=22, condim=3), 40, True),
+    "mixed_c6": lambda: (scenes.mixed_shapes(nworld=3, seed=24, condim=6), 40, True),
+    "cluster_c4": lambda: (scenes.sphere_cluster(nsphere=10, seed=1, condim=4, spread=0.05), 2, True),
+    "pile_c1": lambda: (scenes.dense_pile(nworld=2, nsphere=16, seed=2, ncon_max=128, condim=1), 300, False),
+}
+
+
+def learned_params(s, q, v, tau, seed, b3=(-1.0, 1.0)):
+    """A network normalised on the state's own contact features, with Glorot
+    weights and random biases (output biases uniform in b3): outputs of order
+    one, so facet gains differ by factors up to about e from the heuristic's
+    and from one another (larger with larger output biases)."""
+    from oracle import mlp
+    _, _, out = Oracle(s).step(q.astype(np.float64), v.astype(np.float64),
+                               None if tau is None else tau.astype(np.float64))
+    feats = np.concatenate([out["features"][w, :int(out["ncon"][w])] for w in range(s["nworld"])])
+    p = mlp.init_params(feats, seed)
+    rng = np.random.default_rng(seed)
+    p[mlp.OFF_B1:mlp.OFF_W2] = rng.uniform(-0.3, 0.3, mlp.NH)
+    p[mlp.OFF_B2:mlp.OFF_W3] = rng.uniform(-0.3, 0.3, mlp.NH)
+    p[mlp.OFF_B3:] = rng.uniform(b3[0], b3[1], mlp.NOUT)
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("case,margin", [("mixed_c3", 1e3), ("mixed_c6", 1e3), ("cluster_c4", 1e3),
+                                         ("pile_c1", 1e3), ("mixed_c3", 1e-4), ("pile_c1", 1e-4)])
+def test_step_backward_learned_matches_oracle_fd(torch_cuda, case, margin):
+    """cf_step_backward with learned gains (Sec. III.B: K and D from a
+    network) against central differences of the oracle's learned step: the
+    gains G_f = A exp(clamp(y_f)) differentiated through the network's
+    features (gap, normal and tangential relative velocity, effective mass),
+    the kept-or-fallen-back decision held as the step took it (a margin of
+    1 km keeps every learned gain; 0.1 mm lets some contacts fall back)."""
+    from paper_2603_12185_amd import cfsim
+    s, nsteps, with_tau = LEARNED[case]()
+    rng = np.random.default_rng(sum(map(ord, case)) + int(margin > 1))
+    print(f"case: step_backward learned {case} margin {margin}", flush=True)
+    tau = applied_wrench(s, rng) if with_tau else None
+    q, v = oracle_state(s, nsteps, None if tau is None else tau.astype(np.float64))
+    params = learned_params(s, q, v, tau, seed=3, b3=(-1.0, 1.0) if margin > 1 else (1.0, 2.5))
+    nw, nq, nv = s["nworld"], q.shape[1], v.shape[1]
+    gq_out = rng.normal(size=(nw, nq)).astype(np.float32)
+    gv_out = rng.normal(size=(nw, nv)).astype(np.float32)
+    model = cfsim.Model(s)
+    model.set_learned_impedance(cfsim.ImpedanceNet(params), margin=margin)
+    gq, gv, gtau = model.step_backward(tdev(q), tdev(v), None if tau is None else tdev(tau),
+                                       tdev(gq_out), tdev(gv_out))
+    gq, gv, gtau = gq.cpu().numpy(), gv.cpu().numpy(), gtau.cpu().numpy()
+    worst, ncon, skipped, fell = 0.0, 0, 0, 0
+    for w in range(nw):
+        g_fd, ok, out = step_grad_fd(s, w, q, v, tau, gq_out, gv_out, learned=(params, margin))
+        n = int(out["ncon"][0])
+        ncon += n
+        fell += int(out["fallback"][0, :n].sum())
+        skipped += int((~ok).sum())
+        g = np.concatenate([gq[w], gv[w], gtau[w]])
+        d = (g - g_fd)[ok]
+        rel = np.linalg.norm(d) / np.linalg.norm(g_fd[ok])
+        if rel > REL:
+            i = np.argsort(-np.abs(g - g_fd) * ok)[:6]
+            print("worst components", [(int(k), float(g[k]), float(g_fd[k])) for k in i])
+        worst = max(worst, rel)
+    print(f"learned {case} margin {margin}: contacts {ncon}, fallbacks {fell}, "
+          f"kinked components skipped {skipped}, worst rel {worst:.2e}")
+    assert ncon > 0 and (fell > 0 or margin > 1)
+    assert worst <= REL
+
+
 def test_autograd_step_equals_step_backward(torch_cuda):
     from paper_2603_12185_amd import autograd, cfsim
     torch = torch_cuda
