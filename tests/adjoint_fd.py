@@ -55,7 +55,7 @@ def step_grad_fd(scene, w, q, v, tau, gq_out, gv_out, eps=1e-6, learned=None):
     return g, ok, out
 
 
-def rollout_cost_fd(scene, worlds, q0, v0, tau_seq, cost, comps, eps=1e-6):
+def rollout_cost_fd(scene, worlds, q0, v0, tau_seq, cost, comps, eps=1e-6, learned=None):
     """FD gradient of cost(w, q_T, v_T) (world w's cost of each row, float64) with respect to the
     components `comps` (list of (t, dof)) of tau_seq [T][nw][nv], for each world
     in `worlds`.  Returns (g [len(worlds)][len(comps)], ok) with ok marking
@@ -76,7 +76,7 @@ def rollout_cost_fd(scene, worlds, q0, v0, tau_seq, cost, comps, eps=1e-6):
             tau[t, 2 + 2 * i, d] -= eps
         same = np.ones(nc, bool)
         for t in range(T):
-            q, v, out = o.step(q, v, tau[t])
+            q, v, out = o.step(q, v, tau[t], learned=learned)
             k0 = branch_key(out, 0, width)
             for i in range(nc):
                 if same[i] and (branch_key(out, 1 + 2 * i, width) != k0 or

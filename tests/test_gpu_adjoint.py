@@ -218,6 +218,55 @@ def test_step_backward_learned_matches_oracle_fd(torch_cuda, case, margin):
     assert worst <= REL
 
 
+def test_learned_rollout_gradient_matches_oracle_fd(torch_cuda):
+    """A differentiable rollout through the learned gains: 64 worlds of the
+    pusher scene (6D contacts) with a network on every contact and the 0.1 mm
+    fallback margin, horizon 8, quadratic ball-pose cost; the gradient with
+    respect to the 8 x 12 fingertip forces (torch.autograd over cf_rollout's
+    checkpointed steps) against FP64 central differences of the oracle's
+    learned-gain rollout on 3 worlds."""
+    from paper_2603_12185_amd import autograd, cfsim
+    torch = torch_cuda
+    T, nw, margin = 8, 64, 1e-4
+    s = scenes.pusher_ball(nworld=nw, seed=5)
+    rng = np.random.default_rng(11)
+    tau_seq = pusher_controls(s, T, rng)
+    q0, v0 = s["q0"], s["v0"]
+    q4, v4 = oracle_state(s, 0)
+    o = Oracle(s)
+    q4, v4 = q4.astype(np.float64), v4.astype(np.float64)
+    for t in range(4):  # normalisation from the contacts of the rollout's fifth step
+        q4, v4, _ = o.step(q4, v4, tau_seq[t].astype(np.float64), outputs=False)
+    params = learned_params(s, q4.astype(np.float32), v4.astype(np.float32), tau_seq[4], seed=4, b3=(-0.7, 0.7))
+    target = q0[:, 0:7].astype(np.float64).copy()
+    target[:, 0] += 0.01
+
+    def cost_np(w, q, v):
+        return ((q[:, 0:3] - target[w, 0:3]) ** 2).sum(1) + 0.1 * ((q[:, 3:7] - target[w, 3:7]) ** 2).sum(1)
+
+    model = cfsim.Model(s)
+    model.set_learned_impedance(cfsim.ImpedanceNet(params), margin=margin)
+    tau = tdev(tau_seq).requires_grad_(True)
+    qt, vt = autograd.rollout(model, T, tdev(q0), tdev(v0), tau)
+    tg = tdev(target)
+    c = ((qt[T][:, 0:3] - tg[:, 0:3]) ** 2).sum() + 0.1 * ((qt[T][:, 3:7] - tg[:, 3:7]) ** 2).sum()
+    c.backward()
+    G = tau.grad.cpu().numpy()
+    worlds = [0, 1, 2]
+    comps = [(t, 6 + 6 * f + k) for t in range(T) for f in range(4) for k in range(3)]
+    print("case: learned rollout gradient pusher_ball 64 worlds T=8", flush=True)
+    g_fd, ok = rollout_cost_fd(s, worlds, q0, v0, tau_seq, cost_np, comps, learned=(params, margin))
+    worst = 0.0
+    for wi, w in enumerate(worlds):
+        g = np.array([G[t, w, d] for t, d in comps])
+        rel = np.linalg.norm((g - g_fd[wi])[ok[wi]]) / np.linalg.norm(g_fd[wi][ok[wi]])
+        print(f"world {w}: |g| {np.linalg.norm(g_fd[wi]):.3e} rel {rel:.2e} kinked {(~ok[wi]).sum()}")
+        worst = max(worst, rel)
+    assert ok.mean() > 0.9
+    assert worst <= REL
+    assert np.isfinite(G).all()
+
+
 def test_autograd_step_equals_step_backward(torch_cuda):
     from paper_2603_12185_amd import autograd, cfsim
     torch = torch_cuda
