@@ -285,8 +285,17 @@ cf_status cf_model_get_launch(const cf_model *m, int32_t *collide_block, int32_t
 cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const float *v, int32_t steps,
                             float *best_step_us, float *best_rollout_step_us);
 
-/* Kernel timing.  When enabled, every cf_step records HIP events around its
- * collision and resolution kernels on the step's stream.  cf_model_kernel_times
+/* Kernels of one cf_step: 1 when the narrow phase and the resolution of each
+ * world run in one kernel (worlds of 1 to 64 free bodies without actuators or
+ * learned gains, condim 1, 3 or 4, at the one-wave launch shapes 64/64, and
+ * kernel timing off; a world's resolution then starts as soon as its own
+ * narrow phase ends; results equal the two launches bit for bit), else 2.
+ * Host call, no device work. */
+cf_status cf_model_step_kernels(const cf_model *m, int32_t *nkernels);
+
+/* Kernel timing.  When enabled, every cf_step runs its collision and resolution
+ * kernels apart (never the one-kernel step) and records HIP events around them
+ * on the step's stream.  cf_model_kernel_times
  * waits for the recorded events, returns the summed milliseconds of each
  * kernel and the number of steps since the last call, and resets the sums. */
 cf_status cf_model_set_profiling(cf_model *m, int32_t enable);

@@ -68,6 +68,7 @@ SIGNATURES = {
     "cf_model_get_launch": ([C.c_void_p, _ip, _ip, _ip, _ip], C.c_int32),
     "cf_model_autotune": ([C.c_void_p, C.c_void_p, _fp, _fp, C.c_int32, C.POINTER(C.c_float),
                            C.POINTER(C.c_float)], C.c_int32),
+    "cf_model_step_kernels": ([C.c_void_p, _ip], C.c_int32),
     "cf_model_set_profiling": ([C.c_void_p, C.c_int32], C.c_int32),
     "cf_model_kernel_times": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_int64)], C.c_int32),
@@ -314,6 +315,12 @@ class Model:
         a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(load().cf_model_get_launch(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
         return a.value, b.value, c.value, bool(d.value)
+
+    def step_kernels(self):
+        """1 when cf_step runs the narrow phase and the resolution in one kernel, else 2."""
+        n = C.c_int32()
+        _check(load().cf_model_step_kernels(self._h, C.byref(n)))
+        return n.value
 
     def autotune(self, q, v, steps=20, stream=None):
         """Pick the fastest workgroup sizes on state (q, v); returns (us/step of

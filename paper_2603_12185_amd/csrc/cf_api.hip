@@ -567,6 +567,16 @@ static bool rollout_free(const cf_model *m) {
   return m->lds_rollout_free > 0 && m->lds_rollout_free <= kLdsLimit && !m->d_act && !m->mlp;
 }
 
+// Worlds of at most 64 free bodies (no actuators, no learned gains) at the
+// one-wave launch shapes, condim 1, 3 or 4: cf_step runs the narrow phase and
+// the resolution of each world in one kernel (not while kernel timing is on,
+// which times the two kernels apart).
+static bool step_fused(const cf_model *m) {
+  return !m->prof && !m->mlp && !m->d_act && m->nsub == 0 && m->nb >= 1 && m->nb <= 64 && m->condim != 6 &&
+         m->block_collide == 64 && m->block_resolve == 64 &&
+         std::max(m->lds_collide, m->lds_resolve_free) <= kLdsLimit;
+}
+
 static bool rollout_fused(const cf_model *m) {
   return !m->rollout_steps && !m->mlp && (rollout_free(m) || m->lds_rollout <= kLdsLimit);
 }
@@ -633,6 +643,19 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
   ca.q = q;
   ca.ncon_out = out ? out->ncon : nullptr;
   ca.overflow_out = out ? out->overflow : nullptr;
+  if (step_fused(m)) {
+    cf::ResolveArgs ra = resolve_args(m);
+    ra.q = q; ra.v = v; ra.tau = tau; ra.q_out = q_out; ra.v_out = v_out;
+    if (out) {
+      ra.x_geom = out->geom; ra.x_sub = out->sub; ra.x_dist = out->dist; ra.x_pos = out->pos;
+      ra.x_frame = out->frame; ra.x_imp = out->impulse;
+      ra.x_feat = out->features; ra.x_target = out->target;
+      ra.x_fallback = out->fallback;
+    }
+    const hipError_t e = cf::launch_step_free(ca, ra, m->nw, std::max(m->lds_collide, m->lds_resolve_free), s);
+    if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    return CF_OK;
+  }
   hipError_t e = cf::launch_collide(ca, m->nw, m->block_collide, m->lds_collide, s);
   if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("collide launch: ") + hipGetErrorString(e));
   if (ev && hipEventRecord(ev->e[1], s) != hipSuccess) return set_err(CF_E_DEVICE, "hipEventRecord failed");
@@ -891,6 +914,12 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
   if (best_step_us) *best_step_us = best * 1e3f / steps;
   if (best_rollout_step_us) *best_rollout_step_us = best_r < 1e29f ? best_r * 1e3f / steps : -1.f;
   return st2;
+}
+
+cf_status cf_model_step_kernels(const cf_model *m, int32_t *nkernels) {
+  if (!m || !nkernels) return set_err(CF_E_INVALID_ARG, "model and nkernels must be non-NULL");
+  *nkernels = step_fused(m) ? 1 : 2;
+  return CF_OK;
 }
 
 cf_status cf_model_set_profiling(cf_model *m, int32_t enable) {

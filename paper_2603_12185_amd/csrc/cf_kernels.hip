@@ -2765,6 +2765,85 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
   }
 }
 
+// One step of a world of at most 64 free bodies in one one-wave workgroup:
+// the narrow phase (collide_kernel's) and then the free-body resolution
+// (resolve_free_kernel's) of the same world, the contact records through the
+// workspace as between the two kernels.  A world's resolution starts as soon
+// as its own narrow phase ends, so worlds drift apart within the launch and
+// one world's loads overlap others' arithmetic, where the resolution kernel
+// starts every world on the same burst of loads.  Same device functions, so
+// the results equal the two launches bit for bit.
+template <int CONDIM>
+__global__ __launch_bounds__(64) void step_free_kernel(CollideArgs ca, ResolveArgs ra) {
+  constexpr int BS = 64, K = 512 / BS;
+  extern __shared__ float4 lds[];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  float *sq = reinterpret_cast<float *>(lds);
+  const uint32_t nxt = ca.slots[tid < ca.nslot_pre ? tid : (ca.nslot_pre > 0 ? ca.nslot_pre - 1 : 0)];
+  const int gl = ca.ng > 0 ? ca.ng - 1 : 0;
+  const GeomIn pre[2] = {geom_in(ca, w, tid < ca.ng ? tid : gl), geom_in(ca, w, tid + BS < ca.ng ? tid + BS : gl)};
+  const float *qw = ca.q + (size_t)w * ca.nq;
+  RowStage<BS, K> rq;
+  rq.load(qw, ca.nq);
+  rq.store(sq, qw, ca.nq);
+  __syncthreads();
+  const size_t cbase = (size_t)w * ca.ncon_max;
+  const int found = collide_world<BS, false>(ca, w, sq, lds + pad4(ca.nq) / 4, ca.cnp + cbase, ca.cpos + cbase,
+                                             ca.ncon_max, nxt, pre);
+  const int nc = found < ca.ncon_max ? found : ca.ncon_max;
+  if (tid == 0) {
+    ca.ncon[w] = nc;
+    ca.overflow[w] = found - nc;
+    if (ca.ncon_out) ca.ncon_out[w] = nc;
+    if (ca.overflow_out) ca.overflow_out[w] = found - nc;
+  }
+  // the resolution: the lane's body, the first chunk of the records this
+  // workgroup wrote (visible after collide_world's barrier)
+  const int nb = ra.nb;
+  const bool own = tid < nb;
+  const int b = own ? tid : nb - 1;
+  float qb[7], vb[6], tb[6];
+  {
+    const float *qs = ra.q + (size_t)w * ra.nq + 7 * b, *vs = ra.v + (size_t)w * ra.nv + 6 * b;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qb[i] = qs[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vb[i] = vs[i];
+  }
+  const float4 mi = ra.bmi[(size_t)w * nb + b];
+  const int r0 = tid < nc ? tid : (nc > 0 ? nc - 1 : 0);
+  const float4 cn = ra.cnp[cbase + r0], cp = ra.cpos[cbase + r0];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) tb[i] = 0.f;
+  if (ra.tau) {
+    const float *ts = ra.tau + (size_t)w * ra.nv + 6 * b;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) tb[i] = ts[i];
+  }
+  float qo[7], vo[6];
+  resolve_free_world<CONDIM, BS>(ra, w, qb, vb, tb, mi, nc, cn, cp, ra.cnp + cbase, ra.cpos + cbase, cbase, lds, qo, vo);
+  if (own) {
+    float *qd = ra.q_out + (size_t)w * ra.nq + 7 * tid, *vd = ra.v_out + (size_t)w * ra.nv + 6 * tid;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qd[i] = qo[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) vd[i] = vo[i];
+  }
+}
+
+// condim 1, 3 and 4 (at most 128 VGPRs: four resident worlds per SIMD; at
+// condim 6 the one-wave kernel would hold three, and the two launches are faster)
+hipError_t launch_step_free(const CollideArgs &ca, const ResolveArgs &ra, int nworld, size_t lds, hipStream_t s) {
+  if (ra.nsub > 0 || ra.mlp || ra.act || ra.nb > 64 || ra.nb < 1) return hipErrorInvalidValue;
+  switch (ra.condim) {
+    case 1: hipLaunchKernelGGL((step_free_kernel<1>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
+    case 3: hipLaunchKernelGGL((step_free_kernel<3>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
+    case 4: hipLaunchKernelGGL((step_free_kernel<4>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ---- learned gains on worlds of free bodies (at most 128; lane b owns
 // bodies b and b + 64): four one-wave worlds per workgroup share one LDS copy
 // of the network (WeightsK32, written for the

@@ -425,6 +425,37 @@ def test_rollout_full_pile_matches_steps(torch_cuda):
     assert float(ncon2.double().mean()) > 100, "the settled pile should hold its contacts"
 
 
+@pytest.mark.parametrize("condim", [1, 3, 4, 6])
+def test_one_kernel_step_equals_two_launches(torch_cuda, condim):
+    """cf_step of worlds of free bodies at the one-wave launch shapes runs the
+    narrow phase and the resolution in one kernel at condim 1, 3 and 4: the
+    next state, the contact counts and every exported contact quantity equal
+    those of the two kernels (kernel timing on launches them apart) bit for
+    bit, on a settled pile and on mixed shapes; condim 6 keeps two kernels."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    for s, settle in ((scenes.dense_pile(nworld=64, nsphere=64, seed=3, condim=condim), 300),
+                      (scenes.mixed_shapes(nworld=8, seed=50 + condim, condim=condim), 20)):
+        model = cfsim.Model(s)
+        assert model.step_kernels() == (2 if condim == 6 else 1)
+        q, v = tdev(s["q0"]), tdev(s["v0"])
+        for _ in range(settle):
+            q, v = model.step(q, v)
+        print(f"case: one-kernel step {s['name']} condim {condim}", flush=True)
+        c1 = model.alloc_contacts()
+        q1, v1 = model.step(q, v, contacts=c1)
+        model.set_profiling(True)
+        assert model.step_kernels() == 2
+        c2 = model.alloc_contacts()
+        q2, v2 = model.step(q, v, contacts=c2)
+        model.set_profiling(False)
+        torch.cuda.synchronize()
+        assert torch.equal(q1, q2) and torch.equal(v1, v2)
+        assert int(c1["ncon"].sum()) > 0
+        for k in c1:
+            assert torch.equal(c1[k], c2[k]), k
+
+
 def test_rollout_graph_capture_replays(torch_cuda):
     """A stream capture of cf_rollout replays correctly: three replays with new
     initial states, eager work and synchronisations in between, each checked
