@@ -158,7 +158,8 @@ cf_status cf_model_dims(const cf_model *m, int32_t *nq, int32_t *nv, int32_t *nf
 /* One step of every world (Algorithm 1 preceded by collision detection and
  * followed by integration).  q [nworld][nq], v and tau [nworld][nv] (tau NULL
  * = zero applied force), q_out/v_out same shapes.  All float32, 16-byte
- * aligned device pointers.  out may be NULL. */
+ * aligned device pointers.  out may be NULL.  Two kernels (narrow phase, then
+ * resolution), or one that runs both for each world (cf_model_step_kernels). */
 cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, const float *tau,
                   float *q_out, float *v_out, const cf_contacts *out);
 
