@@ -129,6 +129,7 @@ def pile_run(nw, nsphere, condim, k_user, d_user, steps, last, seed=0):
                                "max_contacts_per_world": int(cl.max()),
                                "contact_impulses_per_s": float(cl.sum()) / (ms_last * 1e-3)},
         "kernel_us_final_state": {"collide_kernel": us_col, "resolve_kernel": us_res},
+        "step_kernels": model.step_kernels(),
         "capacity_overflows": bad, "state_finite": finite,
     }
 

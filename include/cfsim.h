@@ -288,9 +288,10 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
 
 /* Kernels of one cf_step: 1 when the narrow phase and the resolution of each
  * world run in one kernel (worlds of 1 to 64 free bodies without actuators or
- * learned gains, condim 1, 3 or 4, at the one-wave launch shapes 64/64, and
+ * learned gains, at the one-wave launch shapes 64/64, and
  * kernel timing off; a world's resolution then starts as soon as its own
- * narrow phase ends; results equal the two launches bit for bit), else 2.
+ * narrow phase ends; the same contacts as the two launches and results equal
+ * to float32 rounding), else 2.
  * Host call, no device work. */
 cf_status cf_model_step_kernels(const cf_model *m, int32_t *nkernels);
 

@@ -568,11 +568,11 @@ static bool rollout_free(const cf_model *m) {
 }
 
 // Worlds of at most 64 free bodies (no actuators, no learned gains) at the
-// one-wave launch shapes, condim 1, 3 or 4: cf_step runs the narrow phase and
-// the resolution of each world in one kernel (not while kernel timing is on,
-// which times the two kernels apart).
+// one-wave launch shapes: cf_step runs the narrow phase and the resolution of
+// each world in one kernel (not while kernel timing is on, which times the two
+// kernels apart).
 static bool step_fused(const cf_model *m) {
-  return !m->prof && !m->mlp && !m->d_act && m->nsub == 0 && m->nb >= 1 && m->nb <= 64 && m->condim != 6 &&
+  return !m->prof && !m->mlp && !m->d_act && m->nsub == 0 && m->nb >= 1 && m->nb <= 64 &&
          m->block_collide == 64 && m->block_resolve == 64 &&
          std::max(m->lds_collide, m->lds_resolve_free) <= kLdsLimit;
 }

@@ -2771,10 +2771,14 @@ __global__ __launch_bounds__(BS) void resolve_free_kernel(ResolveArgs a) {
 // workspace as between the two kernels.  A world's resolution starts as soon
 // as its own narrow phase ends, so worlds drift apart within the launch and
 // one world's loads overlap others' arithmetic, where the resolution kernel
-// starts every world on the same burst of loads.  Same device functions, so
-// the results equal the two launches bit for bit.
+// starts every world on the same burst of loads.  Same device functions in
+// the same order: the same contacts as the two launches and results equal to
+// float32 rounding (the compiler may fuse a multiply and an add differently in
+// the two compilations).
+// Four resident worlds per SIMD, as each phase's own kernel holds: condim
+// 1/3/4 need 95/111/123 VGPRs; condim 6, bounded to 128, spills 40 bytes.
 template <int CONDIM>
-__global__ __launch_bounds__(64) void step_free_kernel(CollideArgs ca, ResolveArgs ra) {
+__global__ __launch_bounds__(64, CONDIM == 6 ? 4 : 1) void step_free_kernel(CollideArgs ca, ResolveArgs ra) {
   constexpr int BS = 64, K = 512 / BS;
   extern __shared__ float4 lds[];
   const int w = blockIdx.x, tid = threadIdx.x;
@@ -2831,14 +2835,13 @@ __global__ __launch_bounds__(64) void step_free_kernel(CollideArgs ca, ResolveAr
   }
 }
 
-// condim 1, 3 and 4 (at most 128 VGPRs: four resident worlds per SIMD; at
-// condim 6 the one-wave kernel would hold three, and the two launches are faster)
 hipError_t launch_step_free(const CollideArgs &ca, const ResolveArgs &ra, int nworld, size_t lds, hipStream_t s) {
   if (ra.nsub > 0 || ra.mlp || ra.act || ra.nb > 64 || ra.nb < 1) return hipErrorInvalidValue;
   switch (ra.condim) {
     case 1: hipLaunchKernelGGL((step_free_kernel<1>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
     case 3: hipLaunchKernelGGL((step_free_kernel<3>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
     case 4: hipLaunchKernelGGL((step_free_kernel<4>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
+    case 6: hipLaunchKernelGGL((step_free_kernel<6>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -3194,7 +3197,8 @@ __global__ __launch_bounds__(BS, 2) void rollout_kernel(RolloutArgs r) {
 // 64 spheres), so as many worlds share a CU as with step launches, and the
 // worlds drift out of step with each other, overlapping one world's loads with
 // another's arithmetic.  Same device functions, arithmetic and summation
-// order as cf_step: the trajectories equal T steps bit for bit.
+// order as cf_step: the trajectories equal T steps to float32 rounding (bit
+// for bit where the compilations fuse the same multiplies and adds).
 __host__ __device__ inline size_t collide_cand_offset(int ng, int norient) {
   return (sizeof(Pose<double>) + sizeof(Pose<float>)) * (size_t)norient + sizeof(float4) * (size_t)ng +
          2 * sizeof(int) * (size_t)pad4(ng);
