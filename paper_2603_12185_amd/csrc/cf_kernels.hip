@@ -2584,17 +2584,46 @@ __host__ __device__ size_t resolve_free_lds_bytes(int nb, int ng) {
          sizeof(float4) * (size_t)ng;
 }
 
+// The geom table of world w as the free-body resolution stages it: entries
+// threadIdx.x and threadIdx.x + BS of the lane (body, tangential friction,
+// torsional and rolling friction), loaded unconditionally with indices
+// clamped into the arrays (which hold at least one entry); stored only where
+// below ng.
+struct FreeGeomPre {
+  int b0, b1;
+  float u0, u1;
+  float2 f0, f1;
+};
+
+template <int CONDIM, int BS>
+__device__ inline FreeGeomPre free_geom_prefetch(const ResolveArgs &a, int w, int tid) {
+  const int ng = a.ng, gl = ng > 0 ? ng - 1 : 0, g0 = tid < ng ? tid : gl, g1 = tid + BS < ng ? tid + BS : gl;
+  FreeGeomPre G;
+  G.b0 = a.gbody[g0];
+  G.b1 = a.gbody[g1];
+  G.u0 = a.gmu[(size_t)w * ng + g0];
+  G.u1 = a.gmu[(size_t)w * ng + g1];
+  G.f0 = G.f1 = make_float2(0.f, 0.f);
+  if (CONDIM >= 4) {
+    G.f0 = a.gfr2[(size_t)w * ng + g0];
+    G.f1 = a.gfr2[(size_t)w * ng + g1];
+  }
+  return G;
+}
+
 // Resolution of world w of free bodies, lane b owning body b: from the lane's
 // q (7), v (6) and applied-force (6) entries and mass/inertia, the world's nc
 // contacts (the first chunk's records cn, cp of lane threadIdx.x already
 // loaded by the caller, the rest read from cnp/cpos), to the lane's q+ and v+
 // (qo, vo; lanes beyond nb return zeros).  `lds`: resolve_free_lds_bytes();
-// `xbase`: row of the world in the export arrays.  Ends with a workgroup barrier
-// after the last read of the body arrays.
+// `xbase`: row of the world in the export arrays; `gpre`: the caller's
+// free_geom_prefetch of world w, or null.  Ends with a workgroup barrier after
+// the last read of the body arrays.
 template <int CONDIM, int BS>
 __device__ void resolve_free_world(const ResolveArgs &a, int w, const float *qb, const float *vb, const float *tb,
                                    float4 mi, int nc, float4 cn, float4 cp, const float4 *cnp, const float4 *cpos,
-                                   size_t xbase, float4 *lds, float *qo, float *vo, int tid_in = -1) {
+                                   size_t xbase, float4 *lds, float *qo, float *vo, int tid_in = -1,
+                                   const FreeGeomPre *gpre = nullptr) {
   constexpr int NF = CONDIM == 1 ? 1 : CONDIM == 3 ? 4 : CONDIM == 4 ? 6 : 10;
   const int tid = tid_in >= 0 ? tid_in : (int)threadIdx.x;
   const int nb = a.nb, ng = a.ng, nbp = pad4(nb);
@@ -2607,24 +2636,16 @@ __device__ void resolve_free_world(const ResolveArgs &a, int w, const float *qb,
   const Params P = a.p;
   const bool own = tid < nb;
   {
-    // geom table: two entries per lane loaded together, unconditionally
-    // (indices clamped into the arrays, which hold at least one entry), then
+    // geom table: two entries per lane (free_geom_prefetch, or the caller's),
     // stored where they exist; any further entries in a loop
-    const int gl = ng > 0 ? ng - 1 : 0, g0 = tid < ng ? tid : gl, g1 = tid + BS < ng ? tid + BS : gl;
-    const int b0 = a.gbody[g0], b1 = a.gbody[g1];
-    const float u0 = a.gmu[(size_t)w * ng + g0], u1 = a.gmu[(size_t)w * ng + g1];
-    float2 f0 = make_float2(0.f, 0.f), f1 = f0;
-    if (CONDIM >= 4) {
-      f0 = a.gfr2[(size_t)w * ng + g0];
-      f1 = a.gfr2[(size_t)w * ng + g1];
-    }
+    const FreeGeomPre G = gpre ? *gpre : free_geom_prefetch<CONDIM, BS>(a, w, tid);
     if (tid < ng) {
-      gB[tid] = b0;
-      gM[tid] = make_float4(u0, f0.x, f0.y, 0.f);
+      gB[tid] = G.b0;
+      gM[tid] = make_float4(G.u0, G.f0.x, G.f0.y, 0.f);
     }
     if (tid + BS < ng) {
-      gB[tid + BS] = b1;
-      gM[tid + BS] = make_float4(u1, f1.x, f1.y, 0.f);
+      gB[tid + BS] = G.b1;
+      gM[tid + BS] = make_float4(G.u1, G.f1.x, G.f1.y, 0.f);
     }
     for (int g = tid + 2 * BS; g < ng; g += BS) {
       gB[g] = a.gbody[g];
@@ -2789,20 +2810,7 @@ __global__ __launch_bounds__(64, CONDIM == 6 ? 4 : 1) void step_free_kernel(Coll
   const float *qw = ca.q + (size_t)w * ca.nq;
   RowStage<BS, K> rq;
   rq.load(qw, ca.nq);
-  rq.store(sq, qw, ca.nq);
-  __syncthreads();
-  const size_t cbase = (size_t)w * ca.ncon_max;
-  const int found = collide_world<BS, false>(ca, w, sq, lds + pad4(ca.nq) / 4, ca.cnp + cbase, ca.cpos + cbase,
-                                             ca.ncon_max, nxt, pre);
-  const int nc = found < ca.ncon_max ? found : ca.ncon_max;
-  if (tid == 0) {
-    ca.ncon[w] = nc;
-    ca.overflow[w] = found - nc;
-    if (ca.ncon_out) ca.ncon_out[w] = nc;
-    if (ca.overflow_out) ca.overflow_out[w] = found - nc;
-  }
-  // the resolution: the lane's body, the first chunk of the records this
-  // workgroup wrote (visible after collide_world's barrier)
+  // the resolution's per-lane body state, in flight through the narrow phase
   const int nb = ra.nb;
   const bool own = tid < nb;
   const int b = own ? tid : nb - 1;
@@ -2815,6 +2823,21 @@ __global__ __launch_bounds__(64, CONDIM == 6 ? 4 : 1) void step_free_kernel(Coll
     for (int i = 0; i < 6; ++i) vb[i] = vs[i];
   }
   const float4 mi = ra.bmi[(size_t)w * nb + b];
+  const FreeGeomPre gpre = free_geom_prefetch<CONDIM, BS>(ra, w, tid);
+  rq.store(sq, qw, ca.nq);
+  __syncthreads();
+  const size_t cbase = (size_t)w * ca.ncon_max;
+  const int found = collide_world<BS, false>(ca, w, sq, lds + pad4(ca.nq) / 4, ca.cnp + cbase, ca.cpos + cbase,
+                                             ca.ncon_max, nxt, pre);
+  const int nc = found < ca.ncon_max ? found : ca.ncon_max;
+  if (tid == 0) {
+    ca.ncon[w] = nc;
+    ca.overflow[w] = found - nc;
+    if (ca.ncon_out) ca.ncon_out[w] = nc;
+    if (ca.overflow_out) ca.overflow_out[w] = found - nc;
+  }
+  // the resolution: the first chunk of the records this workgroup wrote
+  // (visible after collide_world's barrier)
   const int r0 = tid < nc ? tid : (nc > 0 ? nc - 1 : 0);
   const float4 cn = ra.cnp[cbase + r0], cp = ra.cpos[cbase + r0];
 #pragma unroll
@@ -2825,7 +2848,8 @@ __global__ __launch_bounds__(64, CONDIM == 6 ? 4 : 1) void step_free_kernel(Coll
     for (int i = 0; i < 6; ++i) tb[i] = ts[i];
   }
   float qo[7], vo[6];
-  resolve_free_world<CONDIM, BS>(ra, w, qb, vb, tb, mi, nc, cn, cp, ra.cnp + cbase, ra.cpos + cbase, cbase, lds, qo, vo);
+  resolve_free_world<CONDIM, BS>(ra, w, qb, vb, tb, mi, nc, cn, cp, ra.cnp + cbase, ra.cpos + cbase, cbase, lds, qo, vo,
+                                 -1, &gpre);
   if (own) {
     float *qd = ra.q_out + (size_t)w * ra.nq + 7 * tid, *vd = ra.v_out + (size_t)w * ra.nv + 6 * tid;
 #pragma unroll
