@@ -287,11 +287,12 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
                             float *best_step_us, float *best_rollout_step_us);
 
 /* Kernels of one cf_step: 1 when the narrow phase and the resolution of each
- * world run in one kernel (worlds of 1 to 64 free bodies without actuators or
- * learned gains, at the one-wave launch shapes 64/64, and
- * kernel timing off; a world's resolution then starts as soon as its own
- * narrow phase ends; the same contacts as the two launches and results equal
- * to float32 rounding), else 2.
+ * world run in one kernel (no learned gains, the one-wave launch shapes 64/64,
+ * kernel timing off, the world's LDS within the limit, and either 1 to 64
+ * free bodies without actuators or articulated subtrees, actuated or not; a
+ * world's resolution then starts as soon as its own narrow phase ends; the
+ * same contacts as the two launches and results equal to float32 rounding),
+ * else 2.
  * Host call, no device work. */
 cf_status cf_model_step_kernels(const cf_model *m, int32_t *nkernels);
 

@@ -577,6 +577,13 @@ static bool step_fused(const cf_model *m) {
          std::max(m->lds_collide, m->lds_resolve_free) <= kLdsLimit;
 }
 
+// Models with articulated subtrees (no learned gains) at the one-wave launch
+// shapes: the same, the narrow phase and the general resolution in one kernel.
+static bool step_fused_art(const cf_model *m) {
+  return !m->prof && !m->mlp && m->nsub > 0 && m->nb >= 1 && m->block_collide == 64 && m->block_resolve == 64 &&
+         std::max(m->lds_collide, m->lds_resolve) <= kLdsLimit;
+}
+
 static bool rollout_fused(const cf_model *m) {
   return !m->rollout_steps && !m->mlp && (rollout_free(m) || m->lds_rollout <= kLdsLimit);
 }
@@ -653,6 +660,18 @@ cf_status cf_step(cf_model *m, void *stream, const float *q, const float *v, con
       ra.x_fallback = out->fallback;
     }
     const hipError_t e = cf::launch_step_free(ca, ra, m->nw, std::max(m->lds_collide, m->lds_resolve_free), s);
+    if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    return CF_OK;
+  }
+  if (step_fused_art(m)) {
+    cf::ResolveArgs ra = resolve_args(m);
+    ra.q = q; ra.v = v; ra.tau = tau; ra.q_out = q_out; ra.v_out = v_out;
+    if (out) {
+      ra.x_geom = out->geom; ra.x_sub = out->sub; ra.x_dist = out->dist; ra.x_pos = out->pos;
+      ra.x_frame = out->frame; ra.x_imp = out->impulse;
+      ra.x_fallback = out->fallback;
+    }
+    const hipError_t e = cf::launch_step_art(ca, ra, m->nw, std::max(m->lds_collide, m->lds_resolve), s);
     if (e != hipSuccess) return set_err(CF_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return CF_OK;
   }
@@ -918,7 +937,7 @@ cf_status cf_model_autotune(cf_model *m, void *stream, const float *q, const flo
 
 cf_status cf_model_step_kernels(const cf_model *m, int32_t *nkernels) {
   if (!m || !nkernels) return set_err(CF_E_INVALID_ARG, "model and nkernels must be non-NULL");
-  *nkernels = step_fused(m) ? 1 : 2;
+  *nkernels = step_fused(m) || step_fused_art(m) ? 1 : 2;
   return CF_OK;
 }
 

@@ -181,6 +181,7 @@ hipError_t launch_resolve(const ResolveArgs &a, int nworld, int block, size_t ld
 __host__ __device__ size_t resolve_free_lds_bytes(int nb, int ng);
 hipError_t launch_resolve_free(const ResolveArgs &a, int nworld, int block, size_t lds, hipStream_t s);
 hipError_t launch_step_free(const CollideArgs &ca, const ResolveArgs &ra, int nworld, size_t lds, hipStream_t s);
+hipError_t launch_step_art(const CollideArgs &ca, const ResolveArgs &ra, int nworld, size_t lds, hipStream_t s);
 // The same with learned gains (network image of launch_mlp_pack_k32 in
 // mlp_img), four worlds of at most 128 free bodies per workgroup.
 size_t resolve_learned_k32_lds_bytes(int nb, int ng);

@@ -2208,7 +2208,7 @@ struct LanePre {
 };
 
 template <bool ART>
-__device__ inline LanePre lane_prefetch(const ResolveArgs &a, int w) {
+__device__ inline LanePre lane_prefetch(const ResolveArgs &a, int w, bool frames = true) {
   const int tid = threadIdx.x;
   // every lane loads (indices clamped into the tables; a lane past the dofs,
   // bodies or subtrees holds another entry's values, which it never uses), so
@@ -2230,7 +2230,7 @@ __device__ inline LanePre lane_prefetch(const ResolveArgs &a, int w) {
     L.qadr = bc.qadr;
     L.dadr = bc.dadr;
     L.ipos = bc.ipos;
-    if (a.frames) {
+    if (frames && a.frames) {
       const float4 *f = a.frames + ((size_t)w * a.nb + b) * 5;
 #pragma unroll
       for (int i = 0; i < 5; ++i) L.fr[i] = f[i];
@@ -2866,6 +2866,95 @@ hipError_t launch_step_free(const CollideArgs &ca, const ResolveArgs &ra, int nw
     case 3: hipLaunchKernelGGL((step_free_kernel<3>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
     case 4: hipLaunchKernelGGL((step_free_kernel<4>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
     case 6: hipLaunchKernelGGL((step_free_kernel<6>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// One step of a world with articulated subtrees in one one-wave workgroup:
+// the narrow phase (collide_kernel's, float64 kinematics writing the small
+// subtrees' frames) and then the resolution (resolve_kernel's), the contact
+// records and frames through the model's buffers as between the two kernels
+// (read back by the same workgroup after the narrow phase's barrier) and the
+// q row kept in LDS between the phases.  The resolution's loads that do not
+// depend on the narrow phase (v and tau rows, mass/inertia, actuator, body and
+// subtree records, the geom table) are issued before it and stay in flight
+// through it.  Same device functions in the same order as the two kernels.
+template <int CONDIM>
+__global__ __launch_bounds__(64) void step_art_kernel(CollideArgs ca, ResolveArgs ra) {
+  constexpr int BS = 64, K = 512 / BS;
+  extern __shared__ float4 lds[];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int nq = ra.nq, nv = ra.nv, nb = ra.nb, ng = ra.ng;
+  float *sq = reinterpret_cast<float *>(lds);
+  const uint32_t nxt = ca.slots[tid < ca.nslot_pre ? tid : (ca.nslot_pre > 0 ? ca.nslot_pre - 1 : 0)];
+  const int gl = ng > 0 ? ng - 1 : 0;
+  const GeomIn pre[2] = {geom_in(ca, w, tid < ng ? tid : gl), geom_in(ca, w, tid + BS < ng ? tid + BS : gl)};
+  const float *qw = ca.q + (size_t)w * nq, *vw = ra.v + (size_t)w * nv;
+  const float *tw = ra.tau ? ra.tau + (size_t)w * nv : nullptr;
+  RowStage<BS, K> rq, rv, rt;
+  rq.load(qw, nq);
+  // the resolution's loads, in flight through the narrow phase
+  const float4 mi0 = ra.bmi[(size_t)w * nb + (tid < nb ? tid : (nb > 0 ? nb - 1 : 0))];
+  LanePre L = lane_prefetch<true>(ra, w, false);
+  const int gb0 = ra.gbody[tid < ng ? tid : gl];
+  const float mu0 = ra.gmu[(size_t)w * ng + (tid < ng ? tid : gl)];
+  float2 fr0 = make_float2(0.f, 0.f);
+  if (CONDIM >= 4) fr0 = ra.gfr2[(size_t)w * ng + (tid < ng ? tid : gl)];
+  rv.load(vw, nv);
+  if (tw) rt.load(tw, nv);
+  rq.store(sq, qw, nq);
+  __syncthreads();
+  const size_t cbase = (size_t)w * ca.ncon_max;
+  const int found = collide_world<BS, true>(ca, w, sq, lds + pad4(nq) / 4, ca.cnp + cbase, ca.cpos + cbase,
+                                            ca.ncon_max, nxt, pre);
+  const int nc = found < ca.ncon_max ? found : ca.ncon_max;
+  if (tid == 0) {
+    ca.ncon[w] = nc;
+    ca.overflow[w] = found - nc;
+    if (ca.ncon_out) ca.ncon_out[w] = nc;
+    if (ca.overflow_out) ca.overflow_out[w] = found - nc;
+  }
+  // the resolution: v and tau rows after the q row (over the narrow phase's
+  // scratch), the first chunk of the records and the small subtrees' frames
+  // this workgroup wrote (visible after collide_world's barrier)
+  float *sv = sq + pad4(nq);
+  float *st = sv + pad4(nv);
+  float4 *reg = reinterpret_cast<float4 *>(st + pad4(nv));
+  const int r0 = tid < nc ? tid : (nc > 0 ? nc - 1 : 0);
+  const float4 c0n = ra.cnp[cbase + r0], c0p = ra.cpos[cbase + r0];
+  if (ra.frames) {
+    const int b = tid < nb ? tid : nb - 1;
+    const float4 *f = ra.frames + ((size_t)w * nb + b) * 5;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) L.fr[i] = f[i];
+  }
+  rv.store(sv, vw, nv);
+  if (tw) {
+    rt.store(st, tw, nv);
+  } else {
+    for (int i = tid; i < nv; i += BS) st[i] = 0.f;
+  }
+  const ResolveRegion RR = resolve_region(reg, nb, ng);
+  if (tid < ng) {
+    RR.gB[tid] = gb0;
+    RR.gM[tid] = make_float4(mu0, fr0.x, fr0.y, 0.f);
+  }
+  resolve_geoms<CONDIM, BS>(ra, w, RR.gB, RR.gM, BS);
+  resolve_world<CONDIM, BS, true>(ra, w, sq, sv, st, ra.cnp + cbase, ra.cpos + cbase, nc, c0n, c0p, mi0, reg, cbase,
+                                  true, nullptr, nullptr, nullptr, &L);
+  float *qo = ra.q_out + (size_t)w * nq, *vo = ra.v_out + (size_t)w * nv;
+  for (int i = tid; i < nq; i += BS) qo[i] = sq[i];
+  for (int i = tid; i < nv; i += BS) vo[i] = sv[i];
+}
+
+hipError_t launch_step_art(const CollideArgs &ca, const ResolveArgs &ra, int nworld, size_t lds, hipStream_t s) {
+  if (ra.nsub < 1 || ra.mlp || ra.nb < 1) return hipErrorInvalidValue;
+  switch (ra.condim) {
+    case 1: hipLaunchKernelGGL((step_art_kernel<1>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
+    case 3: hipLaunchKernelGGL((step_art_kernel<3>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
+    case 4: hipLaunchKernelGGL((step_art_kernel<4>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
+    case 6: hipLaunchKernelGGL((step_art_kernel<6>), dim3(nworld), dim3(64), lds, s, ca, ra); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

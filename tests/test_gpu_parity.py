@@ -468,6 +468,62 @@ def test_one_kernel_step_equals_two_launches(torch_cuda, condim):
         print("bitwise equal:", bool(torch.equal(q1, q2) and torch.equal(v1, v2)))
 
 
+@pytest.mark.parametrize("case", ["mix1", "mix3", "mix4", "mix6", "hand3", "hand6", "sib3", "sls6", "bob3",
+                                  "hand6d", "mix3d"])
+def test_one_kernel_articulated_step_equals_two_launches(torch_cuda, case):
+    """cf_step of a model with articulated subtrees at the one-wave launch
+    shapes runs the narrow phase (with the small subtrees' float64 frames)
+    and the general resolution in one kernel: against the two kernels, along
+    a trajectory with contacts (actuator targets on the hand), the contact
+    set is identical and every float32 result equal to rounding (see the
+    free-body test above for why not always bitwise).  A trailing "d": the
+    exact diagonal impedance, compared from the states of the heuristic
+    form's trajectory (articulated trajectories under the diagonal form leave
+    the bounded regime, where rounding differences grow without bound)."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    diag = case.endswith("d")
+    s, T, every, taus = _diag_articulated_case(case.rstrip("d"))
+    traj = cfsim.Model(s)
+    traj.set_launch(64, 64)
+    if diag:
+        sd = dict(s)
+        sd["impedance"] = 1
+        model = cfsim.Model(sd)
+        model.set_launch(64, 64)
+    else:
+        model = traj
+    assert model.step_kernels() == 1 and traj.step_kernels() == 1
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    print(f"case: one-kernel articulated step {case}", flush=True)
+    checked = 0
+    for t in range(T):
+        tau = None if taus is None else tdev(taus[t])
+        if t % every == 0:
+            c1 = model.alloc_contacts()
+            q1, v1 = model.step(q, v, tau=tau, contacts=c1)
+            model.set_profiling(True)
+            assert model.step_kernels() == 2
+            c2 = model.alloc_contacts()
+            q2, v2 = model.step(q, v, tau=tau, contacts=c2)
+            model.set_profiling(False)
+            torch.cuda.synchronize()
+            for k in ("ncon", "overflow", "geom", "sub"):
+                assert torch.equal(c1[k], c2[k]), (t, k)
+            checked += int(c1["ncon"].sum())
+
+            def close(a, b, rel=1e-6):
+                return float((a - b).abs().max()) <= rel * max(float(a.abs().max()), 1.0)
+
+            assert close(q1, q2) and close(v1, v2), t
+            for k in c1:
+                if c1[k].is_floating_point():
+                    assert close(c1[k], c2[k], 1e-5), (t, k)
+        q, v = traj.step(q, v, tau=tau)
+    assert checked > 0
+    print("contacts compared:", checked)
+
+
 def test_rollout_graph_capture_replays(torch_cuda):
     """A stream capture of cf_rollout replays correctly: three replays with new
     initial states, eager work and synchronisations in between, each checked
