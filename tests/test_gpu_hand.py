@@ -68,6 +68,56 @@ def test_hand_parity(torch_cuda, condim):
     assert stats["contacts"] > 200 and box_contacts > 20
 
 
+def test_hand_full_size_sampled(torch_cuda):
+    """The hand's batch at full size (2048 worlds, condim 6) in the launch
+    shape the bench's autotuner picks for it (one wave per world, one kernel
+    per step): every world driven by its own target schedule; at steps 60, 120
+    and 199 the sampled worlds take the oracle's own trajectory states and
+    their step is compared with the oracle's; every world stays finite and
+    within its contact capacity."""
+    from paper_2603_12185_amd import cfsim
+    torch = torch_cuda
+    s = scenes.hand_cube(nworld=2048, seed=5, condim=6)
+    model = cfsim.Model(s)
+    model.set_launch(64, 64)
+    assert model.step_kernels() == 1
+    T, checks = 200, (60, 120, 199)
+    taus = _target_schedule(s, T, 40, 0.35, seed=5)
+    sample = [0, 1, 1023, 2047]
+    ss = scenes.select_worlds(s, sample)
+    o = Oracle(ss)
+    print("case: hand_cube 2048 worlds full size", flush=True)
+    qo, vo = ss["q0"].astype(np.float64), ss["v0"].astype(np.float64)
+    ostates = {}
+    for t in range(T):
+        if t in checks:
+            ostates[t] = (qo.astype(np.float32), vo.astype(np.float32))
+        qo, vo, _ = o.step(qo, vo, tau=taus[t][sample].astype(np.float64), outputs=False)
+    idx = torch.tensor(sample, device="cuda")
+    q, v = tdev(s["q0"]), tdev(s["v0"])
+    stats = None
+    for t in range(T):
+        con = None
+        tau = tdev(taus[t])
+        if t in checks:
+            con = model.alloc_contacts()
+            q[idx], v[idx] = tdev(ostates[t][0]), tdev(ostates[t][1])
+        q1, v1 = model.step(q, v, tau=tau, contacts=con)
+        if con is not None:
+            c = to_np(con)
+            assert (c["ncon"] <= s["ncon_max"]).all() and (c["overflow"] == 0).all()
+            qn, vn = q1.cpu().numpy(), v1.cpu().numpy()
+            assert np.isfinite(qn).all() and np.isfinite(vn).all()
+            sub = {k: val[sample] for k, val in c.items()}
+            stats = compare_step(ss, o, ostates[t][0], ostates[t][1], taus[t][sample], qn[sample], vn[sample],
+                                 sub, stats=stats)
+            print(f"step {t}: mean contacts/world {c['ncon'].mean():.2f} max {c['ncon'].max()}")
+        q, v = q1, v1
+    torch.cuda.synchronize()
+    print("hand full-size sampled parity", stats)
+    assert stats["checked"] >= len(checks) * len(sample) // 2 and stats["contacts"] > 0
+
+
 def test_hand_rollout_matches_steps(torch_cuda):
     """cf_rollout with per-step finger targets (persistent kernel) against
     cf_step from every rollout state: same contact counts, velocities equal to
