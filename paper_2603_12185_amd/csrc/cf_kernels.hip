@@ -2269,6 +2269,9 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
   float4 *bO = RR.bO, *bAx = RR.bAx, *bR = RR.bR;  // articulated bodies only
   float *art = RR.art;
   const Params P = a.p;
+  // the general subtree path's out-of-line calls take the parameters by
+  // reference: their own copy, so that P's fields stay in registers here
+  const Params Pcall = a.p;
   // what the lane reads below, loaded together up front unless the caller
   // has (its actuator, body record, subtree and body frame)
   const LanePre L = pre ? *pre : lane_prefetch<ART>(a, w);
@@ -2340,7 +2343,8 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     if (S.small)
       art_predict_small(S, t & 3, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P, yd);
     else if ((t & 3) == 0)
-      art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, P, yd);
+      art_predict(S, a.body, a.bmi + (size_t)w * nb, sq, sv, st, bC, bV, bW, bO, bAx, bR, art + S.lofs, Pcall,
+                  yd);
     if (yd && (t & 3) == 0)  // the subtree's bodies: where their L^-1 J^T columns are
       for (int k = 0; k < S.nb; ++k) {
         bI0[S.b0 + k] = make_float4(__int_as_float(S.yofs + 6 * S.nd * k), __int_as_float(S.nd),
@@ -2483,7 +2487,7 @@ __device__ void resolve_world(const ResolveArgs &a, int w, float *sq, float *sv,
     if (S.small)
       art_correct_small(S, t & 3, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
     else if ((t & 3) == 0)
-      art_correct(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, P);
+      art_correct(S, a.body, bC, bO, bAx, accF, accT, sq, sv, art + S.lofs, Pcall);
   }
   for (int b = tid; b < nb; b += BS) {
     int qadr = 7 * b, dadr = 6 * b;
