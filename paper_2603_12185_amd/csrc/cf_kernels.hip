@@ -446,7 +446,16 @@ __device__ __attribute__((noinline)) void art_predict(const SubTree S, const Bod
 // after the correction (at nd^2) and v_s (at nd^2 + nd).
 struct SmallChain {
   int n, anc[kSmallSub], jnt[kSmallSub], qadr[kSmallSub], dadr[kSmallSub];
+  uint32_t chain;
+  int q0, d0;
 };
+
+// Entry k of the chain's tables for a lane-dependent k, computed from the
+// subtree record (no indexed access to the tables, which would put them on
+// the stack).
+__device__ inline int chain_anc(const SmallChain &C, int k) { return k < C.n ? (int)((C.chain >> (4 * k)) & 15) : 0; }
+__device__ inline int chain_qadr(const SmallChain &C, int k) { return k < C.n ? C.q0 + k : 0; }
+__device__ inline int chain_dadr(const SmallChain &C, int k) { return k < C.n ? C.d0 + k : 0; }
 
 // x[k] for a lane-dependent k, as selects (no indexed register access).
 template <class T>
@@ -460,6 +469,9 @@ __device__ inline T pick(const T (&x)[kSmallSub], int k) {
 __device__ inline SmallChain small_chain(const SubTree S) {
   SmallChain C;
   C.n = S.nb;
+  C.chain = (uint32_t)S.chain;
+  C.q0 = S.q0;
+  C.d0 = S.d0;
 #pragma unroll
   for (int k = 0; k < kSmallSub; ++k) {
     const bool in = k < C.n;
@@ -507,13 +519,13 @@ __device__ inline void quad_chain(const SubTree S, const SmallChain &C, int k, c
                                   const float *sq, QuadChain<T> &Q) {
   constexpr int N = kSmallSub;
   const bool own = k < C.n;
-  const T th = own ? (T)sq[pick(C.qadr, k)] : T(0);
+  const T th = own ? (T)sq[chain_qadr(C, k)] : T(0);
   T sn, cs;
   sin_cos(th, &sn, &cs);
   const T tj[N] = {quad_bcast<0>(th), quad_bcast<1>(th), quad_bcast<2>(th), quad_bcast<3>(th)};
   const T sj[N] = {quad_bcast<0>(sn), quad_bcast<1>(sn), quad_bcast<2>(sn), quad_bcast<3>(sn)};
   const T cj[N] = {quad_bcast<0>(cs), quad_bcast<1>(cs), quad_bcast<2>(cs), quad_bcast<3>(cs)};
-  const int anc = own ? pick(C.anc, k) : 0;
+  const int anc = own ? chain_anc(C, k) : 0;
   T pR[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)}, po[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -591,7 +603,7 @@ __device__ void art_predict_small(const SubTree S, int k, const float *sv, const
   const int n = C.n;
   const bool own = k < n;
   const int b = S.b0 + k;
-  const int anck = own ? pick(C.anc, k) : 0;
+  const int anck = own ? chain_anc(C, k) : 0;
   const float4 mi = own ? bW[b] : make_float4(0.f, 1.f, 1.f, 1.f);
   const float4 ip = own ? bC[b] : make_float4(0.f, 0.f, 0.f, 0.f);
   struct {
@@ -790,7 +802,7 @@ __device__ void art_correct_small(const SubTree S, int k, const BodyC *B, const 
   const int n = C.n;
   const bool own = k < n;
   const int b = S.b0 + k;
-  const int anck = own ? pick(C.anc, k) : 0;
+  const int anck = own ? chain_anc(C, k) : 0;
   V3 cb = v3(0.f, 0.f, 0.f), F = cb, T = cb;
   if (own) {
     cb = v3(bC[b].x, bC[b].y, bC[b].z);
@@ -835,8 +847,8 @@ __device__ void art_correct_small(const SubTree S, int k, const BodyC *B, const 
     const float pk = pick(p, k);
     blk[n * n + k] = pk;  // z = M^-1 p, read by the adjoint
     const float vp = blk[n * n + n + k] + pk;
-    sv[pick(C.dadr, k)] = vp;
-    sq[pick(C.qadr, k)] += P.h * vp;
+    sv[chain_dadr(C, k)] = vp;
+    sq[chain_qadr(C, k)] += P.h * vp;
   }
 }
 
